@@ -1,0 +1,248 @@
+/*
+ * sgrid.h -- C ABI of the sparse-dense SDF grid renderer for AMD gfx950.
+ *
+ * The method: Dong et al., "Fast Monocular Scene Reconstruction with
+ * Global-Sparse Local-Dense Grids" (CVPR 2023).  A scene is a set of 8^3
+ * voxel blocks allocated only near surfaces and found through a
+ * collision-free spatial hash (Sec. 3.2).  Each voxel stores an SDF value and
+ * C feature channels (colour, optionally semantic logits).  Rays are marched
+ * through the allocated blocks only, sampled uniformly, the SDF and features
+ * are trilinearly interpolated together with the closed-form SDF gradient
+ * (Eq. 17-18), the SDF is turned into density with the Laplace-CDF transform
+ * and colour, depth and normal are alpha-composited (Eq. 12-15,
+ * Sec. 3.5.1).  The backward pass scatters gradients into the voxels.
+ *
+ * Conventions used by every call
+ * -------------------------------
+ *  - Pointers named d_* are DEVICE memory owned by the caller.  The library
+ *    never frees them and keeps no reference after a call returns.
+ *  - sg_stream is a hipStream_t (NULL = the legacy default stream).  Every
+ *    call except sg_grid_build / sg_grid_destroy / sg_grid_num_blocks is
+ *    asynchronous on that stream, allocates nothing and never synchronises,
+ *    so it may be captured in a HIP graph.
+ *  - Return value: SG_OK (0) or a negative sg_status.  All argument checks
+ *    run on the host before any HIP call; on error nothing is launched and
+ *    sg_last_error() returns a message (thread-local, valid until the next
+ *    failing call on the same thread).
+ *  - A grid's geometry: voxel (i,j,k) (integer, global) sits at
+ *    origin + (i,j,k) * voxel_size.  Block b = floor(i/8) per axis; the
+ *    voxel's local index inside its block is lx + 8*ly + 64*lz with
+ *    l = i - 8*b.  Block coordinates must lie in [-2^20, 2^20) per axis.
+ *  - Voxel parameters are one float32 array vox[n_blocks][512][1+C]
+ *    (channel 0 = SDF theta_d, channels 1..C = features theta_c / theta_s),
+ *    row-major, block order = the grid's block index order.
+ *  - Supported feature counts C: 0,1,2,3,4,8,16,19,32.
+ */
+#ifndef SGRID_H
+#define SGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_grid sg_grid;
+typedef void* sg_stream;
+
+typedef enum sg_status {
+  SG_OK = 0,
+  SG_EINVAL = -1, /* bad argument: null pointer, size, unsupported C, ... */
+  SG_ERANGE = -2, /* a block coordinate outside [-2^20, 2^20) */
+  SG_ENOMEM = -3, /* device allocation failed (grid build only) */
+  SG_EHIP = -4,   /* a HIP runtime call failed; message names it */
+  SG_ESTATE = -5  /* object in the wrong state (e.g. destroyed grid) */
+} sg_status;
+
+#define SG_BLOCK_DIM 8
+#define SG_BLOCK_VOXELS 512
+#define SG_COORD_LIMIT 1048576 /* 2^20 */
+#define SG_MAX_SAMPLES_LIMIT 1024
+
+/*
+ * Ray-march and density parameters (Sec. 3.5.1, Eq. 15).
+ *   step        lattice spacing along the ray in world units (> 0): sample k
+ *               sits at t_k = t_near + k*step.  Every kept sample uses
+ *               delta_k = step.
+ *   t_near/far  the lattice covers t_near <= t_k <= t_far (t_far inclusive);
+ *               (t_far - t_near)/step must stay below 2^24.
+ *   beta        scale of the Laplace-CDF density (> 0):
+ *               sigma(f) = (1/beta) * Psi_beta(-f).
+ *   max_samples cap on kept samples per ray, 1..1024; the first max_samples
+ *               valid lattice points are kept, in lattice order.
+ * A lattice point is a valid sample iff the blocks holding all 8 corners of
+ * its interpolation cell are allocated (the sparse grid skips empty space).
+ */
+typedef struct sg_render_params {
+  float step;
+  float t_near;
+  float t_far;
+  float beta;
+  int32_t max_samples;
+} sg_render_params;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* sg_last_error(void);
+
+/* Library version string. */
+const char* sg_version(void);
+
+/*
+ * sg_grid_build -- the collision-free spatial hash over allocated blocks
+ * (Sec. 3.2 and 3.4.1: blocks indexed one-to-one by their integer block
+ * coordinate).
+ *   d_block_coords  int32 [n,3] device, block coordinates (duplicates allowed).
+ *   n               number of input coordinates, 1 <= n <= 2^31-1.
+ *   voxel_size      world edge length of one voxel (> 0, finite).
+ *   origin          host float[3]: world position of voxel (0,0,0).
+ *   d_index_of_input  nullable int32 [n] device: receives the block index of
+ *                   every input row.
+ * Block indices are assigned in order of first occurrence in the input and
+ * duplicates are merged, so the result is deterministic.  Builds the hash
+ * table, the block list and an 8-entry neighbour table per block.  The call
+ * allocates device memory and synchronises the stream (build time only).
+ * Errors: SG_EINVAL (null/size), SG_ERANGE (a coordinate out of range; no
+ * grid is returned), SG_ENOMEM, SG_EHIP.  *out is set only on SG_OK; the
+ * caller releases it with sg_grid_destroy.
+ */
+int sg_grid_build(const int32_t* d_block_coords, int64_t n, float voxel_size,
+                  const float origin[3], sg_stream stream, sg_grid** out,
+                  int32_t* d_index_of_input);
+
+/* Number of allocated (unique) blocks. */
+int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks);
+
+/* World geometry of the grid: voxel_size and origin[3] (host outputs). */
+int sg_grid_geometry(const sg_grid* g, float* voxel_size, float origin[3]);
+
+/* Copy the unique block coordinates, int32 [n_blocks,3], in index order. */
+int sg_grid_block_coords(const sg_grid* g, int32_t* d_out, sg_stream stream);
+
+/*
+ * Copy the neighbour table int32 [n_blocks,8]: entry s = sx + 2*sy + 4*sz
+ * (sx,sy,sz in {0,1}) holds the index of block b + (sx,sy,sz), or -1 if that
+ * block is not allocated.  These are the blocks a trilinear cell whose base
+ * voxel lies in block b can touch (Eq. 17).
+ */
+int sg_grid_neighbors(const sg_grid* g, int32_t* d_out, sg_stream stream);
+
+/*
+ * sg_grid_lookup -- hash query (Sec. 3.2): d_idx[i] = index of block
+ * d_coords[i] (int32 [n,3]) or -1 if not allocated (also -1 for coordinates
+ * outside the representable range).  n may be 0.
+ */
+int sg_grid_lookup(const sg_grid* g, const int32_t* d_coords, int64_t n,
+                   int32_t* d_idx, sg_stream stream);
+
+/* Free the grid's device memory (waits for nothing; the caller makes sure no
+ * launched work still uses the grid).  NULL is accepted. */
+int sg_grid_destroy(sg_grid* g);
+
+/*
+ * sg_rays_pinhole -- camera rays of pixels (the inverse projection of the
+ * pinhole model used in the reprojection of Eq. 3).
+ *   d_cams   float [n_cams,16]: fx, fy, cx, cy, then the camera-to-world
+ *            matrix rows [R | t] (3x4, row-major).  Camera axes: x right,
+ *            y down, z forward.
+ *   d_pix    int32 [R,3]: camera index, pixel column u, pixel row v.  The
+ *            ray passes through the pixel centre (u+0.5, v+0.5).
+ *   d_rays   float [R,6] output: origin t, then the unit world direction
+ *            normalise(R * ((u+0.5-cx)/fx, (v+0.5-cy)/fy, 1)).
+ * A camera index outside [0,n_cams) yields a ray of NaNs (which renders as
+ * an empty ray).  R may be 0.
+ */
+int sg_rays_pinhole(const float* d_cams, int32_t n_cams, const int32_t* d_pix,
+                    int64_t n_rays, float* d_rays, sg_stream stream);
+
+/*
+ * sg_render_forward -- volume rendering through the sparse grid
+ * (Sec. 3.5.1, Eq. 12-15, with f and grad f from Eq. 17-18).
+ * For each ray (o,d) in d_rays float [R,6] (d of unit length; the caller's
+ * contract, not renormalised), samples t_k as described in sg_render_params,
+ * and with theta interpolated trilinearly at x_k = o + t_k d:
+ *   sigma_k = (1/beta) Psi_beta(-f(x_k)),  Psi_beta(s) = 1/2 exp(s/beta) for
+ *             s <= 0, 1 - 1/2 exp(-s/beta) otherwise  (VolSDF's transform)
+ *   w_k     = exp(-sum_{j<k} sigma_j step) * (1 - exp(-sigma_k step))
+ *   feat_out = sum_k w_k c(x_k)       [R,C]  (nullable iff C == 0)
+ *   depth    = sum_k w_k t_k          [R]    (ray distance; not divided by W)
+ *   normal   = sum_k w_k grad f(x_k)  [R,3]  (world frame, not normalised)
+ *   wsum     = sum_k w_k              [R]
+ *   nsamples = number of kept samples [R] int32 (nullable)
+ * d_vox float [n_blocks,512,1+C].  Rays with non-finite o or d, or that keep
+ * no sample, produce exact zeros.  Deterministic: repeated calls give
+ * bit-identical outputs (no atomics).  All outputs are overwritten.
+ */
+int sg_render_forward(const sg_grid* g, const float* d_vox, int32_t C,
+                      const float* d_rays, int64_t n_rays,
+                      const sg_render_params* params, float* d_feat_out,
+                      float* d_depth, float* d_normal, float* d_wsum,
+                      int32_t* d_nsamples, sg_stream stream);
+
+/*
+ * sg_render_backward -- adjoint of sg_render_forward with respect to the
+ * voxel parameters (the differentiable indexer of Sec. 3.2 and the
+ * closed-form gradient of Eq. 18, so no double backward is needed).
+ * Given upstream gradients of a scalar loss L:
+ *   d_g_feat [R,C] (nullable iff C == 0), d_g_depth [R], d_g_normal [R,3],
+ *   d_g_wsum [R] (nullable: treated as zero),
+ * ACCUMULATES dL/dvox into d_grad_vox float [n_blocks,512,1+C] (the caller
+ * zeroes it first).  Per-sample quantities are recomputed from the grid
+ * rather than stored by the forward pass.  Uses float32 atomic adds, so the
+ * summation order (and the last bits) may differ between calls.
+ */
+int sg_render_backward(const sg_grid* g, const float* d_vox, int32_t C,
+                       const float* d_rays, int64_t n_rays,
+                       const sg_render_params* params, const float* d_g_feat,
+                       const float* d_g_depth, const float* d_g_normal,
+                       const float* d_g_wsum, float* d_grad_vox,
+                       sg_stream stream);
+
+/*
+ * sg_render_footprint -- memory-traffic accounting of the render (integer,
+ * exact).  For each ray writes d_counts int32 [R,3] = (S, U, K): kept
+ * samples, distinct voxels read by their interpolation cells, distinct
+ * blocks holding those voxels.  If d_touched (uint8 [n_blocks*512],
+ * nullable) is given, sets d_touched[voxel] = 1 for every voxel read by any
+ * ray (entries never read are left unchanged; the caller zeroes it).
+ */
+int sg_render_footprint(const sg_grid* g, const float* d_rays, int64_t n_rays,
+                        const sg_render_params* params, int32_t* d_counts,
+                        uint8_t* d_touched, sg_stream stream);
+
+/*
+ * sg_l2_loss_grad -- the rendering losses of Eq. 12-14 in squared-L2 form,
+ * averaged over rays:
+ *   L = (1/R) sum_r ( |C_r - C*_r|^2 + lambda_d (D_r - D*_r)^2
+ *                     + lambda_n |N_r - N*_r|^2 )
+ * Inputs: d_feat/d_feat_ref [R,C], d_depth/d_depth_ref [R],
+ * d_normal/d_normal_ref [R,3].  Writes dL/d(feat, depth, normal) into
+ * d_g_feat [R,C], d_g_depth [R], d_g_normal [R,3] and, if d_loss (float[1])
+ * is non-null, the loss value (deterministic two-level reduction).
+ * lambda_d or lambda_n may be 0 (that term's gradient is then zero).
+ */
+int sg_l2_loss_grad(const float* d_feat, const float* d_feat_ref,
+                    const float* d_depth, const float* d_depth_ref,
+                    const float* d_normal, const float* d_normal_ref,
+                    int64_t n_rays, int32_t C, float lambda_d, float lambda_n,
+                    float* d_g_feat, float* d_g_depth, float* d_g_normal,
+                    float* d_loss, sg_stream stream);
+
+/*
+ * sg_optim_step -- one in-place optimiser step on float32 parameters
+ * (Sec. 3.5.4 optimises the voxel parameters directly).
+ *   kind 0: Adam  (m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *                  p -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps))
+ *   kind 1: RMSProp (v = b2 v + (1-b2) g^2;  p -= lr * g / (sqrt(v) + eps));
+ *           d_m is unused and may be NULL, b1 is ignored.
+ *   t is the 1-based step count (Adam bias correction).  n may be 0.
+ */
+int sg_optim_step(int32_t kind, float* d_param, const float* d_grad,
+                  float* d_m, float* d_v, int64_t n, float lr, float b1,
+                  float b2, float eps, int32_t t, sg_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGRID_H */

@@ -1,0 +1,282 @@
+"""CPU oracle of the sparse-dense SDF grid renderer (Dong et al., CVPR 2023).
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg import this package.  The product library
+(``paper_2305_13220_amd``) never does and shares no code with it.
+
+The arithmetic lives in ``sgrid_oracle.c`` (plain C, double precision except
+for the float32 sample-position decisions, built with ``-ffp-contract=off``).
+This module only builds it, loads it with ctypes and marshals numpy arrays.
+
+Every function cites the passage of the paper it follows:
+  * ``build`` / ``lookup`` / ``neighbors``: the collision-free block index of
+    Sec. 3.2 (one-to-one map from block coordinate to block index).
+  * ``render_forward``: volume rendering, Sec. 3.5.1, Eq. 12-15, with the
+    trilinear value and closed-form gradient of Eq. 17-18.
+  * ``render_backward``: its adjoint with respect to the voxel parameters.
+  * ``query``: SDF, gradient and features at points (Eq. 17-18).
+  * ``density``: VolSDF's Laplace-CDF transform named in Sec. 3.5.1.
+  * ``rays_pinhole``: inverse of the pinhole projection used in Eq. 3.
+  * ``footprint``: exact counts of the voxels and blocks each ray reads.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sgrid_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libsgrid_oracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fused multiply-add)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+_I64 = ctypes.c_int64
+_F = ctypes.c_float
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+
+
+def build_grid(coords):
+    """First-occurrence dedup of block coordinates (Sec. 3.2, 3.4.1).
+
+    Returns (block_coords [n,3] int32 in index order, index_of_input [N] int32).
+    Raises ValueError for coordinates outside [-2^20, 2^20).
+    """
+    lib = _load()
+    coords = _c(coords, np.int32).reshape(-1, 3)
+    n = coords.shape[0]
+    out_idx = np.empty(n, np.int32)
+    out_blocks = np.empty((max(n, 1), 3), np.int32)
+    nb = _I64(0)
+    rc = lib.or_build(_p(coords), _I64(n), _p(out_idx), _p(out_blocks), ctypes.byref(nb))
+    if rc == -2:
+        raise ValueError("block coordinate out of range")
+    _check(rc, "build")
+    return out_blocks[: nb.value].copy(), out_idx
+
+
+def lookup(block_coords, query):
+    """Index of each query block coordinate, -1 if absent (Sec. 3.2)."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    q = _c(query, np.int32).reshape(-1, 3)
+    out = np.empty(q.shape[0], np.int32)
+    _check(lib.or_lookup(_p(bc), _I64(bc.shape[0]), _p(q), _I64(q.shape[0]), _p(out)), "lookup")
+    return out
+
+
+def neighbors(block_coords):
+    """[n,8] indices of blocks b + (sx,sy,sz), s = sx + 2 sy + 4 sz, -1 if absent."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    out = np.empty((bc.shape[0], 8), np.int32)
+    _check(lib.or_neighbors(_p(bc), _I64(bc.shape[0]), _p(out)), "neighbors")
+    return out
+
+
+def _geom_args(h, origin, params):
+    org = _c(origin, np.float32).reshape(3)
+    return org, (
+        _F(params["step"]), _F(params["t_near"]), _F(params["t_far"]),
+        _F(params["beta"]), _I32(params["max_samples"]))
+
+
+def density(f, beta):
+    """sigma = (1/beta) Psi_beta(-f) and d sigma / d f (VolSDF transform)."""
+    lib = _load()
+    f = _c(f, np.float64).ravel()
+    s = np.empty_like(f)
+    ds = np.empty_like(f)
+    _check(lib.or_density(_p(f), _I64(f.size), _D(beta), _p(s), _p(ds)), "density")
+    return s, ds
+
+
+def query(block_coords, vox, C, h, origin, points):
+    """Trilinear f, grad f and features at world points (Eq. 17-18).
+
+    vox: [n,512,1+C] (converted to float64).  Returns (valid [m] bool,
+    f [m], grad [m,3], feat [m,C]).
+    """
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    pts = _c(points, np.float32).reshape(-1, 3)
+    m = pts.shape[0]
+    org = _c(origin, np.float32).reshape(3)
+    valid = np.empty(m, np.int32)
+    f = np.empty(m, np.float64)
+    g = np.empty((m, 3), np.float64)
+    feat = np.empty((m, max(C, 1)), np.float64)
+    _check(lib.or_query(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org), _p(pts),
+                        _I64(m), _p(valid), _p(f), _p(g), _p(feat)), "query")
+    return valid.astype(bool), f, g, feat[:, :C]
+
+
+def render_forward(block_coords, vox, C, h, origin, rays, params, with_mag=False):
+    """Volume render every ray (Sec. 3.5.1, Eq. 12-15).
+
+    Returns dict feat [R,C], depth [R], normal [R,3], wsum [R], nsamples [R]
+    (float64 / int32) and, with with_mag, mag_* arrays: sum_k |w_k v_k|.
+    """
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    ry = _c(rays, np.float32).reshape(-1, 6)
+    R = ry.shape[0]
+    org, gp = _geom_args(h, origin, params)
+    out = {
+        "feat": np.zeros((R, max(C, 1)), np.float64), "depth": np.zeros(R),
+        "normal": np.zeros((R, 3)), "wsum": np.zeros(R), "nsamples": np.zeros(R, np.int32),
+        "mag_feat": np.zeros((R, max(C, 1))), "mag_depth": np.zeros(R),
+        "mag_normal": np.zeros((R, 3)), "mag_wsum": np.zeros(R),
+    }
+    rc = lib.or_render_forward(
+        _p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org), _p(ry), _I64(R), *gp,
+        _p(out["feat"]), _p(out["depth"]), _p(out["normal"]), _p(out["wsum"]),
+        _p(out["nsamples"]), _p(out["mag_feat"]) if with_mag else None,
+        _p(out["mag_depth"]) if with_mag else None, _p(out["mag_normal"]) if with_mag else None,
+        _p(out["mag_wsum"]) if with_mag else None)
+    _check(rc, "render_forward")
+    out["feat"] = out["feat"][:, :C]
+    out["mag_feat"] = out["mag_feat"][:, :C]
+    if not with_mag:
+        for k in ("mag_feat", "mag_depth", "mag_normal", "mag_wsum"):
+            del out[k]
+    return out
+
+
+def render_backward(block_coords, vox, C, h, origin, rays, params, g_feat, g_depth, g_normal,
+                    g_wsum=None, with_mag=False):
+    """Gradient of L = sum g.outputs with respect to vox [n,512,1+C] (float64)."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    ry = _c(rays, np.float32).reshape(-1, 6)
+    R = ry.shape[0]
+    org, gp = _geom_args(h, origin, params)
+    gf = _c(g_feat if C > 0 else np.zeros((R, 1)), np.float64)
+    gd = _c(g_depth, np.float64)
+    gn = _c(g_normal, np.float64)
+    gw = None if g_wsum is None else _c(g_wsum, np.float64)
+    grad = np.zeros(vx.shape, np.float64)
+    mag = np.zeros(vx.shape, np.float64) if with_mag else None
+    rc = lib.or_render_backward(
+        _p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org), _p(ry), _I64(R), *gp,
+        _p(gf), _p(gd), _p(gn), _p(gw), _p(grad), _p(mag))
+    _check(rc, "render_backward")
+    return (grad, mag) if with_mag else grad
+
+
+def ray_samples(block_coords, h, origin, ray, params):
+    """Kept samples of one ray: dict k, t, i [n,3], u [n,3], blk [n,8], loc [n,8]."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    ry = _c(ray, np.float32).reshape(6)
+    org, gp = _geom_args(h, origin, params)
+    M = int(params["max_samples"])
+    k = np.empty(M, np.int32)
+    t = np.empty(M, np.float32)
+    i = np.empty((M, 3), np.int32)
+    u = np.empty((M, 3), np.float32)
+    blk = np.empty((M, 8), np.int64)
+    loc = np.empty((M, 8), np.int32)
+    n = _I32(0)
+    _check(lib.or_ray_samples(_p(bc), _I64(bc.shape[0]), _F(h), _p(org), _p(ry), *gp, _p(k),
+                              _p(t), _p(i), _p(u), _p(blk), _p(loc), ctypes.byref(n)),
+           "ray_samples")
+    n = n.value
+    return {"k": k[:n], "t": t[:n], "i": i[:n], "u": u[:n], "blk": blk[:n], "loc": loc[:n]}
+
+
+def footprint(block_coords, h, origin, rays, params, with_touched=False):
+    """Per-ray (S, U, K) counts [R,3] and optionally the touched-voxel map."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    ry = _c(rays, np.float32).reshape(-1, 6)
+    R = ry.shape[0]
+    org, gp = _geom_args(h, origin, params)
+    counts = np.empty((R, 3), np.int32)
+    touched = np.zeros(bc.shape[0] * 512, np.uint8) if with_touched else None
+    _check(lib.or_render_footprint(_p(bc), _I64(bc.shape[0]), _F(h), _p(org), _p(ry), _I64(R),
+                                   *gp, _p(counts), _p(touched)), "footprint")
+    return (counts, touched) if with_touched else counts
+
+
+def rays_pinhole(cams, pix):
+    """Unit camera rays [R,6] (float64) through pixel centres (pinhole, Eq. 3)."""
+    lib = _load()
+    cm = _c(cams, np.float32).reshape(-1, 16)
+    px = _c(pix, np.int32).reshape(-1, 3)
+    out = np.empty((px.shape[0], 6), np.float64)
+    _check(lib.or_rays_pinhole(_p(cm), _I32(cm.shape[0]), _p(px), _I64(px.shape[0]), _p(out)),
+           "rays_pinhole")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Glue of the training step (Sec. 3.5.4), plain numpy definitions.
+
+def l2_loss_grad(feat, feat_ref, depth, depth_ref, normal, normal_ref, lambda_d, lambda_n):
+    """Squared-L2 forms of Eq. 12-14, averaged over rays: (loss, g_feat, g_depth, g_normal)."""
+    feat, feat_ref = np.asarray(feat, np.float64), np.asarray(feat_ref, np.float64)
+    depth, depth_ref = np.asarray(depth, np.float64), np.asarray(depth_ref, np.float64)
+    normal, normal_ref = np.asarray(normal, np.float64), np.asarray(normal_ref, np.float64)
+    R = depth.shape[0]
+    dc, dd, dn = feat - feat_ref, depth - depth_ref, normal - normal_ref
+    loss = (np.sum(dc * dc) + lambda_d * np.sum(dd * dd) + lambda_n * np.sum(dn * dn)) / max(R, 1)
+    return loss, 2.0 * dc / R, 2.0 * lambda_d * dd / R, 2.0 * lambda_n * dn / R
+
+
+def optim_step(kind, p, g, m, v, lr, b1, b2, eps, t):
+    """One Adam (kind 0, Kingma & Ba 2015, Alg. 1) or RMSProp (kind 1) step, float64."""
+    p, g = np.asarray(p, np.float64).copy(), np.asarray(g, np.float64)
+    m = None if m is None else np.asarray(m, np.float64).copy()
+    v = np.asarray(v, np.float64).copy()
+    if kind == 0:
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mhat = m / (1 - b1 ** t)
+        vhat = v / (1 - b2 ** t)
+        p = p - lr * mhat / (np.sqrt(vhat) + eps)
+    else:
+        v = b2 * v + (1 - b2) * g * g
+        p = p - lr * g / (np.sqrt(v) + eps)
+    return p, m, v

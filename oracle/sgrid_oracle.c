@@ -1,0 +1,688 @@
+/*
+ * sgrid_oracle.c -- plain, slow CPU oracle of the sparse-dense SDF grid
+ * renderer of Dong et al., "Fast Monocular Scene Reconstruction with
+ * Global-Sparse Local-Dense Grids" (CVPR 2023).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this file; the product library never
+ * does, and the two share no code.
+ *
+ * Precision.  The paper fixes none.  Where a floating-point value decides an
+ * integer (which voxel and block a sample falls in, whether a lattice point
+ * is inside [t_near, t_far]) the decision is taken in float32 with exactly
+ * one rounding per operation -- build with -ffp-contract=off so that no
+ * multiply-add is fused -- because that is the precision the GPU kernels
+ * take it in.  Every other quantity (trilinear weights, SDF, gradient,
+ * features, density, compositing, adjoint) is evaluated in double.
+ *
+ * Readings of the paper used here (each is also listed in the design notes):
+ *  - voxel (i,j,k) sits at origin + (i,j,k)*h; block = floor(i/8); local
+ *    index lx + 8 ly + 64 lz;
+ *  - samples lie on the per-ray lattice t_k = t_near + k*step; a lattice
+ *    point is kept iff the blocks of all 8 corners of its cell exist
+ *    (sampling "in the sparse grid where valid blocks are allocated",
+ *    Sec. 3.5.1); the first max_samples kept points are used;
+ *  - delta_k = step for every kept sample (skipped space has no density);
+ *  - density sigma = (1/beta) Psi_beta(-f), Psi_beta the zero-mean Laplace
+ *    CDF with scale beta (VolSDF's transform named in Sec. 3.5.1);
+ *  - depth is the ray distance t, the normal the raw gradient of Eq. 18,
+ *    colour the raw interpolated features; no normalisation.
+ *
+ * Error codes: 0 ok, -1 bad argument, -2 coordinate out of range,
+ * -3 out of memory.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define COORD_LIMIT 1048576 /* block coordinates lie in [-2^20, 2^20) */
+#define VOX_PER_BLOCK 512
+#define POS_LIMIT 16777216.0f /* |voxel-space position| beyond this: no block */
+
+/* ------------------------------------------------------------------------ */
+/* Block index: a sorted table of (packed coordinate, index), searched with
+ * bsearch.  The plain definition of the hash of Sec. 3.2: a one-to-one map
+ * from an allocated block coordinate to its index. */
+
+typedef struct {
+  int64_t key;
+  int64_t pos; /* build: input position; lookup table: block index */
+} entry;
+
+static int64_t pack_key(int32_t x, int32_t y, int32_t z) {
+  if (x < -COORD_LIMIT || x >= COORD_LIMIT || y < -COORD_LIMIT ||
+      y >= COORD_LIMIT || z < -COORD_LIMIT || z >= COORD_LIMIT)
+    return -1;
+  return (((int64_t)x + COORD_LIMIT) << 42) | (((int64_t)y + COORD_LIMIT) << 21) |
+         ((int64_t)z + COORD_LIMIT);
+}
+
+static int cmp_entry(const void* a, const void* b) {
+  const entry* ea = (const entry*)a;
+  const entry* eb = (const entry*)b;
+  if (ea->key != eb->key) return ea->key < eb->key ? -1 : 1;
+  if (ea->pos != eb->pos) return ea->pos < eb->pos ? -1 : 1;
+  return 0;
+}
+
+static int cmp_key_only(const void* a, const void* b) {
+  const entry* ea = (const entry*)a;
+  const entry* eb = (const entry*)b;
+  if (ea->key != eb->key) return ea->key < eb->key ? -1 : 1;
+  return 0;
+}
+
+typedef struct {
+  int64_t n;
+  entry* e; /* sorted by key; pos = block index */
+} table;
+
+static int table_make(table* t, const int32_t* block_coords, int64_t n) {
+  t->n = n;
+  t->e = (entry*)malloc((size_t)(n > 0 ? n : 1) * sizeof(entry));
+  if (!t->e) return -3;
+  for (int64_t b = 0; b < n; ++b) {
+    t->e[b].key = pack_key(block_coords[3 * b], block_coords[3 * b + 1],
+                           block_coords[3 * b + 2]);
+    if (t->e[b].key < 0) {
+      free(t->e);
+      return -2;
+    }
+    t->e[b].pos = b;
+  }
+  qsort(t->e, (size_t)n, sizeof(entry), cmp_entry);
+  return 0;
+}
+
+static void table_free(table* t) { free(t->e); }
+
+/* Index of block (x,y,z) or -1. */
+static int64_t table_find(const table* t, int32_t x, int32_t y, int32_t z) {
+  entry q;
+  q.key = pack_key(x, y, z);
+  if (q.key < 0) return -1;
+  q.pos = 0;
+  const entry* hit =
+      (const entry*)bsearch(&q, t->e, (size_t)t->n, sizeof(entry), cmp_key_only);
+  return hit ? hit->pos : -1;
+}
+
+/* floor(j / 8) for any int32 j. */
+static int32_t floor_div8(int32_t j) {
+  return (j >= 0) ? j / 8 : -((-j + 7) / 8);
+}
+
+static int32_t mod8(int32_t j) { return j - 8 * floor_div8(j); }
+
+/*
+ * Grid build: deduplicate block coordinates, index them in order of first
+ * occurrence.  out_block_coords receives the unique coordinates in index
+ * order ([n,3] capacity), out_index_of_input the index of every input row.
+ */
+int or_build(const int32_t* coords, int64_t n, int32_t* out_index_of_input,
+             int32_t* out_block_coords, int64_t* out_n_blocks) {
+  if (n < 0 || (n > 0 && (!coords || !out_block_coords)) || !out_n_blocks)
+    return -1;
+  entry* all = (entry*)malloc((size_t)(n > 0 ? n : 1) * sizeof(entry));
+  if (!all) return -3;
+  for (int64_t i = 0; i < n; ++i) {
+    all[i].key = pack_key(coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]);
+    if (all[i].key < 0) {
+      free(all);
+      return -2;
+    }
+    all[i].pos = i;
+  }
+  /* Sorting by (key, position) puts each group's first occurrence first. */
+  qsort(all, (size_t)n, sizeof(entry), cmp_entry);
+  /* first[i] = 1 iff input row i is the first occurrence of its key. */
+  unsigned char* first = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  int64_t* group_first = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  if (!first || !group_first) {
+    free(all);
+    free(first);
+    free(group_first);
+    return -3;
+  }
+  for (int64_t s = 0; s < n; ++s) {
+    if (s == 0 || all[s].key != all[s - 1].key) first[all[s].pos] = 1;
+  }
+  /* Indices in input order of first occurrence. */
+  int32_t* idx_of_pos = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  if (!idx_of_pos) {
+    free(all);
+    free(first);
+    free(group_first);
+    return -3;
+  }
+  int64_t nb = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (first[i]) {
+      idx_of_pos[i] = (int32_t)nb;
+      out_block_coords[3 * nb] = coords[3 * i];
+      out_block_coords[3 * nb + 1] = coords[3 * i + 1];
+      out_block_coords[3 * nb + 2] = coords[3 * i + 2];
+      ++nb;
+    }
+  }
+  /* Every row takes the index of its group's first occurrence. */
+  for (int64_t s = 0; s < n; ++s) {
+    if (s == 0 || all[s].key != all[s - 1].key) group_first[s] = all[s].pos;
+    else group_first[s] = group_first[s - 1];
+    if (out_index_of_input)
+      out_index_of_input[all[s].pos] = idx_of_pos[group_first[s]];
+  }
+  *out_n_blocks = nb;
+  free(all);
+  free(first);
+  free(group_first);
+  free(idx_of_pos);
+  return 0;
+}
+
+/* Lookup of arbitrary coordinates against a block list (index order). */
+int or_lookup(const int32_t* block_coords, int64_t n_blocks,
+              const int32_t* query, int64_t m, int32_t* out_idx) {
+  if (n_blocks < 0 || m < 0) return -1;
+  table t;
+  int rc = table_make(&t, block_coords, n_blocks);
+  if (rc) return rc;
+  for (int64_t i = 0; i < m; ++i)
+    out_idx[i] = (int32_t)table_find(&t, query[3 * i], query[3 * i + 1], query[3 * i + 2]);
+  table_free(&t);
+  return 0;
+}
+
+/* Neighbour table: nbr[b][sx + 2 sy + 4 sz] = index of block b + (sx,sy,sz). */
+int or_neighbors(const int32_t* block_coords, int64_t n_blocks, int32_t* out_nbr) {
+  table t;
+  int rc = table_make(&t, block_coords, n_blocks);
+  if (rc) return rc;
+  for (int64_t b = 0; b < n_blocks; ++b)
+    for (int s = 0; s < 8; ++s)
+      out_nbr[8 * b + s] = (int32_t)table_find(
+          &t, block_coords[3 * b] + (s & 1), block_coords[3 * b + 1] + ((s >> 1) & 1),
+          block_coords[3 * b + 2] + ((s >> 2) & 1));
+  table_free(&t);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampling along a ray (Sec. 3.5.1): lattice t_k, fp32 positions, validity. */
+
+typedef struct {
+  float h, inv_h;      /* voxel size and its float32 reciprocal 1.0f/h */
+  float org[3];        /* world position of voxel (0,0,0) */
+  float step, t_near, t_far, beta;
+  int32_t max_samples;
+} geom;
+
+typedef struct {
+  int32_t k;       /* lattice index */
+  float t;         /* t_k, float32 */
+  int32_t i[3];    /* base voxel of the interpolation cell */
+  float u[3];      /* position inside the cell, float32 */
+  int64_t blk[8];  /* block of corner a = ax + 2 ay + 4 az */
+  int32_t loc[8];  /* local index of that corner inside its block */
+} sample;
+
+/*
+ * Locate voxel-space point (x,y,z) (float32): base voxel, fraction and the
+ * 8 corner blocks.  Returns 1 iff all 8 corner blocks are allocated.
+ */
+static int locate(const table* tb, const float xv[3], sample* s) {
+  for (int a = 0; a < 3; ++a) {
+    if (!(fabsf(xv[a]) < POS_LIMIT)) return 0; /* also rejects NaN */
+    float fl = floorf(xv[a]);
+    s->i[a] = (int32_t)fl;
+    s->u[a] = xv[a] - fl;
+  }
+  for (int a = 0; a < 8; ++a) {
+    int32_t jx = s->i[0] + (a & 1);
+    int32_t jy = s->i[1] + ((a >> 1) & 1);
+    int32_t jz = s->i[2] + ((a >> 2) & 1);
+    int64_t b = table_find(tb, floor_div8(jx), floor_div8(jy), floor_div8(jz));
+    if (b < 0) return 0;
+    s->blk[a] = b;
+    s->loc[a] = mod8(jx) + 8 * mod8(jy) + 64 * mod8(jz);
+  }
+  return 1;
+}
+
+/*
+ * All kept samples of one ray, in lattice order.  Returns their number
+ * (<= g->max_samples).  Rays with a non-finite component keep none.
+ */
+static int ray_samples(const table* tb, const geom* g, const float ray[6], sample* out) {
+  for (int a = 0; a < 6; ++a)
+    if (!isfinite(ray[a])) return 0;
+  float ov[3], dv[3];
+  for (int a = 0; a < 3; ++a) {
+    ov[a] = (ray[a] - g->org[a]) * g->inv_h;
+    dv[a] = ray[3 + a] * g->inv_h;
+  }
+  int n = 0;
+  for (int32_t k = 0; n < g->max_samples; ++k) {
+    float t = g->t_near + (float)k * g->step;
+    if (!(t <= g->t_far)) break;
+    float xv[3];
+    for (int a = 0; a < 3; ++a) {
+      float td = t * dv[a];
+      xv[a] = ov[a] + td;
+    }
+    sample s;
+    if (locate(tb, xv, &s)) {
+      s.k = k;
+      s.t = t;
+      out[n++] = s;
+    }
+  }
+  return n;
+}
+
+static int geom_make(geom* g, float h, const float org[3], float step, float t_near,
+                     float t_far, float beta, int32_t max_samples) {
+  if (!(h > 0) || !isfinite(h) || !(step > 0) || !(beta > 0) || !isfinite(t_near) ||
+      !isfinite(t_far) || max_samples < 1 || max_samples > 1024)
+    return -1;
+  if (!((t_far - t_near) / step < 16777216.0f)) return -1;
+  g->h = h;
+  g->inv_h = 1.0f / h;
+  for (int a = 0; a < 3; ++a) g->org[a] = org[a];
+  g->step = step;
+  g->t_near = t_near;
+  g->t_far = t_far;
+  g->beta = beta;
+  g->max_samples = max_samples;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interpolation (Eq. 17-18) and density, in double. */
+
+/* r_a and dr_a/du (per axis) for corner a at fraction u. */
+static void corner_weights(const float uf[3], double r[8], double dr[8][3]) {
+  double u[3] = {uf[0], uf[1], uf[2]};
+  for (int a = 0; a < 8; ++a) {
+    int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    double wx = ax ? u[0] : 1.0 - u[0];
+    double wy = ay ? u[1] : 1.0 - u[1];
+    double wz = az ? u[2] : 1.0 - u[2];
+    r[a] = wx * wy * wz;
+    dr[a][0] = (ax ? 1.0 : -1.0) * wy * wz;
+    dr[a][1] = (ay ? 1.0 : -1.0) * wx * wz;
+    dr[a][2] = (az ? 1.0 : -1.0) * wx * wy;
+  }
+}
+
+/* f, grad f (world units) and C features at a located sample. */
+static void interpolate(const sample* s, const double* vox, int C, double h,
+                        double* f, double grad[3], double* feat) {
+  double r[8], dr[8][3];
+  corner_weights(s->u, r, dr);
+  *f = 0.0;
+  grad[0] = grad[1] = grad[2] = 0.0;
+  for (int ch = 0; ch < C; ++ch) feat[ch] = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const double* th = vox + ((size_t)s->blk[a] * VOX_PER_BLOCK + (size_t)s->loc[a]) * (size_t)(1 + C);
+    *f += r[a] * th[0];
+    for (int ax = 0; ax < 3; ++ax) grad[ax] += dr[a][ax] * th[0] / h;
+    for (int ch = 0; ch < C; ++ch) feat[ch] += r[a] * th[1 + ch];
+  }
+}
+
+/* Laplace-CDF density sigma(f) = (1/beta) Psi_beta(-f) and d sigma / d f. */
+static double density(double f, double beta, double* dsigma_df) {
+  double s = -f, psi;
+  if (s <= 0.0) psi = 0.5 * exp(s / beta);
+  else psi = 1.0 - 0.5 * exp(-s / beta);
+  if (dsigma_df) *dsigma_df = -exp(-fabs(f) / beta) / (2.0 * beta * beta);
+  return psi / beta;
+}
+
+int or_density(const double* f, int64_t n, double beta, double* sigma, double* dsigma) {
+  if (!(beta > 0)) return -1;
+  for (int64_t i = 0; i < n; ++i) sigma[i] = density(f[i], beta, dsigma ? &dsigma[i] : NULL);
+  return 0;
+}
+
+/* Point query (Eq. 17-18) at world points p [m,3]: valid flag, f, grad, feat. */
+int or_query(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
+             float h, const float org[3], const float* p, int64_t m, int32_t* valid,
+             double* f, double* grad, double* feat) {
+  if (C < 0 || !(h > 0)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  float inv_h = 1.0f / h;
+  for (int64_t q = 0; q < m; ++q) {
+    float xv[3];
+    for (int a = 0; a < 3; ++a) xv[a] = (p[3 * q + a] - org[a]) * inv_h;
+    sample s;
+    valid[q] = locate(&tb, xv, &s);
+    if (valid[q]) {
+      interpolate(&s, vox, C, (double)h, &f[q], &grad[3 * q], C ? &feat[(size_t)C * q] : NULL);
+    } else {
+      f[q] = 0.0;
+      grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0;
+      for (int ch = 0; ch < C; ++ch) feat[(size_t)C * q + ch] = 0.0;
+    }
+  }
+  table_free(&tb);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward render (Eq. 12-15). */
+
+/*
+ * For every ray: feat_out [R,C], depth [R], normal [R,3], wsum [R],
+ * nsamples [R]; plus the magnitudes sum_k |w_k v_k| of every output element
+ * (mag_* arrays, same shapes, nullable) used to scale tolerances.
+ */
+int or_render_forward(const int32_t* block_coords, int64_t n_blocks, const double* vox,
+                      int32_t C, float h, const float org[3], const float* rays, int64_t R,
+                      float step, float t_near, float t_far, float beta, int32_t max_samples,
+                      double* feat_out, double* depth, double* normal, double* wsum,
+                      int32_t* nsamples, double* mag_feat, double* mag_depth,
+                      double* mag_normal, double* mag_wsum) {
+  if (C < 0 || C > 64 || R < 0) return -1;
+  geom g;
+  if (geom_make(&g, h, org, step, t_near, t_far, beta, max_samples)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  sample* smp = (sample*)malloc((size_t)max_samples * sizeof(sample));
+  double* c = (double*)malloc((size_t)(C > 0 ? C : 1) * sizeof(double));
+  if (!smp || !c) {
+    free(smp);
+    free(c);
+    table_free(&tb);
+    return -3;
+  }
+  for (int64_t r = 0; r < R; ++r) {
+    int n = ray_samples(&tb, &g, rays + 6 * r, smp);
+    double accC[64], magC[64], accN[3] = {0, 0, 0}, magN[3] = {0, 0, 0};
+    double accD = 0, magD = 0, accW = 0;
+    for (int ch = 0; ch < C; ++ch) accC[ch] = magC[ch] = 0.0;
+    double tau = 0.0; /* sum_{j<k} sigma_j delta_j */
+    for (int q = 0; q < n; ++q) {
+      double f, grad[3];
+      interpolate(&smp[q], vox, C, (double)h, &f, grad, c);
+      double sigma = density(f, (double)beta, NULL);
+      double T = exp(-tau);
+      double alpha = -expm1(-sigma * (double)step); /* 1 - exp(-sigma delta) */
+      double w = T * alpha;
+      for (int ch = 0; ch < C; ++ch) {
+        accC[ch] += w * c[ch];
+        magC[ch] += fabs(w * c[ch]);
+      }
+      accD += w * (double)smp[q].t;
+      magD += fabs(w * (double)smp[q].t);
+      for (int a = 0; a < 3; ++a) {
+        accN[a] += w * grad[a];
+        magN[a] += fabs(w * grad[a]);
+      }
+      accW += w;
+      tau += sigma * (double)step;
+    }
+    for (int ch = 0; ch < C; ++ch) {
+      feat_out[(size_t)C * r + ch] = accC[ch];
+      if (mag_feat) mag_feat[(size_t)C * r + ch] = magC[ch];
+    }
+    depth[r] = accD;
+    for (int a = 0; a < 3; ++a) normal[3 * r + a] = accN[a];
+    wsum[r] = accW;
+    if (nsamples) nsamples[r] = n;
+    if (mag_depth) mag_depth[r] = magD;
+    if (mag_normal)
+      for (int a = 0; a < 3; ++a) mag_normal[3 * r + a] = magN[a];
+    if (mag_wsum) mag_wsum[r] = accW;
+  }
+  free(smp);
+  free(c);
+  table_free(&tb);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backward: the adjoint of the forward render w.r.t. every voxel parameter. */
+
+/*
+ * Accumulates dL/dvox into grad_vox [n_blocks,512,1+C] for
+ * L = sum_r g_feat.feat + g_depth depth + g_normal.normal + g_wsum wsum.
+ * Derivation from Eq. 15: with s_k = dL/dw_k,
+ *   dL/dsigma_k = delta (T_{k+1} s_k - sum_{j>k} w_j s_j),
+ * T_{k+1} = exp(-sum_{j<=k} sigma_j delta); then through sigma(f) to the 8
+ * corner SDF values (trilinear weights r_a), plus the normal term
+ * w_k g_normal . grad_theta(grad f_k) (Eq. 18), and w_k r_a g_feat for the
+ * features.  mag_vox (nullable) receives the sum of the absolute values of
+ * every product term of that expansion, to scale tolerances.
+ */
+int or_render_backward(const int32_t* block_coords, int64_t n_blocks, const double* vox,
+                       int32_t C, float h, const float org[3], const float* rays, int64_t R,
+                       float step, float t_near, float t_far, float beta, int32_t max_samples,
+                       const double* g_feat, const double* g_depth, const double* g_normal,
+                       const double* g_wsum, double* grad_vox, double* mag_vox) {
+  if (C < 0 || C > 64 || R < 0) return -1;
+  geom g;
+  if (geom_make(&g, h, org, step, t_near, t_far, beta, max_samples)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  int M = max_samples;
+  size_t Cc = (size_t)(C > 0 ? C : 1);
+  sample* smp = (sample*)malloc((size_t)M * sizeof(sample));
+  double* F = (double*)malloc((size_t)M * sizeof(double));
+  double* G = (double*)malloc((size_t)M * 3 * sizeof(double));
+  double* Cf = (double*)malloc((size_t)M * Cc * sizeof(double));
+  double* SIG = (double*)malloc((size_t)M * sizeof(double));
+  double* DSIG = (double*)malloc((size_t)M * sizeof(double));
+  double* W = (double*)malloc((size_t)M * sizeof(double));
+  double* TN = (double*)malloc((size_t)M * sizeof(double));
+  double* S = (double*)malloc((size_t)M * sizeof(double));
+  double* SA = (double*)malloc((size_t)M * sizeof(double));
+  if (!smp || !F || !G || !Cf || !SIG || !DSIG || !W || !TN || !S || !SA) {
+    rc = -3;
+    goto done;
+  }
+  for (int64_t r = 0; r < R; ++r) {
+    int n = ray_samples(&tb, &g, rays + 6 * r, smp);
+    if (n == 0) continue;
+    const double* gC = C ? g_feat + (size_t)C * r : NULL;
+    double gD = g_depth[r];
+    const double* gN = g_normal + 3 * r;
+    double gW = g_wsum ? g_wsum[r] : 0.0;
+    /* forward quantities */
+    double tau = 0.0;
+    for (int q = 0; q < n; ++q) {
+      interpolate(&smp[q], vox, C, (double)h, &F[q], &G[3 * q], Cf + Cc * q);
+      SIG[q] = density(F[q], (double)beta, &DSIG[q]);
+      double T = exp(-tau);
+      double alpha = -expm1(-SIG[q] * (double)step);
+      W[q] = T * alpha;
+      tau += SIG[q] * (double)step;
+      TN[q] = exp(-tau); /* T_{k+1} */
+      /* s_k = dL/dw_k, and its absolute-term counterpart */
+      double s = gD * (double)smp[q].t + gW, sa = fabs(gD * (double)smp[q].t) + fabs(gW);
+      for (int ch = 0; ch < C; ++ch) {
+        s += gC[ch] * Cf[Cc * q + ch];
+        sa += fabs(gC[ch] * Cf[Cc * q + ch]);
+      }
+      for (int a = 0; a < 3; ++a) {
+        s += gN[a] * G[3 * q + a];
+        sa += fabs(gN[a] * G[3 * q + a]);
+      }
+      S[q] = s;
+      SA[q] = sa;
+    }
+    /* reverse pass: suffix sums sum_{j>k} w_j s_j */
+    double suf = 0.0, sufa = 0.0;
+    for (int q = n - 1; q >= 0; --q) {
+      double dsig = (double)step * (TN[q] * S[q] - suf);
+      double magsig = (double)step * (TN[q] * SA[q] + sufa);
+      double df = dsig * DSIG[q];
+      double magf = magsig * fabs(DSIG[q]);
+      double rr[8], dr[8][3];
+      corner_weights(smp[q].u, rr, dr);
+      for (int a = 0; a < 8; ++a) {
+        size_t base = ((size_t)smp[q].blk[a] * VOX_PER_BLOCK + (size_t)smp[q].loc[a]) * (size_t)(1 + C);
+        double gn = 0.0, gna = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+          gn += dr[a][ax] * gN[ax];
+          gna += fabs(dr[a][ax] * gN[ax]);
+        }
+        grad_vox[base] += rr[a] * df + W[q] * gn / (double)h;
+        if (mag_vox) mag_vox[base] += rr[a] * magf + W[q] * gna / (double)h;
+        for (int ch = 0; ch < C; ++ch) {
+          grad_vox[base + 1 + ch] += W[q] * rr[a] * gC[ch];
+          if (mag_vox) mag_vox[base + 1 + ch] += fabs(W[q] * rr[a] * gC[ch]);
+        }
+      }
+      suf += W[q] * S[q];
+      sufa += W[q] * SA[q];
+    }
+  }
+  rc = 0;
+done:
+  free(smp);
+  free(F);
+  free(G);
+  free(Cf);
+  free(SIG);
+  free(DSIG);
+  free(W);
+  free(TN);
+  free(S);
+  free(SA);
+  table_free(&tb);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sample lists and memory-footprint counts. */
+
+/*
+ * Kept samples of ray r (one ray): writes up to max_samples rows of
+ * k, base voxel i[3], and the 8 corner block indices; returns the count
+ * through *n_out.
+ */
+int or_ray_samples(const int32_t* block_coords, int64_t n_blocks, float h,
+                   const float org[3], const float* ray, float step, float t_near,
+                   float t_far, float beta, int32_t max_samples, int32_t* out_k,
+                   float* out_t, int32_t* out_i, float* out_u, int64_t* out_blk,
+                   int32_t* out_loc, int32_t* n_out) {
+  geom g;
+  if (geom_make(&g, h, org, step, t_near, t_far, beta, max_samples)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  sample* smp = (sample*)malloc((size_t)max_samples * sizeof(sample));
+  if (!smp) {
+    table_free(&tb);
+    return -3;
+  }
+  int n = ray_samples(&tb, &g, ray, smp);
+  for (int q = 0; q < n; ++q) {
+    out_k[q] = smp[q].k;
+    out_t[q] = smp[q].t;
+    for (int a = 0; a < 3; ++a) {
+      out_i[3 * q + a] = smp[q].i[a];
+      out_u[3 * q + a] = smp[q].u[a];
+    }
+    for (int a = 0; a < 8; ++a) {
+      out_blk[8 * q + a] = smp[q].blk[a];
+      out_loc[8 * q + a] = smp[q].loc[a];
+    }
+  }
+  *n_out = n;
+  free(smp);
+  table_free(&tb);
+  return 0;
+}
+
+static int cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int64_t count_distinct(int64_t* v, int64_t n) {
+  if (n == 0) return 0;
+  qsort(v, (size_t)n, sizeof(int64_t), cmp_i64);
+  int64_t d = 1;
+  for (int64_t i = 1; i < n; ++i)
+    if (v[i] != v[i - 1]) ++d;
+  return d;
+}
+
+/*
+ * Per ray: S = kept samples, U = distinct voxels read (8 corners per sample),
+ * K = distinct blocks holding them; counts [R,3].  touched (nullable,
+ * uint8 [n_blocks*512]) is set to 1 for every voxel read by any ray.
+ */
+int or_render_footprint(const int32_t* block_coords, int64_t n_blocks, float h,
+                        const float org[3], const float* rays, int64_t R, float step,
+                        float t_near, float t_far, float beta, int32_t max_samples,
+                        int32_t* counts, uint8_t* touched) {
+  geom g;
+  if (geom_make(&g, h, org, step, t_near, t_far, beta, max_samples)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  sample* smp = (sample*)malloc((size_t)max_samples * sizeof(sample));
+  int64_t* vox_ids = (int64_t*)malloc((size_t)max_samples * 8 * sizeof(int64_t));
+  int64_t* blk_ids = (int64_t*)malloc((size_t)max_samples * 8 * sizeof(int64_t));
+  if (!smp || !vox_ids || !blk_ids) {
+    free(smp);
+    free(vox_ids);
+    free(blk_ids);
+    table_free(&tb);
+    return -3;
+  }
+  for (int64_t r = 0; r < R; ++r) {
+    int n = ray_samples(&tb, &g, rays + 6 * r, smp);
+    int64_t m = 0;
+    for (int q = 0; q < n; ++q)
+      for (int a = 0; a < 8; ++a) {
+        vox_ids[m] = smp[q].blk[a] * VOX_PER_BLOCK + smp[q].loc[a];
+        blk_ids[m] = smp[q].blk[a];
+        if (touched) touched[vox_ids[m]] = 1;
+        ++m;
+      }
+    counts[3 * r] = n;
+    counts[3 * r + 1] = (int32_t)count_distinct(vox_ids, m);
+    counts[3 * r + 2] = (int32_t)count_distinct(blk_ids, m);
+  }
+  free(smp);
+  free(vox_ids);
+  free(blk_ids);
+  table_free(&tb);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Camera rays: inverse pinhole projection (the model of Eq. 3), in double. */
+
+int or_rays_pinhole(const float* cams, int32_t n_cams, const int32_t* pix, int64_t R,
+                    double* rays) {
+  for (int64_t r = 0; r < R; ++r) {
+    int32_t c = pix[3 * r];
+    if (c < 0 || c >= n_cams) {
+      for (int a = 0; a < 6; ++a) rays[6 * r + a] = NAN;
+      continue;
+    }
+    const float* K = cams + 16 * (size_t)c;
+    const float* M = K + 4; /* rows of [R | t] */
+    double x = ((double)pix[3 * r + 1] + 0.5 - K[2]) / K[0];
+    double y = ((double)pix[3 * r + 2] + 0.5 - K[3]) / K[1];
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = M[4 * a] * x + M[4 * a + 1] * y + M[4 * a + 2] * 1.0;
+    double nrm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int a = 0; a < 3; ++a) {
+      rays[6 * r + a] = M[4 * a + 3];
+      rays[6 * r + 3 + a] = d[a] / nrm;
+    }
+  }
+  return 0;
+}
