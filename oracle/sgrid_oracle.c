@@ -316,19 +316,32 @@ static void corner_weights(const float uf[3], double r[8], double dr[8][3]) {
   }
 }
 
-/* f, grad f (world units) and C features at a located sample. */
+/*
+ * f, grad f (world units) and C features at a located sample.  The gradient
+ * of Eq. 18, sum_a (dr_a/du) theta_a / h, is evaluated grouped by the edges
+ * of the cell: d f/d u_x = sum over the 4 x-edges of (product of the other two
+ * weights) * (theta at x=1 - theta at x=0), likewise for y and z.  This is
+ * the same polynomial; grouping the two ends of each edge first makes a
+ * direction in which the SDF is constant give exactly zero.
+ */
 static void interpolate(const sample* s, const double* vox, int C, double h,
                         double* f, double grad[3], double* feat) {
-  double r[8], dr[8][3];
+  double r[8], dr[8][3], th0[8];
   corner_weights(s->u, r, dr);
   *f = 0.0;
-  grad[0] = grad[1] = grad[2] = 0.0;
   for (int ch = 0; ch < C; ++ch) feat[ch] = 0.0;
   for (int a = 0; a < 8; ++a) {
     const double* th = vox + ((size_t)s->blk[a] * VOX_PER_BLOCK + (size_t)s->loc[a]) * (size_t)(1 + C);
+    th0[a] = th[0];
     *f += r[a] * th[0];
-    for (int ax = 0; ax < 3; ++ax) grad[ax] += dr[a][ax] * th[0] / h;
     for (int ch = 0; ch < C; ++ch) feat[ch] += r[a] * th[1 + ch];
+  }
+  for (int ax = 0; ax < 3; ++ax) {
+    const int bit = 1 << ax;
+    double g = 0.0;
+    for (int a = 0; a < 8; ++a)
+      if (!(a & bit)) g += dr[a | bit][ax] * (th0[a | bit] - th0[a]); /* dr of the x=1 end: +w w */
+    grad[ax] = g / h;
   }
 }
 

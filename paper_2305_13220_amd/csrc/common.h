@@ -1,0 +1,167 @@
+// Internals shared by the HIP translation units of libsgrid (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sgrid.h"
+
+namespace sg {
+
+constexpr int kWave = 64;
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int32_t kCoordLimit = SG_COORD_LIMIT;
+
+// ---------------------------------------------------------------------------
+// Error reporting (host).
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SG_HIP_CHECK(expr)                              \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return ::sg::hip_fail(_e, #expr); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Hash table of allocated blocks: open addressing, linear probing, 16-byte
+// slots so one load returns the key, the block index and the neighbour mask.
+struct alignas(16) Slot {
+  uint64_t key;   // packed block coordinate, kEmptyKey if free
+  int32_t idx;    // block index
+  int32_t nmask;  // bit s set iff block + (s&1, s>>1&1, s>>2&1) is allocated
+};
+
+// 21 bits per axis, offset by 2^20; callers check the range first.
+__host__ __device__ inline uint64_t pack_key(int32_t x, int32_t y, int32_t z) {
+  return ((uint64_t)(uint32_t)(x + kCoordLimit) << 42) |
+         ((uint64_t)(uint32_t)(y + kCoordLimit) << 21) |
+         (uint64_t)(uint32_t)(z + kCoordLimit);
+}
+
+__host__ __device__ inline bool in_range(int32_t x, int32_t y, int32_t z) {
+  return x >= -kCoordLimit && x < kCoordLimit && y >= -kCoordLimit && y < kCoordLimit &&
+         z >= -kCoordLimit && z < kCoordLimit;
+}
+
+// 64-bit finaliser (MurmurHash3 fmix64): spreads neighbouring coordinates.
+__host__ __device__ inline uint64_t mix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+// Device view of a built grid.
+struct GridView {
+  const Slot* slots;
+  uint64_t mask;        // capacity - 1 (power of two)
+  const int32_t* nbr;   // [n,8]
+  int64_t n_blocks;
+  int32_t bmin[3], bmax[3];  // bounding box of allocated block coordinates
+  float h, inv_h;
+  float org[3];
+};
+
+// Probe for block (x,y,z); returns the slot contents (idx = -1 if absent).
+__device__ inline void probe(const GridView& g, int32_t x, int32_t y, int32_t z, int32_t& idx,
+                             int32_t& nmask) {
+  idx = -1;
+  nmask = 0;
+  if (!in_range(x, y, z)) return;
+  const uint64_t key = pack_key(x, y, z);
+  uint64_t s = mix64(key) & g.mask;
+  for (;;) {
+    const Slot e = g.slots[s];
+    if (e.key == key) {
+      idx = e.idx;
+      nmask = e.nmask;
+      return;
+    }
+    if (e.key == kEmptyKey) return;
+    s = (s + 1) & g.mask;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers.
+__device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(-1, __builtin_amdgcn_mbcnt_lo(-1, 0)); }
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Number of set bits of m strictly below this lane.
+__device__ inline int rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ inline float shfl(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ inline int shfl(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+
+// Inclusive prefix sum over the 64 lanes (lane order).
+__device__ inline float wave_inclusive_sum(float v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    float o = shfl(v, l - off < 0 ? l : l - off);
+    if (l >= off) v += o;
+  }
+  return v;
+}
+
+// Inclusive suffix sum over the 64 lanes: lane l gets sum over lanes >= l.
+__device__ inline float wave_inclusive_suffix_sum(float v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    float o = shfl(v, l + off >= kWave ? l : l + off);
+    if (l + off < kWave) v += o;
+  }
+  return v;
+}
+
+// Sum over all 64 lanes, result in every lane (fixed butterfly order:
+// deterministic).
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+__device__ inline int wave_sum_int(int v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+}  // namespace sg
+
+// Host-side grid object behind the opaque sg_grid handle.
+struct sg_grid {
+  uint32_t magic;
+  int device;
+  sg::Slot* d_slots;
+  uint64_t capacity;
+  int32_t* d_nbr;          // [n,8]
+  int32_t* d_coords;       // [n,3]
+  int64_t n_blocks;
+  int32_t bmin[3], bmax[3];
+  float h;
+  float org[3];
+};
+
+namespace sg {
+constexpr uint32_t kGridMagic = 0x53475244u;  // "SGRD"
+int check_grid(const sg_grid* g);
+GridView view_of(const sg_grid* g);
+}  // namespace sg

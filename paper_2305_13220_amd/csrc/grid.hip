@@ -1,0 +1,471 @@
+// Collision-free spatial hash over allocated 8^3 blocks (Sec. 3.2, 3.4.1):
+// build with first-occurrence indexing, neighbour table, lookup.
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace sg {
+
+// ---------------------------------------------------------------------------
+// Errors.
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_grid(const sg_grid* g) {
+  if (!g) return fail(SG_EINVAL, "grid is NULL");
+  if (g->magic != kGridMagic) return fail(SG_ESTATE, "grid handle is not a live grid");
+  return SG_OK;
+}
+
+GridView view_of(const sg_grid* g) {
+  GridView v;
+  v.slots = g->d_slots;
+  v.mask = g->capacity - 1;
+  v.nbr = g->d_nbr;
+  v.n_blocks = g->n_blocks;
+  for (int a = 0; a < 3; ++a) {
+    v.bmin[a] = g->bmin[a];
+    v.bmax[a] = g->bmax[a];
+    v.org[a] = g->org[a];
+  }
+  v.h = g->h;
+  v.inv_h = 1.0f / g->h;  // one correctly rounded float32 division
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Build kernels.
+struct alignas(16) BuildSlot {
+  uint64_t key;
+  int32_t first;  // smallest input position holding this key
+  int32_t idx;    // assigned block index
+};
+
+__global__ void k_pack(const int32_t* __restrict__ coords, int64_t n, uint64_t* __restrict__ keys,
+                       int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
+  if (!in_range(x, y, z)) {
+    atomicOr(bad, 1);
+    keys[i] = kEmptyKey;
+    return;
+  }
+  keys[i] = pack_key(x, y, z);
+}
+
+__global__ void k_fill_build(BuildSlot* __restrict__ s, uint64_t cap) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap) return;
+  s[i].key = kEmptyKey;
+  s[i].first = INT_MAX;
+  s[i].idx = -1;
+}
+
+__global__ void k_fill_slots(Slot* __restrict__ s, uint64_t cap) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap) return;
+  s[i].key = kEmptyKey;
+  s[i].idx = -1;
+  s[i].nmask = 0;
+}
+
+__device__ inline uint64_t find_build(const BuildSlot* s, uint64_t mask, uint64_t key) {
+  uint64_t p = mix64(key) & mask;
+  while (s[p].key != key) p = (p + 1) & mask;  // key is known to be present
+  return p;
+}
+
+__global__ void k_insert_first(const uint64_t* __restrict__ keys, int64_t n, BuildSlot* s,
+                               uint64_t mask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = keys[i];
+  uint64_t p = mix64(key) & mask;
+  for (;;) {
+    unsigned long long prev =
+        atomicCAS((unsigned long long*)&s[p].key, (unsigned long long)kEmptyKey,
+                  (unsigned long long)key);
+    if (prev == kEmptyKey || prev == key) {
+      atomicMin(&s[p].first, (int32_t)i);
+      return;
+    }
+    p = (p + 1) & mask;
+  }
+}
+
+__global__ void k_mark_first(const uint64_t* __restrict__ keys, int64_t n, const BuildSlot* s,
+                             uint64_t mask, int32_t* __restrict__ flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flags[i] = (s[find_build(s, mask, keys[i])].first == (int32_t)i) ? 1 : 0;
+}
+
+__global__ void k_assign(const uint64_t* __restrict__ keys, const int32_t* __restrict__ coords,
+                         int64_t n, BuildSlot* s, uint64_t mask, const int32_t* __restrict__ flags,
+                         const int32_t* __restrict__ offs, int32_t* __restrict__ out_coords) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flags[i]) return;
+  const int32_t idx = offs[i];
+  s[find_build(s, mask, keys[i])].idx = idx;
+  out_coords[3 * idx] = coords[3 * i];
+  out_coords[3 * idx + 1] = coords[3 * i + 1];
+  out_coords[3 * idx + 2] = coords[3 * i + 2];
+}
+
+__global__ void k_index_of_input(const uint64_t* __restrict__ keys, int64_t n, const BuildSlot* s,
+                                 uint64_t mask, int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = s[find_build(s, mask, keys[i])].idx;
+}
+
+__global__ void k_insert_unique(const int32_t* __restrict__ coords, int64_t n, Slot* s,
+                                uint64_t mask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = pack_key(coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]);
+  uint64_t p = mix64(key) & mask;
+  for (;;) {
+    unsigned long long prev =
+        atomicCAS((unsigned long long*)&s[p].key, (unsigned long long)kEmptyKey,
+                  (unsigned long long)key);
+    if (prev == kEmptyKey) {
+      s[p].idx = (int32_t)i;
+      return;
+    }
+    p = (p + 1) & mask;
+  }
+}
+
+// Neighbour table, neighbour mask in the block's own slot, bounding box.
+__global__ void k_neighbors(const int32_t* __restrict__ coords, int64_t n, Slot* s, uint64_t mask,
+                            int32_t* __restrict__ nbr, int32_t* __restrict__ bbox) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t x = coords[3 * i], y = coords[3 * i + 1], z = coords[3 * i + 2];
+  GridView v;
+  v.slots = s;
+  v.mask = mask;
+  int32_t nm = 0;
+  for (int q = 0; q < 8; ++q) {
+    int32_t idx, unused;
+    probe(v, x + (q & 1), y + ((q >> 1) & 1), z + ((q >> 2) & 1), idx, unused);
+    nbr[8 * i + q] = idx;
+    if (idx >= 0) nm |= 1 << q;
+  }
+  const uint64_t key = pack_key(x, y, z);
+  uint64_t p = mix64(key) & mask;
+  while (s[p].key != key) p = (p + 1) & mask;
+  s[p].nmask = nm;
+  atomicMin(&bbox[0], x);
+  atomicMin(&bbox[1], y);
+  atomicMin(&bbox[2], z);
+  atomicMax(&bbox[3], x);
+  atomicMax(&bbox[4], y);
+  atomicMax(&bbox[5], z);
+}
+
+__global__ void k_init_bbox(int32_t* bbox) {
+  if (threadIdx.x < 3) bbox[threadIdx.x] = INT_MAX;
+  else if (threadIdx.x < 6) bbox[threadIdx.x] = INT_MIN;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum of int32 flags (build time only).
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int wave_inclusive_sum_int(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int o = shfl(v, l - off < 0 ? l : l - off);
+    if (l >= off) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of kScanThreads values held one per thread; returns the
+// exclusive prefix of this thread and the block total.
+__device__ inline int block_exclusive_scan(int v, int& total) {
+  __shared__ int wave_tot[kScanThreads / kWave];
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  int inc = wave_inclusive_sum_int(v);
+  if (l == kWave - 1) wave_tot[w] = inc;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int j = 0; j < kScanThreads / kWave; ++j) {
+    if (j < w) before += wave_tot[j];
+    total += wave_tot[j];
+  }
+  __syncthreads();
+  return before + inc - v;
+}
+
+__global__ void k_scan_tiles(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ out,
+                             int32_t* __restrict__ tile_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int vals[kScanItems];
+  int s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    vals[j] = (base + j < n) ? in[base + j] : 0;
+    s += vals[j];
+  }
+  int total;
+  int pre = block_exclusive_scan(s, total);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = pre;
+    pre += vals[j];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(int32_t* sums, int64_t m) {
+  int carry = 0;
+  for (int64_t start = 0; start < m; start += kScanThreads) {
+    int64_t i = start + threadIdx.x;
+    int v = (i < m) ? sums[i] : 0;
+    int total;
+    int pre = block_exclusive_scan(v, total);
+    if (i < m) sums[i] = carry + pre;
+    carry += total;
+  }
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int add = sums[blockIdx.x];
+  for (int j = threadIdx.x; j < kScanTile; j += kScanThreads)
+    if (base + j < n) out[base + j] += add;
+}
+
+__global__ void k_lookup(GridView g, const int32_t* __restrict__ q, int64_t n,
+                         int32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t idx, nm;
+  probe(g, q[3 * i], q[3 * i + 1], q[3 * i + 2], idx, nm);
+  out[i] = idx;
+}
+
+static unsigned grid1d(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+static uint64_t pow2_at_least(uint64_t x) {
+  uint64_t c = 64;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+// Frees every device pointer it holds on scope exit.
+struct DevFree {
+  std::vector<void*> ptrs;
+  ~DevFree() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t alloc(T** p, size_t bytes) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, bytes ? bytes : 16);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release(void* p) {
+    for (auto& q : ptrs)
+      if (q == p) q = nullptr;
+  }
+};
+
+#define SG_ALLOC(holder, ptr, bytes)                                              \
+  do {                                                                            \
+    hipError_t _e = (holder).alloc(&(ptr), (bytes));                              \
+    if (_e != hipSuccess) {                                                       \
+      (void)hipGetLastError();                                                    \
+      return fail(SG_ENOMEM, std::string("device allocation of ") +               \
+                                 std::to_string((size_t)(bytes)) + " bytes failed"); \
+    }                                                                             \
+  } while (0)
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_last_error.c_str(); }
+
+const char* sg_version(void) { return "sgrid 0.1 (gfx950)"; }
+
+int sg_grid_build(const int32_t* d_block_coords, int64_t n, float voxel_size,
+                  const float origin[3], sg_stream stream, sg_grid** out,
+                  int32_t* d_index_of_input) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d_block_coords) return fail(SG_EINVAL, "d_block_coords is NULL");
+  if (n < 1 || n > (int64_t)INT_MAX) return fail(SG_EINVAL, "n must be in [1, 2^31-1]");
+  if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size))
+    return fail(SG_EINVAL, "voxel_size must be finite and > 0");
+  if (!origin) return fail(SG_EINVAL, "origin is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(SG_EINVAL, "origin must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  SG_HIP_CHECK(hipGetDevice(&dev));
+
+  DevFree tmp;
+  uint64_t* d_keys;
+  int* d_bad;
+  int32_t *d_flags, *d_offs, *d_sums, *d_tmp_coords;
+  BuildSlot* d_bslots;
+  const uint64_t cap1 = pow2_at_least(2 * (uint64_t)n);
+  const int64_t n_tiles = (n + kScanTile - 1) / kScanTile;
+  SG_ALLOC(tmp, d_keys, sizeof(uint64_t) * n);
+  SG_ALLOC(tmp, d_bad, sizeof(int));
+  SG_ALLOC(tmp, d_flags, sizeof(int32_t) * n);
+  SG_ALLOC(tmp, d_offs, sizeof(int32_t) * n);
+  SG_ALLOC(tmp, d_sums, sizeof(int32_t) * n_tiles);
+  SG_ALLOC(tmp, d_tmp_coords, sizeof(int32_t) * 3 * n);
+  SG_ALLOC(tmp, d_bslots, sizeof(BuildSlot) * cap1);
+
+  const int T = 256;
+  SG_HIP_CHECK(hipMemsetAsync(d_bad, 0, sizeof(int), s));
+  k_pack<<<grid1d(n, T), T, 0, s>>>(d_block_coords, n, d_keys, d_bad);
+  int bad = 0;
+  SG_HIP_CHECK(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  SG_HIP_CHECK(hipStreamSynchronize(s));
+  if (bad) return fail(SG_ERANGE, "a block coordinate lies outside [-2^20, 2^20)");
+
+  k_fill_build<<<grid1d((int64_t)cap1, T), T, 0, s>>>(d_bslots, cap1);
+  k_insert_first<<<grid1d(n, T), T, 0, s>>>(d_keys, n, d_bslots, cap1 - 1);
+  k_mark_first<<<grid1d(n, T), T, 0, s>>>(d_keys, n, d_bslots, cap1 - 1, d_flags);
+  k_scan_tiles<<<(unsigned)n_tiles, kScanThreads, 0, s>>>(d_flags, n, d_offs, d_sums);
+  k_scan_sums<<<1, kScanThreads, 0, s>>>(d_sums, n_tiles);
+  k_scan_add<<<(unsigned)n_tiles, kScanThreads, 0, s>>>(d_offs, n, d_sums);
+  int32_t last_off = 0, last_flag = 0;
+  SG_HIP_CHECK(hipMemcpyAsync(&last_off, d_offs + (n - 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+  SG_HIP_CHECK(hipMemcpyAsync(&last_flag, d_flags + (n - 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+  SG_HIP_CHECK(hipStreamSynchronize(s));
+  const int64_t nu = (int64_t)last_off + last_flag;
+  k_assign<<<grid1d(n, T), T, 0, s>>>(d_keys, d_block_coords, n, d_bslots, cap1 - 1, d_flags,
+                                      d_offs, d_tmp_coords);
+  if (d_index_of_input)
+    k_index_of_input<<<grid1d(n, T), T, 0, s>>>(d_keys, n, d_bslots, cap1 - 1, d_index_of_input);
+
+  DevFree keep;
+  sg_grid* g = new sg_grid();
+  g->magic = 0;
+  g->device = dev;
+  g->n_blocks = nu;
+  g->h = voxel_size;
+  for (int a = 0; a < 3; ++a) g->org[a] = origin[a];
+  g->capacity = pow2_at_least(2 * (uint64_t)nu);
+  struct Guard {
+    sg_grid* g;
+    ~Guard() { delete g; }
+  } guard{g};
+  int32_t* d_bbox;
+  SG_ALLOC(keep, g->d_coords, sizeof(int32_t) * 3 * nu);
+  SG_ALLOC(keep, g->d_slots, sizeof(Slot) * g->capacity);
+  SG_ALLOC(keep, g->d_nbr, sizeof(int32_t) * 8 * nu);
+  SG_ALLOC(tmp, d_bbox, sizeof(int32_t) * 6);
+  SG_HIP_CHECK(hipMemcpyAsync(g->d_coords, d_tmp_coords, sizeof(int32_t) * 3 * nu,
+                              hipMemcpyDeviceToDevice, s));
+  k_fill_slots<<<grid1d((int64_t)g->capacity, T), T, 0, s>>>(g->d_slots, g->capacity);
+  k_insert_unique<<<grid1d(nu, T), T, 0, s>>>(g->d_coords, nu, g->d_slots, g->capacity - 1);
+  k_init_bbox<<<1, 64, 0, s>>>(d_bbox);
+  k_neighbors<<<grid1d(nu, T), T, 0, s>>>(g->d_coords, nu, g->d_slots, g->capacity - 1, g->d_nbr,
+                                          d_bbox);
+  int32_t bbox[6];
+  SG_HIP_CHECK(hipMemcpyAsync(bbox, d_bbox, sizeof(bbox), hipMemcpyDeviceToHost, s));
+  SG_HIP_CHECK(hipGetLastError());
+  SG_HIP_CHECK(hipStreamSynchronize(s));
+  for (int a = 0; a < 3; ++a) {
+    g->bmin[a] = bbox[a];
+    g->bmax[a] = bbox[3 + a];
+  }
+  g->magic = kGridMagic;
+  keep.ptrs.clear();  // ownership moves to the grid
+  guard.g = nullptr;
+  *out = g;
+  return SG_OK;
+}
+
+int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!n_blocks) return fail(SG_EINVAL, "n_blocks is NULL");
+  *n_blocks = g->n_blocks;
+  return SG_OK;
+}
+
+int sg_grid_geometry(const sg_grid* g, float* voxel_size, float origin[3]) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!voxel_size || !origin) return fail(SG_EINVAL, "output pointer is NULL");
+  *voxel_size = g->h;
+  for (int a = 0; a < 3; ++a) origin[a] = g->org[a];
+  return SG_OK;
+}
+
+int sg_grid_block_coords(const sg_grid* g, int32_t* d_out, sg_stream stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!d_out) return fail(SG_EINVAL, "d_out is NULL");
+  SG_HIP_CHECK(hipMemcpyAsync(d_out, g->d_coords, sizeof(int32_t) * 3 * g->n_blocks,
+                              hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SG_OK;
+}
+
+int sg_grid_neighbors(const sg_grid* g, int32_t* d_out, sg_stream stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!d_out) return fail(SG_EINVAL, "d_out is NULL");
+  SG_HIP_CHECK(hipMemcpyAsync(d_out, g->d_nbr, sizeof(int32_t) * 8 * g->n_blocks,
+                              hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SG_OK;
+}
+
+int sg_grid_lookup(const sg_grid* g, const int32_t* d_coords, int64_t n, int32_t* d_idx,
+                   sg_stream stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (n < 0) return fail(SG_EINVAL, "n must be >= 0");
+  if (n == 0) return SG_OK;
+  if (!d_coords || !d_idx) return fail(SG_EINVAL, "d_coords / d_idx is NULL");
+  k_lookup<<<grid1d(n, 256), 256, 0, (hipStream_t)stream>>>(view_of(g), d_coords, n, d_idx);
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_grid_destroy(sg_grid* g) {
+  if (!g) return SG_OK;
+  if (g->magic != kGridMagic) return fail(SG_ESTATE, "grid handle is not a live grid");
+  g->magic = 0;
+  (void)hipFree(g->d_slots);
+  (void)hipFree(g->d_nbr);
+  (void)hipFree(g->d_coords);
+  delete g;
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,679 @@
+// Differentiable volume rendering through the sparse-dense grid
+// (Sec. 3.5.1, Eq. 12-15 with the trilinear value and gradient of Eq. 17-18).
+//
+// One wavefront per ray.  Phase 1 (march): the 64 lanes test 64 consecutive
+// lattice points t_k = t_near + k*step at a time -- float32 position, floor,
+// block, hash probe, neighbour mask -- and the kept (k, block) pairs are
+// compacted in lattice order into the wave's LDS list.  Phase 2 (shade):
+// lanes take 64 kept samples at a time, gather the 8 corners, interpolate,
+// convert SDF to density and composite with a wave prefix sum of
+// sigma*step.  The backward pass stores per-sample (w, dL/dw, T_{k+1}, f) in
+// LDS during a recompute pass, then walks the chunks in reverse with wave
+// suffix sums, merges the contributions of consecutive samples that share a
+// cell, and scatters them with float32 atomic adds.
+#include <cmath>
+#include <climits>
+
+#include "common.h"
+
+namespace sg {
+
+struct Params {
+  float step, t_near, t_far, beta, inv_beta;
+  int32_t max_samples;
+};
+
+struct March {
+  float ov[3], dv[3];  // voxel-space origin and direction (float32, as rounded)
+  int32_t k_lo, k_hi;  // lattice indices to examine, inclusive
+};
+
+// t_k and x_k exactly as float32 with one rounding per operation: these
+// values decide integers (voxel, block) and must not be contracted.
+__device__ __forceinline__ float lattice_t(const Params& p, int32_t k) {
+#pragma clang fp contract(off)
+  const float kf = (float)k;
+  const float ks = kf * p.step;
+  return p.t_near + ks;
+}
+
+__device__ __forceinline__ float lattice_x(float ov, float dv, float t) {
+#pragma clang fp contract(off)
+  const float td = t * dv;
+  return ov + td;
+}
+
+__device__ __forceinline__ float to_voxel(float x, float org, float inv_h) {
+#pragma clang fp contract(off)
+  const float d = x - org;
+  return d * inv_h;
+}
+
+constexpr float kPosLimit = 16777216.0f;  // 2^24 voxels: no block beyond
+constexpr int32_t kKMax = 1 << 24;
+
+// Ray set-up: voxel-space ray, inclusive lattice range, clipped to the
+// grid's bounding box with a margin that covers float32 position error.
+__device__ bool march_setup(const GridView& g, const float* __restrict__ ray, const Params& p,
+                            March& m) {
+  float r[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    r[a] = ray[a];
+    if (!isfinite(r[a])) return false;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m.ov[a] = to_voxel(r[a], g.org[a], g.inv_h);
+    m.dv[a] = r[3 + a] * g.inv_h;
+  }
+  // last lattice point with t_k <= t_far (t_far inclusive)
+  double est = floor(((double)p.t_far - (double)p.t_near) / (double)p.step);
+  int32_t kh = (int32_t)fmin(fmax(est, -1.0), (double)kKMax);
+  while (kh + 1 <= kKMax && lattice_t(p, kh + 1) <= p.t_far) ++kh;
+  while (kh >= 0 && !(lattice_t(p, kh) <= p.t_far)) --kh;
+  if (kh < 0) return false;
+  // bounding-box clip in double
+  double maxo = 0.0, maxd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    maxo = fmax(maxo, fabs((double)m.ov[a]));
+    maxd = fmax(maxd, fabs((double)m.dv[a]));
+  }
+  const double tabs = fmax(fabs((double)p.t_near), fabs((double)p.t_far));
+  const double margin = 2.0 + 1e-6 * (maxo + tabs * maxd);
+  double t0 = -1e300, t1 = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    const double lo = 8.0 * g.bmin[a] - margin, hi = 8.0 * ((double)g.bmax[a] + 1.0) + margin;
+    const double o = m.ov[a], d = m.dv[a];
+    if (d == 0.0) {
+      if (o < lo || o > hi) return false;
+    } else {
+      double ta = (lo - o) / d, tb = (hi - o) / d;
+      t0 = fmax(t0, fmin(ta, tb));
+      t1 = fmin(t1, fmax(ta, tb));
+    }
+  }
+  if (t0 > t1) return false;
+  const double kl = ceil((t0 - (double)p.t_near) / (double)p.step) - 2.0;
+  const double ku = floor((t1 - (double)p.t_near) / (double)p.step) + 2.0;
+  if (ku < 0.0 || kl > (double)kh) return false;
+  m.k_lo = kl < 0.0 ? 0 : (int32_t)kl;
+  m.k_hi = ku > (double)kh ? kh : (int32_t)ku;
+  return m.k_lo <= m.k_hi;
+}
+
+// Bits s = sx + 2 sy + 4 sz of the neighbour blocks a cell with local base
+// voxel l touches: sx may be 1 only if l.x == 7, etc.
+__device__ __forceinline__ int need_mask(int lx, int ly, int lz) {
+  int need = 1;
+  if (lx == 7) need |= need << 1;
+  if (ly == 7) need |= need << 2;
+  if (lz == 7) need |= need << 4;
+  return need;
+}
+
+// Phase 1: kept samples of the ray, in lattice order, into q[0..n) (n <= M).
+__device__ int march_collect(const GridView& g, const March& m, const Params& p, int2* q) {
+  const int lane = lane_id();
+  int n = 0;
+  for (int32_t k0 = m.k_lo; k0 <= m.k_hi && n < p.max_samples; k0 += kWave) {
+    const int32_t k = k0 + lane;
+    bool valid = false;
+    int32_t idx = -1;
+    if (k <= m.k_hi) {
+      const float t = lattice_t(p, k);
+      float x[3];
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        x[a] = lattice_x(m.ov[a], m.dv[a], t);
+        ok = ok && (fabsf(x[a]) < kPosLimit);
+      }
+      if (ok) {
+        const int32_t ix = (int32_t)floorf(x[0]), iy = (int32_t)floorf(x[1]),
+                      iz = (int32_t)floorf(x[2]);
+        const int32_t bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
+        if (bx >= g.bmin[0] && bx <= g.bmax[0] && by >= g.bmin[1] && by <= g.bmax[1] &&
+            bz >= g.bmin[2] && bz <= g.bmax[2]) {
+          int32_t nm;
+          probe(g, bx, by, bz, idx, nm);
+          const int need = need_mask(ix & 7, iy & 7, iz & 7);
+          valid = idx >= 0 && (nm & need) == need;
+        }
+      }
+    }
+    const uint64_t bal = __ballot(valid);
+    const int r = rank_below(bal);
+    if (valid && n + r < p.max_samples) q[n + r] = make_int2(k, idx);
+    n = min(p.max_samples, n + (int)__popcll(bal));
+  }
+  wave_sync();
+  return n;
+}
+
+// The interpolation cell of a kept sample: t, fraction u, and the element
+// offset (block * 512 + local) of each of the 8 corners a = ax + 2 ay + 4 az.
+struct Cell {
+  float t;
+  float u[3];
+  int32_t off[8];
+};
+
+__device__ __forceinline__ void locate(const GridView& g, const March& m, const Params& p, int2 e,
+                                       Cell& c) {
+  c.t = lattice_t(p, e.x);
+  int32_t i[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = lattice_x(m.ov[a], m.dv[a], c.t);
+    const float fl = floorf(x);
+    i[a] = (int32_t)fl;
+    c.u[a] = x - fl;
+  }
+  const int4* row = reinterpret_cast<const int4*>(g.nbr + 8 * (int64_t)e.y);
+  const int4 n0 = row[0], n1 = row[1];
+  const int32_t nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+  const int lx = i[0] & 7, ly = i[1] & 7, lz = i[2] & 7;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int cx = lx + (a & 1), cy = ly + ((a >> 1) & 1), cz = lz + ((a >> 2) & 1);
+    const int s = (cx >> 3) | ((cy >> 3) << 1) | ((cz >> 3) << 2);
+    c.off[a] = nb[s] * SG_BLOCK_VOXELS + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7);
+  }
+}
+
+// Trilinear weights r_a and their u-derivatives (Eq. 17-18).
+__device__ __forceinline__ void corner_weights(const float u[3], float r[8], float dr[8][3]) {
+  const float wx[2] = {1.0f - u[0], u[0]}, wy[2] = {1.0f - u[1], u[1]}, wz[2] = {1.0f - u[2], u[2]};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    r[a] = wx[ax] * wy[ay] * wz[az];
+    dr[a][0] = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az];
+    dr[a][1] = (ay ? 1.0f : -1.0f) * wx[ax] * wz[az];
+    dr[a][2] = (az ? 1.0f : -1.0f) * wx[ax] * wy[ay];
+  }
+}
+
+// Load the 1 + C parameters of one voxel.
+template <int C>
+__device__ __forceinline__ void load_voxel(const float* __restrict__ vox, int32_t off, float th[1 + C]) {
+  constexpr int V = 1 + C;
+  const float* src = vox + (int64_t)off * V;
+  if constexpr (V % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < V / 4; ++j) {
+      const float4 v = reinterpret_cast<const float4*>(src)[j];
+      th[4 * j] = v.x;
+      th[4 * j + 1] = v.y;
+      th[4 * j + 2] = v.z;
+      th[4 * j + 3] = v.w;
+    }
+  } else if constexpr (V % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < V / 2; ++j) {
+      const float2 v = reinterpret_cast<const float2*>(src)[j];
+      th[2 * j] = v.x;
+      th[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) th[j] = src[j];
+  }
+}
+
+// f, grad f (world units) and features at a located cell.  Each gradient
+// component is a positive-weighted sum of raw differences of neighbouring
+// SDF values, e.g. d/du_x = sum_{y,z} w_y w_z (theta_{1yz} - theta_{0yz}):
+// the same polynomial as sum_a (dr_a/du) theta_a, evaluated without the
+// cancellation between corners (and exactly zero where the SDF is flat).
+template <int C>
+__device__ __forceinline__ void interpolate(const float* __restrict__ vox, const Cell& c, float inv_h,
+                                            float& f, float grad[3], float feat[C > 0 ? C : 1]) {
+  const float wx[2] = {1.0f - c.u[0], c.u[0]}, wy[2] = {1.0f - c.u[1], c.u[1]},
+              wz[2] = {1.0f - c.u[2], c.u[2]};
+  float sdf[8];
+  f = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) feat[ch] = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    float th[1 + C];
+    load_voxel<C>(vox, c.off[a], th);
+    const float r = wx[a & 1] * wy[(a >> 1) & 1] * wz[(a >> 2) & 1];
+    sdf[a] = th[0];
+    f += r * th[0];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) feat[ch] += r * th[1 + ch];
+  }
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int lo = q & 1, hi = q >> 1;  // the two coordinates held fixed
+    const int c0x = 2 * lo + 4 * hi;    // corner (0, lo, hi)
+    const int c0y = lo + 4 * hi;        // corner (lo, 0, hi)
+    const int c0z = lo + 2 * hi;        // corner (lo, hi, 0)
+    gx += wy[lo] * wz[hi] * (sdf[c0x | 1] - sdf[c0x]);
+    gy += wx[lo] * wz[hi] * (sdf[c0y | 2] - sdf[c0y]);
+    gz += wx[lo] * wy[hi] * (sdf[c0z | 4] - sdf[c0z]);
+  }
+  grad[0] = gx * inv_h;
+  grad[1] = gy * inv_h;
+  grad[2] = gz * inv_h;
+}
+
+// Laplace-CDF density sigma = Psi_beta(-f)/beta; e = exp(-|f|/beta)/2.
+__device__ __forceinline__ float density(float f, const Params& p, float& e) {
+  e = 0.5f * expf(-fabsf(f) * p.inv_beta);
+  const float psi = (f >= 0.0f) ? e : 1.0f - e;
+  return psi * p.inv_beta;
+}
+
+// Exclusive prefix within the wave from an inclusive one.
+__device__ __forceinline__ float exclusive_from_inclusive(float incl) {
+  const int l = lane_id();
+  const float prev = shfl(incl, l > 0 ? l - 1 : 0);
+  return l > 0 ? prev : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Forward.
+template <int C>
+__global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __restrict__ vox,
+                                                    const float* __restrict__ rays, int64_t R,
+                                                    Params p, float* __restrict__ feat_out,
+                                                    float* __restrict__ depth,
+                                                    float* __restrict__ normal,
+                                                    float* __restrict__ wsum,
+                                                    int32_t* __restrict__ nsamples) {
+  extern __shared__ int2 lds_q[];
+  const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+  int2* q = lds_q + (int64_t)w * p.max_samples;
+  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
+    March m;
+    int n = 0;
+    if (march_setup(g, rays + 6 * r, p, m)) n = march_collect(g, m, p, q);
+    float accC[C > 0 ? C : 1], accD = 0.0f, accN[3] = {0.0f, 0.0f, 0.0f}, accW = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
+    float tau = 0.0f;
+    for (int c0 = 0; c0 < n; c0 += kWave) {
+      const int j = c0 + lane;
+      const bool act = j < n;
+      float sd = 0.0f, f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
+      Cell cell;
+      cell.t = 0.0f;
+      if (act) {
+        locate(g, m, p, q[j], cell);
+        interpolate<C>(vox, cell, g.inv_h, f, grad, col);
+        float e;
+        sd = density(f, p, e) * p.step;
+      }
+      const float incl = wave_inclusive_sum(sd);
+      const float excl = exclusive_from_inclusive(incl);
+      if (act) {
+        const float T = expf(-(tau + excl));
+        const float alpha = -expm1f(-sd);
+        const float wt = T * alpha;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) accC[ch] += wt * col[ch];
+        accD += wt * cell.t;
+        accN[0] += wt * grad[0];
+        accN[1] += wt * grad[1];
+        accN[2] += wt * grad[2];
+        accW += wt;
+      }
+      tau += shfl(incl, kWave - 1);
+    }
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
+    accD = wave_sum(accD);
+    accN[0] = wave_sum(accN[0]);
+    accN[1] = wave_sum(accN[1]);
+    accN[2] = wave_sum(accN[2]);
+    accW = wave_sum(accW);
+    if (lane == 0) {
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) feat_out[(int64_t)C * r + ch] = accC[ch];
+      depth[r] = accD;
+      normal[3 * r] = accN[0];
+      normal[3 * r + 1] = accN[1];
+      normal[3 * r + 2] = accN[2];
+      wsum[r] = accW;
+      if (nsamples) nsamples[r] = n;
+    }
+    wave_sync();  // q is reused by the next ray of this wave
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward.
+struct SampleState {
+  float w, s, tn, f;  // weight, dL/dw, T_{k+1}, SDF
+};
+
+template <int C>
+__global__ __launch_bounds__(256) void k_render_bwd(
+    GridView g, const float* __restrict__ vox, const float* __restrict__ rays, int64_t R, Params p,
+    const float* __restrict__ g_feat, const float* __restrict__ g_depth,
+    const float* __restrict__ g_normal, const float* __restrict__ g_wsum,
+    float* __restrict__ grad_vox) {
+  extern __shared__ int2 lds_q[];
+  constexpr int V = 1 + C;
+  const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+  int2* q = lds_q + (int64_t)w * p.max_samples;
+  SampleState* st =
+      reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples) + (int64_t)w * p.max_samples;
+  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
+    March m;
+    int n = 0;
+    if (march_setup(g, rays + 6 * r, p, m)) n = march_collect(g, m, p, q);
+    if (n == 0) continue;  // wave-uniform
+    float gC[C > 0 ? C : 1];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) gC[ch] = g_feat[(int64_t)C * r + ch];
+    const float gD = g_depth[r];
+    const float gN[3] = {g_normal[3 * r], g_normal[3 * r + 1], g_normal[3 * r + 2]};
+    const float gW = g_wsum ? g_wsum[r] : 0.0f;
+    // pass 1: recompute the forward quantities of every sample
+    float tau = 0.0f;
+    for (int c0 = 0; c0 < n; c0 += kWave) {
+      const int j = c0 + lane;
+      const bool act = j < n;
+      float sd = 0.0f, f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
+      Cell cell;
+      cell.t = 0.0f;
+      if (act) {
+        locate(g, m, p, q[j], cell);
+        interpolate<C>(vox, cell, g.inv_h, f, grad, col);
+        float e;
+        sd = density(f, p, e) * p.step;
+      }
+      const float incl = wave_inclusive_sum(sd);
+      const float excl = exclusive_from_inclusive(incl);
+      if (act) {
+        const float T = expf(-(tau + excl));
+        const float alpha = -expm1f(-sd);
+        SampleState s;
+        s.w = T * alpha;
+        s.tn = expf(-(tau + incl));
+        float dw = gD * cell.t + gW + gN[0] * grad[0] + gN[1] * grad[1] + gN[2] * grad[2];
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) dw += gC[ch] * col[ch];
+        s.s = dw;
+        s.f = f;
+        st[j] = s;
+      }
+      tau += shfl(incl, kWave - 1);
+    }
+    wave_sync();
+    // pass 2: reverse, suffix sums, scatter
+    float carry = 0.0f;
+    const int last = (n - 1) / kWave * kWave;
+    for (int c0 = last; c0 >= 0; c0 -= kWave) {
+      const int j = c0 + lane;
+      const bool act = j < n;
+      SampleState s = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (act) s = st[j];
+      const float ws = s.w * s.s;
+      const float suf = wave_inclusive_suffix_sum(ws);
+      // every lane takes part in the shuffle: a lane outside the exec mask
+      // would read back as zero
+      const float nxt = shfl(suf, lane < kWave - 1 ? lane + 1 : lane);
+      const float later = lane < kWave - 1 ? nxt : 0.0f;
+      const float total = shfl(suf, 0);
+      float esdf[8], qf[8];
+      int key = -1 - lane;
+      Cell cell;
+      if (act) {
+        const float dsig = p.step * (s.tn * s.s - (carry + later));
+        const float e = 0.5f * expf(-fabsf(s.f) * p.inv_beta);
+        const float dsig_df = -e * p.inv_beta * p.inv_beta;
+        const float df = dsig * dsig_df;
+        locate(g, m, p, q[j], cell);
+        float rr[8], dr[8][3];
+        corner_weights(cell.u, rr, dr);
+        const float wih = s.w * g.inv_h;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          esdf[a] = rr[a] * df + wih * (dr[a][0] * gN[0] + dr[a][1] * gN[1] + dr[a][2] * gN[2]);
+          qf[a] = s.w * rr[a];
+        }
+        key = cell.off[0];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) esdf[a] = qf[a] = 0.0f;
+      }
+      // merge consecutive samples that share a cell (segmented suffix sum)
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int src = lane + off < kWave ? lane + off : lane;
+        const int kn = shfl(key, src);
+        const bool same = (lane + off < kWave) && kn == key;
+        if (!__any(same)) break;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const float o1 = shfl(esdf[a], src), o2 = shfl(qf[a], src);
+          if (same) {
+            esdf[a] += o1;
+            qf[a] += o2;
+          }
+        }
+      }
+      const int kp = shfl(key, lane > 0 ? lane - 1 : 0);
+      const bool head = act && (lane == 0 || kp != key);
+      if (head) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          float* dst = grad_vox + (int64_t)cell.off[a] * V;
+          unsafeAtomicAdd(dst, esdf[a]);
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) unsafeAtomicAdd(dst + 1 + ch, qf[a] * gC[ch]);
+        }
+      }
+      carry += total;
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Footprint: per-ray (S, U, K) and the touched-voxel map.
+__global__ __launch_bounds__(256) void k_footprint(GridView g, const float* __restrict__ rays,
+                                                   int64_t R, Params p, int32_t* __restrict__ counts,
+                                                   uint8_t* __restrict__ touched) {
+  extern __shared__ int2 lds_q[];
+  const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+  int2* q = lds_q + (int64_t)w * p.max_samples;
+  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
+    March m;
+    int n = 0;
+    if (march_setup(g, rays + 6 * r, p, m)) n = march_collect(g, m, p, q);
+    int pi[3] = {0, 0, 0};  // base voxel of the previous chunk's last sample
+    int vox_total = 0, blk_total = 0;
+    for (int c0 = 0; c0 < n; c0 += kWave) {
+      const int j = c0 + lane;
+      const bool act = j < n;
+      int i[3] = {0, 0, 0};
+      if (act) {
+        const float t = lattice_t(p, q[j].x);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) i[a] = (int32_t)floorf(lattice_x(m.ov[a], m.dv[a], t));
+        if (touched) {
+          Cell cell;
+          locate(g, m, p, q[j], cell);
+#pragma unroll
+          for (int a = 0; a < 8; ++a) touched[cell.off[a]] = 1;
+        }
+      }
+      int prev[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int up = shfl(i[a], lane > 0 ? lane - 1 : 0);
+        prev[a] = lane > 0 ? up : pi[a];
+      }
+      int nv = 0, nb = 0;
+      if (act) {
+        // voxels: the 2x2x2 corner cube minus its overlap with the previous one
+        int ov = 1, bsz = 1, bov = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int d = abs(i[a] - prev[a]);
+          ov *= d < 2 ? 2 - d : 0;
+          const int lo = i[a] >> 3, hi = (i[a] + 1) >> 3;
+          const int plo = prev[a] >> 3, phi = (prev[a] + 1) >> 3;
+          bsz *= hi - lo + 1;
+          const int o = min(hi, phi) - max(lo, plo) + 1;
+          bov *= o > 0 ? o : 0;
+        }
+        const bool first = (j == 0);
+        nv = 8 - (first ? 0 : ov);
+        nb = bsz - (first ? 0 : bov);
+      }
+      vox_total += wave_sum_int(nv);
+      blk_total += wave_sum_int(nb);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) pi[a] = shfl(i[a], kWave - 1);
+    }
+    if (lane == 0) {
+      counts[3 * r] = n;
+      counts[3 * r + 1] = vox_total;
+      counts[3 * r + 2] = blk_total;
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+static bool supported_C(int C) {
+  switch (C) {
+    case 0: case 1: case 2: case 3: case 4: case 8: case 16: case 19: case 32:
+      return true;
+    default:
+      return false;
+  }
+}
+
+static int check_params(const sg_render_params* prm, Params& p) {
+  if (!prm) return fail(SG_EINVAL, "params is NULL");
+  if (!(prm->step > 0.0f) || !std::isfinite(prm->step)) return fail(SG_EINVAL, "step must be finite and > 0");
+  if (!(prm->beta > 0.0f) || !std::isfinite(prm->beta)) return fail(SG_EINVAL, "beta must be finite and > 0");
+  if (!std::isfinite(prm->t_near) || !std::isfinite(prm->t_far))
+    return fail(SG_EINVAL, "t_near / t_far must be finite");
+  if (prm->max_samples < 1 || prm->max_samples > SG_MAX_SAMPLES_LIMIT)
+    return fail(SG_EINVAL, "max_samples must be in [1, 1024]");
+  if (!((prm->t_far - prm->t_near) / prm->step < 16777216.0f))
+    return fail(SG_EINVAL, "(t_far - t_near) / step must be below 2^24");
+  p.step = prm->step;
+  p.t_near = prm->t_near;
+  p.t_far = prm->t_far;
+  p.beta = prm->beta;
+  p.inv_beta = 1.0f / prm->beta;
+  p.max_samples = prm->max_samples;
+  return SG_OK;
+}
+
+struct Launch {
+  unsigned blocks;
+  unsigned threads;
+  size_t lds;
+};
+
+// Waves per workgroup: 4, fewer if the per-wave LDS list is large.
+static Launch plan(int64_t R, size_t lds_per_wave) {
+  int wpb = 4;
+  while (wpb > 1 && lds_per_wave * wpb > 64 * 1024) wpb >>= 1;
+  Launch l;
+  l.threads = (unsigned)(wpb * kWave);
+  int64_t blocks = (R + wpb - 1) / wpb;
+  const int64_t cap = 1 << 22;
+  l.blocks = (unsigned)(blocks < cap ? blocks : cap);
+  l.lds = lds_per_wave * wpb;
+  return l;
+}
+
+#define SG_DISPATCH_C(C, ...)                         \
+  switch (C) {                                        \
+    case 0: { constexpr int CC = 0; __VA_ARGS__; } break;   \
+    case 1: { constexpr int CC = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int CC = 2; __VA_ARGS__; } break;   \
+    case 3: { constexpr int CC = 3; __VA_ARGS__; } break;   \
+    case 4: { constexpr int CC = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int CC = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int CC = 16; __VA_ARGS__; } break; \
+    case 19: { constexpr int CC = 19; __VA_ARGS__; } break; \
+    case 32: { constexpr int CC = 32; __VA_ARGS__; } break; \
+    default: break;                                   \
+  }
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int sg_render_forward(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
+                      int64_t n_rays, const sg_render_params* params, float* d_feat_out,
+                      float* d_depth, float* d_normal, float* d_wsum, int32_t* d_nsamples,
+                      sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
+  if (n_rays == 0) return SG_OK;
+  if (!d_vox || !d_rays || !d_depth || !d_normal || !d_wsum || (C > 0 && !d_feat_out))
+    return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const Launch l = plan(n_rays, sizeof(int2) * p.max_samples);
+  hipStream_t s = (hipStream_t)stream;
+  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_fwd<CC>, dim3(l.blocks), dim3(l.threads), l.lds, s,
+                                      g, d_vox, d_rays, n_rays, p, d_feat_out, d_depth, d_normal,
+                                      d_wsum, d_nsamples));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
+                       int64_t n_rays, const sg_render_params* params, const float* d_g_feat,
+                       const float* d_g_depth, const float* d_g_normal, const float* d_g_wsum,
+                       float* d_grad_vox, sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
+  if (n_rays == 0) return SG_OK;
+  if (!d_vox || !d_rays || !d_g_depth || !d_g_normal || !d_grad_vox || (C > 0 && !d_g_feat))
+    return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const Launch l = plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples);
+  hipStream_t s = (hipStream_t)stream;
+  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_bwd<CC>, dim3(l.blocks), dim3(l.threads), l.lds, s,
+                                      g, d_vox, d_rays, n_rays, p, d_g_feat, d_g_depth, d_g_normal,
+                                      d_g_wsum, d_grad_vox));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_render_footprint(const sg_grid* grid, const float* d_rays, int64_t n_rays,
+                        const sg_render_params* params, int32_t* d_counts, uint8_t* d_touched,
+                        sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
+  if (n_rays == 0) return SG_OK;
+  if (!d_rays || !d_counts) return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const Launch l = plan(n_rays, sizeof(int2) * p.max_samples);
+  hipLaunchKernelGGL(k_footprint, dim3(l.blocks), dim3(l.threads), l.lds, (hipStream_t)stream, g,
+                     d_rays, n_rays, p, d_counts, d_touched);
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+}  // extern "C"

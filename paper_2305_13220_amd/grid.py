@@ -1,0 +1,251 @@
+"""Python face of the sparse-dense grid and its render calls.
+
+Thin wrappers over the C ABI in include/sgrid.h (see _lib.py): they check
+arguments, allocate output tensors with torch and launch the library's HIP
+kernels on the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import SgridError, check, lib, ptr, stream_ptr, want
+
+SUPPORTED_C = (0, 1, 2, 3, 4, 8, 16, 19, 32)
+
+
+@dataclass(frozen=True)
+class RenderParams:
+    """Lattice spacing, t range (t_far inclusive), Laplace scale, sample cap."""
+    step: float
+    t_near: float
+    t_far: float
+    beta: float
+    max_samples: int = 128
+
+    def c(self):
+        return _lib.RenderParamsC(self.step, self.t_near, self.t_far, self.beta, self.max_samples)
+
+    @staticmethod
+    def of(p):
+        if isinstance(p, RenderParams):
+            return p
+        return RenderParams(p["step"], p["t_near"], p["t_far"], p["beta"], p["max_samples"])
+
+
+class Grid:
+    """Hash of allocated 8^3 blocks (collision-free, first-occurrence indices)."""
+
+    def __init__(self, block_coords: torch.Tensor, voxel_size: float, origin=(0.0, 0.0, 0.0),
+                 return_index: bool = False):
+        want(block_coords, "block_coords", torch.int32, (None, 3))
+        self.device = block_coords.device
+        n = block_coords.shape[0]
+        org = (ctypes.c_float * 3)(*[float(x) for x in origin])
+        handle = ctypes.c_void_p()
+        idx = torch.empty(n, dtype=torch.int32, device=self.device) if return_index else None
+        with torch.cuda.device(self.device):
+            check(lib().sg_grid_build(ptr(block_coords), n, ctypes.c_float(voxel_size), org,
+                                      stream_ptr(self.device), ctypes.byref(handle), ptr(idx)),
+                  "sg_grid_build")
+        self._h = handle
+        self.index_of_input = idx
+        nb = ctypes.c_int64()
+        check(lib().sg_grid_num_blocks(self._h, ctypes.byref(nb)), "sg_grid_num_blocks")
+        self.n_blocks = nb.value
+        vs = ctypes.c_float()
+        o = (ctypes.c_float * 3)()
+        check(lib().sg_grid_geometry(self._h, ctypes.byref(vs), o), "sg_grid_geometry")
+        self.voxel_size = vs.value
+        self.origin = tuple(o)
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise SgridError("grid has been destroyed")
+        return self._h
+
+    def block_coords(self):
+        out = torch.empty((self.n_blocks, 3), dtype=torch.int32, device=self.device)
+        check(lib().sg_grid_block_coords(self.handle, ptr(out), stream_ptr(self.device)),
+              "sg_grid_block_coords")
+        return out
+
+    def neighbors(self):
+        out = torch.empty((self.n_blocks, 8), dtype=torch.int32, device=self.device)
+        check(lib().sg_grid_neighbors(self.handle, ptr(out), stream_ptr(self.device)),
+              "sg_grid_neighbors")
+        return out
+
+    def lookup(self, coords: torch.Tensor):
+        want(coords, "coords", torch.int32, (None, 3), self.device)
+        out = torch.empty(coords.shape[0], dtype=torch.int32, device=self.device)
+        check(lib().sg_grid_lookup(self.handle, ptr(coords), coords.shape[0], ptr(out),
+                                   stream_ptr(self.device)), "sg_grid_lookup")
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            check(lib().sg_grid_destroy(self._h), "sg_grid_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _check_vox(grid, vox, C):
+    if C not in SUPPORTED_C:
+        raise ValueError(f"C={C} unsupported; supported: {SUPPORTED_C}")
+    want(vox, "vox", torch.float32, (grid.n_blocks, 512, 1 + C), grid.device)
+
+
+def render_forward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, out=None):
+    """Colour/feature, depth, normal, weight sum and sample count per ray."""
+    params = RenderParams.of(params)
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    want(rays, "rays", torch.float32, (None, 6), grid.device)
+    R = rays.shape[0]
+    dev = grid.device
+    if out is None:
+        out = {"feat": torch.empty((R, C), dtype=torch.float32, device=dev),
+               "depth": torch.empty(R, dtype=torch.float32, device=dev),
+               "normal": torch.empty((R, 3), dtype=torch.float32, device=dev),
+               "wsum": torch.empty(R, dtype=torch.float32, device=dev),
+               "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
+    prm = params.c()
+    check(lib().sg_render_forward(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
+                                  ptr(out["feat"]) if C else None, ptr(out["depth"]),
+                                  ptr(out["normal"]), ptr(out["wsum"]), ptr(out.get("nsamples")),
+                                  stream_ptr(dev)), "sg_render_forward")
+    return out
+
+
+def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g_feat, g_depth,
+                    g_normal, g_wsum=None, grad_vox=None):
+    """Accumulate dL/dvox for upstream gradients of the render outputs."""
+    params = RenderParams.of(params)
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    want(rays, "rays", torch.float32, (None, 6), grid.device)
+    R = rays.shape[0]
+    if C:
+        want(g_feat, "g_feat", torch.float32, (R, C), grid.device)
+    want(g_depth, "g_depth", torch.float32, (R,), grid.device)
+    want(g_normal, "g_normal", torch.float32, (R, 3), grid.device)
+    if g_wsum is not None:
+        want(g_wsum, "g_wsum", torch.float32, (R,), grid.device)
+    if grad_vox is None:
+        grad_vox = torch.zeros_like(vox)
+    else:
+        want(grad_vox, "grad_vox", torch.float32, tuple(vox.shape), grid.device)
+    prm = params.c()
+    check(lib().sg_render_backward(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
+                                   ptr(g_feat) if C else None, ptr(g_depth), ptr(g_normal),
+                                   ptr(g_wsum), ptr(grad_vox), stream_ptr(grid.device)),
+          "sg_render_backward")
+    return grad_vox
+
+
+def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
+    """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
+    params = RenderParams.of(params)
+    want(rays, "rays", torch.float32, (None, 6), grid.device)
+    R = rays.shape[0]
+    counts = torch.empty((R, 3), dtype=torch.int32, device=grid.device)
+    tmap = torch.zeros(grid.n_blocks * 512, dtype=torch.uint8, device=grid.device) if touched else None
+    prm = params.c()
+    check(lib().sg_render_footprint(grid.handle, ptr(rays), R, ctypes.byref(prm), ptr(counts),
+                                    ptr(tmap), stream_ptr(grid.device)), "sg_render_footprint")
+    return (counts, tmap) if touched else counts
+
+
+def rays_pinhole(cams: torch.Tensor, pix: torch.Tensor):
+    """Unit rays [R,6] through pixel centres of pinhole cameras [n,16]."""
+    want(cams, "cams", torch.float32, (None, 16))
+    want(pix, "pix", torch.int32, (None, 3), cams.device)
+    out = torch.empty((pix.shape[0], 6), dtype=torch.float32, device=cams.device)
+    check(lib().sg_rays_pinhole(ptr(cams), cams.shape[0], ptr(pix), pix.shape[0], ptr(out),
+                                stream_ptr(cams.device)), "sg_rays_pinhole")
+    return out
+
+
+def l2_loss_grad(pred, ref, lambda_d=0.1, lambda_n=0.05, with_loss=False, out=None):
+    """Gradient (and optionally value) of the squared-L2 rendering loss."""
+    R = pred["depth"].shape[0]
+    C = pred["feat"].shape[1]
+    dev = pred["depth"].device
+    for k, shp in (("feat", (R, C)), ("depth", (R,)), ("normal", (R, 3))):
+        want(pred[k], "pred." + k, torch.float32, shp, dev)
+        want(ref[k], "ref." + k, torch.float32, shp, dev)
+    if out is None:
+        out = {"feat": torch.empty((R, C), dtype=torch.float32, device=dev),
+               "depth": torch.empty(R, dtype=torch.float32, device=dev),
+               "normal": torch.empty((R, 3), dtype=torch.float32, device=dev)}
+    loss = torch.empty(1, dtype=torch.float32, device=dev) if with_loss else None
+    check(lib().sg_l2_loss_grad(ptr(pred["feat"]) if C else None, ptr(ref["feat"]) if C else None,
+                                ptr(pred["depth"]), ptr(ref["depth"]), ptr(pred["normal"]),
+                                ptr(ref["normal"]), R, C, ctypes.c_float(lambda_d),
+                                ctypes.c_float(lambda_n), ptr(out["feat"]) if C else None,
+                                ptr(out["depth"]), ptr(out["normal"]), ptr(loss), stream_ptr(dev)),
+          "sg_l2_loss_grad")
+    return (out, loss) if with_loss else out
+
+
+def optim_step(kind: int, param, grad, m, v, lr, b1, b2, eps, t):
+    """In-place Adam (kind 0) or RMSProp (kind 1) step on float32 tensors."""
+    want(param, "param", torch.float32)
+    n = param.numel()
+    for name, x in (("grad", grad), ("v", v)):
+        want(x, name, torch.float32, None, param.device)
+        if x.numel() != n:
+            raise ValueError(f"{name} has {x.numel()} elements, expected {n}")
+    if kind == 0:
+        want(m, "m", torch.float32, None, param.device)
+        if m.numel() != n:
+            raise ValueError("m has the wrong size")
+    check(lib().sg_optim_step(kind, ptr(param), ptr(grad), ptr(m) if kind == 0 else None, ptr(v), n,
+                              ctypes.c_float(lr), ctypes.c_float(b1), ctypes.c_float(b2),
+                              ctypes.c_float(eps), t, stream_ptr(param.device)), "sg_optim_step")
+
+
+class SdfRender(torch.autograd.Function):
+    """Differentiable render: vox -> (feat, depth, normal, wsum).
+
+    The backward recomputes the samples from the grid (nothing per-sample is
+    saved) and accumulates into a freshly zeroed gradient tensor.
+    """
+
+    @staticmethod
+    def forward(ctx, vox, grid, rays, params):
+        out = render_forward(grid, vox.detach(), rays, params)
+        ctx.grid, ctx.params = grid, params
+        ctx.save_for_backward(vox, rays)
+        ctx.mark_non_differentiable(out["nsamples"])
+        return out["feat"], out["depth"], out["normal"], out["wsum"], out["nsamples"]
+
+    @staticmethod
+    def backward(ctx, g_feat, g_depth, g_normal, g_wsum, _g_ns):
+        vox, rays = ctx.saved_tensors
+        R = rays.shape[0]
+        C = vox.shape[-1] - 1
+        z = lambda *s: torch.zeros(s, dtype=torch.float32, device=vox.device)
+        g_feat = z(R, C) if g_feat is None else g_feat.contiguous()
+        g_depth = z(R) if g_depth is None else g_depth.contiguous()
+        g_normal = z(R, 3) if g_normal is None else g_normal.contiguous()
+        g_wsum = None if g_wsum is None else g_wsum.contiguous()
+        grad = render_backward(ctx.grid, vox.detach(), rays, ctx.params, g_feat, g_depth,
+                               g_normal, g_wsum)
+        return grad, None, None, None
+
+
+def render(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params):
+    """Differentiable render; returns (feat, depth, normal, wsum, nsamples)."""
+    return SdfRender.apply(vox, grid, rays, RenderParams.of(params))

@@ -1,0 +1,59 @@
+"""GPU grid build / lookup / neighbour table: bit-exact against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _build(coords, return_index=True):
+    import paper_2305_13220_amd as sg
+    return sg.Grid(to_dev(coords, torch.int32), 0.02, (0.1, -0.2, 0.3), return_index=return_index)
+
+
+@pytest.mark.parametrize("n,lo,hi,seed", [(1, -3, 3, 0), (50, -2, 2, 1), (3000, -6, 6, 2),
+                                          (200000, -40, 40, 3)])
+def test_build_matches_oracle(n, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    coords = rng.integers(lo, hi, size=(n, 3)).astype(np.int32)
+    g = _build(coords)
+    blocks_or, idx_or = oracle.build_grid(coords)
+    assert g.n_blocks == blocks_or.shape[0]
+    np.testing.assert_array_equal(g.block_coords().cpu().numpy(), blocks_or)
+    np.testing.assert_array_equal(g.index_of_input.cpu().numpy(), idx_or)
+    np.testing.assert_array_equal(g.neighbors().cpu().numpy(), oracle.neighbors(blocks_or))
+    # lookups over the bounding box plus a margin, and random far queries
+    blo, bhi = blocks_or.min(0) - 2, blocks_or.max(0) + 2
+    q = np.stack(np.meshgrid(*[np.arange(blo[a], bhi[a] + 1) for a in range(3)], indexing="ij"),
+                 -1).reshape(-1, 3).astype(np.int32)
+    q = np.concatenate([q, rng.integers(-2 ** 31, 2 ** 31 - 1, size=(1000, 3))]).astype(np.int32)
+    np.testing.assert_array_equal(g.lookup(to_dev(q)).cpu().numpy(), oracle.lookup(blocks_or, q))
+    g.destroy()
+
+
+def test_extreme_coordinates_and_range_error():
+    import paper_2305_13220_amd as sg
+    lim = 1 << 20
+    coords = np.array([[-lim, -lim, -lim], [lim - 1, lim - 1, lim - 1], [0, 0, 0],
+                       [lim - 1, -lim, 5], [0, 0, 0]], np.int32)
+    g = _build(coords)
+    np.testing.assert_array_equal(g.index_of_input.cpu().numpy(), [0, 1, 2, 3, 2])
+    q = np.array([[lim, 0, 0], [-lim - 1, 0, 0], [lim - 1, lim - 1, lim - 1]], np.int32)
+    np.testing.assert_array_equal(g.lookup(to_dev(q)).cpu().numpy(), [-1, -1, 1])
+    nb = g.neighbors().cpu().numpy()
+    assert (nb[1] == [1, -1, -1, -1, -1, -1, -1, -1]).all()
+    g.destroy()
+    with pytest.raises(sg.SgridError, match="status -2"):
+        _build(np.array([[0, 0, 0], [lim, 0, 0]], np.int32))
+
+
+def test_sphere_grid_matches_oracle():
+    from synth import workloads
+    w = workloads.sphere_tiny()
+    g = _build(w["block_coords"])
+    np.testing.assert_array_equal(g.block_coords().cpu().numpy(), w["block_coords"])
+    np.testing.assert_array_equal(g.index_of_input.cpu().numpy(), np.arange(494))
+    np.testing.assert_array_equal(g.neighbors().cpu().numpy(), oracle.neighbors(w["block_coords"]))

@@ -1,0 +1,244 @@
+"""GPU render forward / backward / footprint against the oracle.
+
+Same seeded inputs on both sides (scene arrays and float32 rays from the
+input generators).  Bars: sample counts and footprint counts bit-exact;
+colour, depth, normal and weight sum within 1e-5 of the oracle relative to
+sum_k |w_k v_k|; gradients within 1e-4 relative to the sum of absolute
+values of their terms; rays with no samples exactly zero; repeated forward
+calls bit-identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import (RTOL_BWD, assert_close_mag, check_forward, dev, make_grid, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _sg():
+    import paper_2305_13220_amd as sg
+    return sg
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    from synth import workloads
+    w = workloads.sphere_tiny()
+    return w, make_grid(w), to_dev(w["vox"]), to_dev(w["rays"])
+
+
+@pytest.fixture(scope="module")
+def room():
+    from synth import workloads
+    w = workloads.room_2cm()
+    return w, make_grid(w), to_dev(w["vox"]), to_dev(w["rays"])
+
+
+def _oracle_fwd(w, rays, C=3, vox=None, params=None):
+    return oracle.render_forward(w["block_coords"], w["vox"] if vox is None else vox, C, w["h"],
+                                 w["origin"], rays, params or w["params"], with_mag=True)
+
+
+def test_forward_sphere_full_frame(sphere):
+    w, g, vox, rays = sphere
+    out = _sg().render_forward(g, vox, rays, w["params"])
+    check_forward(out, _oracle_fwd(w, w["rays"]), what="sphere 64x48")
+
+
+def test_forward_room_full_batch(room):
+    """All 65,536 rays of the room batch in the benchmark's launch."""
+    w, g, vox, rays = room
+    out = _sg().render_forward(g, vox, rays, w["params"])
+    check_forward(out, _oracle_fwd(w, w["rays"]), what="room 2cm 65536 rays")
+
+
+def test_forward_is_deterministic(room):
+    w, g, vox, rays = room
+    a = _sg().render_forward(g, vox, rays, w["params"])
+    b = _sg().render_forward(g, vox, rays, w["params"])
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("max_samples", [1, 2, 63, 64, 65, 300, 1024])
+def test_forward_sample_caps(sphere, max_samples):
+    w, g, vox, rays = sphere
+    prm = dict(w["params"], max_samples=max_samples)
+    sub = w["rays"][::7]
+    out = _sg().render_forward(g, vox, to_dev(sub), prm)
+    check_forward(out, _oracle_fwd(w, sub, params=prm), what=f"cap {max_samples}")
+
+
+def test_forward_edge_rays(sphere):
+    w, g, vox, _ = sphere
+    h = float(w["h"])
+    rays = np.array([
+        [3, 3, 3, 1, 0, 0],                      # misses the grid
+        [0, 0, 5, 0, 0, 1],                      # points away
+        [np.nan, 0, 0, 1, 0, 0],                 # non-finite origin
+        [0, 0, -1.5, 0, np.inf, 1],              # non-finite direction
+        [0, 0, -1.5, 0, 0, 1],                   # along +z through the centre
+        [-1.5, 0, 0, 1, 0, 0],                   # along +x on voxel faces y = z = 0
+        [-1.5, 8 * h, 8 * h, 1, 0, 0],           # on block faces
+        [-1.5, 0.5 * h, -0.25 * h, 1, 0, 0],     # axis-aligned, mid-voxel
+        [0.0, 0.0, 0.0, 0.6, 0.8, 0.0],          # starts inside the sphere
+        [1.2, 1.2, 1.2, -0.57735026, -0.57735026, -0.57735026],  # diagonal
+    ], np.float32)
+    out = _sg().render_forward(g, vox, to_dev(rays), w["params"])
+    check_forward(out, _oracle_fwd(w, rays), what="edge rays")
+    assert out["nsamples"][4].item() > 0 and out["nsamples"][0].item() == 0
+    # t_near > t_far, and zero rays
+    prm = dict(w["params"], t_near=2.0, t_far=1.0)
+    out = _sg().render_forward(g, vox, to_dev(rays), prm)
+    assert out["nsamples"].sum().item() == 0 and not out["wsum"].any()
+    empty = _sg().render_forward(g, vox, to_dev(np.zeros((0, 6), np.float32)), w["params"])
+    assert empty["depth"].numel() == 0
+
+
+@pytest.mark.parametrize("C", [0, 1, 19])
+def test_forward_feature_counts(C):
+    from synth import scenes
+    w = scenes.sphere_scene(h=1.0 / 32, radius=0.4, band_vox=3, seed=5, C=max(C, 1))
+    vox_np = w["vox"][..., : 1 + C].copy()
+    if C == 19:
+        rng = np.random.default_rng(9)
+        vox_np = np.concatenate([w["vox"][..., :2], rng.normal(size=w["vox"].shape[:2] + (18,))],
+                                -1).astype(np.float32)
+    from synth import cameras
+    cams = cameras.orbit_cams(seed=6, n=2, radius=1.2, W=40, H=30, f=40.0)
+    pix = cameras.random_pixels(2, 40, 30, 1500, seed=7)
+    rays = cameras.pixel_rays(cams, pix)
+    prm = {"step": float(np.float32(1 / 64)), "t_near": 0.0, "t_far": 2.5,
+           "beta": float(np.float32(1 / 32)), "max_samples": 128}
+    g = make_grid(w)
+    out = _sg().render_forward(g, to_dev(vox_np), to_dev(rays), prm)
+    ref = oracle.render_forward(w["block_coords"], vox_np, C, w["h"], w["origin"], rays, prm,
+                                with_mag=True)
+    check_forward(out, ref, what=f"C={C}")
+
+
+def _upstream(R, C, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=(R, C)).astype(np.float32), rng.normal(size=R).astype(np.float32),
+            rng.normal(size=(R, 3)).astype(np.float32), rng.normal(size=R).astype(np.float32))
+
+
+def _check_backward(w, g, vox, rays_np, C, seed, with_wsum=True, what="backward"):
+    R = rays_np.shape[0]
+    gf, gd, gn, gw = _upstream(R, C, seed)
+    grad = _sg().render_backward(g, vox, to_dev(rays_np), w["params"], to_dev(gf), to_dev(gd),
+                                 to_dev(gn), to_dev(gw) if with_wsum else None)
+    ref, mag = oracle.render_backward(w["block_coords"], w["vox"], C, w["h"], w["origin"], rays_np,
+                                      w["params"], gf, gd, gn, gw if with_wsum else None,
+                                      with_mag=True)
+    got = grad.cpu().numpy()
+    assert_close_mag(got, ref, mag, RTOL_BWD, what)
+    untouched = mag == 0
+    assert not np.any(got[untouched]), f"{what}: gradient written to untouched voxels"
+
+
+def test_backward_sphere_full_frame(sphere):
+    w, g, vox, _ = sphere
+    _check_backward(w, g, vox, w["rays"], 3, seed=1, what="sphere backward")
+
+
+def test_backward_room(room):
+    w, g, vox, _ = room
+    _check_backward(w, g, vox, w["rays"][:8192], 3, seed=2, with_wsum=False, what="room backward")
+
+
+def test_backward_room_full_batch(room):
+    """The benchmark's batch (65,536 rays) in its launch configuration."""
+    w, g, vox, _ = room
+    _check_backward(w, g, vox, w["rays"], 3, seed=3, what="room backward full batch")
+
+
+@pytest.mark.parametrize("max_samples", [1, 65, 1024])
+def test_backward_sample_caps(sphere, max_samples):
+    w, g, vox, _ = sphere
+    w2 = dict(w, params=dict(w["params"], max_samples=max_samples))
+    _check_backward(w2, g, vox, w["rays"][::5], 3, seed=4, what=f"backward cap {max_samples}")
+
+
+def test_autograd_function_matches_direct(sphere):
+    w, g, vox, rays = sphere
+    sg = _sg()
+    v = vox.clone().requires_grad_(True)
+    feat, depth, normal, wsum, ns = sg.render(g, v, rays, w["params"])
+    tgt = torch.rand_like(feat)
+    loss = ((feat - tgt) ** 2).sum() + 0.1 * (depth ** 2).sum() + 0.05 * (normal ** 2).sum()
+    loss.backward()
+    direct = sg.render_backward(g, vox, rays, w["params"], (2 * (feat - tgt)).detach().contiguous(),
+                                (0.2 * depth).detach().contiguous(),
+                                (0.1 * normal).detach().contiguous())
+    # two backward launches: float32 atomics may sum in different orders
+    torch.testing.assert_close(v.grad, direct, rtol=1e-5, atol=1e-6 * direct.abs().max().item())
+
+
+def test_footprint_bit_exact(room, sphere):
+    for w, g, _, rays in (sphere, room):
+        sub = w["rays"][:4096]
+        counts, touched = _sg().render_footprint(g, to_dev(sub), w["params"], touched=True)
+        ref, ref_t = oracle.footprint(w["block_coords"], w["h"], w["origin"], sub, w["params"],
+                                      with_touched=True)
+        np.testing.assert_array_equal(counts.cpu().numpy(), ref)
+        np.testing.assert_array_equal(touched.cpu().numpy(), ref_t)
+
+
+def test_rays_pinhole_matches_oracle(room):
+    w = room[0]
+    sg = _sg()
+    pix = w["pix"][:20000].copy()
+    pix[:3, 0] = [-1, 30, 29]
+    got = sg.rays_pinhole(to_dev(w["cams"]), to_dev(pix)).cpu().numpy()
+    ref = oracle.rays_pinhole(w["cams"], pix)
+    assert np.isnan(got[:2]).all() and np.isnan(ref[:2]).all()
+    np.testing.assert_allclose(got[2:], ref[2:], rtol=0, atol=2e-6)
+
+
+def test_l2_loss_grad_and_optimiser():
+    sg = _sg()
+    rng = np.random.default_rng(8)
+    R, C = 3001, 3
+    pred = {"feat": rng.normal(size=(R, C)), "depth": rng.normal(size=R), "normal": rng.normal(size=(R, 3))}
+    ref = {k: rng.normal(size=v.shape) for k, v in pred.items()}
+    f32 = {k: v.astype(np.float32) for k, v in pred.items()}
+    r32 = {k: v.astype(np.float32) for k, v in ref.items()}
+    out, loss = sg.l2_loss_grad({k: to_dev(v) for k, v in f32.items()},
+                                {k: to_dev(v) for k, v in r32.items()}, 0.1, 0.05, with_loss=True)
+    L, gc, gd, gn = oracle.l2_loss_grad(f32["feat"], r32["feat"], f32["depth"], r32["depth"],
+                                        f32["normal"], r32["normal"], 0.1, 0.05)
+    assert loss.item() == pytest.approx(L, rel=1e-5)
+    np.testing.assert_allclose(out["feat"].cpu().numpy(), gc, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(out["depth"].cpu().numpy(), gd, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(out["normal"].cpu().numpy(), gn, rtol=1e-6, atol=1e-12)
+    for kind in (0, 1):
+        n = 100003
+        p0 = rng.normal(size=n).astype(np.float32)
+        p = to_dev(p0)
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        mr, vr, pr = np.zeros(n), np.zeros(n), p0.astype(np.float64)
+        # the kernel receives float32 hyper-parameters: the oracle takes the same values
+        lr, b1, b2, eps = (float(np.float32(x)) for x in (1e-2, 0.9, 0.999, 1e-8))
+        for t in range(1, 4):
+            gr = rng.normal(size=n).astype(np.float32)
+            sg.optim_step(kind, p, to_dev(gr), m, v, lr, b1, b2, eps, t)
+            pr, mr, vr = oracle.optim_step(kind, pr, gr, mr if kind == 0 else None, vr, lr, b1,
+                                           b2, eps, t)
+        np.testing.assert_allclose(p.cpu().numpy(), pr, rtol=0, atol=2e-6)
+
+
+def test_invalid_arguments_raise(sphere):
+    w, g, vox, rays = sphere
+    sg = _sg()
+    with pytest.raises(sg.SgridError, match="max_samples"):
+        sg.render_forward(g, vox, rays, dict(w["params"], max_samples=0))
+    with pytest.raises(sg.SgridError, match="beta"):
+        sg.render_forward(g, vox, rays, dict(w["params"], beta=0.0))
+    with pytest.raises(sg.SgridError, match="2\\^24"):
+        sg.render_forward(g, vox, rays, dict(w["params"], step=1e-9))
+    with pytest.raises(ValueError):
+        sg.render_forward(g, vox[:10], rays, w["params"])
