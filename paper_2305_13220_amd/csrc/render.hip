@@ -352,6 +352,16 @@ struct SampleState {
   float w, s, tn, f;  // weight, dL/dw, T_{k+1}, SDF
 };
 
+// Per-wave LDS staging of one chunk's scatter.  Rows are padded to an odd
+// number of words so that lanes writing the same column hit distinct banks.
+struct BwdScratch {
+  float val[kWave][17];   // per sample: SDF-gradient term of corners 0..7, then w * r_a
+  int32_t off[kWave][9];  // element offsets of the 8 corners
+  int32_t key[kWave];     // cell id (offset of corner 0), unique negative if unused
+  int32_t heads[kWave];   // lanes that start a run of samples in one cell
+  float gC[32];           // upstream feature gradient of the ray
+};
+
 template <int C>
 __global__ __launch_bounds__(256) void k_render_bwd(
     GridView g, const float* __restrict__ vox, const float* __restrict__ rays, int64_t R, Params p,
@@ -360,10 +370,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(
     float* __restrict__ grad_vox) {
   extern __shared__ int2 lds_q[];
   constexpr int V = 1 + C;
+  constexpr int PER = 8 * V;  // scatter values per cell
   const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
   int2* q = lds_q + (int64_t)w * p.max_samples;
   SampleState* st =
       reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples) + (int64_t)w * p.max_samples;
+  BwdScratch* sc = reinterpret_cast<BwdScratch*>(
+                       reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples) +
+                       (int64_t)wpb * p.max_samples) + w;
   for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
     March m;
     int n = 0;
@@ -372,6 +386,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
     float gC[C > 0 ? C : 1];
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) gC[ch] = g_feat[(int64_t)C * r + ch];
+    if (lane < C) sc->gC[lane] = g_feat[(int64_t)C * r + lane];
     const float gD = g_depth[r];
     const float gN[3] = {g_normal[3 * r], g_normal[3 * r + 1], g_normal[3 * r + 2]};
     const float gW = g_wsum ? g_wsum[r] : 0.0f;
@@ -407,7 +422,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       tau += shfl(incl, kWave - 1);
     }
     wave_sync();
-    // pass 2: reverse, suffix sums, scatter
+    // pass 2: chunks in reverse; suffix sums give dL/dsigma; per-corner terms
+    // are staged in LDS, merged over runs of samples in one cell, then
+    // scattered with lanes laid out as (cell, corner, channel) so that each
+    // atomic instruction touches few cache lines.
     float carry = 0.0f;
     const int last = (n - 1) / kWave * kWave;
     for (int c0 = last; c0 >= 0; c0 -= kWave) {
@@ -422,57 +440,54 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       const float nxt = shfl(suf, lane < kWave - 1 ? lane + 1 : lane);
       const float later = lane < kWave - 1 ? nxt : 0.0f;
       const float total = shfl(suf, 0);
-      float esdf[8], qf[8];
       int key = -1 - lane;
-      Cell cell;
       if (act) {
         const float dsig = p.step * (s.tn * s.s - (carry + later));
         const float e = 0.5f * expf(-fabsf(s.f) * p.inv_beta);
-        const float dsig_df = -e * p.inv_beta * p.inv_beta;
-        const float df = dsig * dsig_df;
+        const float df = dsig * (-e * p.inv_beta * p.inv_beta);
+        Cell cell;
         locate(g, m, p, q[j], cell);
-        float rr[8], dr[8][3];
-        corner_weights(cell.u, rr, dr);
+        const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
+                    wz[2] = {1.0f - cell.u[2], cell.u[2]};
         const float wih = s.w * g.inv_h;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          esdf[a] = rr[a] * df + wih * (dr[a][0] * gN[0] + dr[a][1] * gN[1] + dr[a][2] * gN[2]);
-          qf[a] = s.w * rr[a];
+          const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+          const float ra = wx[ax] * wy[ay] * wz[az];
+          const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gN[0] +
+                           (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gN[1] +
+                           (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gN[2];
+          sc->val[lane][a] = ra * df + wih * gn;
+          sc->val[lane][8 + a] = s.w * ra;
+          sc->off[lane][a] = cell.off[a];
         }
         key = cell.off[0];
-      } else {
-#pragma unroll
-        for (int a = 0; a < 8; ++a) esdf[a] = qf[a] = 0.0f;
       }
-      // merge consecutive samples that share a cell (segmented suffix sum)
-      for (int off = 1; off < kWave; off <<= 1) {
-        const int src = lane + off < kWave ? lane + off : lane;
-        const int kn = shfl(key, src);
-        const bool same = (lane + off < kWave) && kn == key;
-        if (!__any(same)) break;
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const float o1 = shfl(esdf[a], src), o2 = shfl(qf[a], src);
-          if (same) {
-            esdf[a] += o1;
-            qf[a] += o2;
-          }
-        }
-      }
+      sc->key[lane] = key;
       const int kp = shfl(key, lane > 0 ? lane - 1 : 0);
       const bool head = act && (lane == 0 || kp != key);
+      const uint64_t hm = __ballot(head);
+      const int H = (int)__popcll(hm);
+      wave_sync();
       if (head) {
+        // positions are monotone per axis, so a cell's samples are adjacent
+        for (int l2 = lane + 1; l2 < kWave && sc->key[l2] == key; ++l2) {
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          float* dst = grad_vox + (int64_t)cell.off[a] * V;
-          unsafeAtomicAdd(dst, esdf[a]);
-#pragma unroll
-          for (int ch = 0; ch < C; ++ch) unsafeAtomicAdd(dst + 1 + ch, qf[a] * gC[ch]);
+          for (int a = 0; a < 16; ++a) sc->val[lane][a] += sc->val[l2][a];
         }
+        sc->heads[rank_below(hm)] = lane;
       }
+      wave_sync();
+      for (int idx = lane; idx < H * PER; idx += kWave) {
+        const int hh = idx / PER, rem = idx - hh * PER;
+        const int a = rem / V, ch = rem - a * V;
+        const int hl = sc->heads[hh];
+        const float v = ch == 0 ? sc->val[hl][a] : sc->val[hl][8 + a] * sc->gC[ch > 0 ? ch - 1 : 0];
+        unsafeAtomicAdd(grad_vox + (int64_t)sc->off[hl][a] * V + ch, v);
+      }
+      wave_sync();  // the staging rows are rewritten by the next chunk
       carry += total;
     }
-    wave_sync();
   }
 }
 
@@ -649,7 +664,8 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   if (!d_vox || !d_rays || !d_g_depth || !d_g_normal || !d_grad_vox || (C > 0 && !d_g_feat))
     return fail(SG_EINVAL, "a required pointer is NULL");
   const GridView g = view_of(grid);
-  const Launch l = plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples);
+  const Launch l =
+      plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch));
   hipStream_t s = (hipStream_t)stream;
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_bwd<CC>, dim3(l.blocks), dim3(l.threads), l.lds, s,
                                       g, d_vox, d_rays, n_rays, p, d_g_feat, d_g_depth, d_g_normal,
