@@ -110,6 +110,40 @@ int sg_grid_build(const int32_t* d_block_coords, int64_t n, float voxel_size,
                   const float origin[3], sg_stream stream, sg_grid** out,
                   int32_t* d_index_of_input);
 
+/*
+ * Build options.  dense_map_max_cells: besides the hash, build a dense map
+ * of the grid's bounding box in blocks (one int32 per block cell: block
+ * index and neighbour mask, or the Chebyshev distance to the nearest
+ * allocated block) when the box has at most this many cells; the renderer
+ * then resolves blocks and skips empty space through it instead of probing
+ * the hash.  0 disables the map; a negative value selects the default
+ * SG_DEFAULT_DENSE_MAP_CELLS (2^28 cells = 1 GiB).  Results are identical
+ * with and without the map.
+ */
+#define SG_DEFAULT_DENSE_MAP_CELLS 268435456LL
+typedef struct sg_build_options {
+  int64_t dense_map_max_cells;
+} sg_build_options;
+
+/* sg_grid_build with options (NULL = defaults); otherwise identical. */
+int sg_grid_build_ex(const int32_t* d_block_coords, int64_t n, float voxel_size,
+                     const float origin[3], sg_stream stream, sg_grid** out,
+                     int32_t* d_index_of_input, const sg_build_options* options);
+
+/*
+ * Dense block map geometry: dims[3] (all 0 if the grid has no map) and the
+ * block coordinate bmin[3] of its first cell.  Cell (x,y,z) is at
+ * ((z - bmin.z) * dims.y + (y - bmin.y)) * dims.x + (x - bmin.x).
+ */
+int sg_grid_dense_map(const sg_grid* g, int32_t dims[3], int32_t bmin[3]);
+
+/* Copy the dense map (int32 [dims.z*dims.y*dims.x]): entry >= 0 is
+ * block_index * 256 + neighbour mask (bit s as in sg_grid_neighbors); entry
+ * -D (1 <= D <= 32) means every block within Chebyshev distance D-1 is
+ * unallocated (distances beyond 32 are stored as 32).  SG_ESTATE if the grid
+ * has no map. */
+int sg_grid_copy_dense_map(const sg_grid* g, int32_t* d_out, sg_stream stream);
+
 /* Number of allocated (unique) blocks. */
 int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks);
 

@@ -20,6 +20,10 @@ class SgridError(RuntimeError):
     pass
 
 
+class BuildOptionsC(ctypes.Structure):
+    _fields_ = [("dense_map_max_cells", ctypes.c_int64)]
+
+
 class RenderParamsC(ctypes.Structure):
     _fields_ = [("step", ctypes.c_float), ("t_near", ctypes.c_float), ("t_far", ctypes.c_float),
                 ("beta", ctypes.c_float), ("max_samples", ctypes.c_int32)]
@@ -36,6 +40,9 @@ _SIGNATURES = {
     "sg_last_error": ([], ctypes.c_char_p),
     "sg_version": ([], ctypes.c_char_p),
     "sg_grid_build": ([_vp, _i64, _f, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "sg_grid_build_ex": ([_vp, _i64, _f, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "sg_grid_dense_map": ([_vp, _vp, _vp], ctypes.c_int),
+    "sg_grid_copy_dense_map": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_num_blocks": ([_vp, _vp], ctypes.c_int),
     "sg_grid_geometry": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_block_coords": ([_vp, _vp, _vp], ctypes.c_int),

@@ -66,7 +66,15 @@ struct GridView {
   int32_t bmin[3], bmax[3];  // bounding box of allocated block coordinates
   float h, inv_h;
   float org[3];
+  // Dense block map over the bounding box (nullptr: use the hash).  Entry
+  // of block b, at ((bz-bmin.z)*dim.y + by-bmin.y)*dim.x + bx-bmin.x:
+  //   >= 0: idx * 256 + neighbour mask of the allocated block
+  //   <  0: -D, every block within Chebyshev distance D-1 of b is empty
+  const int32_t* map;
+  int32_t mdim[3];
 };
+
+constexpr int kMapMaxDist = 32;  // distances are capped (a conservative bound)
 
 // Probe for block (x,y,z); returns the slot contents (idx = -1 if absent).
 __device__ inline void probe(const GridView& g, int32_t x, int32_t y, int32_t z, int32_t& idx,
@@ -86,6 +94,30 @@ __device__ inline void probe(const GridView& g, int32_t x, int32_t y, int32_t z,
     if (e.key == kEmptyKey) return;
     s = (s + 1) & g.mask;
   }
+}
+
+// Allocation state of block (x,y,z): idx (-1 if absent), neighbour mask,
+// and for an absent block a Chebyshev radius D >= 1 of emptiness around it.
+__device__ inline void block_state(const GridView& g, int32_t x, int32_t y, int32_t z,
+                                   int32_t& idx, int32_t& nmask, int32_t& dist) {
+  dist = 1;
+  if (g.map) {
+    idx = -1;
+    nmask = 0;
+    const int32_t rx = x - g.bmin[0], ry = y - g.bmin[1], rz = z - g.bmin[2];
+    if ((uint32_t)rx >= (uint32_t)g.mdim[0] || (uint32_t)ry >= (uint32_t)g.mdim[1] ||
+        (uint32_t)rz >= (uint32_t)g.mdim[2])
+      return;
+    const int32_t e = g.map[((int64_t)rz * g.mdim[1] + ry) * g.mdim[0] + rx];
+    if (e >= 0) {
+      idx = e >> 8;
+      nmask = e & 255;
+    } else {
+      dist = -e;
+    }
+    return;
+  }
+  probe(g, x, y, z, idx, nmask);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,6 +190,8 @@ struct sg_grid {
   int32_t bmin[3], bmax[3];
   float h;
   float org[3];
+  int32_t* d_map;          // dense block map over the bounding box, or nullptr
+  int32_t mdim[3];
 };
 
 namespace sg {

@@ -45,6 +45,8 @@ GridView view_of(const sg_grid* g) {
   }
   v.h = g->h;
   v.inv_h = 1.0f / g->h;  // one correctly rounded float32 division
+  v.map = g->d_map;
+  for (int a = 0; a < 3; ++a) v.mdim[a] = g->mdim[a];
   return v;
 }
 
@@ -257,6 +259,45 @@ __global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* 
     if (base + j < n) out[base + j] += add;
 }
 
+// Dense block map: allocated blocks first, then Chebyshev distances by
+// repeated 26-neighbour dilation (in place: a cell labelled in round r is
+// never mistaken for one of round r-1).
+__global__ void k_map_fill(int32_t* __restrict__ map, int64_t cells) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cells) map[i] = -kMapMaxDist;
+}
+
+__global__ void k_map_blocks(const int32_t* __restrict__ coords, const int32_t* __restrict__ nbr,
+                             int64_t n, int32_t bx0, int32_t by0, int32_t bz0, int32_t dx,
+                             int32_t dy, int32_t* __restrict__ map) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int nm = 0;
+  for (int q = 0; q < 8; ++q)
+    if (nbr[8 * i + q] >= 0) nm |= 1 << q;
+  const int64_t cell = ((int64_t)(coords[3 * i + 2] - bz0) * dy + (coords[3 * i + 1] - by0)) * dx +
+                       (coords[3 * i] - bx0);
+  map[cell] = (int32_t)(i * 256 + nm);
+}
+
+__global__ void k_map_dilate(int32_t* map, int32_t dx, int32_t dy, int32_t dz, int32_t r) {
+  const int64_t cells = (int64_t)dx * dy * dz;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cells || map[i] != -kMapMaxDist) return;
+  const int32_t x = (int32_t)(i % dx), y = (int32_t)((i / dx) % dy), z = (int32_t)(i / ((int64_t)dx * dy));
+  for (int oz = -1; oz <= 1; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int32_t X = x + ox, Y = y + oy, Z = z + oz;
+        if (X < 0 || Y < 0 || Z < 0 || X >= dx || Y >= dy || Z >= dz) continue;
+        const int32_t e = map[((int64_t)Z * dy + Y) * dx + X];
+        if ((r == 1 && e >= 0) || (r > 1 && e == -(r - 1))) {
+          map[i] = -r;
+          return;
+        }
+      }
+}
+
 __global__ void k_lookup(GridView g, const int32_t* __restrict__ q, int64_t n,
                          int32_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,6 +358,15 @@ const char* sg_version(void) { return "sgrid 0.1 (gfx950)"; }
 int sg_grid_build(const int32_t* d_block_coords, int64_t n, float voxel_size,
                   const float origin[3], sg_stream stream, sg_grid** out,
                   int32_t* d_index_of_input) {
+  return sg_grid_build_ex(d_block_coords, n, voxel_size, origin, stream, out, d_index_of_input,
+                          nullptr);
+}
+
+int sg_grid_build_ex(const int32_t* d_block_coords, int64_t n, float voxel_size,
+                     const float origin[3], sg_stream stream, sg_grid** out,
+                     int32_t* d_index_of_input, const sg_build_options* options) {
+  int64_t map_limit = SG_DEFAULT_DENSE_MAP_CELLS;
+  if (options && options->dense_map_max_cells >= 0) map_limit = options->dense_map_max_cells;
   if (!out) return fail(SG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!d_block_coords) return fail(SG_EINVAL, "d_block_coords is NULL");
@@ -403,6 +453,24 @@ int sg_grid_build(const int32_t* d_block_coords, int64_t n, float voxel_size,
     g->bmin[a] = bbox[a];
     g->bmax[a] = bbox[3 + a];
   }
+  g->d_map = nullptr;
+  g->mdim[0] = g->mdim[1] = g->mdim[2] = 0;
+  // The box may span up to 2^21 blocks per axis: decide in floating point
+  // before forming the (then small) integer cell count.
+  double cells_d = 1.0;
+  for (int a = 0; a < 3; ++a) cells_d *= (double)g->bmax[a] - (double)g->bmin[a] + 1.0;
+  if (cells_d <= (double)map_limit && nu < (int64_t(1) << 23)) {
+    const int64_t cells = (int64_t)cells_d;
+    for (int a = 0; a < 3; ++a) g->mdim[a] = g->bmax[a] - g->bmin[a] + 1;
+    SG_ALLOC(keep, g->d_map, sizeof(int32_t) * cells);
+    k_map_fill<<<grid1d(cells, T), T, 0, s>>>(g->d_map, cells);
+    k_map_blocks<<<grid1d(nu, T), T, 0, s>>>(g->d_coords, g->d_nbr, nu, g->bmin[0], g->bmin[1],
+                                            g->bmin[2], g->mdim[0], g->mdim[1], g->d_map);
+    for (int r = 1; r < kMapMaxDist; ++r)
+      k_map_dilate<<<grid1d(cells, T), T, 0, s>>>(g->d_map, g->mdim[0], g->mdim[1], g->mdim[2], r);
+    SG_HIP_CHECK(hipGetLastError());
+    SG_HIP_CHECK(hipStreamSynchronize(s));
+  }
   g->magic = kGridMagic;
   keep.ptrs.clear();  // ownership moves to the grid
   guard.g = nullptr;
@@ -415,6 +483,28 @@ int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks) {
   if (rc) return rc;
   if (!n_blocks) return fail(SG_EINVAL, "n_blocks is NULL");
   *n_blocks = g->n_blocks;
+  return SG_OK;
+}
+
+int sg_grid_dense_map(const sg_grid* g, int32_t dims[3], int32_t bmin[3]) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!dims || !bmin) return fail(SG_EINVAL, "output pointer is NULL");
+  for (int a = 0; a < 3; ++a) {
+    dims[a] = g->mdim[a];
+    bmin[a] = g->bmin[a];
+  }
+  return SG_OK;
+}
+
+int sg_grid_copy_dense_map(const sg_grid* g, int32_t* d_out, sg_stream stream) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!g->d_map) return fail(SG_ESTATE, "grid has no dense block map");
+  if (!d_out) return fail(SG_EINVAL, "d_out is NULL");
+  SG_HIP_CHECK(hipMemcpyAsync(d_out, g->d_map,
+                              sizeof(int32_t) * (size_t)g->mdim[0] * g->mdim[1] * g->mdim[2],
+                              hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return SG_OK;
 }
 
@@ -464,6 +554,7 @@ int sg_grid_destroy(sg_grid* g) {
   (void)hipFree(g->d_slots);
   (void)hipFree(g->d_nbr);
   (void)hipFree(g->d_coords);
+  if (g->d_map) (void)hipFree(g->d_map);
   delete g;
   return SG_OK;
 }

@@ -112,14 +112,59 @@ __device__ __forceinline__ int need_mask(int lx, int ly, int lz) {
   return need;
 }
 
+// True iff lattice point k lies (as float32) in a block within Chebyshev
+// distance r of block c.
+__device__ __forceinline__ bool in_block_cube(const March& m, const Params& p, int32_t k,
+                                              const int32_t c[3], int32_t r) {
+  const float t = lattice_t(p, k);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = lattice_x(m.ov[a], m.dv[a], t);
+    if (!(fabsf(x) < kPosLimit)) return false;
+    const int32_t b = ((int32_t)floorf(x)) >> 3;
+    if (b < c[a] - r || b > c[a] + r) return false;
+  }
+  return true;
+}
+
+// Lattice point k lies in the empty block c whose Chebyshev ball of radius
+// D-1 holds no allocated block.  Returns the last lattice index j >= k that
+// still lies in that ball.  Each coordinate of the float32 position is
+// monotone in k, so the lattice points in the ball form one run: if k and j
+// both lie in it, every point between them does too and can be skipped.
+__device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, const int32_t c[3],
+                                 int32_t D, int32_t k_hi) {
+  double t_exit = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    const double d = m.dv[a], o = m.ov[a];
+    if (d > 0.0) t_exit = fmin(t_exit, (8.0 * ((double)c[a] + D) - o) / d);
+    else if (d < 0.0) t_exit = fmin(t_exit, (8.0 * ((double)c[a] - D + 1) - o) / d);
+  }
+  const double est = floor((t_exit - (double)p.t_near) / (double)p.step);
+  int32_t hi = est >= (double)k_hi ? k_hi : (est <= (double)k ? k : (int32_t)est);
+  if (in_block_cube(m, p, hi, c, D - 1)) return hi;
+  int32_t lo = k;  // invariant: lo inside, hi outside
+  while (hi - lo > 1) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (in_block_cube(m, p, mid, c, D - 1)) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Phase 1: kept samples of the ray, in lattice order, into q[0..n) (n <= M).
+// The 64 lanes test 64 consecutive lattice points; when the last of them
+// lies in an empty block with empty surroundings (dense map), the run of
+// lattice points inside that empty region is skipped.
 __device__ int march_collect(const GridView& g, const March& m, const Params& p, int2* q) {
   const int lane = lane_id();
   int n = 0;
-  for (int32_t k0 = m.k_lo; k0 <= m.k_hi && n < p.max_samples; k0 += kWave) {
+  int32_t k0 = m.k_lo;
+  while (k0 <= m.k_hi && n < p.max_samples) {
     const int32_t k = k0 + lane;
     bool valid = false;
-    int32_t idx = -1;
+    int32_t idx = -1, dist = 0;
+    int32_t b[3] = {0, 0, 0};
     if (k <= m.k_hi) {
       const float t = lattice_t(p, k);
       float x[3];
@@ -132,11 +177,14 @@ __device__ int march_collect(const GridView& g, const March& m, const Params& p,
       if (ok) {
         const int32_t ix = (int32_t)floorf(x[0]), iy = (int32_t)floorf(x[1]),
                       iz = (int32_t)floorf(x[2]);
-        const int32_t bx = ix >> 3, by = iy >> 3, bz = iz >> 3;
-        if (bx >= g.bmin[0] && bx <= g.bmax[0] && by >= g.bmin[1] && by <= g.bmax[1] &&
-            bz >= g.bmin[2] && bz <= g.bmax[2]) {
+        b[0] = ix >> 3;
+        b[1] = iy >> 3;
+        b[2] = iz >> 3;
+        dist = 1;
+        if (b[0] >= g.bmin[0] && b[0] <= g.bmax[0] && b[1] >= g.bmin[1] && b[1] <= g.bmax[1] &&
+            b[2] >= g.bmin[2] && b[2] <= g.bmax[2]) {
           int32_t nm;
-          probe(g, bx, by, bz, idx, nm);
+          block_state(g, b[0], b[1], b[2], idx, nm, dist);
           const int need = need_mask(ix & 7, iy & 7, iz & 7);
           valid = idx >= 0 && (nm & need) == need;
         }
@@ -146,6 +194,9 @@ __device__ int march_collect(const GridView& g, const March& m, const Params& p,
     const int r = rank_below(bal);
     if (valid && n + r < p.max_samples) q[n + r] = make_int2(k, idx);
     n = min(p.max_samples, n + (int)__popcll(bal));
+    int32_t next = k0 + kWave;
+    if (lane == kWave - 1 && idx < 0 && dist >= 2) next = empty_run_end(m, p, k, b, dist, m.k_hi) + 1;
+    k0 = __builtin_amdgcn_readlane(next, kWave - 1);
   }
   wave_sync();
   return n;

@@ -40,17 +40,19 @@ class Grid:
     """Hash of allocated 8^3 blocks (collision-free, first-occurrence indices)."""
 
     def __init__(self, block_coords: torch.Tensor, voxel_size: float, origin=(0.0, 0.0, 0.0),
-                 return_index: bool = False):
+                 return_index: bool = False, dense_map_max_cells: int = -1):
+        """dense_map_max_cells: 0 = hash only; < 0 = library default."""
         want(block_coords, "block_coords", torch.int32, (None, 3))
         self.device = block_coords.device
         n = block_coords.shape[0]
         org = (ctypes.c_float * 3)(*[float(x) for x in origin])
         handle = ctypes.c_void_p()
         idx = torch.empty(n, dtype=torch.int32, device=self.device) if return_index else None
+        opts = _lib.BuildOptionsC(int(dense_map_max_cells))
         with torch.cuda.device(self.device):
-            check(lib().sg_grid_build(ptr(block_coords), n, ctypes.c_float(voxel_size), org,
-                                      stream_ptr(self.device), ctypes.byref(handle), ptr(idx)),
-                  "sg_grid_build")
+            check(lib().sg_grid_build_ex(ptr(block_coords), n, ctypes.c_float(voxel_size), org,
+                                         stream_ptr(self.device), ctypes.byref(handle), ptr(idx),
+                                         ctypes.byref(opts)), "sg_grid_build_ex")
         self._h = handle
         self.index_of_input = idx
         nb = ctypes.c_int64()
@@ -73,6 +75,18 @@ class Grid:
         check(lib().sg_grid_block_coords(self.handle, ptr(out), stream_ptr(self.device)),
               "sg_grid_block_coords")
         return out
+
+    def dense_map(self):
+        """(map int32 [dz,dy,dx] or None, bmin (x,y,z)) of the dense block map."""
+        dims = (ctypes.c_int32 * 3)()
+        bmin = (ctypes.c_int32 * 3)()
+        check(lib().sg_grid_dense_map(self.handle, dims, bmin), "sg_grid_dense_map")
+        if dims[0] == 0:
+            return None, tuple(bmin)
+        out = torch.empty((dims[2], dims[1], dims[0]), dtype=torch.int32, device=self.device)
+        check(lib().sg_grid_copy_dense_map(self.handle, ptr(out), stream_ptr(self.device)),
+              "sg_grid_copy_dense_map")
+        return out, tuple(bmin)
 
     def neighbors(self):
         out = torch.empty((self.n_blocks, 8), dtype=torch.int32, device=self.device)

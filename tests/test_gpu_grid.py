@@ -57,3 +57,46 @@ def test_sphere_grid_matches_oracle():
     np.testing.assert_array_equal(g.block_coords().cpu().numpy(), w["block_coords"])
     np.testing.assert_array_equal(g.index_of_input.cpu().numpy(), np.arange(494))
     np.testing.assert_array_equal(g.neighbors().cpu().numpy(), oracle.neighbors(w["block_coords"]))
+
+
+@pytest.mark.parametrize("workload", ["sphere", "random"])
+def test_dense_map_matches_brute_force(workload):
+    """Map entry: index*256 + neighbour mask for allocated blocks, else minus
+    the Chebyshev distance to the nearest allocated block, capped at 32."""
+    from scipy import ndimage
+    if workload == "sphere":
+        from synth import workloads
+        coords = workloads.sphere_tiny()["block_coords"]
+    else:
+        rng = np.random.default_rng(17)
+        coords = rng.integers(-30, 40, size=(300, 3)).astype(np.int32)
+    g = _build(coords, return_index=False)
+    m, bmin = g.dense_map()
+    assert m is not None
+    m = m.cpu().numpy()
+    blocks, _ = oracle.build_grid(coords)
+    nbr = oracle.neighbors(blocks)
+    lo = blocks.min(0)
+    assert tuple(bmin) == tuple(lo)
+    dims = blocks.max(0) - lo + 1
+    assert m.shape == (dims[2], dims[1], dims[0])
+    occ = np.zeros((dims[2], dims[1], dims[0]), bool)
+    want = np.zeros(occ.shape, np.int64)
+    for i, b in enumerate(blocks):
+        z, y, x = b[2] - lo[2], b[1] - lo[1], b[0] - lo[0]
+        occ[z, y, x] = True
+        want[z, y, x] = i * 256 + sum(1 << s for s in range(8) if nbr[i, s] >= 0)
+    d = ndimage.distance_transform_cdt(~occ, metric="chessboard")
+    want[~occ] = -np.minimum(d[~occ], 32)
+    np.testing.assert_array_equal(m, want)
+    g.destroy()
+
+
+def test_hash_only_grid_has_no_map():
+    from synth import workloads
+    import paper_2305_13220_amd as sg
+    w = workloads.sphere_tiny()
+    g = sg.Grid(to_dev(w["block_coords"], torch.int32), float(w["h"]), dense_map_max_cells=0)
+    m, _ = g.dense_map()
+    assert m is None
+    g.destroy()

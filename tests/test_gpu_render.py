@@ -54,6 +54,42 @@ def test_forward_room_full_batch(room):
     check_forward(out, _oracle_fwd(w, w["rays"]), what="room 2cm 65536 rays")
 
 
+@pytest.fixture(scope="module")
+def room_hash_only():
+    from synth import workloads
+    import paper_2305_13220_amd as sg
+    w = workloads.room_2cm()
+    g = sg.Grid(to_dev(w["block_coords"], torch.int32), float(w["h"]),
+                tuple(float(x) for x in w["origin"]), dense_map_max_cells=0)
+    assert g.dense_map()[0] is None
+    return w, g, to_dev(w["vox"]), to_dev(w["rays"])
+
+
+def test_dense_map_and_hash_paths_agree(room, room_hash_only):
+    """Empty-space skipping through the dense map changes no result bit."""
+    w, g, vox, rays = room
+    _, gh, _, _ = room_hash_only
+    a = _sg().render_forward(g, vox, rays, w["params"])
+    b = _sg().render_forward(gh, vox, rays, w["params"])
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    ca = _sg().render_footprint(g, rays, w["params"])
+    cb = _sg().render_footprint(gh, rays, w["params"])
+    assert torch.equal(ca, cb)
+
+
+def test_forward_hash_path_matches_oracle(room_hash_only):
+    w, g, vox, _ = room_hash_only
+    sub = w["rays"][:8192]
+    out = _sg().render_forward(g, vox, to_dev(sub), w["params"])
+    check_forward(out, _oracle_fwd(w, sub), what="room hash-only path")
+
+
+def test_backward_hash_path_matches_oracle(room_hash_only):
+    w, g, vox, _ = room_hash_only
+    _check_backward(w, g, vox, w["rays"][:4096], 3, seed=5, what="room backward hash-only path")
+
+
 def test_forward_is_deterministic(room):
     w, g, vox, rays = room
     a = _sg().render_forward(g, vox, rays, w["params"])
