@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--rays", type=int, default=65536)
     ap.add_argument("--cpu-rays", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-mib", type=int, default=0,
+                    help="run one elementwise kernel over a tensor of this size first "
+                         "(reads and writes it once: a reference for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -134,6 +137,11 @@ def main():
            "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
     gout = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
             "normal": torch.empty((R, 3), device=dev)}
+    if args.calib_mib > 0:
+        a = torch.ones(args.calib_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
+        del a, b
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f}s: {grid.n_blocks} blocks, {R} rays")
 

@@ -140,34 +140,37 @@ __device__ inline float shfl(float v, int src) {
 }
 __device__ inline int shfl(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
 
-// Inclusive prefix sum over the 64 lanes (lane order).
+// DPP moves (data-parallel primitives of the GFX9 vector ALU): the source
+// lane is read through the instruction's operand path, with no LDS round
+// trip.  Lanes whose source does not exist (or whose row is masked off)
+// read 0.
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, kRowMask, 0xf, true));
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
+
+// Inclusive prefix sum over the 64 lanes (lane order): a Hillis-Steele scan
+// inside each 16-lane row, then the row totals are carried upwards with row
+// broadcasts.  Fixed order, so the result is deterministic.
 __device__ inline float wave_inclusive_sum(float v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    float o = shfl(v, l - off < 0 ? l : l - off);
-    if (l >= off) v += o;
-  }
+  v += dpp<kRowShr1>(v);
+  v += dpp<kRowShr2>(v);
+  v += dpp<kRowShr4>(v);
+  v += dpp<kRowShr8>(v);
+  v += dpp<kRowBcast15, 0xa>(v);  // row 0 -> row 1, row 2 -> row 3
+  v += dpp<kRowBcast31, 0xc>(v);  // rows 0-1 -> rows 2-3
   return v;
 }
 
-// Inclusive suffix sum over the 64 lanes: lane l gets sum over lanes >= l.
-__device__ inline float wave_inclusive_suffix_sum(float v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    float o = shfl(v, l + off >= kWave ? l : l + off);
-    if (l + off < kWave) v += o;
-  }
-  return v;
-}
+// Value of lane l-1 (0 in lane 0): turns an inclusive scan into an exclusive one.
+__device__ inline float wave_shift_up(float v) { return dpp<kWaveShr1>(v); }
 
-// Sum over all 64 lanes, result in every lane (fixed butterfly order:
-// deterministic).
+// Sum over all 64 lanes, in every lane (deterministic).
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
-  return v;
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_inclusive_sum(v)), kWave - 1));
 }
 
 __device__ inline int wave_sum_int(int v) {

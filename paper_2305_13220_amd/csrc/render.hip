@@ -1,18 +1,24 @@
 // Differentiable volume rendering through the sparse-dense grid
 // (Sec. 3.5.1, Eq. 12-15 with the trilinear value and gradient of Eq. 17-18).
 //
-// One wavefront per ray.  Phase 1 (march): the 64 lanes test 64 consecutive
-// lattice points t_k = t_near + k*step at a time -- float32 position, floor,
-// block, hash probe, neighbour mask -- and the kept (k, block) pairs are
-// compacted in lattice order into the wave's LDS list.  Phase 2 (shade):
-// lanes take 64 kept samples at a time, gather the 8 corners, interpolate,
-// convert SDF to density and composite with a wave prefix sum of
-// sigma*step.  The backward pass stores per-sample (w, dL/dw, T_{k+1}, f) in
-// LDS during a recompute pass, then walks the chunks in reverse with wave
-// suffix sums, merges the contributions of consecutive samples that share a
-// cell, and scatters them with float32 atomic adds.
-#include <cmath>
+// Waves are persistent over a strided set of rays (the next ray's origin and
+// direction are fetched while the current one is processed); each ray is
+// handled by one wavefront.
+//   March: the 64 lanes test 64 consecutive lattice points t_k = t_near +
+//   k*step at a time -- float32 position, floor, block, block state (dense
+//   map or hash), neighbour mask -- and the kept (k, block) pairs are
+//   compacted in lattice order into the wave's LDS list.  Runs of lattice
+//   points inside empty regions of the dense map are skipped exactly.
+//   Shade: lanes take 64 kept samples at a time, gather the 8 corners,
+//   interpolate, convert SDF to density and composite with a DPP prefix sum
+//   of sigma*step.
+//   Backward: a recompute pass stores per-sample (w, dL/dw, T_{k+1}, f) in
+//   LDS; the reverse pass maps samples to lanes in reverse order so that the
+//   suffix sums of the adjoint are prefix sums over lanes, stages the
+//   per-corner terms in LDS, merges runs of samples in one cell and scatters
+//   them with float32 atomic adds laid out as (cell, corner, channel).
 #include <climits>
+#include <cmath>
 
 #include "common.h"
 
@@ -21,6 +27,8 @@ namespace sg {
 struct Params {
   float step, t_near, t_far, beta, inv_beta;
   int32_t max_samples;
+  int32_t k_max;     // last lattice index with t_k <= t_far (-1: none)
+  double inv_step;   // 1 / step
 };
 
 struct March {
@@ -30,11 +38,15 @@ struct March {
 
 // t_k and x_k exactly as float32 with one rounding per operation: these
 // values decide integers (voxel, block) and must not be contracted.
-__device__ __forceinline__ float lattice_t(const Params& p, int32_t k) {
+__host__ __device__ __forceinline__ float lattice_t(float t_near, float step, int32_t k) {
 #pragma clang fp contract(off)
   const float kf = (float)k;
-  const float ks = kf * p.step;
-  return p.t_near + ks;
+  const float ks = kf * step;
+  return t_near + ks;
+}
+
+__device__ __forceinline__ float lattice_t(const Params& p, int32_t k) {
+  return lattice_t(p.t_near, p.step, k);
 }
 
 __device__ __forceinline__ float lattice_x(float ov, float dv, float t) {
@@ -52,28 +64,19 @@ __device__ __forceinline__ float to_voxel(float x, float org, float inv_h) {
 constexpr float kPosLimit = 16777216.0f;  // 2^24 voxels: no block beyond
 constexpr int32_t kKMax = 1 << 24;
 
-// Ray set-up: voxel-space ray, inclusive lattice range, clipped to the
-// grid's bounding box with a margin that covers float32 position error.
-__device__ bool march_setup(const GridView& g, const float* __restrict__ ray, const Params& p,
-                            March& m) {
-  float r[6];
+// Ray set-up: voxel-space ray and the lattice range clipped to the grid's
+// bounding box, with a margin that covers float32 position error (points
+// outside the clipped range cannot lie in an allocated block).
+__device__ bool march_setup(const GridView& g, const float r[6], const Params& p, March& m) {
 #pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    r[a] = ray[a];
+  for (int a = 0; a < 6; ++a)
     if (!isfinite(r[a])) return false;
-  }
+  if (p.k_max < 0) return false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     m.ov[a] = to_voxel(r[a], g.org[a], g.inv_h);
     m.dv[a] = r[3 + a] * g.inv_h;
   }
-  // last lattice point with t_k <= t_far (t_far inclusive)
-  double est = floor(((double)p.t_far - (double)p.t_near) / (double)p.step);
-  int32_t kh = (int32_t)fmin(fmax(est, -1.0), (double)kKMax);
-  while (kh + 1 <= kKMax && lattice_t(p, kh + 1) <= p.t_far) ++kh;
-  while (kh >= 0 && !(lattice_t(p, kh) <= p.t_far)) --kh;
-  if (kh < 0) return false;
-  // bounding-box clip in double
   double maxo = 0.0, maxd = 0.0;
   for (int a = 0; a < 3; ++a) {
     maxo = fmax(maxo, fabs((double)m.ov[a]));
@@ -88,17 +91,18 @@ __device__ bool march_setup(const GridView& g, const float* __restrict__ ray, co
     if (d == 0.0) {
       if (o < lo || o > hi) return false;
     } else {
-      double ta = (lo - o) / d, tb = (hi - o) / d;
+      const double inv = 1.0 / d;
+      const double ta = (lo - o) * inv, tb = (hi - o) * inv;
       t0 = fmax(t0, fmin(ta, tb));
       t1 = fmin(t1, fmax(ta, tb));
     }
   }
   if (t0 > t1) return false;
-  const double kl = ceil((t0 - (double)p.t_near) / (double)p.step) - 2.0;
-  const double ku = floor((t1 - (double)p.t_near) / (double)p.step) + 2.0;
-  if (ku < 0.0 || kl > (double)kh) return false;
+  const double kl = ceil((t0 - (double)p.t_near) * p.inv_step) - 2.0;
+  const double ku = floor((t1 - (double)p.t_near) * p.inv_step) + 2.0;
+  if (ku < 0.0 || kl > (double)p.k_max) return false;
   m.k_lo = kl < 0.0 ? 0 : (int32_t)kl;
-  m.k_hi = ku > (double)kh ? kh : (int32_t)ku;
+  m.k_hi = ku > (double)p.k_max ? p.k_max : (int32_t)ku;
   return m.k_lo <= m.k_hi;
 }
 
@@ -132,16 +136,17 @@ __device__ __forceinline__ bool in_block_cube(const March& m, const Params& p, i
 // still lies in that ball.  Each coordinate of the float32 position is
 // monotone in k, so the lattice points in the ball form one run: if k and j
 // both lie in it, every point between them does too and can be skipped.
+// The exit estimate only seeds the search; membership is decided exactly.
 __device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, const int32_t c[3],
                                  int32_t D, int32_t k_hi) {
-  double t_exit = 1e300;
+  float t_exit = 3.0e38f;
   for (int a = 0; a < 3; ++a) {
-    const double d = m.dv[a], o = m.ov[a];
-    if (d > 0.0) t_exit = fmin(t_exit, (8.0 * ((double)c[a] + D) - o) / d);
-    else if (d < 0.0) t_exit = fmin(t_exit, (8.0 * ((double)c[a] - D + 1) - o) / d);
+    const float d = m.dv[a], o = m.ov[a];
+    if (d > 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] + D) - o) / d);
+    else if (d < 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] - D + 1) - o) / d);
   }
-  const double est = floor((t_exit - (double)p.t_near) / (double)p.step);
-  int32_t hi = est >= (double)k_hi ? k_hi : (est <= (double)k ? k : (int32_t)est);
+  const float est = floorf((t_exit - p.t_near) * (float)p.inv_step);
+  int32_t hi = est >= (float)k_hi ? k_hi : (est <= (float)k ? k : (int32_t)est);
   if (in_block_cube(m, p, hi, c, D - 1)) return hi;
   int32_t lo = k;  // invariant: lo inside, hi outside
   while (hi - lo > 1) {
@@ -152,10 +157,10 @@ __device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, con
   return lo;
 }
 
-// Phase 1: kept samples of the ray, in lattice order, into q[0..n) (n <= M).
-// The 64 lanes test 64 consecutive lattice points; when the last of them
-// lies in an empty block with empty surroundings (dense map), the run of
-// lattice points inside that empty region is skipped.
+// March: kept samples of the ray, in lattice order, into q[0..n) (n <= M).
+// When the last of the 64 tested points lies in an empty block with empty
+// surroundings (dense map), the run of lattice points inside that empty
+// region is skipped.
 __device__ int march_collect(const GridView& g, const March& m, const Params& p, int2* q) {
   const int lane = lane_id();
   int n = 0;
@@ -233,19 +238,6 @@ __device__ __forceinline__ void locate(const GridView& g, const March& m, const 
   }
 }
 
-// Trilinear weights r_a and their u-derivatives (Eq. 17-18).
-__device__ __forceinline__ void corner_weights(const float u[3], float r[8], float dr[8][3]) {
-  const float wx[2] = {1.0f - u[0], u[0]}, wy[2] = {1.0f - u[1], u[1]}, wz[2] = {1.0f - u[2], u[2]};
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-    r[a] = wx[ax] * wy[ay] * wz[az];
-    dr[a][0] = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az];
-    dr[a][1] = (ay ? 1.0f : -1.0f) * wx[ax] * wz[az];
-    dr[a][2] = (az ? 1.0f : -1.0f) * wx[ax] * wy[ay];
-  }
-}
-
 // Load the 1 + C parameters of one voxel.
 template <int C>
 __device__ __forceinline__ void load_voxel(const float* __restrict__ vox, int32_t off, float th[1 + C]) {
@@ -320,12 +312,27 @@ __device__ __forceinline__ float density(float f, const Params& p, float& e) {
   return psi * p.inv_beta;
 }
 
-// Exclusive prefix within the wave from an inclusive one.
-__device__ __forceinline__ float exclusive_from_inclusive(float incl) {
-  const int l = lane_id();
-  const float prev = shfl(incl, l > 0 ? l - 1 : 0);
-  return l > 0 ? prev : 0.0f;
-}
+// Rays of one wave: r, r + stride, ...; the next ray is loaded (scalar
+// loads: the index is wave-uniform) while the current one is processed.
+struct RayStream {
+  int64_t r, stride, R;
+  float cur[6], nxt[6];
+  __device__ RayStream(const float* __restrict__ rays, int64_t first, int64_t stride_, int64_t R_)
+      : r(first), stride(stride_), R(R_) {
+    if (r < R)
+      for (int a = 0; a < 6; ++a) nxt[a] = rays[6 * r + a];
+  }
+  __device__ bool next(const float* __restrict__ rays) {
+    if (r >= R) return false;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) cur[a] = nxt[a];
+    const int64_t rn = r + stride;
+    if (rn < R)
+      for (int a = 0; a < 6; ++a) nxt[a] = rays[6 * rn + a];
+    return true;
+  }
+  __device__ void advance() { r += stride; }
+};
 
 // ---------------------------------------------------------------------------
 // Forward.
@@ -338,12 +345,15 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
                                                     float* __restrict__ wsum,
                                                     int32_t* __restrict__ nsamples) {
   extern __shared__ int2 lds_q[];
-  const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+  const int wpb = blockDim.x / kWave, lane = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int2* q = lds_q + (int64_t)w * p.max_samples;
-  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
+  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  for (; rs.next(rays); rs.advance()) {
+    const int64_t r = rs.r;
     March m;
     int n = 0;
-    if (march_setup(g, rays + 6 * r, p, m)) n = march_collect(g, m, p, q);
+    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, q);
     float accC[C > 0 ? C : 1], accD = 0.0f, accN[3] = {0.0f, 0.0f, 0.0f}, accW = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
@@ -361,7 +371,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
         sd = density(f, p, e) * p.step;
       }
       const float incl = wave_inclusive_sum(sd);
-      const float excl = exclusive_from_inclusive(incl);
+      const float excl = wave_shift_up(incl);
       if (act) {
         const float T = expf(-(tau + excl));
         const float alpha = -expm1f(-sd);
@@ -374,7 +384,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
         accN[2] += wt * grad[2];
         accW += wt;
       }
-      tau += shfl(incl, kWave - 1);
+      tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
     }
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
@@ -422,17 +432,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   extern __shared__ int2 lds_q[];
   constexpr int V = 1 + C;
   constexpr int PER = 8 * V;  // scatter values per cell
-  const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+  const int wpb = blockDim.x / kWave, lane = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int2* q = lds_q + (int64_t)w * p.max_samples;
-  SampleState* st =
-      reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples) + (int64_t)w * p.max_samples;
-  BwdScratch* sc = reinterpret_cast<BwdScratch*>(
-                       reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples) +
-                       (int64_t)wpb * p.max_samples) + w;
-  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
+  SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples);
+  SampleState* st = st_base + (int64_t)w * p.max_samples;
+  BwdScratch* sc = reinterpret_cast<BwdScratch*>(st_base + (int64_t)wpb * p.max_samples) + w;
+  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  for (; rs.next(rays); rs.advance()) {
+    const int64_t r = rs.r;
     March m;
     int n = 0;
-    if (march_setup(g, rays + 6 * r, p, m)) n = march_collect(g, m, p, q);
+    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, q);
     if (n == 0) continue;  // wave-uniform
     float gC[C > 0 ? C : 1];
 #pragma unroll
@@ -456,7 +467,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         sd = density(f, p, e) * p.step;
       }
       const float incl = wave_inclusive_sum(sd);
-      const float excl = exclusive_from_inclusive(incl);
+      const float excl = wave_shift_up(incl);
       if (act) {
         const float T = expf(-(tau + excl));
         const float alpha = -expm1f(-sd);
@@ -470,27 +481,25 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         s.f = f;
         st[j] = s;
       }
-      tau += shfl(incl, kWave - 1);
+      tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
     }
     wave_sync();
-    // pass 2: chunks in reverse; suffix sums give dL/dsigma; per-corner terms
-    // are staged in LDS, merged over runs of samples in one cell, then
-    // scattered with lanes laid out as (cell, corner, channel) so that each
-    // atomic instruction touches few cache lines.
+    // pass 2: chunks in reverse with lanes in reverse sample order (lane l
+    // holds sample c0 + 63 - l), so sum_{j>k} w_j s_j is an exclusive prefix
+    // sum over lanes.  Per-corner terms are staged in LDS, merged over runs
+    // of samples in one cell, then scattered with lanes laid out as (cell,
+    // corner, channel) so that each atomic instruction covers few lines.
     float carry = 0.0f;
     const int last = (n - 1) / kWave * kWave;
     for (int c0 = last; c0 >= 0; c0 -= kWave) {
-      const int j = c0 + lane;
+      const int j = c0 + (kWave - 1 - lane);
       const bool act = j < n;
       SampleState s = {0.0f, 0.0f, 0.0f, 0.0f};
       if (act) s = st[j];
       const float ws = s.w * s.s;
-      const float suf = wave_inclusive_suffix_sum(ws);
-      // every lane takes part in the shuffle: a lane outside the exec mask
-      // would read back as zero
-      const float nxt = shfl(suf, lane < kWave - 1 ? lane + 1 : lane);
-      const float later = lane < kWave - 1 ? nxt : 0.0f;
-      const float total = shfl(suf, 0);
+      const float incl = wave_inclusive_sum(ws);
+      const float later = wave_shift_up(incl);
+      const float total = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
       int key = -1 - lane;
       if (act) {
         const float dsig = p.step * (s.tn * s.s - (carry + later));
@@ -548,12 +557,15 @@ __global__ __launch_bounds__(256) void k_footprint(GridView g, const float* __re
                                                    int64_t R, Params p, int32_t* __restrict__ counts,
                                                    uint8_t* __restrict__ touched) {
   extern __shared__ int2 lds_q[];
-  const int wpb = blockDim.x / kWave, w = threadIdx.x / kWave, lane = lane_id();
+  const int wpb = blockDim.x / kWave, lane = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int2* q = lds_q + (int64_t)w * p.max_samples;
-  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < R; r += (int64_t)gridDim.x * wpb) {
+  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  for (; rs.next(rays); rs.advance()) {
+    const int64_t r = rs.r;
     March m;
     int n = 0;
-    if (march_setup(g, rays + 6 * r, p, m)) n = march_collect(g, m, p, q);
+    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, q);
     int pi[3] = {0, 0, 0};  // base voxel of the previous chunk's last sample
     int vox_total = 0, blk_total = 0;
     for (int c0 = 0; c0 < n; c0 += kWave) {
@@ -579,7 +591,9 @@ __global__ __launch_bounds__(256) void k_footprint(GridView g, const float* __re
       }
       int nv = 0, nb = 0;
       if (act) {
-        // voxels: the 2x2x2 corner cube minus its overlap with the previous one
+        // voxels: the 2x2x2 corner cube minus its overlap with the previous
+        // one (per-axis monotone positions: a voxel shared with any earlier
+        // sample is shared with the previous one)
         int ov = 1, bsz = 1, bov = 1;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -620,6 +634,16 @@ static bool supported_C(int C) {
   }
 }
 
+// Last lattice index k >= -1 with t_near + k*step <= t_far, evaluated with
+// the same float32 operations as the kernels.
+static int32_t last_lattice_index(float t_near, float step, float t_far) {
+  double est = std::floor(((double)t_far - (double)t_near) / (double)step);
+  int32_t k = (int32_t)std::fmin(std::fmax(est, -1.0), (double)kKMax);
+  while (k + 1 <= kKMax && lattice_t(t_near, step, k + 1) <= t_far) ++k;
+  while (k >= 0 && !(lattice_t(t_near, step, k) <= t_far)) --k;
+  return k;
+}
+
 static int check_params(const sg_render_params* prm, Params& p) {
   if (!prm) return fail(SG_EINVAL, "params is NULL");
   if (!(prm->step > 0.0f) || !std::isfinite(prm->step)) return fail(SG_EINVAL, "step must be finite and > 0");
@@ -636,6 +660,8 @@ static int check_params(const sg_render_params* prm, Params& p) {
   p.beta = prm->beta;
   p.inv_beta = 1.0f / prm->beta;
   p.max_samples = prm->max_samples;
+  p.k_max = last_lattice_index(prm->t_near, prm->step, prm->t_far);
+  p.inv_step = 1.0 / (double)prm->step;
   return SG_OK;
 }
 
@@ -645,15 +671,18 @@ struct Launch {
   size_t lds;
 };
 
-// Waves per workgroup: 4, fewer if the per-wave LDS list is large.
+// Waves per workgroup: 4, fewer if the per-wave LDS is large.  Waves loop
+// over rays; the grid gives each wave about kRaysPerWave rays.
+constexpr int kRaysPerWave = 4;
+
 static Launch plan(int64_t R, size_t lds_per_wave) {
   int wpb = 4;
   while (wpb > 1 && lds_per_wave * wpb > 64 * 1024) wpb >>= 1;
   Launch l;
   l.threads = (unsigned)(wpb * kWave);
-  int64_t blocks = (R + wpb - 1) / wpb;
+  int64_t blocks = (R + (int64_t)wpb * kRaysPerWave - 1) / ((int64_t)wpb * kRaysPerWave);
   const int64_t cap = 1 << 22;
-  l.blocks = (unsigned)(blocks < cap ? blocks : cap);
+  l.blocks = (unsigned)(blocks < 1 ? 1 : (blocks < cap ? blocks : cap));
   l.lds = lds_per_wave * wpb;
   return l;
 }
