@@ -3,9 +3,11 @@
 Workload (one GPU): the 6 x 6 x 3 m synthetic room at 2 cm voxels
 (11,542 allocated 8^3 blocks, SDF + RGB), batches of 65,536 random pixels
 from 30 seeded 640x480 poses, step 1 cm, t in [0, 12] m, beta = 2 cm, at
-most 128 samples per ray.  One step = camera rays for the batch, forward
-render (colour, depth, normal), squared-L2 loss gradient against renders
-of the same room with a second texture, gradient zeroing, backward render.
+most 128 samples per ray.  One step = camera rays for the batch, gradient
+zeroing, and the fused training kernel: forward render (colour, depth,
+normal), squared-L2 losses against renders of the same room with a second
+texture, and the backward scatter into the voxels.  The same step built
+from the separate forward / loss-gradient / backward calls is timed too.
 Inputs are resident on the GPU before timing starts.
 
 Prints one JSON line.  `roofline` is for the dominant kernel, timed with
@@ -13,6 +15,15 @@ HIP events on its own stream over the timed steps; its algorithmic bytes
 come from exact per-ray footprint counts (samples, distinct voxels,
 distinct blocks).  `cpu_baseline` times the CPU oracle on a bounded
 sample of the same batch on the host.
+
+`serving` measures render serving over three resident grids (the room at
+2 cm, the same room at 1 cm, a second room at 2 cm; C = 3): seeded Poisson
+arrivals of full-frame requests (320x240, 640x480, 1296x968 or 1920x1080,
+uniform), at 0.5x, 0.8x and 1.2x of the plain path's measured capacity,
+served (i) by the plain path, one rays + forward call per request in
+arrival order, and (ii) by packed multi-grid launches replayed from a HIP
+graph with an 8 GiB budget for in-flight outputs.  Latency = GPU completion
+time - arrival time; p50 / p99 over the requests of each point.
 """
 from __future__ import annotations
 
@@ -35,7 +46,15 @@ def log(*a):
 
 
 def algorithmic_bytes(counts, C):
-    """Per-launch algorithmic bytes of forward and backward from (S, U, K)."""
+    """Per-launch algorithmic bytes from exact per-ray (S, U, K) counts.
+
+    Per ray: 24 B of ray, 16 B per distinct block (hash entry), V = 4(1+C)
+    bytes per distinct voxel read, the same per distinct voxel whose gradient
+    is accumulated, O = 4(C+5) bytes of outputs, O-4 bytes of upstream
+    gradients or reference values.  Forward: 24 + 16K + VU + O.  Separate
+    backward (recomputes the forward): 24 + 16K + 2VU + O + (O-4).  Fused
+    training step: 24 + 16K + 2VU + O (outputs written) + (O-4) (references).
+    """
     import numpy as np
     c = counts.astype(np.int64)
     K = c[:, 2].sum()
@@ -45,7 +64,8 @@ def algorithmic_bytes(counts, C):
     O = 4 * (C + 1 + 3 + 1)
     fwd = R * 24 + 16 * K + V * U + R * O
     bwd = R * 24 + 16 * K + 2 * V * U + R * O + R * (O - 4)
-    return int(fwd), int(bwd)
+    fused = R * 24 + 16 * K + 2 * V * U + R * O + R * (O - 4)
+    return int(fwd), int(bwd), int(fused)
 
 
 def source_hash():
@@ -91,6 +111,74 @@ def cpu_baseline(w, n_rays):
                       f"backward, single thread ({dt:.1f} s)"}
 
 
+RESOLUTIONS = ((320, 240), (640, 480), (1296, 968), (1920, 1080))
+
+
+def serve_bench(args, dev):
+    import numpy as np
+    import torch
+
+    import paper_2305_13220_amd as sg
+    from paper_2305_13220_amd.serve import (PackedServer, PlainServer, latency_stats,
+                                            poisson_requests)
+    from synth import scenes, workloads
+    t0 = time.perf_counter()
+    grids, poses, blocks = [], [], []
+    for sc, prm, cams in workloads.serving_grids():
+        g = sg.Grid(torch.from_numpy(sc["block_coords"]).to(dev), float(sc["h"]),
+                    tuple(float(x) for x in sc["origin"]))
+        grids.append((g, torch.from_numpy(sc["vox"]).to(dev), prm))
+        poses.append(list(cams))
+        blocks.append(g.n_blocks)
+    log(f"serving setup {time.perf_counter() - t0:.1f}s: blocks {blocks}")
+
+    def reqs(n, qps, k):
+        return poisson_requests(n, qps, len(grids), poses, RESOLUTIONS,
+                                seed=[0, scenes.SEED_ARRIVALS, k])
+
+    plain = PlainServer(grids, 3, keep_outputs=False)
+    packed = PackedServer(grids, 3, hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)),
+                          keep_outputs=False)
+    plain.run(reqs(16, 1e9, 1), realtime=False)  # warm-up: code, allocator, graphs
+    packed.run(reqs(16, 1e9, 1), realtime=False)
+
+    def capacity(server, n):
+        r = reqs(n, 1e9, 2)
+        server.run(r, realtime=False)
+        st = latency_stats(r)
+        span = max(q.done for q in r) - min(q.arrival for q in r)
+        return n / span, st["rays_per_s"]
+
+    n_cal = max(16, args.serve_requests // 5)
+    cap_plain, rays_plain = capacity(plain, n_cal)
+    cap_packed, rays_packed = capacity(packed, n_cal)
+    log(f"capacity: plain {cap_plain:.1f} req/s, packed {cap_packed:.1f} req/s")
+    points = []
+    for k, load in enumerate((0.5, 0.8, 1.2)):
+        qps = load * cap_plain
+        a = reqs(args.serve_requests, qps, 10 + k)
+        plain.run(a, realtime=True)
+        b = reqs(args.serve_requests, qps, 10 + k)
+        packed.run(b, realtime=True)
+        pt = {"load": load, "qps": round(qps, 2),
+              "plain": {kk: round(v, 3) if isinstance(v, float) else v
+                        for kk, v in latency_stats(a).items()},
+              "packed": {kk: round(v, 3) if isinstance(v, float) else v
+                         for kk, v in latency_stats(b).items()}}
+        log(f"load {load}: plain p50/p99 {pt['plain']['p50_ms']}/{pt['plain']['p99_ms']} ms, "
+            f"packed {pt['packed']['p50_ms']}/{pt['packed']['p99_ms']} ms")
+        points.append(pt)
+    head = points[1]
+    return {"grids": "room 2 cm, room 1 cm, second room 2 cm (C=3)", "blocks": blocks,
+            "resolutions": [f"{w}x{h}" for w, h in RESOLUTIONS],
+            "requests_per_point": args.serve_requests,
+            "capacity_req_per_s": {"plain": round(cap_plain, 2), "packed": round(cap_packed, 2)},
+            "capacity_rays_per_s": {"plain": rays_plain, "packed": rays_packed},
+            "p50_ms_at_0.8": {"plain": head["plain"]["p50_ms"], "packed": head["packed"]["p50_ms"]},
+            "p99_ms_at_0.8": {"plain": head["plain"]["p99_ms"], "packed": head["packed"]["p99_ms"]},
+            "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +187,10 @@ def main():
     ap.add_argument("--rays", type=int, default=65536)
     ap.add_argument("--cpu-rays", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests per arrival-rate point of the serving measurement")
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="run one elementwise kernel over a tensor of this size first "
                          "(reads and writes it once: a reference for memory counters)")
@@ -145,12 +237,28 @@ def main():
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f}s: {grid.n_blocks} blocks, {R} rays")
 
-    ev = []
+    def events(k):
+        return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
 
-    def step(timed):
+    fused_ev, sep_ev = [], []
+
+    def step_fused(timed):
+        """camera rays -> zero gradients -> fused forward + L2 loss + backward"""
         rr = sg.rays_pinhole(cams, pix)
+        grad.zero_()
+        e = events(2) if timed else None
         if timed:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record()
+        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
+        if timed:
+            e[1].record()
+            fused_ev.append(e)
+
+    def step_separate(timed):
+        """camera rays -> forward -> loss gradient -> zero gradients -> backward"""
+        rr = sg.rays_pinhole(cams, pix)
+        e = events(4) if timed else None
+        if timed:
             e[0].record()
         sg.render_forward(grid, vox, rr, params, out=out)
         if timed:
@@ -163,46 +271,96 @@ def main():
                            None, grad_vox=grad)
         if timed:
             e[3].record()
-            ev.append(e)
+            sep_ev.append(e)
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
-        step(True)
-    end.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
+    def run(step):
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        start, end = events(2)
+        start.record()
+        for _ in range(args.steps):
+            step(True)
+        end.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / args.steps
 
-    counts = sg.render_footprint(grid, rays, params).cpu().numpy()
-    fb, bb = algorithmic_bytes(counts, C)
+    ms = run(step_fused)
+    ms_sep = run(step_separate)
+    fused_each = np.array([e[0].elapsed_time(e[1]) for e in fused_ev])
+    fused_ms = float(fused_each.mean())
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in sep_ev]))
+    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in sep_ev]))
+
+    # cold caches: 1 GiB written between steps evicts L2 and the Infinity Cache
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(max(5, min(args.steps, 20))):
+        rr = sg.rays_pinhole(cams, pix)
+        grad.zero_()
+        flush.fill_(1.0)
+        e = events(2)
+        e[0].record()
+        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
+        e[1].record()
+        cold.append(e)
+    torch.cuda.synchronize()
+    cold_ms = float(np.median([e[0].elapsed_time(e[1]) for e in cold]))
+    # empirical HBM ceiling: device copy of 1 GiB (reads 1 GiB, writes 1 GiB)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    flush.copy_(src)
+    e = events(2)
+    e[0].record()
+    for _ in range(5):
+        flush.copy_(src)
+    e[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e[0].elapsed_time(e[1]) * 1e-3) / 1e9
+    del flush, src
+
+    counts, touched = sg.render_footprint(grid, rays, params, touched=True)
+    counts = counts.cpu().numpy()
+    fb, bb, fused_b = algorithmic_bytes(counts, C)
+    # compulsory traffic of the whole batch: every touched voxel read and its
+    # gradient written once, every block entry once, the per-ray inputs/outputs
+    u_all = int(touched.sum().item())
+    k_all = int(touched.view(-1, 512).any(dim=1).sum().item())
+    comp_b = 2 * 4 * (1 + C) * u_all + 16 * k_all + R * (24 + 4 * (C + 5) + 4 * (C + 4))
     S = int(counts[:, 0].sum())
-    dominant = "backward" if bwd_ms >= fwd_ms else "forward"
-    k_ms, k_bytes = (bwd_ms, bb) if dominant == "backward" else (fwd_ms, fb)
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    kname = "k_render_bwd<3>" if dominant == "backward" else "k_render_fwd<3>"
+    kname = "k_render_bwd<3, true>"
+    achieved = fused_b / (fused_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(kname, "room_2cm_65536"), "kernel": kname,
-            "algorithmic_bytes_per_launch": k_bytes, "launch_ms": round(k_ms, 4)}
+            "algorithmic_bytes_per_launch": fused_b, "launch_ms": round(fused_ms, 4),
+            "launch_ms_p50": round(float(np.median(fused_each)), 4),
+            "launch_ms_p90": round(float(np.percentile(fused_each, 90)), 4),
+            "launch_ms_cold": round(cold_ms, 4),
+            "compulsory_bytes_per_launch": comp_b,
+            "compulsory_frac": round(comp_b / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "copy_ceiling_GBps": round(copy_gbs, 1)}
     res = {
         "metric": METRIC, "value": R / (ms * 1e-3), "unit": "rays/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "room_2cm_65536", "scene": "6x6x3 m room, 20 primitives, h=2 cm",
                    "blocks": grid.n_blocks, "rays_per_step": R, "step_m": 0.01, "t_far_m": 12.0,
-                   "beta_m": 0.02, "max_samples": 128, "C": C},
+                   "beta_m": 0.02, "max_samples": 128, "C": C, "loss": "L2 colour + 0.1 depth "
+                   "+ 0.05 normal"},
         "samples_per_s": S / (ms * 1e-3),
         "mean_samples_per_ray": S / R,
-        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
-        "fwd_bwd_hbm_roofline_pct": round(100 * (fb + bb) / ((fwd_ms + bwd_ms) * 1e-3) / 1e9
-                                          / HBM_PEAK_GBS, 2),
+        "fused_kernel_ms": round(fused_ms, 4),
         "roofline": roof,
+        "separate_calls": {"ms_per_step": round(ms_sep, 4), "rays_per_s": R / (ms_sep * 1e-3),
+                           "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
+                           "forward_hbm_frac": round(fb / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "backward_hbm_frac": round(bb / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic_forward": measured_traffic("k_render_fwd<3>", "room_2cm_65536"),
+                           "traffic_backward": measured_traffic("k_render_bwd<3, false>",
+                                                                "room_2cm_65536")},
     }
+    if not args.no_serve:
+        res["serving"] = serve_bench(args, dev)
     if not args.no_cpu:
         import oracle
         oracle.build(force=False)

@@ -233,6 +233,82 @@ int sg_render_backward(const sg_grid* g, const float* d_vox, int32_t C,
                        sg_stream stream);
 
 /*
+ * sg_render_l2_step -- one training step of the rendering losses, fused:
+ * forward render, squared-L2 losses of Eq. 12-14 against reference values,
+ * and their gradient with respect to the voxels (Sec. 3.5.1, 3.5.4), with
+ *   L = (1/R) sum_r ( |C_r - C*_r|^2 + lambda_d (D_r - D*_r)^2
+ *                     + lambda_n |N_r - N*_r|^2 ).
+ * Writes the forward outputs exactly as sg_render_forward does (bit for
+ * bit), d_loss_ray[r] (nullable, [R]) = ray r's term of L (so L is their
+ * sum), and ACCUMULATES dL/dvox into d_grad_vox [n_blocks,512,1+C] exactly as
+ * sg_l2_loss_grad followed by sg_render_backward would (up to the order of
+ * the float32 atomic adds).  Each ray is marched and its corners gathered
+ * once.  d_ref_feat [R,C] (nullable iff C == 0), d_ref_depth [R],
+ * d_ref_normal [R,3].
+ */
+int sg_render_l2_step(const sg_grid* g, const float* d_vox, int32_t C, const float* d_rays,
+                      int64_t n_rays, const sg_render_params* params, const float* d_ref_feat,
+                      const float* d_ref_depth, const float* d_ref_normal, float lambda_d,
+                      float lambda_n, float* d_feat_out, float* d_depth, float* d_normal,
+                      float* d_wsum, int32_t* d_nsamples, float* d_loss_ray, float* d_grad_vox,
+                      sg_stream stream);
+
+/*
+ * Packed multi-grid rendering for a render server.  A launch renders the
+ * pixel ranges ("slots") of several requests over several resident grids;
+ * every pixel's result is bit-identical to sg_rays_pinhole +
+ * sg_render_forward on that pixel alone, whatever else is packed with it.
+ *
+ * sg_packed_grid: opaque device-copyable descriptor of one grid + its
+ * voxels + march parameters, filled on the host by sg_packed_grid_desc; the
+ * caller copies an array of them to device memory (the grid and d_vox must
+ * outlive every launch that uses the descriptor).
+ */
+typedef struct sg_packed_grid {
+  unsigned char opaque[512];
+} sg_packed_grid;
+
+int sg_packed_grid_desc(const sg_grid* g, const float* d_vox, int32_t C,
+                        const sg_render_params* params, sg_packed_grid* out);
+
+/*
+ * One slot: pixels [pixel_begin, pixel_begin + count) (row-major linear
+ * index, u = pixel % width, v = pixel / width) of a request rendered on grid
+ * `grid` with pinhole camera `cam` (layout as in sg_rays_pinhole).  Outputs
+ * are written at the pixel's index: feat [.,C], depth [.], normal [.,3],
+ * wsum [.], nsamples [.] (nullable); the caller sizes them for every pixel
+ * its slots name.  ray_base = sum of count over the slots before this one.
+ */
+typedef struct sg_render_slot {
+  int32_t grid;
+  int32_t width;
+  int64_t pixel_begin;
+  int64_t count;
+  int64_t ray_base;
+  float cam[16];
+  float* feat;
+  float* depth;
+  float* normal;
+  float* wsum;
+  int32_t* nsamples;
+} sg_render_slot;
+
+/*
+ * Render the first min(*d_n_slots, max_slots) slots of d_slots (device
+ * memory; *d_n_slots is read on the device, so a captured launch can be
+ * replayed after the tables change).  All grids used must have feature
+ * count C and max_samples <= max_samples_cap; slots naming another grid are
+ * skipped.  d_grids is an array of n_grids descriptors (512 bytes each,
+ * 8-byte aligned; SG_EINVAL otherwise).  launch_rays sizes the launch
+ * (waves loop over however many rays the slots hold).  Asynchronous,
+ * allocates nothing, graph-capturable.
+ */
+int sg_render_forward_packed(const sg_packed_grid* d_grids, int32_t n_grids,
+                             const sg_render_slot* d_slots, const int32_t* d_n_slots,
+                             int32_t max_slots, int32_t C, int32_t max_samples_cap,
+                             int64_t launch_rays, sg_stream stream);
+
+/*
  * sg_render_footprint -- memory-traffic accounting of the render (integer,
  * exact).  For each ray writes d_counts int32 [R,3] = (S, U, K): kept
  * samples, distinct voxels read by their interpolation cells, distinct

@@ -18,18 +18,10 @@ __global__ void k_rays_pinhole(const float* __restrict__ cams, int32_t n_cams,
     for (int a = 0; a < 6; ++a) out[a] = __int_as_float(0x7fc00000);
     return;
   }
-  const float* K = cams + 16 * (int64_t)c;
-  const float x = ((float)pix[3 * r + 1] + 0.5f - K[2]) / K[0];
-  const float y = ((float)pix[3 * r + 2] + 0.5f - K[3]) / K[1];
-  float d[3];
+  float ray[6];
+  pinhole_ray(cams + 16 * (int64_t)c, pix[3 * r + 1], pix[3 * r + 2], ray);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) d[a] = K[4 + 4 * a] * x + K[5 + 4 * a] * y + K[6 + 4 * a];
-  const float inv = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    out[a] = K[7 + 4 * a];
-    out[3 + a] = d[a] * inv;
-  }
+  for (int a = 0; a < 6; ++a) out[a] = ray[a];
 }
 
 __global__ void k_l2_grad(const float* __restrict__ feat, const float* __restrict__ feat_ref,

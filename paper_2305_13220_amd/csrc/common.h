@@ -120,6 +120,31 @@ __device__ inline void block_state(const GridView& g, int32_t x, int32_t y, int3
   probe(g, x, y, z, idx, nmask);
 }
 
+// Camera ray through the centre of pixel (u, v) of a pinhole camera
+// K = [fx, fy, cx, cy, R|t (3x4 row-major, camera-to-world)], camera axes x
+// right, y down, z forward: origin t, direction normalise(R ((u + 0.5 - cx) /
+// fx, (v + 0.5 - cy) / fy, 1)).  No operation is fused, so every kernel that
+// calls this produces the same bits.
+__device__ inline void pinhole_ray(const float* __restrict__ K, int32_t u, int32_t v, float out[6]) {
+#pragma clang fp contract(off)
+  const float x = ((float)u + 0.5f - K[2]) / K[0];
+  const float y = ((float)v + 0.5f - K[3]) / K[1];
+  float d[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float p0 = K[4 + 4 * a] * x;
+    const float p1 = K[5 + 4 * a] * y;
+    d[a] = (p0 + p1) + K[6 + 4 * a];
+  }
+  const float s0 = d[0] * d[0], s1 = d[1] * d[1], s2 = d[2] * d[2];
+  const float inv = 1.0f / sqrtf((s0 + s1) + s2);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    out[a] = K[7 + 4 * a];
+    out[3 + a] = d[a] * inv;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Wave helpers.
 __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(-1, __builtin_amdgcn_mbcnt_lo(-1, 0)); }
@@ -156,6 +181,9 @@ constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
 // inside each 16-lane row, then the row totals are carried upwards with row
 // broadcasts.  Fixed order, so the result is deterministic.
 __device__ inline float wave_inclusive_sum(float v) {
+  // the adds are kept apart from whatever produced v (no contraction), so a
+  // value reduces to the same bits whichever kernel computed it
+#pragma clang fp contract(off)
   v += dpp<kRowShr1>(v);
   v += dpp<kRowShr2>(v);
   v += dpp<kRowShr4>(v);

@@ -19,6 +19,7 @@
 //   them with float32 atomic adds laid out as (cell, corner, channel).
 #include <climits>
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 
@@ -336,6 +337,70 @@ struct RayStream {
 
 // ---------------------------------------------------------------------------
 // Forward.
+
+// One ray: march, shade, composite; lane 0 writes output row o.
+template <int C>
+__device__ __forceinline__ void render_ray(const GridView& g, const float* __restrict__ vox,
+                                           const Params& p, const float ray[6], int2* q, int64_t o,
+                                           float* __restrict__ feat_out, float* __restrict__ depth,
+                                           float* __restrict__ normal, float* __restrict__ wsum,
+                                           int32_t* __restrict__ nsamples) {
+  const int lane = lane_id();
+  March m;
+  int n = 0;
+  if (march_setup(g, ray, p, m)) n = march_collect(g, m, p, q);
+  float accC[C > 0 ? C : 1], accD = 0.0f, accN[3] = {0.0f, 0.0f, 0.0f}, accW = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
+  float tau = 0.0f;
+  for (int c0 = 0; c0 < n; c0 += kWave) {
+    const int j = c0 + lane;
+    const bool act = j < n;
+    float sd = 0.0f, f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
+    Cell cell;
+    cell.t = 0.0f;
+    if (act) {
+      locate(g, m, p, q[j], cell);
+      interpolate<C>(vox, cell, g.inv_h, f, grad, col);
+      float e;
+      sd = density(f, p, e) * p.step;
+    }
+    const float incl = wave_inclusive_sum(sd);
+    const float excl = wave_shift_up(incl);
+    if (act) {
+      const float T = expf(-(tau + excl));
+      const float alpha = -expm1f(-sd);
+      const float wt = T * alpha;
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) accC[ch] += wt * col[ch];
+      accD += wt * cell.t;
+      accN[0] += wt * grad[0];
+      accN[1] += wt * grad[1];
+      accN[2] += wt * grad[2];
+      accW += wt;
+    }
+    tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
+  }
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
+  accD = wave_sum(accD);
+  accN[0] = wave_sum(accN[0]);
+  accN[1] = wave_sum(accN[1]);
+  accN[2] = wave_sum(accN[2]);
+  accW = wave_sum(accW);
+  if (lane == 0) {
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) feat_out[(int64_t)C * o + ch] = accC[ch];
+    depth[o] = accD;
+    normal[3 * o] = accN[0];
+    normal[3 * o + 1] = accN[1];
+    normal[3 * o + 2] = accN[2];
+    wsum[o] = accW;
+    if (nsamples) nsamples[o] = n;
+  }
+  wave_sync();  // q is reused by the next ray of this wave
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __restrict__ vox,
                                                     const float* __restrict__ rays, int64_t R,
@@ -345,15 +410,348 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
                                                     float* __restrict__ wsum,
                                                     int32_t* __restrict__ nsamples) {
   extern __shared__ int2 lds_q[];
-  const int wpb = blockDim.x / kWave, lane = lane_id();
+  const int wpb = blockDim.x / kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int2* q = lds_q + (int64_t)w * p.max_samples;
   RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  for (; rs.next(rays); rs.advance())
+    render_ray<C>(g, vox, p, rs.cur, q, rs.r, feat_out, depth, normal, wsum, nsamples);
+}
+
+// ---------------------------------------------------------------------------
+// Packed multi-grid render for serving: one launch renders the pixel ranges
+// ("slots") of several requests over several resident grids.  Rays are made
+// in the kernel from each slot's camera (the same pinhole function as
+// sg_rays_pinhole) and rendered by the same per-ray code as
+// sg_render_forward, so each pixel's result does not depend on what else is
+// packed with it.  The slot count is read from device memory: the launch can
+// be captured once in a graph and replayed with new tables.
+struct PackedGrid {
+  GridView view;
+  const float* vox;
+  Params params;
+  int32_t C;
+};
+static_assert(sizeof(PackedGrid) <= sizeof(sg_packed_grid), "descriptor does not fit");
+
+template <int C>
+__global__ __launch_bounds__(256) void k_render_packed(const sg_packed_grid* __restrict__ grids,
+                                                       int32_t n_grids,
+                                                       const sg_render_slot* __restrict__ slots,
+                                                       const int32_t* __restrict__ d_n_slots,
+                                                       int32_t max_slots, int32_t q_cap) {
+  extern __shared__ int2 lds_q[];
+  const int wpb = blockDim.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int2* q = lds_q + (int64_t)w * q_cap;
+  const int32_t ns = min(*d_n_slots, max_slots);
+  if (ns <= 0) return;
+  const int64_t total = slots[ns - 1].ray_base + slots[ns - 1].count;
+  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < total; r += (int64_t)gridDim.x * wpb) {
+    int32_t lo = 0, hi = ns - 1;  // last slot with ray_base <= r
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (slots[mid].ray_base <= r) lo = mid;
+      else hi = mid - 1;
+    }
+    const sg_render_slot& S = slots[lo];
+    const int32_t gi = S.grid;
+    // slots whose ranges leave a gap: rays in the gap belong to no slot
+    if (gi < 0 || gi >= n_grids || S.width <= 0 || r - S.ray_base >= S.count) continue;
+    // descriptors are sg_packed_grid-sized (512 B) records, not PackedGrid-sized
+    const PackedGrid& G = *reinterpret_cast<const PackedGrid*>(grids + gi);
+    if (G.C != C || G.params.max_samples > q_cap) continue;
+    const int64_t pix = S.pixel_begin + (r - S.ray_base);
+    float ray[6];
+    pinhole_ray(S.cam, (int32_t)(pix % S.width), (int32_t)(pix / S.width), ray);
+    render_ray<C>(G.view, G.vox, G.params, ray, q, pix, S.feat, S.depth, S.normal, S.wsum,
+                  S.nsamples);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward.
+struct SampleState {
+  float w, s, tn, f;  // weight, dL/dw, T_{k+1}, SDF
+};
+
+// Per-wave LDS staging of one chunk's scatter.  During staging and merging
+// the arrays are column-major (entry [j][lane]: 64 lanes write 64
+// consecutive words); the merged sums are then compacted, row-major by head
+// rank, into the same memory for the scatter.
+struct BwdScratch {
+  float val[16 * kWave];   // SDF-gradient term of corners 0..7, then w * r_a
+  int32_t off[8 * kWave];  // element offsets of the 8 corners
+  int32_t key[kWave];      // cell id (offset of corner 0), unique negative if unused
+  float gC[32];            // upstream feature gradient of the ray
+};
+
+// Adjoint scatter of one chunk.  Lane holds a sample (act) with its cell,
+// weight w and dL/df; the per-corner terms
+//   dL/dtheta_d[a] += r_a dL/df + w (dr_a/du . g_N) / h      (Eq. 17-18)
+//   dL/dtheta_c[a] += w r_a g_C
+// are staged in LDS, runs of lanes in one cell are merged (positions are
+// monotone per axis, so a cell's samples are adjacent in either lane
+// order), and the sums are added to grad_vox with lanes laid out as (cell,
+// corner, channel) so that each atomic instruction covers few lines.
+template <int C>
+__device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Cell& cell, float w,
+                                              float df, const float gN[3], float inv_h,
+                                              float* __restrict__ grad_vox) {
+  constexpr int V = 1 + C;
+  constexpr int PER = 8 * V;  // scatter values per cell
+  const int lane = lane_id();
+  int key = -1 - lane;
+  if (act) {
+    const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
+                wz[2] = {1.0f - cell.u[2], cell.u[2]};
+    const float wih = w * inv_h;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      const float ra = wx[ax] * wy[ay] * wz[az];
+      const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gN[0] +
+                       (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gN[1] +
+                       (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gN[2];
+      sc->val[a * kWave + lane] = ra * df + wih * gn;
+      sc->val[(8 + a) * kWave + lane] = w * ra;
+      sc->off[a * kWave + lane] = cell.off[a];
+    }
+    key = cell.off[0];
+  }
+  sc->key[lane] = key;
+  const int kp = shfl(key, lane > 0 ? lane - 1 : 0);
+  const bool head = act && (lane == 0 || kp != key);
+  const uint64_t hm = __ballot(head);
+  const int H = (int)__popcll(hm);
+  wave_sync();
+  // merge each run into its first lane
+  float mv[16];
+  int32_t mo[8];
+  if (head) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) mv[j] = sc->val[j * kWave + lane];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) mo[a] = sc->off[a * kWave + lane];
+    for (int l2 = lane + 1; l2 < kWave && sc->key[l2] == key; ++l2) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) mv[j] += sc->val[j * kWave + l2];
+    }
+  }
+  wave_sync();
+  // compact: row-major by head rank (all staged reads are done)
+  if (head) {
+    const int rk = rank_below(hm);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sc->val[rk * 16 + j] = mv[j];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) sc->off[rk * 8 + a] = mo[a];
+  }
+  wave_sync();
+#pragma unroll 2
+  for (int idx = lane; idx < H * PER; idx += kWave) {
+    const int hh = idx / PER, rem = idx - hh * PER;
+    const int a = rem / V, ch = rem - a * V;
+    const float v = sc->val[hh * 16 + (ch == 0 ? a : 8 + a)];
+    const float mult = ch == 0 ? 1.0f : sc->gC[ch > 0 ? ch - 1 : 0];
+    const int32_t o = sc->off[hh * 8 + a];
+    unsafeAtomicAdd(grad_vox + (int64_t)o * V + ch, v * mult);
+  }
+  wave_sync();  // the staging arrays are rewritten by the next chunk
+}
+
+// Sum over lanes m > l of v_m (lane order), without cancellation: the wave
+// is reversed, prefix-summed and reversed back.
+__device__ __forceinline__ float wave_exclusive_suffix_sum(float v) {
+  const int lane = lane_id();
+  const float rev = shfl(v, kWave - 1 - lane);
+  const float ex = wave_shift_up(wave_inclusive_sum(rev));
+  return shfl(ex, kWave - 1 - lane);
+}
+
+// Reference values of the squared-L2 rendering losses (Eq. 12-14) for the
+// fused training step; L = (1/R) sum_r |C - C*|^2 + lambda_d (D - D*)^2 +
+// lambda_n |N - N*|^2.
+struct L2Ref {
+  const float* feat;    // [R,C]
+  const float* depth;   // [R]
+  const float* normal;  // [R,3]
+  float lambda_d, lambda_n;
+  float* loss_ray;      // [R] nullable: each ray's term of L
+};
+
+// Upstream gradients g = dL/d(feat, depth, normal, wsum) of one ray.
+template <int C>
+struct Upstream {
+  float gC[C > 0 ? C : 1];
+  float gD, gN[3], gW;
+};
+
+// Per-ray inputs, loaded before the march so that their latency is hidden:
+// the upstream gradients (backward) or the reference outputs (fused step).
+template <int C, bool FUSED>
+__device__ __forceinline__ void load_ray_inputs(int64_t r, const float* __restrict__ g_feat,
+                                                const float* __restrict__ g_depth,
+                                                const float* __restrict__ g_normal,
+                                                const float* __restrict__ g_wsum, const L2Ref& ref,
+                                                Upstream<C>& v) {
+  const float* fc = FUSED ? ref.feat : g_feat;
+  const float* fd = FUSED ? ref.depth : g_depth;
+  const float* fn = FUSED ? ref.normal : g_normal;
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) v.gC[ch] = fc[(int64_t)C * r + ch];
+  v.gD = fd[r];
+  v.gN[0] = fn[3 * r];
+  v.gN[1] = fn[3 * r + 1];
+  v.gN[2] = fn[3 * r + 2];
+  v.gW = (!FUSED && g_wsum) ? g_wsum[r] : 0.0f;
+}
+
+// Stage the ray's upstream feature gradient in LDS for the scatter
+// (selects: a dynamic index into a register array would go to scratch).
+template <int C>
+__device__ __forceinline__ void stage_gC(const Upstream<C>& up, BwdScratch* sc) {
+  const int lane = lane_id();
+  float mine = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) mine = lane == ch ? up.gC[ch] : mine;
+  if (lane < C) sc->gC[lane] = mine;
+}
+
+// Forward outputs of a ray are reduced over the wave and written by lane 0;
+// the fused step then turns them into the upstream gradients of the L2 loss.
+template <int C>
+__device__ __forceinline__ void write_outputs_and_l2_grad(
+    int64_t r, int64_t R, int n, float accC[C > 0 ? C : 1], float accD, float accN[3], float accW,
+    float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
+    float* __restrict__ wsum, int32_t* __restrict__ nsamples, const L2Ref& ref,
+    const Upstream<C>& refv, Upstream<C>& up, BwdScratch* sc) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
+  accD = wave_sum(accD);
+  accN[0] = wave_sum(accN[0]);
+  accN[1] = wave_sum(accN[1]);
+  accN[2] = wave_sum(accN[2]);
+  accW = wave_sum(accW);
+  const float s2 = 2.0f / (float)R;
+  float loss = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) {
+    const float d = accC[ch] - refv.gC[ch];
+    up.gC[ch] = s2 * d;
+    loss += d * d;
+  }
+  const float dd = accD - refv.gD;
+  up.gD = s2 * ref.lambda_d * dd;
+  loss += ref.lambda_d * dd * dd;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float dn = accN[a] - refv.gN[a];
+    up.gN[a] = s2 * ref.lambda_n * dn;
+    loss += ref.lambda_n * dn * dn;
+  }
+  up.gW = 0.0f;
+  stage_gC<C>(up, sc);
+  if (lane == 0) {
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) feat_out[(int64_t)C * r + ch] = accC[ch];
+    depth[r] = accD;
+    normal[3 * r] = accN[0];
+    normal[3 * r + 1] = accN[1];
+    normal[3 * r + 2] = accN[2];
+    wsum[r] = accW;
+    if (nsamples) nsamples[r] = n;
+    if (ref.loss_ray) ref.loss_ray[r] = loss / (float)R;
+  }
+}
+
+// The adjoint of the render (FUSED = false: upstream gradients are inputs),
+// or the whole training step of the L2 rendering losses (FUSED = true: the
+// forward outputs are written and the upstream gradients formed in
+// registers from the reference values, then the same adjoint runs).
+template <int C, bool FUSED>
+__global__ __launch_bounds__(256) void k_render_bwd(
+    GridView g, const float* __restrict__ vox, const float* __restrict__ rays, int64_t R, Params p,
+    const float* __restrict__ g_feat, const float* __restrict__ g_depth,
+    const float* __restrict__ g_normal, const float* __restrict__ g_wsum, L2Ref ref,
+    float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
+    float* __restrict__ wsum, int32_t* __restrict__ nsamples, float* __restrict__ grad_vox,
+    bool keep_v) {
+  extern __shared__ int2 lds_q[];
+  const int wpb = blockDim.x / kWave, lane = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int2* q = lds_q + (int64_t)w * p.max_samples;
+  SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples);
+  SampleState* st = st_base + (int64_t)w * p.max_samples;
+  BwdScratch* sc_base = reinterpret_cast<BwdScratch*>(st_base + (int64_t)wpb * p.max_samples);
+  BwdScratch* sc = sc_base + w;
+  // Fused multi-chunk rays: t, grad f and features of every sample, kept
+  // from pass 1 for pass 2 (structure of arrays [4 + C][max_samples]) when
+  // the launch has the room; otherwise pass 2 interpolates again.
+  float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (4 + C) * p.max_samples;
+  const int M = p.max_samples;
+  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   for (; rs.next(rays); rs.advance()) {
     const int64_t r = rs.r;
+    Upstream<C> pre, up;
+    load_ray_inputs<C, FUSED>(r, g_feat, g_depth, g_normal, g_wsum, ref, pre);
     March m;
     int n = 0;
     if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, q);
+    if constexpr (!FUSED) {
+      if (n == 0) continue;  // wave-uniform: nothing to scatter
+      up = pre;
+      stage_gC<C>(up, sc);
+    }
+    if (n <= kWave) {
+      // One chunk: every per-sample quantity stays in this lane's registers.
+      const bool act = lane < n;
+      float sd = 0.0f, f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) col[ch] = 0.0f;
+      Cell cell;
+      cell.t = 0.0f;
+      if (act) {
+        locate(g, m, p, q[lane], cell);
+        interpolate<C>(vox, cell, g.inv_h, f, grad, col);
+        float e;
+        sd = density(f, p, e) * p.step;
+      }
+      const float incl = wave_inclusive_sum(sd);
+      const float excl = wave_shift_up(incl);
+      float wt = 0.0f, tn = 0.0f;
+      if (act) {
+        wt = expf(-excl) * -expm1f(-sd);
+        tn = expf(-incl);
+      }
+      if constexpr (FUSED) {
+        float accC[C > 0 ? C : 1], accN[3];
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) accC[ch] = wt * col[ch];
+        accN[0] = wt * grad[0];
+        accN[1] = wt * grad[1];
+        accN[2] = wt * grad[2];
+        write_outputs_and_l2_grad<C>(r, R, n, accC, wt * cell.t, accN, wt, feat_out, depth, normal,
+                                     wsum, nsamples, ref, pre, up, sc);
+        if (n == 0) continue;
+      }
+      float s = up.gD * cell.t + up.gW + up.gN[0] * grad[0] + up.gN[1] * grad[1] +
+                up.gN[2] * grad[2];
+#pragma unroll
+      for (int ch = 0; ch < C; ++ch) s += up.gC[ch] * col[ch];
+      const float later = wave_exclusive_suffix_sum(act ? wt * s : 0.0f);
+      float df = 0.0f;
+      if (act) {
+        const float dsig = p.step * (tn * s - later);
+        const float e = 0.5f * expf(-fabsf(f) * p.inv_beta);
+        df = dsig * (-e * p.inv_beta * p.inv_beta);
+      }
+      scatter_chunk<C>(sc, act, cell, wt, df, up.gN, g.inv_h, grad_vox);
+      continue;
+    }
+    // Several chunks.  Pass 1: recompute the forward quantities of every
+    // sample, in lattice order.
     float accC[C > 0 ? C : 1], accD = 0.0f, accN[3] = {0.0f, 0.0f, 0.0f}, accW = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
@@ -373,179 +771,85 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
       const float incl = wave_inclusive_sum(sd);
       const float excl = wave_shift_up(incl);
       if (act) {
-        const float T = expf(-(tau + excl));
-        const float alpha = -expm1f(-sd);
-        const float wt = T * alpha;
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) accC[ch] += wt * col[ch];
-        accD += wt * cell.t;
-        accN[0] += wt * grad[0];
-        accN[1] += wt * grad[1];
-        accN[2] += wt * grad[2];
-        accW += wt;
-      }
-      tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
-    }
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
-    accD = wave_sum(accD);
-    accN[0] = wave_sum(accN[0]);
-    accN[1] = wave_sum(accN[1]);
-    accN[2] = wave_sum(accN[2]);
-    accW = wave_sum(accW);
-    if (lane == 0) {
-#pragma unroll
-      for (int ch = 0; ch < C; ++ch) feat_out[(int64_t)C * r + ch] = accC[ch];
-      depth[r] = accD;
-      normal[3 * r] = accN[0];
-      normal[3 * r + 1] = accN[1];
-      normal[3 * r + 2] = accN[2];
-      wsum[r] = accW;
-      if (nsamples) nsamples[r] = n;
-    }
-    wave_sync();  // q is reused by the next ray of this wave
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Backward.
-struct SampleState {
-  float w, s, tn, f;  // weight, dL/dw, T_{k+1}, SDF
-};
-
-// Per-wave LDS staging of one chunk's scatter.  Rows are padded to an odd
-// number of words so that lanes writing the same column hit distinct banks.
-struct BwdScratch {
-  float val[kWave][17];   // per sample: SDF-gradient term of corners 0..7, then w * r_a
-  int32_t off[kWave][9];  // element offsets of the 8 corners
-  int32_t key[kWave];     // cell id (offset of corner 0), unique negative if unused
-  int32_t heads[kWave];   // lanes that start a run of samples in one cell
-  float gC[32];           // upstream feature gradient of the ray
-};
-
-template <int C>
-__global__ __launch_bounds__(256) void k_render_bwd(
-    GridView g, const float* __restrict__ vox, const float* __restrict__ rays, int64_t R, Params p,
-    const float* __restrict__ g_feat, const float* __restrict__ g_depth,
-    const float* __restrict__ g_normal, const float* __restrict__ g_wsum,
-    float* __restrict__ grad_vox) {
-  extern __shared__ int2 lds_q[];
-  constexpr int V = 1 + C;
-  constexpr int PER = 8 * V;  // scatter values per cell
-  const int wpb = blockDim.x / kWave, lane = lane_id();
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  int2* q = lds_q + (int64_t)w * p.max_samples;
-  SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples);
-  SampleState* st = st_base + (int64_t)w * p.max_samples;
-  BwdScratch* sc = reinterpret_cast<BwdScratch*>(st_base + (int64_t)wpb * p.max_samples) + w;
-  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
-  for (; rs.next(rays); rs.advance()) {
-    const int64_t r = rs.r;
-    March m;
-    int n = 0;
-    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, q);
-    if (n == 0) continue;  // wave-uniform
-    float gC[C > 0 ? C : 1];
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch) gC[ch] = g_feat[(int64_t)C * r + ch];
-    if (lane < C) sc->gC[lane] = g_feat[(int64_t)C * r + lane];
-    const float gD = g_depth[r];
-    const float gN[3] = {g_normal[3 * r], g_normal[3 * r + 1], g_normal[3 * r + 2]};
-    const float gW = g_wsum ? g_wsum[r] : 0.0f;
-    // pass 1: recompute the forward quantities of every sample
-    float tau = 0.0f;
-    for (int c0 = 0; c0 < n; c0 += kWave) {
-      const int j = c0 + lane;
-      const bool act = j < n;
-      float sd = 0.0f, f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
-      Cell cell;
-      cell.t = 0.0f;
-      if (act) {
-        locate(g, m, p, q[j], cell);
-        interpolate<C>(vox, cell, g.inv_h, f, grad, col);
-        float e;
-        sd = density(f, p, e) * p.step;
-      }
-      const float incl = wave_inclusive_sum(sd);
-      const float excl = wave_shift_up(incl);
-      if (act) {
-        const float T = expf(-(tau + excl));
-        const float alpha = -expm1f(-sd);
         SampleState s;
-        s.w = T * alpha;
+        s.w = expf(-(tau + excl)) * -expm1f(-sd);
         s.tn = expf(-(tau + incl));
-        float dw = gD * cell.t + gW + gN[0] * grad[0] + gN[1] * grad[1] + gN[2] * grad[2];
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) dw += gC[ch] * col[ch];
-        s.s = dw;
         s.f = f;
+        if constexpr (FUSED) {
+          if (keep_v) {
+            vst[j] = cell.t;
+            vst[M + j] = grad[0];
+            vst[2 * M + j] = grad[1];
+            vst[3 * M + j] = grad[2];
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) vst[(4 + ch) * M + j] = col[ch];
+          }
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) accC[ch] += s.w * col[ch];
+          accD += s.w * cell.t;
+          accN[0] += s.w * grad[0];
+          accN[1] += s.w * grad[1];
+          accN[2] += s.w * grad[2];
+          accW += s.w;
+          s.s = 0.0f;  // formed in pass 2, once the outputs are known
+        } else {
+          float dw = up.gD * cell.t + up.gW + up.gN[0] * grad[0] + up.gN[1] * grad[1] +
+                     up.gN[2] * grad[2];
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) dw += up.gC[ch] * col[ch];
+          s.s = dw;
+        }
         st[j] = s;
       }
       tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
     }
+    if constexpr (FUSED)
+      write_outputs_and_l2_grad<C>(r, R, n, accC, accD, accN, accW, feat_out, depth, normal, wsum,
+                                   nsamples, ref, pre, up, sc);
     wave_sync();
-    // pass 2: chunks in reverse with lanes in reverse sample order (lane l
+    // Pass 2: chunks in reverse with lanes in reverse sample order (lane l
     // holds sample c0 + 63 - l), so sum_{j>k} w_j s_j is an exclusive prefix
-    // sum over lanes.  Per-corner terms are staged in LDS, merged over runs
-    // of samples in one cell, then scattered with lanes laid out as (cell,
-    // corner, channel) so that each atomic instruction covers few lines.
+    // sum over lanes.
     float carry = 0.0f;
     const int last = (n - 1) / kWave * kWave;
     for (int c0 = last; c0 >= 0; c0 -= kWave) {
       const int j = c0 + (kWave - 1 - lane);
       const bool act = j < n;
       SampleState s = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (act) s = st[j];
+      Cell cell;
+      cell.t = 0.0f;
+      if (act) {
+        s = st[j];
+        locate(g, m, p, q[j], cell);
+        if constexpr (FUSED) {
+          float f, grad[3], col[C > 0 ? C : 1];
+          if (keep_v) {
+            grad[0] = vst[M + j];
+            grad[1] = vst[2 * M + j];
+            grad[2] = vst[3 * M + j];
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) col[ch] = vst[(4 + ch) * M + j];
+          } else {
+            interpolate<C>(vox, cell, g.inv_h, f, grad, col);
+          }
+          float dw = up.gD * cell.t + up.gW + up.gN[0] * grad[0] + up.gN[1] * grad[1] +
+                     up.gN[2] * grad[2];
+#pragma unroll
+          for (int ch = 0; ch < C; ++ch) dw += up.gC[ch] * col[ch];
+          s.s = dw;
+        }
+      }
       const float ws = s.w * s.s;
       const float incl = wave_inclusive_sum(ws);
       const float later = wave_shift_up(incl);
       const float total = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
-      int key = -1 - lane;
+      float df = 0.0f;
       if (act) {
         const float dsig = p.step * (s.tn * s.s - (carry + later));
         const float e = 0.5f * expf(-fabsf(s.f) * p.inv_beta);
-        const float df = dsig * (-e * p.inv_beta * p.inv_beta);
-        Cell cell;
-        locate(g, m, p, q[j], cell);
-        const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
-                    wz[2] = {1.0f - cell.u[2], cell.u[2]};
-        const float wih = s.w * g.inv_h;
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-          const float ra = wx[ax] * wy[ay] * wz[az];
-          const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gN[0] +
-                           (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gN[1] +
-                           (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gN[2];
-          sc->val[lane][a] = ra * df + wih * gn;
-          sc->val[lane][8 + a] = s.w * ra;
-          sc->off[lane][a] = cell.off[a];
-        }
-        key = cell.off[0];
+        df = dsig * (-e * p.inv_beta * p.inv_beta);
       }
-      sc->key[lane] = key;
-      const int kp = shfl(key, lane > 0 ? lane - 1 : 0);
-      const bool head = act && (lane == 0 || kp != key);
-      const uint64_t hm = __ballot(head);
-      const int H = (int)__popcll(hm);
-      wave_sync();
-      if (head) {
-        // positions are monotone per axis, so a cell's samples are adjacent
-        for (int l2 = lane + 1; l2 < kWave && sc->key[l2] == key; ++l2) {
-#pragma unroll
-          for (int a = 0; a < 16; ++a) sc->val[lane][a] += sc->val[l2][a];
-        }
-        sc->heads[rank_below(hm)] = lane;
-      }
-      wave_sync();
-      for (int idx = lane; idx < H * PER; idx += kWave) {
-        const int hh = idx / PER, rem = idx - hh * PER;
-        const int a = rem / V, ch = rem - a * V;
-        const int hl = sc->heads[hh];
-        const float v = ch == 0 ? sc->val[hl][a] : sc->val[hl][8 + a] * sc->gC[ch > 0 ? ch - 1 : 0];
-        unsafeAtomicAdd(grad_vox + (int64_t)sc->off[hl][a] * V + ch, v);
-      }
-      wave_sync();  // the staging rows are rewritten by the next chunk
+      scatter_chunk<C>(sc, act, cell, s.w, df, up.gN, g.inv_h, grad_vox);
       carry += total;
     }
   }
@@ -747,9 +1051,87 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   const Launch l =
       plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch));
   hipStream_t s = (hipStream_t)stream;
-  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_bwd<CC>, dim3(l.blocks), dim3(l.threads), l.lds, s,
-                                      g, d_vox, d_rays, n_rays, p, d_g_feat, d_g_depth, d_g_normal,
-                                      d_g_wsum, d_grad_vox));
+  const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, nullptr};
+  SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false>), dim3(l.blocks), dim3(l.threads),
+                                      l.lds, s, g, d_vox, d_rays, n_rays, p, d_g_feat, d_g_depth,
+                                      d_g_normal, d_g_wsum, none, nullptr, nullptr, nullptr,
+                                      nullptr, nullptr, d_grad_vox, false));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
+                      int64_t n_rays, const sg_render_params* params, const float* d_ref_feat,
+                      const float* d_ref_depth, const float* d_ref_normal, float lambda_d,
+                      float lambda_n, float* d_feat_out, float* d_depth, float* d_normal,
+                      float* d_wsum, int32_t* d_nsamples, float* d_loss_ray, float* d_grad_vox,
+                      sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
+  if (n_rays == 0) return SG_OK;
+  if (!std::isfinite(lambda_d) || !std::isfinite(lambda_n))
+    return fail(SG_EINVAL, "lambda_d / lambda_n must be finite");
+  if (!d_vox || !d_rays || !d_ref_depth || !d_ref_normal || !d_depth || !d_normal || !d_wsum ||
+      !d_grad_vox || (C > 0 && (!d_ref_feat || !d_feat_out)))
+    return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  // Per-wave LDS: sample list, per-sample state, scatter staging, and (when
+  // four waves per workgroup still fit 64 KiB) the values pass 2 reuses.
+  const size_t base =
+      (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch);
+  const size_t vbytes = sizeof(float) * (size_t)(4 + C) * p.max_samples;
+  const bool keep_v = (base + vbytes) * 4 <= 64 * 1024;
+  const Launch l = plan(n_rays, base + (keep_v ? vbytes : 0));
+  const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, d_loss_ray};
+  hipStream_t s = (hipStream_t)stream;
+  SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true>), dim3(l.blocks), dim3(l.threads),
+                                      l.lds, s, g, d_vox, d_rays, n_rays, p, nullptr, nullptr,
+                                      nullptr, nullptr, ref, d_feat_out, d_depth, d_normal,
+                                      d_wsum, d_nsamples, d_grad_vox, keep_v));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_packed_grid_desc(const sg_grid* grid, const float* d_vox, int32_t C,
+                        const sg_render_params* params, sg_packed_grid* out) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (!d_vox || !out) return fail(SG_EINVAL, "a required pointer is NULL");
+  PackedGrid d;
+  memset(&d, 0, sizeof(d));
+  d.view = view_of(grid);
+  d.vox = d_vox;
+  d.params = p;
+  d.C = C;
+  memset(out, 0, sizeof(*out));
+  memcpy(out->opaque, &d, sizeof(d));
+  return SG_OK;
+}
+
+int sg_render_forward_packed(const sg_packed_grid* d_grids, int32_t n_grids,
+                             const sg_render_slot* d_slots, const int32_t* d_n_slots,
+                             int32_t max_slots, int32_t C, int32_t max_samples_cap,
+                             int64_t launch_rays, sg_stream stream) {
+  if (!d_grids || !d_slots || !d_n_slots) return fail(SG_EINVAL, "a required pointer is NULL");
+  if (n_grids < 1 || max_slots < 1) return fail(SG_EINVAL, "n_grids and max_slots must be >= 1");
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (max_samples_cap < 1 || max_samples_cap > SG_MAX_SAMPLES_LIMIT)
+    return fail(SG_EINVAL, "max_samples_cap must be in [1, 1024]");
+  if (launch_rays < 1) return fail(SG_EINVAL, "launch_rays must be >= 1");
+  const Launch l = plan(launch_rays, sizeof(int2) * max_samples_cap);
+  hipStream_t s = (hipStream_t)stream;
+  if (reinterpret_cast<uintptr_t>(d_grids) % alignof(PackedGrid) != 0)
+    return fail(SG_EINVAL, "d_grids must be 8-byte aligned");
+  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_packed<CC>, dim3(l.blocks), dim3(l.threads), l.lds,
+                                      s, d_grids, n_grids, d_slots, d_n_slots, max_slots,
+                                      max_samples_cap));
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

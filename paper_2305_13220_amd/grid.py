@@ -168,6 +168,45 @@ def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g
     return grad_vox
 
 
+def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, ref, lambda_d=0.1,
+                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False):
+    """Fused forward + squared-L2 loss + gradient (accumulated into grad_vox).
+
+    ref: dict of reference "feat" [R,C], "depth" [R], "normal" [R,3].
+    Returns (outputs dict, grad_vox[, loss_per_ray]).
+    """
+    params = RenderParams.of(params)
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    want(rays, "rays", torch.float32, (None, 6), grid.device)
+    R = rays.shape[0]
+    dev = grid.device
+    if C:
+        want(ref["feat"], "ref.feat", torch.float32, (R, C), dev)
+    want(ref["depth"], "ref.depth", torch.float32, (R,), dev)
+    want(ref["normal"], "ref.normal", torch.float32, (R, 3), dev)
+    if out is None:
+        out = {"feat": torch.empty((R, C), dtype=torch.float32, device=dev),
+               "depth": torch.empty(R, dtype=torch.float32, device=dev),
+               "normal": torch.empty((R, 3), dtype=torch.float32, device=dev),
+               "wsum": torch.empty(R, dtype=torch.float32, device=dev),
+               "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
+    if grad_vox is None:
+        grad_vox = torch.zeros_like(vox)
+    else:
+        want(grad_vox, "grad_vox", torch.float32, tuple(vox.shape), dev)
+    loss = torch.empty(R, dtype=torch.float32, device=dev) if with_loss else None
+    prm = params.c()
+    check(lib().sg_render_l2_step(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
+                                  ptr(ref["feat"]) if C else None, ptr(ref["depth"]),
+                                  ptr(ref["normal"]), ctypes.c_float(lambda_d),
+                                  ctypes.c_float(lambda_n), ptr(out["feat"]) if C else None,
+                                  ptr(out["depth"]), ptr(out["normal"]), ptr(out["wsum"]),
+                                  ptr(out.get("nsamples")), ptr(loss), ptr(grad_vox),
+                                  stream_ptr(dev)), "sg_render_l2_step")
+    return (out, grad_vox, loss) if with_loss else (out, grad_vox)
+
+
 def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
     """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
     params = RenderParams.of(params)

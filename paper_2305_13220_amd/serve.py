@@ -1,0 +1,327 @@
+"""Render serving on one GPU: resident grids, HBM-budget admission, continuous
+batching into packed multi-grid launches replayed from a HIP graph.
+
+A request asks for a full frame (width x height, pinhole camera) of one of
+the resident grids.  Arriving requests are admitted in order while the
+output buffers of the requests in flight fit a device-memory budget.  Every
+tick packs up to `tick_rays` pixels, taken in admission order from the
+unfinished requests (a large request spans several ticks; several requests
+share a tick), into a slot table that is copied to the device and rendered
+by one `sg_render_forward_packed` launch.  Two table buffers and two
+captured graphs alternate, so the host fills one table while the GPU renders
+the other.  A request completes with the tick that renders its last pixels.
+
+`PlainServer` is the baseline: each request, in arrival order, gets its own
+`sg_rays_pinhole` + `sg_render_forward` calls.  Both report per-request
+latency (completion - arrival) from GPU events; completion times are GPU
+timestamps relative to a reference event recorded with a known host time.
+Results are identical per pixel in both paths (same per-ray code).
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from ._lib import check, lib, ptr, stream_ptr
+from .grid import Grid, RenderParams, rays_pinhole, render_forward
+
+
+class SlotC(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("pixel_begin", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("ray_base", ctypes.c_int64), ("cam", ctypes.c_float * 16),
+                ("feat", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("normal", ctypes.c_void_p), ("wsum", ctypes.c_void_p),
+                ("nsamples", ctypes.c_void_p)]
+
+
+SLOT_DTYPE = np.dtype({
+    "names": ["grid", "width", "pixel_begin", "count", "ray_base", "cam", "feat", "depth",
+              "normal", "wsum", "nsamples"],
+    "formats": ["<i4", "<i4", "<i8", "<i8", "<i8", ("<f4", (16,)), "<u8", "<u8", "<u8", "<u8",
+                "<u8"],
+    "offsets": [SlotC.grid.offset, SlotC.width.offset, SlotC.pixel_begin.offset,
+                SlotC.count.offset, SlotC.ray_base.offset, SlotC.cam.offset, SlotC.feat.offset,
+                SlotC.depth.offset, SlotC.normal.offset, SlotC.wsum.offset,
+                SlotC.nsamples.offset],
+    "itemsize": ctypes.sizeof(SlotC)})
+
+PACKED_GRID_BYTES = 512
+
+
+
+
+@dataclass
+class Request:
+    rid: int
+    grid: int
+    cam: np.ndarray        # float32 [16]
+    width: int
+    height: int
+    arrival: float         # seconds, relative to the start of the run
+    out: dict = field(default=None, repr=False)
+    done: float = None     # completion time, seconds relative to the start of the run
+
+    @property
+    def pixels(self):
+        return self.width * self.height
+
+    def out_bytes(self, C):
+        return self.pixels * 4 * (C + 6)
+
+
+def alloc_outputs(n, C, device):
+    return {"feat": torch.empty((n, C), dtype=torch.float32, device=device),
+            "depth": torch.empty(n, dtype=torch.float32, device=device),
+            "normal": torch.empty((n, 3), dtype=torch.float32, device=device),
+            "wsum": torch.empty(n, dtype=torch.float32, device=device),
+            "nsamples": torch.empty(n, dtype=torch.int32, device=device)}
+
+
+class _Clock:
+    """GPU completion times relative to a host-timed reference event."""
+
+    def __init__(self):
+        torch.cuda.synchronize()
+        self.ref = torch.cuda.Event(enable_timing=True)
+        self.ref.record()
+        torch.cuda.synchronize()
+        self.t0 = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def event_time(self, ev):
+        return self.ref.elapsed_time(ev) * 1e-3
+
+
+class PackedServer:
+    """Continuous batching of render requests into packed, graph-replayed launches."""
+
+    def __init__(self, grids, C=3, hbm_budget_bytes=8 << 30, tick_rays=1 << 20, max_slots=256,
+                 use_graph=True, keep_outputs=True):
+        """grids: list of (Grid, vox tensor, RenderParams or dict).  With
+        keep_outputs False a request's outputs are released when it completes."""
+        L = lib()
+        self.C = C
+        self.dev = grids[0][0].device
+        self.budget = int(hbm_budget_bytes)
+        self.tick_rays = int(tick_rays)
+        self.max_slots = int(max_slots)
+        descs = (ctypes.c_ubyte * (PACKED_GRID_BYTES * len(grids)))()
+        cap = 1
+        for i, (g, vox, prm) in enumerate(grids):
+            prm = RenderParams.of(prm)
+            if vox.shape[-1] - 1 != C:
+                raise ValueError("every resident grid must have C feature channels")
+            cap = max(cap, prm.max_samples)
+            pc = prm.c()
+            check(L.sg_packed_grid_desc(g.handle, ptr(vox), C, ctypes.byref(pc),
+                                        ctypes.byref(descs, PACKED_GRID_BYTES * i)),
+                  "sg_packed_grid_desc")
+        self.keep = grids  # grids and voxels must outlive the launches
+        self.n_grids = len(grids)
+        self.q_cap = cap
+        self.d_grids = torch.frombuffer(bytearray(descs), dtype=torch.uint8).to(self.dev)
+        n = self.max_slots
+        self.h_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8).pin_memory()
+                        for _ in range(2)]
+        self.h_count = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(2)]
+        self.d_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
+                        for _ in range(2)]
+        self.d_count = [torch.zeros(1, dtype=torch.int32, device=self.dev) for _ in range(2)]
+        self.graphs = [None, None]
+        self.use_graph = use_graph
+        self.busy = [None, None]  # end event of the tick that last used each table
+        self.next_b = 0
+        self.keep_outputs = keep_outputs
+
+    def _launch(self, b):
+        check(lib().sg_render_forward_packed(ptr(self.d_grids), self.n_grids, ptr(self.d_slots[b]),
+                                             ptr(self.d_count[b]), self.max_slots, self.C,
+                                             self.q_cap, self.tick_rays, stream_ptr(self.dev)),
+              "sg_render_forward_packed")
+
+    def _render(self, b):
+        if not self.use_graph:
+            self._launch(b)
+            return
+        if self.graphs[b] is None:
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream(self.dev)
+            s.wait_stream(torch.cuda.current_stream(self.dev))
+            with torch.cuda.stream(s):
+                self._launch(b)  # warm-up outside capture
+            torch.cuda.current_stream(self.dev).wait_stream(s)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                self._launch(b)
+            self.graphs[b] = g
+            torch.cuda.synchronize()
+        self.graphs[b].replay()
+
+    def tick(self, work):
+        """Render one tick: work = list of (request, pixel_begin, count).  Returns its end event."""
+        b = self.next_b
+        self.next_b ^= 1
+        if self.busy[b] is not None:
+            self.busy[b].synchronize()  # the table is free once its tick has finished
+        slots = np.zeros(len(work), dtype=SLOT_DTYPE)
+        base = 0
+        for i, (req, p0, cnt) in enumerate(work):
+            o = req.out
+            slots[i] = (req.grid, req.width, p0, cnt, base, req.cam, o["feat"].data_ptr(),
+                        o["depth"].data_ptr(), o["normal"].data_ptr(), o["wsum"].data_ptr(),
+                        o["nsamples"].data_ptr())
+            base += cnt
+        raw = slots.view(np.uint8)
+        self.h_slots[b][: raw.size].copy_(torch.from_numpy(raw))
+        self.h_count[b][0] = len(work)
+        self.d_slots[b][: raw.size].copy_(self.h_slots[b][: raw.size], non_blocking=True)
+        self.d_count[b].copy_(self.h_count[b], non_blocking=True)
+        self._render(b)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        self.busy[b] = ev
+        return ev
+
+    def run(self, requests, realtime=True):
+        """Serve requests (sorted by arrival); fills req.done; returns the requests."""
+        clock = _Clock()
+        pending = list(requests)
+        admitted = []  # requests with pixels left to schedule: [req, next_pixel]
+        in_flight_bytes = 0
+        inflight = []  # (end event, [requests completed by it], bytes released)
+        i = 0
+        while i < len(pending) or admitted or inflight:
+            now = clock.now() if realtime else float("inf")
+            # admission by device-memory budget, in arrival order
+            while i < len(pending) and pending[i].arrival <= now:
+                req = pending[i]
+                need = req.out_bytes(self.C)
+                if admitted or inflight:
+                    if in_flight_bytes + need > self.budget:
+                        break
+                req.out = alloc_outputs(req.pixels, self.C, self.dev)
+                in_flight_bytes += need
+                admitted.append([req, 0])
+                i += 1
+            # retire finished ticks
+            keep = []
+            for ev, finished, freed in inflight:
+                if ev.query():
+                    t = clock.event_time(ev)
+                    for r in finished:
+                        r.done = t
+                        if not self.keep_outputs:
+                            r.out = None
+                    in_flight_bytes -= freed
+                else:
+                    keep.append((ev, finished, freed))
+            inflight = keep
+            if not admitted:
+                if inflight:
+                    time.sleep(0.0002)
+                elif i < len(pending):
+                    wait = pending[i].arrival - clock.now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.002))
+                continue
+            # pack one tick
+            work, budget, finished, freed = [], self.tick_rays, [], 0
+            while admitted and budget > 0 and len(work) < self.max_slots:
+                req, nxt = admitted[0]
+                cnt = min(budget, req.pixels - nxt)
+                work.append((req, nxt, cnt))
+                budget -= cnt
+                if nxt + cnt == req.pixels:
+                    admitted.pop(0)
+                    finished.append(req)
+                    freed += req.out_bytes(self.C)
+                else:
+                    admitted[0][1] = nxt + cnt
+            ev = self.tick(work)
+            inflight.append((ev, finished, freed))
+        torch.cuda.synchronize()
+        return requests
+
+
+class PlainServer:
+    """Baseline: one sg_rays_pinhole + sg_render_forward per request, in arrival order."""
+
+    def __init__(self, grids, C=3, keep_outputs=True):
+        self.grids = grids
+        self.C = C
+        self.dev = grids[0][0].device
+        self.keep_outputs = keep_outputs
+        self._pix = {}  # (W, H) -> int32 [W*H, 3] pixel table (camera 0), made once
+
+    def render(self, req, cam_row=None):
+        g, vox, prm = self.grids[req.grid]
+        W, H = req.width, req.height
+        pix = self._pix.get((W, H))
+        if pix is None:
+            v, u = torch.meshgrid(torch.arange(H, device=self.dev),
+                                  torch.arange(W, device=self.dev), indexing="ij")
+            pix = torch.stack([torch.zeros_like(u).reshape(-1), u.reshape(-1), v.reshape(-1)],
+                              -1).to(torch.int32)
+            self._pix[(W, H)] = pix
+        if cam_row is None:
+            cam = torch.from_numpy(np.asarray(req.cam, np.float32).reshape(1, 16)).to(self.dev)
+        else:  # a row of pinned memory: the copy does not wait for the GPU queue
+            cam_row.copy_(torch.from_numpy(np.asarray(req.cam, np.float32).reshape(1, 16)))
+            cam = cam_row.to(self.dev, non_blocking=True)
+        rays = rays_pinhole(cam, pix)
+        req.out = render_forward(g, vox, rays, prm)
+
+    def run(self, requests, realtime=True):
+        """Serve requests in arrival order; fills req.done.  With keep_outputs
+        False the outputs are released after launch (stream order makes the
+        memory safe to reuse), as a server that hands results on would."""
+        cams = torch.empty((len(requests), 16), dtype=torch.float32).pin_memory()
+        clock = _Clock()
+        pend = []
+        for i, req in enumerate(requests):
+            if realtime:
+                while clock.now() < req.arrival:
+                    time.sleep(min(0.002, max(0.0, req.arrival - clock.now())))
+            self.render(req, cams[i:i + 1])
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            if not self.keep_outputs:
+                req.out = None
+            pend.append((req, ev))
+        torch.cuda.synchronize()
+        for req, ev in pend:
+            req.done = clock.event_time(ev)
+        return requests
+
+
+def poisson_requests(n, qps, n_grids, cams_per_grid, resolutions, seed=0, fov_deg=60.0):
+    """Seeded requests: Poisson arrivals at rate qps, uniform grid, resolution
+    and camera (pose from cams_per_grid[grid], intrinsics from the resolution)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / qps, size=n))
+    reqs = []
+    for i in range(n):
+        gi = int(rng.integers(0, n_grids))
+        W, H = resolutions[int(rng.integers(0, len(resolutions)))]
+        poses = cams_per_grid[gi]
+        cam = np.array(poses[int(rng.integers(0, len(poses)))], np.float32).copy()
+        f = (W / 2) / np.tan(np.deg2rad(fov_deg) / 2)
+        cam[:4] = (f, f, W / 2, H / 2)
+        reqs.append(Request(i, gi, cam, W, H, float(t[i])))
+    return reqs
+
+
+def latency_stats(requests):
+    lat = np.array([r.done - r.arrival for r in requests]) * 1e3
+    span = max(r.done for r in requests) - min(r.arrival for r in requests)
+    px = sum(r.pixels for r in requests)
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "rays_per_s": px / span, "requests": len(requests)}

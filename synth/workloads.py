@@ -11,6 +11,9 @@
                 step 0.5 cm, beta=h, 128 max.
   room_2cm_noisy  room_2cm with Gaussian noise (0.5 voxel on SDF, 0.1 on
                 RGB) as the starting point and the clean grid as target.
+  serving_grids three resident grids for render serving: the room at 2 cm,
+                the same room at 1 cm (SDF + RGB), a second seeded room at
+                2 cm; 30 seeded poses each.
 """
 from __future__ import annotations
 
@@ -84,4 +87,17 @@ def _room(seed, h, n_sem):
     key = ("room", seed, h, n_sem)
     if key not in _CACHE:
         _CACHE[key] = scenes.room_scene(h=h, band_vox=3, seed=seed, n_sem=n_sem)
+    return _CACHE[key]
+
+
+def serving_grids(seed=0):
+    """[(scene dict, params, cams [30,16])] for the three resident grids."""
+    key = ("serving", seed)
+    if key not in _CACHE:
+        out = []
+        for sd, h in ((seed, 0.02), (seed, 0.01), (seed + 1, 0.02)):
+            sc = _room(sd, h, 0)
+            cams = cameras.room_cams(sc["meta"]["objects"], seed=sd, n=30, W=640, H=480)
+            out.append((sc, params(h / 2, 0.0, 12.0, h, 128), cams))
+        _CACHE[key] = out
     return _CACHE[key]

@@ -30,7 +30,7 @@ def test_exports_every_declared_function(L):
     assert len(names) >= 15
     for n in names:
         assert hasattr(L, n), f"{n} declared in sgrid.h but not exported"
-    assert set(names) <= set(_lib.exported_symbols()) | {"sg_render_forward_packed"}
+    assert set(names) <= set(_lib.exported_symbols())
 
 
 def test_version_and_empty_error(L):
@@ -77,6 +77,25 @@ def test_render_validation(L):
     assert L.sg_render_backward(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, None,
                                 fake, None) == -1
     assert L.sg_render_footprint(None, fake, 10, ctypes.byref(p), fake, None, None) == -1
+    f = ctypes.c_float
+    assert L.sg_render_l2_step(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, f(0.1),
+                               f(0.05), fake, fake, fake, fake, None, None, fake, None) == -1
+
+
+def test_packed_validation(L):
+    from paper_2305_13220_amd._lib import RenderParamsC
+    from paper_2305_13220_amd.serve import SLOT_DTYPE, SlotC
+    p = RenderParamsC(0.01, 0.0, 12.0, 0.02, 128)
+    fake = ctypes.c_void_p(16)
+    desc = (ctypes.c_ubyte * 512)()
+    assert L.sg_packed_grid_desc(None, fake, 3, ctypes.byref(p), desc) == -1
+    assert L.sg_render_forward_packed(None, 1, fake, fake, 4, 3, 128, 100, None) == -1
+    assert L.sg_render_forward_packed(fake, 0, fake, fake, 4, 3, 128, 100, None) == -1
+    assert L.sg_render_forward_packed(fake, 1, fake, fake, 4, 5, 128, 100, None) == -1
+    assert L.sg_render_forward_packed(fake, 1, fake, fake, 4, 3, 2000, 100, None) == -1
+    # the numpy slot record matches the C struct layout
+    assert SLOT_DTYPE.itemsize == ctypes.sizeof(SlotC) == 136
+    assert SLOT_DTYPE.fields["cam"][1] == 32 and SLOT_DTYPE.fields["nsamples"][1] == 128
 
 
 def test_aux_validation(L):

@@ -12,7 +12,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import (RTOL_BWD, assert_close_mag, check_forward, dev, make_grid, to_dev)
+from gpu_helpers import (ATOL, RTOL_BWD, RTOL_FWD, assert_close_mag, check_forward, dev, make_grid,
+                         to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -278,3 +279,64 @@ def test_invalid_arguments_raise(sphere):
         sg.render_forward(g, vox, rays, dict(w["params"], step=1e-9))
     with pytest.raises(ValueError):
         sg.render_forward(g, vox[:10], rays, w["params"])
+
+
+def _fused_check(w, g, vox, rays_np, seed, what, max_samples=None):
+    """Fused forward + L2 loss + backward against (a) the separate GPU calls
+    and (b) the oracle's forward -> loss gradient -> adjoint."""
+    sg = _sg()
+    prm = dict(w["params"]) if max_samples is None else dict(w["params"], max_samples=max_samples)
+    R = rays_np.shape[0]
+    rng = np.random.default_rng(seed)
+    ref_np = {"feat": rng.uniform(0, 1, size=(R, 3)).astype(np.float32),
+              "depth": rng.uniform(0, 4, size=R).astype(np.float32),
+              "normal": rng.normal(size=(R, 3)).astype(np.float32)}
+    ref = {k: to_dev(v) for k, v in ref_np.items()}
+    rays = to_dev(rays_np)
+    out, grad, loss = sg.render_l2_step(g, vox, rays, prm, ref, 0.1, 0.05, with_loss=True)
+    fwd = sg.render_forward(g, vox, rays, prm)
+    for k in fwd:
+        assert torch.equal(out[k], fwd[k]), f"{what}: fused {k} differs from render_forward"
+    gl = sg.l2_loss_grad(fwd, ref, 0.1, 0.05)
+    sep = sg.render_backward(g, vox, rays, prm, gl["feat"], gl["depth"], gl["normal"])
+    torch.testing.assert_close(grad, sep, rtol=1e-5, atol=1e-6 * sep.abs().max().item())
+    # oracle chain
+    o = oracle.render_forward(w["block_coords"], w["vox"], 3, w["h"], w["origin"], rays_np, prm,
+                              with_mag=True)
+    L, gc, gd, gn = oracle.l2_loss_grad(o["feat"], ref_np["feat"], o["depth"], ref_np["depth"],
+                                        o["normal"], ref_np["normal"], 0.1, 0.05)
+    assert loss.sum().item() == pytest.approx(L, rel=1e-4)
+    gref, mag = oracle.render_backward(w["block_coords"], w["vox"], 3, w["h"], w["origin"],
+                                       rays_np, prm, gc, gd, gn, None, with_mag=True)
+    # The kernel differentiates the loss at its own float32 forward, which
+    # is within RTOL_FWD * mag of the oracle's; where feat ~ ref that shift
+    # is a large relative change of the upstream gradient 2 (feat - ref) / R.
+    # Its effect on the adjoint is bounded by the adjoint's magnitude with
+    # the upstream shift (plus the rounding of the difference) as input.
+    u = np.finfo(np.float32).eps
+
+    def shift(mag_out, out, ref_out, lam):
+        return 2.0 * lam / R * (RTOL_FWD * mag_out + u * (np.abs(out) + np.abs(ref_out)))
+
+    dc = shift(o["mag_feat"], o["feat"], ref_np["feat"], 1.0)
+    dd = shift(o["mag_depth"], o["depth"], ref_np["depth"], 0.1)
+    dn = shift(o["mag_normal"], o["normal"], ref_np["normal"], 0.05)
+    _, mag_up = oracle.render_backward(w["block_coords"], w["vox"], 3, w["h"], w["origin"],
+                                       rays_np, prm, dc, dd, dn, None, with_mag=True)
+    assert_close_mag(grad.cpu().numpy(), gref, mag, RTOL_BWD, what, atol=mag_up + ATOL)
+
+
+def test_fused_l2_step_sphere(sphere):
+    w, g, vox, _ = sphere
+    _fused_check(w, g, vox, w["rays"], seed=11, what="fused sphere")
+
+
+def test_fused_l2_step_multichunk(sphere):
+    """max_samples 1024: rays with more than 64 samples take the chunked path."""
+    w, g, vox, _ = sphere
+    _fused_check(w, g, vox, w["rays"][::3], seed=12, what="fused sphere 1024", max_samples=1024)
+
+
+def test_fused_l2_step_room_full_batch(room):
+    w, g, vox, _ = room
+    _fused_check(w, g, vox, w["rays"], seed=13, what="fused room 65536")

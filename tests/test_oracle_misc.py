@@ -94,3 +94,13 @@ def test_l2_loss_grad_matches_autograd(oracle_lib):
     assert loss == pytest.approx(L.item(), rel=1e-13)
     for mine, ref in ((gc, t[0]), (gd, t[2]), (gn, t[4])):
         np.testing.assert_allclose(mine, ref.grad.numpy(), rtol=1e-13)
+
+
+def test_paper_hyperparameters_fixture():
+    """The loss weights the losses use are the paper's (supplement)."""
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hyperparameters.json")))
+    assert d["lambda_depth"]["value"] == 0.1 and d["lambda_normal"]["value"] == 0.05
+    assert d["block_dim"]["value"] == 8
+    assert d["rays_per_image"]["value"] * d["images_per_batch"]["value"] == 65536
