@@ -4,11 +4,12 @@ Workload (one GPU): the 6 x 6 x 3 m synthetic room at 2 cm voxels
 (11,542 allocated 8^3 blocks, SDF + RGB), batches of 65,536 random pixels
 from 30 seeded 640x480 poses, step 1 cm, t in [0, 12] m, beta = 2 cm, at
 most 128 samples per ray.  One step = camera rays for the batch, gradient
-zeroing, and the fused training kernel: forward render (colour, depth,
-normal), squared-L2 losses against renders of the same room with a second
-texture, and the backward scatter into the voxels.  The same step built
-from the separate forward / loss-gradient / backward calls is timed too.
-Inputs are resident on the GPU before timing starts.
+zeroing, the block march (sample lists), and the fused training kernel:
+forward render (colour, depth, normal), squared-L2 losses against renders
+of the same room with a second texture, and the backward scatter into the
+voxels.  The same step built from the separate forward / loss-gradient /
+backward calls is timed too.  Inputs are resident on the GPU before timing
+starts.
 
 Prints one JSON line.  `roofline` is for the dominant kernel, timed with
 HIP events on its own stream over the timed steps; its algorithmic bytes
@@ -241,36 +242,45 @@ def main():
         return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
 
     fused_ev, sep_ev = [], []
+    lists = torch.empty(sg.list_bytes(R, params), dtype=torch.uint8, device=dev)
 
     def step_fused(timed):
-        """camera rays -> zero gradients -> fused forward + L2 loss + backward"""
+        """camera rays -> zero gradients -> march -> fused forward + L2 loss + backward"""
         rr = sg.rays_pinhole(cams, pix)
         grad.zero_()
-        e = events(2) if timed else None
+        e = events(3) if timed else None
         if timed:
             e[0].record()
-        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
+        sg.march(grid, rr, params, out=lists)
         if timed:
             e[1].record()
+        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out,
+                          lists=lists)
+        if timed:
+            e[2].record()
             fused_ev.append(e)
 
     def step_separate(timed):
-        """camera rays -> forward -> loss gradient -> zero gradients -> backward"""
+        """camera rays -> march -> forward -> loss gradient -> zero gradients -> backward
+        (the backward reuses the forward's sample lists, as the autograd path does)"""
         rr = sg.rays_pinhole(cams, pix)
-        e = events(4) if timed else None
+        e = events(5) if timed else None
         if timed:
             e[0].record()
-        sg.render_forward(grid, vox, rr, params, out=out)
+        sg.march(grid, rr, params, out=lists)
         if timed:
             e[1].record()
+        sg.render_forward(grid, vox, rr, params, out=out, lists=lists)
+        if timed:
+            e[2].record()
         sg.l2_loss_grad(out, target, 0.1, 0.05, out=gout)
         grad.zero_()
         if timed:
-            e[2].record()
-        sg.render_backward(grid, vox, rr, params, gout["feat"], gout["depth"], gout["normal"],
-                           None, grad_vox=grad)
-        if timed:
             e[3].record()
+        sg.render_backward(grid, vox, rr, params, gout["feat"], gout["depth"], gout["normal"],
+                           None, grad_vox=grad, lists=lists)
+        if timed:
+            e[4].record()
             sep_ev.append(e)
 
     def run(step):
@@ -287,10 +297,12 @@ def main():
 
     ms = run(step_fused)
     ms_sep = run(step_separate)
-    fused_each = np.array([e[0].elapsed_time(e[1]) for e in fused_ev])
+    march_each = np.array([e[0].elapsed_time(e[1]) for e in fused_ev])
+    fused_each = np.array([e[1].elapsed_time(e[2]) for e in fused_ev])
+    march_ms = float(march_each.mean())
     fused_ms = float(fused_each.mean())
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in sep_ev]))
-    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in sep_ev]))
+    fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sep_ev]))
+    bwd_ms = float(np.mean([e[3].elapsed_time(e[4]) for e in sep_ev]))
 
     # cold caches: 1 GiB written between steps evicts L2 and the Infinity Cache
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -301,7 +313,9 @@ def main():
         flush.fill_(1.0)
         e = events(2)
         e[0].record()
-        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
+        sg.march(grid, rr, params, out=lists)
+        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out,
+                          lists=lists)
         e[1].record()
         cold.append(e)
     torch.cuda.synchronize()
@@ -327,7 +341,7 @@ def main():
     k_all = int(touched.view(-1, 512).any(dim=1).sum().item())
     comp_b = 2 * 4 * (1 + C) * u_all + 16 * k_all + R * (24 + 4 * (C + 5) + 4 * (C + 4))
     S = int(counts[:, 0].sum())
-    kname = "k_render_bwd<3, true>"
+    kname = "k_render_bwd<3, true, true>"
     achieved = fused_b / (fused_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -335,7 +349,10 @@ def main():
             "algorithmic_bytes_per_launch": fused_b, "launch_ms": round(fused_ms, 4),
             "launch_ms_p50": round(float(np.median(fused_each)), 4),
             "launch_ms_p90": round(float(np.percentile(fused_each, 90)), 4),
-            "launch_ms_cold": round(cold_ms, 4),
+            "march_kernel": "k_march", "march_ms": round(march_ms, 4),
+            "step_kernels_frac": round(fused_b / ((fused_ms + march_ms) * 1e-3) / 1e9 /
+                                       HBM_PEAK_GBS, 4),
+            "step_kernels_ms_cold": round(cold_ms, 4),
             "compulsory_bytes_per_launch": comp_b,
             "compulsory_frac": round(comp_b / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "copy_ceiling_GBps": round(copy_gbs, 1)}
@@ -350,13 +367,17 @@ def main():
         "samples_per_s": S / (ms * 1e-3),
         "mean_samples_per_ray": S / R,
         "fused_kernel_ms": round(fused_ms, 4),
+        "march_kernel_ms": round(march_ms, 4),
         "roofline": roof,
         "separate_calls": {"ms_per_step": round(ms_sep, 4), "rays_per_s": R / (ms_sep * 1e-3),
                            "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
                            "forward_hbm_frac": round(fb / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                            "backward_hbm_frac": round(bb / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "traffic_forward": measured_traffic("k_render_fwd<3>", "room_2cm_65536"),
-                           "traffic_backward": measured_traffic("k_render_bwd<3, false>",
+                           "march_ms": round(float(np.mean([e[0].elapsed_time(e[1])
+                                                            for e in sep_ev])), 4),
+                           "traffic_forward": measured_traffic("k_render_fwd<3, true>",
+                                                               "room_2cm_65536"),
+                           "traffic_backward": measured_traffic("k_render_bwd<3, false, true>",
                                                                 "room_2cm_65536")},
     }
     if not args.no_serve:

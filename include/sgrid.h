@@ -190,6 +190,31 @@ int sg_rays_pinhole(const float* d_cams, int32_t n_cams, const int32_t* d_pix,
                     int64_t n_rays, float* d_rays, sg_stream stream);
 
 /*
+ * Sample lists (optional).  sg_render_march runs the block march of
+ * Sec. 3.5.1 for every ray on its own and writes each ray's kept samples to
+ * d_lists: [n_rays][max_samples] pairs (lattice index k, block index) in
+ * lattice order, then [n_rays] int32 counts.  sg_render_forward,
+ * sg_render_backward and sg_render_l2_step take (d_lists, lists_bytes):
+ * given a buffer filled by sg_render_march for the same grid, rays and
+ * params (and not written since), they read the samples from it instead of
+ * marching; with (NULL, 0) they march themselves.  Results are
+ * bit-identical either way; one list can serve a forward and its backward.
+ * A list that does not match its call gives wrong outputs but no access
+ * outside the grid or the buffer.  The buffer is device memory owned by the
+ * caller, 8-byte aligned, at least sg_render_list_bytes(n_rays,
+ * params) bytes; SG_EINVAL otherwise, or if bytes are given without a
+ * pointer.
+ *
+ * sg_render_list_bytes returns n_rays * max_samples * 8 + n_rays * 4,
+ * or 0 if the arguments are invalid.
+ */
+size_t sg_render_list_bytes(int64_t n_rays, const sg_render_params* params);
+
+int sg_render_march(const sg_grid* g, const float* d_rays, int64_t n_rays,
+                    const sg_render_params* params, void* d_lists, size_t lists_bytes,
+                    sg_stream stream);
+
+/*
  * sg_render_forward -- volume rendering through the sparse grid
  * (Sec. 3.5.1, Eq. 12-15, with f and grad f from Eq. 17-18).
  * For each ray (o,d) in d_rays float [R,6] (d of unit length; the caller's
@@ -211,7 +236,8 @@ int sg_render_forward(const sg_grid* g, const float* d_vox, int32_t C,
                       const float* d_rays, int64_t n_rays,
                       const sg_render_params* params, float* d_feat_out,
                       float* d_depth, float* d_normal, float* d_wsum,
-                      int32_t* d_nsamples, sg_stream stream);
+                      int32_t* d_nsamples, const void* d_lists,
+                      size_t lists_bytes, sg_stream stream);
 
 /*
  * sg_render_backward -- adjoint of sg_render_forward with respect to the
@@ -230,6 +256,7 @@ int sg_render_backward(const sg_grid* g, const float* d_vox, int32_t C,
                        const sg_render_params* params, const float* d_g_feat,
                        const float* d_g_depth, const float* d_g_normal,
                        const float* d_g_wsum, float* d_grad_vox,
+                       const void* d_lists, size_t lists_bytes,
                        sg_stream stream);
 
 /*
@@ -251,7 +278,7 @@ int sg_render_l2_step(const sg_grid* g, const float* d_vox, int32_t C, const flo
                       const float* d_ref_depth, const float* d_ref_normal, float lambda_d,
                       float lambda_n, float* d_feat_out, float* d_depth, float* d_normal,
                       float* d_wsum, int32_t* d_nsamples, float* d_loss_ray, float* d_grad_vox,
-                      sg_stream stream);
+                      const void* d_lists, size_t lists_bytes, sg_stream stream);
 
 /*
  * Packed multi-grid rendering for a render server.  A launch renders the

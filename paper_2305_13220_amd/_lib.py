@@ -50,15 +50,17 @@ _SIGNATURES = {
     "sg_grid_lookup": ([_vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "sg_grid_destroy": ([_vp], ctypes.c_int),
     "sg_rays_pinhole": ([_vp, _i32, _vp, _i64, _vp, _vp], ctypes.c_int),
-    "sg_render_forward": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-                          ctypes.c_int),
-    "sg_render_backward": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
-                           ctypes.c_int),
+    "sg_render_list_bytes": ([_i64, _vp], ctypes.c_size_t),
+    "sg_render_march": ([_vp, _vp, _i64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "sg_render_forward": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                           ctypes.c_size_t, _vp], ctypes.c_int),
+    "sg_render_backward": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                            ctypes.c_size_t, _vp], ctypes.c_int),
     "sg_render_footprint": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "sg_packed_grid_desc": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "sg_render_forward_packed": ([_vp, _i32, _vp, _vp, _i32, _i32, _i32, _i64, _vp], ctypes.c_int),
     "sg_render_l2_step": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _f, _f, _vp, _vp, _vp,
-                           _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+                           _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "sg_l2_loss_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _f, _f, _vp, _vp, _vp, _vp, _vp],
                         ctypes.c_int),
     "sg_optim_step": ([_i32, _vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp], ctypes.c_int),

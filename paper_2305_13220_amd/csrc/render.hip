@@ -29,7 +29,7 @@ struct Params {
   float step, t_near, t_far, beta, inv_beta;
   int32_t max_samples;
   int32_t k_max;     // last lattice index with t_k <= t_far (-1: none)
-  double inv_step;   // 1 / step
+  float inv_step;    // 1 / step (rounded; used only for conservative estimates)
 };
 
 struct March {
@@ -65,45 +65,61 @@ __device__ __forceinline__ float to_voxel(float x, float org, float inv_h) {
 constexpr float kPosLimit = 16777216.0f;  // 2^24 voxels: no block beyond
 constexpr int32_t kKMax = 1 << 24;
 
-// Ray set-up: voxel-space ray and the lattice range clipped to the grid's
-// bounding box, with a margin that covers float32 position error (points
-// outside the clipped range cannot lie in an allocated block).
-__device__ bool march_setup(const GridView& g, const float r[6], const Params& p, March& m) {
-#pragma unroll
-  for (int a = 0; a < 6; ++a)
-    if (!isfinite(r[a])) return false;
-  if (p.k_max < 0) return false;
+__device__ __forceinline__ void ray_to_voxel(const GridView& g, const float r[6], March& m) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     m.ov[a] = to_voxel(r[a], g.org[a], g.inv_h);
     m.dv[a] = r[3 + a] * g.inv_h;
   }
-  double maxo = 0.0, maxd = 0.0;
+}
+
+// Ray set-up: voxel-space ray and the lattice range clipped to the grid's
+// bounding box.  The clip is computed in float32 with an approximate
+// reciprocal and is conservative: the box is widened by 2 voxels plus 1e-5
+// of every magnitude involved (float32 lattice positions, the box corners
+// and this computation are off by far less), the t interval by 1e-5 of its
+// ends, and the index range by 2 plus 1e-5 of its ends.  Lattice points
+// outside the range therefore cannot lie in an allocated block.
+__device__ bool march_setup(const GridView& g, const float r[6], const Params& p, March& m) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+    if (!isfinite(r[a])) return false;
+  if (p.k_max < 0) return false;
+  ray_to_voxel(g, r, m);
+  float maxo = 0.0f, maxd = 0.0f, maxb = 0.0f;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    maxo = fmax(maxo, fabs((double)m.ov[a]));
-    maxd = fmax(maxd, fabs((double)m.dv[a]));
+    maxo = fmaxf(maxo, fabsf(m.ov[a]));
+    maxd = fmaxf(maxd, fabsf(m.dv[a]));
+    maxb = fmaxf(maxb, fmaxf(fabsf(8.0f * (float)g.bmin[a]), fabsf(8.0f * (float)(g.bmax[a] + 1))));
   }
-  const double tabs = fmax(fabs((double)p.t_near), fabs((double)p.t_far));
-  const double margin = 2.0 + 1e-6 * (maxo + tabs * maxd);
-  double t0 = -1e300, t1 = 1e300;
+  const float tabs = fmaxf(fabsf(p.t_near), fabsf(p.t_far));
+  const float margin = 2.0f + 1e-5f * (maxo + maxb + tabs * maxd);
+  float t0 = -INFINITY, t1 = INFINITY;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double lo = 8.0 * g.bmin[a] - margin, hi = 8.0 * ((double)g.bmax[a] + 1.0) + margin;
-    const double o = m.ov[a], d = m.dv[a];
-    if (d == 0.0) {
+    const float lo = 8.0f * (float)g.bmin[a] - margin;
+    const float hi = 8.0f * (float)(g.bmax[a] + 1) + margin;
+    const float o = m.ov[a], d = m.dv[a];
+    if (d == 0.0f) {
       if (o < lo || o > hi) return false;
     } else {
-      const double inv = 1.0 / d;
-      const double ta = (lo - o) * inv, tb = (hi - o) * inv;
-      t0 = fmax(t0, fmin(ta, tb));
-      t1 = fmin(t1, fmax(ta, tb));
+      // fmaxf / fminf drop a NaN operand (0 * inf), which only widens
+      const float inv = __builtin_amdgcn_rcpf(d);
+      const float ta = (lo - o) * inv, tb = (hi - o) * inv;
+      t0 = fmaxf(t0, fminf(ta, tb));
+      t1 = fminf(t1, fmaxf(ta, tb));
     }
   }
-  if (t0 > t1) return false;
-  const double kl = ceil((t0 - (double)p.t_near) * p.inv_step) - 2.0;
-  const double ku = floor((t1 - (double)p.t_near) * p.inv_step) + 2.0;
-  if (ku < 0.0 || kl > (double)p.k_max) return false;
-  m.k_lo = kl < 0.0 ? 0 : (int32_t)kl;
-  m.k_hi = ku > (double)p.k_max ? p.k_max : (int32_t)ku;
+  t0 -= 1e-5f * fabsf(t0);
+  t1 += 1e-5f * fabsf(t1);
+  if (!(t0 <= t1)) return false;
+  const float fl = (t0 - p.t_near) * p.inv_step, fu = (t1 - p.t_near) * p.inv_step;
+  const float kl = floorf(fl - 1e-5f * fabsf(fl)) - 2.0f;
+  const float ku = ceilf(fu + 1e-5f * fabsf(fu)) + 2.0f;
+  if (!(ku >= 0.0f) || !(kl <= (float)p.k_max)) return false;
+  m.k_lo = kl <= 0.0f ? 0 : (int32_t)kl;
+  m.k_hi = ku >= (float)p.k_max ? p.k_max : (int32_t)ku;
   return m.k_lo <= m.k_hi;
 }
 
@@ -141,13 +157,17 @@ __device__ __forceinline__ bool in_block_cube(const March& m, const Params& p, i
 __device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, const int32_t c[3],
                                  int32_t D, int32_t k_hi) {
   float t_exit = 3.0e38f;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float d = m.dv[a], o = m.ov[a];
-    if (d > 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] + D) - o) / d);
-    else if (d < 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] - D + 1) - o) / d);
+    const float inv = __builtin_amdgcn_rcpf(d);  // an estimate is all that is needed here
+    if (d > 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] + D) - o) * inv);
+    else if (d < 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] - D + 1) - o) * inv);
   }
-  const float est = floorf((t_exit - p.t_near) * (float)p.inv_step);
-  int32_t hi = est >= (float)k_hi ? k_hi : (est <= (float)k ? k : (int32_t)est);
+  const float est = floorf((t_exit - p.t_near) * p.inv_step);
+  // NaN (0 * inf from the reciprocal of a tiny d) falls back to k: the
+  // result is always in [k, k_hi], so the march advances.
+  int32_t hi = !(est > (float)k) ? k : (est >= (float)k_hi ? k_hi : (int32_t)est);
   if (in_block_cube(m, p, hi, c, D - 1)) return hi;
   int32_t lo = k;  // invariant: lo inside, hi outside
   while (hi - lo > 1) {
@@ -162,10 +182,57 @@ __device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, con
 // When the last of the 64 tested points lies in an empty block with empty
 // surroundings (dense map), the run of lattice points inside that empty
 // region is skipped.
+// One lattice point against the dense block map, without branches: every
+// lane loads a map entry (index clamped into the map), and out-of-range
+// points read as empty with distance 1.
+__device__ __forceinline__ void map_point(const GridView& g, const March& m, const Params& p,
+                                          int32_t k, bool in_range, bool& valid, int32_t& idx,
+                                          int32_t& dist, int32_t b[3]) {
+  const float t = lattice_t(p, k);
+  int32_t i[3];
+  bool ok = in_range;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = lattice_x(m.ov[a], m.dv[a], t);
+    ok = ok && (fabsf(x) < kPosLimit);
+    i[a] = (int32_t)floorf(fabsf(x) < kPosLimit ? x : 0.0f);
+    b[a] = i[a] >> 3;
+  }
+  const uint32_t rx = (uint32_t)(b[0] - g.bmin[0]), ry = (uint32_t)(b[1] - g.bmin[1]),
+                 rz = (uint32_t)(b[2] - g.bmin[2]);
+  const bool inb = ok && rx < (uint32_t)g.mdim[0] && ry < (uint32_t)g.mdim[1] &&
+                   rz < (uint32_t)g.mdim[2];
+  // at most 2^28 cells: the index fits 32 bits
+  const int32_t cell = inb ? (int32_t)((rz * (uint32_t)g.mdim[1] + ry) * (uint32_t)g.mdim[0] + rx) : 0;
+  int32_t e = g.map[cell];
+  e = inb ? e : -1;
+  idx = e >= 0 ? (e >> 8) : -1;
+  dist = e >= 0 ? 0 : -e;
+  const int need = need_mask(i[0] & 7, i[1] & 7, i[2] & 7);
+  valid = e >= 0 && ((e & 255) & need) == need;
+}
+
 __device__ int march_collect(const GridView& g, const March& m, const Params& p, int2* q) {
   const int lane = lane_id();
   int n = 0;
   int32_t k0 = m.k_lo;
+  if (g.map) {
+    while (k0 <= m.k_hi && n < p.max_samples) {
+      const int32_t k = k0 + lane;
+      bool valid;
+      int32_t idx, dist, b[3];
+      map_point(g, m, p, k, k <= m.k_hi, valid, idx, dist, b);
+      const uint64_t bal = __ballot(valid);
+      const int r = rank_below(bal);
+      if (valid && n + r < p.max_samples) q[n + r] = make_int2(k, idx);
+      n = min(p.max_samples, n + (int)__popcll(bal));
+      int32_t next = k0 + kWave;
+      if (lane == kWave - 1 && idx < 0 && dist >= 2) next = empty_run_end(m, p, k, b, dist, m.k_hi) + 1;
+      k0 = __builtin_amdgcn_readlane(next, kWave - 1);
+    }
+    wave_sync();
+    return n;
+  }
   while (k0 <= m.k_hi && n < p.max_samples) {
     const int32_t k = k0 + lane;
     bool valid = false;
@@ -227,7 +294,11 @@ __device__ __forceinline__ void locate(const GridView& g, const March& m, const 
     i[a] = (int32_t)fl;
     c.u[a] = x - fl;
   }
-  const int4* row = reinterpret_cast<const int4*>(g.nbr + 8 * (int64_t)e.y);
+  // Entries come from this call's march or from a caller's list buffer;
+  // clamping keeps a stale list from addressing outside the grid (it then
+  // renders wrong values, never faults).
+  const int64_t bi = min(max((int64_t)e.y, (int64_t)0), g.n_blocks - 1);
+  const int4* row = reinterpret_cast<const int4*>(g.nbr + 8 * bi);
   const int4 n0 = row[0], n1 = row[1];
   const int32_t nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
   const int lx = i[0] & 7, ly = i[1] & 7, lz = i[2] & 7;
@@ -235,7 +306,7 @@ __device__ __forceinline__ void locate(const GridView& g, const March& m, const 
   for (int a = 0; a < 8; ++a) {
     const int cx = lx + (a & 1), cy = ly + ((a >> 1) & 1), cz = lz + ((a >> 2) & 1);
     const int s = (cx >> 3) | ((cy >> 3) << 1) | ((cz >> 3) << 2);
-    c.off[a] = nb[s] * SG_BLOCK_VOXELS + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7);
+    c.off[a] = max(nb[s], 0) * SG_BLOCK_VOXELS + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7);
   }
 }
 
@@ -336,19 +407,79 @@ struct RayStream {
 };
 
 // ---------------------------------------------------------------------------
+// Sample lists.  With a caller workspace the march runs as its own light
+// kernel (few registers, so many waves per SIMD hide the dependent block
+// lookups) and writes each ray's kept samples (lattice index, block index)
+// to list[r * max_samples + i], i < counts[r]; the shading kernels then read
+// the list instead of marching.  Without a workspace they march themselves.
+// Both give the same samples in the same order, so the results are
+// bit-identical.
+struct SampleList {
+  int2* q;          // [R][max_samples]
+  int32_t* counts;  // [R]
+};
+
+__global__ __launch_bounds__(256) void k_march(GridView g, const float* __restrict__ rays, int64_t R,
+                                               Params p, SampleList L) {
+  const int wpb = blockDim.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  for (; rs.next(rays); rs.advance()) {
+    March m;
+    int n = 0;
+    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, L.q + rs.r * p.max_samples);
+    if (lane_id() == 0) L.counts[rs.r] = n;
+  }
+}
+
+// List prefetch: the count and first kWave entries of the wave's next ray
+// are loaded while the current ray is processed; at the next ray they are
+// copied into the wave's LDS queue, so the shading reads LDS as it does
+// after an in-kernel march.
+struct ListPrefetch {
+  int n = 0;
+  int2 e = make_int2(0, 0);
+  __device__ void load(const SampleList& L, int M, int64_t r, int64_t R) {
+    if (r < R) {
+      n = L.counts[r];
+      if (lane_id() < M) e = L.q[r * M + lane_id()];
+    }
+  }
+};
+
+// The samples of ray r into the wave's LDS queue q: from the list if there
+// is one (entries beyond the prefetched first kWave are read here), else
+// marched.  m.ov / m.dv are set whenever n > 0.
+template <bool LIST>
+__device__ __forceinline__ int ray_samples(const GridView& g, const float ray[6], const Params& p,
+                                           const SampleList& L, ListPrefetch& pf, int64_t r,
+                                           int64_t r_next, int64_t R, March& m, int2* q) {
+  if constexpr (LIST) {
+    const int M = p.max_samples;
+    const int n = min(max(pf.n, 0), M);  // a stale list cannot overrun its row
+    const int lane = lane_id();
+    if (lane < M) q[lane] = pf.e;
+    for (int j = kWave + lane; j < n; j += kWave) q[j] = L.q[r * M + j];
+    pf.load(L, M, r_next, R);
+    wave_sync();
+    if (n > 0) ray_to_voxel(g, ray, m);
+    return n;
+  } else {
+    return march_setup(g, ray, p, m) ? march_collect(g, m, p, q) : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward.
 
 // One ray: march, shade, composite; lane 0 writes output row o.
 template <int C>
-__device__ __forceinline__ void render_ray(const GridView& g, const float* __restrict__ vox,
-                                           const Params& p, const float ray[6], int2* q, int64_t o,
-                                           float* __restrict__ feat_out, float* __restrict__ depth,
-                                           float* __restrict__ normal, float* __restrict__ wsum,
-                                           int32_t* __restrict__ nsamples) {
+__device__ __forceinline__ void shade_ray(const GridView& g, const float* __restrict__ vox,
+                                          const Params& p, const March& m, int n, const int2* q,
+                                          int64_t o, float* __restrict__ feat_out,
+                                          float* __restrict__ depth, float* __restrict__ normal,
+                                          float* __restrict__ wsum, int32_t* __restrict__ nsamples) {
   const int lane = lane_id();
-  March m;
-  int n = 0;
-  if (march_setup(g, ray, p, m)) n = march_collect(g, m, p, q);
   float accC[C > 0 ? C : 1], accD = 0.0f, accN[3] = {0.0f, 0.0f, 0.0f}, accW = 0.0f;
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
@@ -402,9 +533,22 @@ __device__ __forceinline__ void render_ray(const GridView& g, const float* __res
 }
 
 template <int C>
+__device__ __forceinline__ void render_ray(const GridView& g, const float* __restrict__ vox,
+                                           const Params& p, const float ray[6], int2* q, int64_t o,
+                                           float* __restrict__ feat_out, float* __restrict__ depth,
+                                           float* __restrict__ normal, float* __restrict__ wsum,
+                                           int32_t* __restrict__ nsamples) {
+  March m;
+  int n = 0;
+  if (march_setup(g, ray, p, m)) n = march_collect(g, m, p, q);
+  shade_ray<C>(g, vox, p, m, n, q, o, feat_out, depth, normal, wsum, nsamples);
+}
+
+template <int C, bool LIST>
 __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __restrict__ vox,
                                                     const float* __restrict__ rays, int64_t R,
-                                                    Params p, float* __restrict__ feat_out,
+                                                    Params p, SampleList L,
+                                                    float* __restrict__ feat_out,
                                                     float* __restrict__ depth,
                                                     float* __restrict__ normal,
                                                     float* __restrict__ wsum,
@@ -412,10 +556,15 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
   extern __shared__ int2 lds_q[];
   const int wpb = blockDim.x / kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  int2* q = lds_q + (int64_t)w * p.max_samples;
+  int2* const q = lds_q + (int64_t)w * p.max_samples;
   RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
-  for (; rs.next(rays); rs.advance())
-    render_ray<C>(g, vox, p, rs.cur, q, rs.r, feat_out, depth, normal, wsum, nsamples);
+  ListPrefetch pf;
+  if (LIST) pf.load(L, p.max_samples, rs.r, R);
+  for (; rs.next(rays); rs.advance()) {
+    March m;
+    const int n = ray_samples<LIST>(g, rs.cur, p, L, pf, rs.r, rs.r + rs.stride, R, m, q);
+    shade_ray<C>(g, vox, p, m, n, q, rs.r, feat_out, depth, normal, wsum, nsamples);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -670,9 +819,10 @@ __device__ __forceinline__ void write_outputs_and_l2_grad(
 // or the whole training step of the L2 rendering losses (FUSED = true: the
 // forward outputs are written and the upstream gradients formed in
 // registers from the reference values, then the same adjoint runs).
-template <int C, bool FUSED>
+template <int C, bool FUSED, bool LIST>
 __global__ __launch_bounds__(256) void k_render_bwd(
     GridView g, const float* __restrict__ vox, const float* __restrict__ rays, int64_t R, Params p,
+    SampleList L,
     const float* __restrict__ g_feat, const float* __restrict__ g_depth,
     const float* __restrict__ g_normal, const float* __restrict__ g_wsum, L2Ref ref,
     float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
@@ -681,7 +831,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   extern __shared__ int2 lds_q[];
   const int wpb = blockDim.x / kWave, lane = lane_id();
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  int2* q = lds_q + (int64_t)w * p.max_samples;
+  int2* const q = lds_q + (int64_t)w * p.max_samples;
   SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples);
   SampleState* st = st_base + (int64_t)w * p.max_samples;
   BwdScratch* sc_base = reinterpret_cast<BwdScratch*>(st_base + (int64_t)wpb * p.max_samples);
@@ -692,13 +842,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (4 + C) * p.max_samples;
   const int M = p.max_samples;
   RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  ListPrefetch pf;
+  if (LIST) pf.load(L, M, rs.r, R);
   for (; rs.next(rays); rs.advance()) {
     const int64_t r = rs.r;
     Upstream<C> pre, up;
     load_ray_inputs<C, FUSED>(r, g_feat, g_depth, g_normal, g_wsum, ref, pre);
     March m;
-    int n = 0;
-    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, q);
+    const int n = ray_samples<LIST>(g, rs.cur, p, L, pf, r, r + rs.stride, R, m, q);
     if constexpr (!FUSED) {
       if (n == 0) continue;  // wave-uniform: nothing to scatter
       up = pre;
@@ -965,7 +1116,7 @@ static int check_params(const sg_render_params* prm, Params& p) {
   p.inv_beta = 1.0f / prm->beta;
   p.max_samples = prm->max_samples;
   p.k_max = last_lattice_index(prm->t_near, prm->step, prm->t_far);
-  p.inv_step = 1.0 / (double)prm->step;
+  p.inv_step = (float)(1.0 / (double)prm->step);
   return SG_OK;
 }
 
@@ -1005,16 +1156,73 @@ static Launch plan(int64_t R, size_t lds_per_wave) {
     default: break;                                   \
   }
 
+// Workspace of the sample lists: [R][max_samples] int2, then [R] int32.
+static bool list_bytes(int64_t R, int32_t M, size_t& bytes) {
+  const double b = (double)R * (double)M * 8.0 + (double)R * 4.0;
+  if (R < 0 || M < 1 || b > 9.0e18) return false;
+  bytes = (size_t)R * (size_t)M * 8u + (size_t)R * 4u;
+  return true;
+}
+
+// Validate an optional sample-list buffer and view it.
+static int list_view(const void* d_lists, size_t bytes, int64_t R, const Params& p, SampleList& L,
+                     bool& use) {
+  use = false;
+  L = {nullptr, nullptr};
+  if (!d_lists) {
+    if (bytes != 0) return fail(SG_EINVAL, "list bytes given without a list buffer");
+    return SG_OK;
+  }
+  size_t need;
+  if (!list_bytes(R, p.max_samples, need)) return fail(SG_ERANGE, "list size overflows");
+  if (bytes < need) return fail(SG_EINVAL, "list buffer smaller than sg_render_list_bytes");
+  if (reinterpret_cast<uintptr_t>(d_lists) % 8 != 0)
+    return fail(SG_EINVAL, "list buffer must be 8-byte aligned");
+  char* base = static_cast<char*>(const_cast<void*>(d_lists));
+  L.q = reinterpret_cast<int2*>(base);
+  L.counts = reinterpret_cast<int32_t*>(base + (size_t)R * p.max_samples * 8u);
+  use = true;
+  return SG_OK;
+}
+
 }  // namespace sg
 
 using namespace sg;
 
 extern "C" {
 
+size_t sg_render_list_bytes(int64_t n_rays, const sg_render_params* params) {
+  Params p;
+  if (n_rays < 0 || check_params(params, p)) return 0;
+  size_t b;
+  return list_bytes(n_rays, p.max_samples, b) ? b : 0;
+}
+
+int sg_render_march(const sg_grid* grid, const float* d_rays, int64_t n_rays,
+                    const sg_render_params* params, void* d_lists, size_t lists_bytes,
+                    sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
+  if (n_rays == 0) return SG_OK;
+  if (!d_rays || !d_lists) return fail(SG_EINVAL, "a required pointer is NULL");
+  SampleList L;
+  bool list;
+  if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
+  const GridView g = view_of(grid);
+  const Launch l = plan(n_rays, 0);
+  hipLaunchKernelGGL(k_march, dim3(l.blocks), dim3(l.threads), 0, (hipStream_t)stream, g, d_rays,
+                     n_rays, p, L);
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
 int sg_render_forward(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
                       int64_t n_rays, const sg_render_params* params, float* d_feat_out,
                       float* d_depth, float* d_normal, float* d_wsum, int32_t* d_nsamples,
-                      sg_stream stream) {
+                      const void* d_lists, size_t lists_bytes, sg_stream stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   Params p;
@@ -1025,11 +1233,20 @@ int sg_render_forward(const sg_grid* grid, const float* d_vox, int32_t C, const 
   if (!d_vox || !d_rays || !d_depth || !d_normal || !d_wsum || (C > 0 && !d_feat_out))
     return fail(SG_EINVAL, "a required pointer is NULL");
   const GridView g = view_of(grid);
-  const Launch l = plan(n_rays, sizeof(int2) * p.max_samples);
   hipStream_t s = (hipStream_t)stream;
-  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_fwd<CC>, dim3(l.blocks), dim3(l.threads), l.lds, s,
-                                      g, d_vox, d_rays, n_rays, p, d_feat_out, d_depth, d_normal,
-                                      d_wsum, d_nsamples));
+  SampleList L;
+  bool list;
+  if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
+  const Launch l = plan(n_rays, sizeof(int2) * p.max_samples);
+  if (list) {
+    SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_fwd<CC, true>), dim3(l.blocks), dim3(l.threads),
+                                        l.lds, s, g, d_vox, d_rays, n_rays, p, L, d_feat_out,
+                                        d_depth, d_normal, d_wsum, d_nsamples));
+  } else {
+    SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_fwd<CC, false>), dim3(l.blocks), dim3(l.threads),
+                                        l.lds, s, g, d_vox, d_rays, n_rays, p, L, d_feat_out,
+                                        d_depth, d_normal, d_wsum, d_nsamples));
+  }
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }
@@ -1037,7 +1254,8 @@ int sg_render_forward(const sg_grid* grid, const float* d_vox, int32_t C, const 
 int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
                        int64_t n_rays, const sg_render_params* params, const float* d_g_feat,
                        const float* d_g_depth, const float* d_g_normal, const float* d_g_wsum,
-                       float* d_grad_vox, sg_stream stream) {
+                       float* d_grad_vox, const void* d_lists, size_t lists_bytes,
+                       sg_stream stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   Params p;
@@ -1048,14 +1266,24 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   if (!d_vox || !d_rays || !d_g_depth || !d_g_normal || !d_grad_vox || (C > 0 && !d_g_feat))
     return fail(SG_EINVAL, "a required pointer is NULL");
   const GridView g = view_of(grid);
+  hipStream_t s = (hipStream_t)stream;
+  SampleList L;
+  bool list;
+  if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
   const Launch l =
       plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch));
-  hipStream_t s = (hipStream_t)stream;
   const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, nullptr};
-  SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false>), dim3(l.blocks), dim3(l.threads),
-                                      l.lds, s, g, d_vox, d_rays, n_rays, p, d_g_feat, d_g_depth,
-                                      d_g_normal, d_g_wsum, none, nullptr, nullptr, nullptr,
-                                      nullptr, nullptr, d_grad_vox, false));
+  if (list) {
+    SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, true>), dim3(l.blocks),
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        d_g_feat, d_g_depth, d_g_normal, d_g_wsum, none, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, d_grad_vox, false));
+  } else {
+    SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, false>), dim3(l.blocks),
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        d_g_feat, d_g_depth, d_g_normal, d_g_wsum, none, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, d_grad_vox, false));
+  }
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }
@@ -1065,7 +1293,7 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
                       const float* d_ref_depth, const float* d_ref_normal, float lambda_d,
                       float lambda_n, float* d_feat_out, float* d_depth, float* d_normal,
                       float* d_wsum, int32_t* d_nsamples, float* d_loss_ray, float* d_grad_vox,
-                      sg_stream stream) {
+                      const void* d_lists, size_t lists_bytes, sg_stream stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   Params p;
@@ -1079,7 +1307,11 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
       !d_grad_vox || (C > 0 && (!d_ref_feat || !d_feat_out)))
     return fail(SG_EINVAL, "a required pointer is NULL");
   const GridView g = view_of(grid);
-  // Per-wave LDS: sample list, per-sample state, scatter staging, and (when
+  hipStream_t s = (hipStream_t)stream;
+  SampleList L;
+  bool list;
+  if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
+  // Per-wave LDS: sample queue, per-sample state, scatter staging, and (when
   // four waves per workgroup still fit 64 KiB) the values pass 2 reuses.
   const size_t base =
       (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch);
@@ -1087,11 +1319,17 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   const bool keep_v = (base + vbytes) * 4 <= 64 * 1024;
   const Launch l = plan(n_rays, base + (keep_v ? vbytes : 0));
   const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, d_loss_ray};
-  hipStream_t s = (hipStream_t)stream;
-  SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true>), dim3(l.blocks), dim3(l.threads),
-                                      l.lds, s, g, d_vox, d_rays, n_rays, p, nullptr, nullptr,
-                                      nullptr, nullptr, ref, d_feat_out, d_depth, d_normal,
-                                      d_wsum, d_nsamples, d_grad_vox, keep_v));
+  if (list) {
+    SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true, true>), dim3(l.blocks),
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        nullptr, nullptr, nullptr, nullptr, ref, d_feat_out,
+                                        d_depth, d_normal, d_wsum, d_nsamples, d_grad_vox, keep_v));
+  } else {
+    SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true, false>), dim3(l.blocks),
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        nullptr, nullptr, nullptr, nullptr, ref, d_feat_out,
+                                        d_depth, d_normal, d_wsum, d_nsamples, d_grad_vox, keep_v));
+  }
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

@@ -120,7 +120,53 @@ def _check_vox(grid, vox, C):
     want(vox, "vox", torch.float32, (grid.n_blocks, 512, 1 + C), grid.device)
 
 
-def render_forward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, out=None):
+# Sample lists up to this size are made by default (memory from torch's
+# caching allocator); beyond it the shading kernels march in place.
+LISTS_AUTO_MAX = 4 << 30
+
+
+def list_bytes(n_rays: int, params) -> int:
+    """Bytes of the sample lists of n_rays rays (sg_render_list_bytes)."""
+    prm = RenderParams.of(params).c()
+    return int(lib().sg_render_list_bytes(int(n_rays), ctypes.byref(prm)))
+
+
+def march(grid: Grid, rays: torch.Tensor, params, out: torch.Tensor = None) -> torch.Tensor:
+    """Run the block march alone: the kept samples of every ray, as a uint8
+    buffer that render_forward / render_backward / render_l2_step accept as
+    `lists` for the same grid, rays and params."""
+    params = RenderParams.of(params)
+    want(rays, "rays", torch.float32, (None, 6), grid.device)
+    R = rays.shape[0]
+    nb = list_bytes(R, params)
+    if out is None:
+        out = torch.empty(max(nb, 8), dtype=torch.uint8, device=grid.device)
+    want(out, "lists", torch.uint8, (None,), grid.device)
+    prm = params.c()
+    check(lib().sg_render_march(grid.handle, ptr(rays), R, ctypes.byref(prm), ptr(out), out.numel(),
+                                stream_ptr(grid.device)), "sg_render_march")
+    return out
+
+
+def _lists(lists, grid, rays, params):
+    """(pointer, bytes, buffer) for a render call.  "auto" marches into a new
+    buffer when it is at most LISTS_AUTO_MAX bytes; None lets the shading
+    kernel march; a uint8 tensor from march() is used as given."""
+    if lists is None:
+        return None, 0, None
+    if isinstance(lists, str):
+        if lists != "auto":
+            raise ValueError("lists must be 'auto', None or a buffer from march()")
+        nb = list_bytes(rays.shape[0], params)
+        if nb == 0 or nb > LISTS_AUTO_MAX:
+            return None, 0, None
+        lists = march(grid, rays, params)
+    want(lists, "lists", torch.uint8, (None,), grid.device)
+    return ptr(lists), lists.numel(), lists
+
+
+def render_forward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, out=None,
+                   lists="auto"):
     """Colour/feature, depth, normal, weight sum and sample count per ray."""
     params = RenderParams.of(params)
     C = vox.shape[-1] - 1
@@ -135,15 +181,16 @@ def render_forward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, ou
                "wsum": torch.empty(R, dtype=torch.float32, device=dev),
                "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
     prm = params.c()
+    wp, wb, _keep = _lists(lists, grid, rays, params)
     check(lib().sg_render_forward(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
                                   ptr(out["feat"]) if C else None, ptr(out["depth"]),
                                   ptr(out["normal"]), ptr(out["wsum"]), ptr(out.get("nsamples")),
-                                  stream_ptr(dev)), "sg_render_forward")
+                                  wp, wb, stream_ptr(dev)), "sg_render_forward")
     return out
 
 
 def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g_feat, g_depth,
-                    g_normal, g_wsum=None, grad_vox=None):
+                    g_normal, g_wsum=None, grad_vox=None, lists="auto"):
     """Accumulate dL/dvox for upstream gradients of the render outputs."""
     params = RenderParams.of(params)
     C = vox.shape[-1] - 1
@@ -161,15 +208,16 @@ def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g
     else:
         want(grad_vox, "grad_vox", torch.float32, tuple(vox.shape), grid.device)
     prm = params.c()
+    wp, wb, _keep = _lists(lists, grid, rays, params)
     check(lib().sg_render_backward(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
                                    ptr(g_feat) if C else None, ptr(g_depth), ptr(g_normal),
-                                   ptr(g_wsum), ptr(grad_vox), stream_ptr(grid.device)),
+                                   ptr(g_wsum), ptr(grad_vox), wp, wb, stream_ptr(grid.device)),
           "sg_render_backward")
     return grad_vox
 
 
 def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, ref, lambda_d=0.1,
-                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False):
+                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False, lists="auto"):
     """Fused forward + squared-L2 loss + gradient (accumulated into grad_vox).
 
     ref: dict of reference "feat" [R,C], "depth" [R], "normal" [R,3].
@@ -197,12 +245,13 @@ def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, re
         want(grad_vox, "grad_vox", torch.float32, tuple(vox.shape), dev)
     loss = torch.empty(R, dtype=torch.float32, device=dev) if with_loss else None
     prm = params.c()
+    wp, wb, _keep = _lists(lists, grid, rays, params)
     check(lib().sg_render_l2_step(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
                                   ptr(ref["feat"]) if C else None, ptr(ref["depth"]),
                                   ptr(ref["normal"]), ctypes.c_float(lambda_d),
                                   ctypes.c_float(lambda_n), ptr(out["feat"]) if C else None,
                                   ptr(out["depth"]), ptr(out["normal"]), ptr(out["wsum"]),
-                                  ptr(out.get("nsamples")), ptr(loss), ptr(grad_vox),
+                                  ptr(out.get("nsamples")), ptr(loss), ptr(grad_vox), wp, wb,
                                   stream_ptr(dev)), "sg_render_l2_step")
     return (out, grad_vox, loss) if with_loss else (out, grad_vox)
 
@@ -272,14 +321,16 @@ def optim_step(kind: int, param, grad, m, v, lr, b1, b2, eps, t):
 class SdfRender(torch.autograd.Function):
     """Differentiable render: vox -> (feat, depth, normal, wsum).
 
-    The backward recomputes the samples from the grid (nothing per-sample is
-    saved) and accumulates into a freshly zeroed gradient tensor.
+    The backward recomputes the per-sample values from the grid (only the
+    sample lists of the march, which do not depend on vox, are kept from the
+    forward) and accumulates into a freshly zeroed gradient tensor.
     """
 
     @staticmethod
     def forward(ctx, vox, grid, rays, params):
-        out = render_forward(grid, vox.detach(), rays, params)
-        ctx.grid, ctx.params = grid, params
+        _, _, lists = _lists("auto", grid, rays, params)
+        out = render_forward(grid, vox.detach(), rays, params, lists=lists)
+        ctx.grid, ctx.params, ctx.lists = grid, params, lists
         ctx.save_for_backward(vox, rays)
         ctx.mark_non_differentiable(out["nsamples"])
         return out["feat"], out["depth"], out["normal"], out["wsum"], out["nsamples"]
@@ -295,7 +346,8 @@ class SdfRender(torch.autograd.Function):
         g_normal = z(R, 3) if g_normal is None else g_normal.contiguous()
         g_wsum = None if g_wsum is None else g_wsum.contiguous()
         grad = render_backward(ctx.grid, vox.detach(), rays, ctx.params, g_feat, g_depth,
-                               g_normal, g_wsum)
+                               g_normal, g_wsum, lists=ctx.lists)
+        ctx.lists = None
         return grad, None, None, None
 
 

@@ -73,13 +73,28 @@ def test_render_validation(L):
     p = RenderParamsC(0.01, 0.0, 12.0, 0.02, 128)
     fake = ctypes.c_void_p(16)
     assert L.sg_render_forward(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, fake,
-                               None, None) == -1
+                               None, None, 0, None) == -1
     assert L.sg_render_backward(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, None,
-                                fake, None) == -1
+                                fake, None, 0, None) == -1
     assert L.sg_render_footprint(None, fake, 10, ctypes.byref(p), fake, None, None) == -1
     f = ctypes.c_float
     assert L.sg_render_l2_step(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, f(0.1),
-                               f(0.05), fake, fake, fake, fake, None, None, fake, None) == -1
+                               f(0.05), fake, fake, fake, fake, None, None, fake, None, 0,
+                               None) == -1
+
+
+def test_workspace_size(L):
+    """Sample-list workspace: [R][max_samples] (k, block) int32 pairs + [R] counts."""
+    from paper_2305_13220_amd._lib import RenderParamsC
+    for R, M in ((1, 1), (65536, 128), (1254528, 1024)):
+        p = RenderParamsC(0.01, 0.0, 12.0, 0.02, M)
+        assert L.sg_render_list_bytes(R, ctypes.byref(p)) == R * M * 8 + R * 4
+    p = RenderParamsC(0.01, 0.0, 12.0, 0.02, 128)
+    assert L.sg_render_list_bytes(0, ctypes.byref(p)) == 0
+    assert L.sg_render_list_bytes(-1, ctypes.byref(p)) == 0
+    bad = RenderParamsC(0.01, 0.0, 12.0, 0.02, 0)
+    assert L.sg_render_list_bytes(10, ctypes.byref(bad)) == 0
+    assert L.sg_render_list_bytes(10, None) == 0
 
 
 def test_packed_validation(L):

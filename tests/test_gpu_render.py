@@ -340,3 +340,85 @@ def test_fused_l2_step_multichunk(sphere):
 def test_fused_l2_step_room_full_batch(room):
     w, g, vox, _ = room
     _fused_check(w, g, vox, w["rays"], seed=13, what="fused room 65536")
+
+
+def test_march_kernel_and_inkernel_march_agree(room):
+    """With a workspace the march runs as its own kernel; without, the
+    shading kernels march.  Forward outputs are bit-identical; gradients
+    agree up to the order of the float32 atomic adds."""
+    w, g, vox, rays = room
+    sg = _sg()
+    a = sg.render_forward(g, vox, rays, w["params"], lists="auto")
+    b = sg.render_forward(g, vox, rays, w["params"], lists=None)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    R = rays.shape[0]
+    gf, gd, gn, gw = (to_dev(x) for x in _upstream(R, 3, 21))
+    ga = sg.render_backward(g, vox, rays, w["params"], gf, gd, gn, gw, lists="auto")
+    gb = sg.render_backward(g, vox, rays, w["params"], gf, gd, gn, gw, lists=None)
+    torch.testing.assert_close(ga, gb, rtol=1e-5, atol=1e-6 * gb.abs().max().item())
+    ref = {"feat": a["feat"].flip(0).contiguous(), "depth": a["depth"].flip(0).contiguous(),
+           "normal": a["normal"].flip(0).contiguous()}
+    oa, fa = sg.render_l2_step(g, vox, rays, w["params"], ref, lists="auto")
+    ob, fb = sg.render_l2_step(g, vox, rays, w["params"], ref, lists=None)
+    for k in oa:
+        assert torch.equal(oa[k], ob[k]), k
+    torch.testing.assert_close(fa, fb, rtol=1e-5, atol=1e-6 * fb.abs().max().item())
+
+
+@pytest.mark.parametrize("max_samples", [1, 65, 1024])
+def test_inkernel_march_sample_caps(sphere, max_samples):
+    """The in-kernel march path (no workspace) against the oracle."""
+    w, g, vox, rays = sphere
+    prm = dict(w["params"], max_samples=max_samples)
+    sub = w["rays"][::5]
+    out = _sg().render_forward(g, vox, to_dev(sub), prm, lists=None)
+    check_forward(out, _oracle_fwd(w, sub, params=prm), what=f"in-kernel march, cap {max_samples}")
+    R = sub.shape[0]
+    gf, gd, gn, gw = _upstream(R, 3, 31)
+    grad = _sg().render_backward(g, vox, to_dev(sub), prm, to_dev(gf), to_dev(gd), to_dev(gn),
+                                 to_dev(gw), lists=None)
+    ref, mag = oracle.render_backward(w["block_coords"], w["vox"], 3, w["h"], w["origin"], sub,
+                                      prm, gf, gd, gn, gw, with_mag=True)
+    assert_close_mag(grad.cpu().numpy(), ref, mag, RTOL_BWD, f"in-kernel march bwd, cap {max_samples}")
+
+
+def test_list_buffer_validation_and_reuse(sphere):
+    w, g, vox, rays = sphere
+    sg = _sg()
+    R = rays.shape[0]
+    need = sg.list_bytes(R, w["params"])
+    assert need == R * 128 * 8 + R * 4
+    small = torch.empty(need - 1, dtype=torch.uint8, device=dev())
+    with pytest.raises(sg.SgridError):
+        sg.march(g, rays, w["params"], out=small)
+    with pytest.raises(sg.SgridError):
+        sg.render_forward(g, vox, rays, w["params"], lists=small)
+    big = torch.empty(need + 8, dtype=torch.uint8, device=dev())
+    with pytest.raises(sg.SgridError):
+        sg.march(g, rays, w["params"], out=big[1:])  # misaligned
+    lists = sg.march(g, rays, w["params"], out=big[8:])
+    ref = sg.render_forward(g, vox, rays, w["params"], lists=None)
+    # one list serves several calls
+    for _ in range(2):
+        out = sg.render_forward(g, vox, rays, w["params"], lists=lists)
+        for k in out:
+            assert torch.equal(out[k], ref[k]), k
+    n = ref["nsamples"]
+    counts = lists[R * 128 * 8:R * 128 * 8 + 4 * R].view(torch.int32)
+    assert torch.equal(counts, n)
+
+
+def test_stale_list_is_safe(sphere, room):
+    """A list made for other rays gives other values, but stays in bounds."""
+    w, g, vox, rays = sphere
+    wr, gr, voxr, raysr = room
+    sg = _sg()
+    R = rays.shape[0]
+    lists = sg.march(gr, raysr[:R].contiguous(), w["params"])
+    out = sg.render_forward(g, vox, rays, w["params"], lists=lists)
+    grad = sg.render_backward(g, vox, rays, w["params"], *(to_dev(x) for x in _upstream(R, 3, 3)),
+                              lists=lists)
+    torch.cuda.synchronize()
+    assert out["nsamples"].max().item() <= 128
+    assert grad.shape == vox.shape
