@@ -432,17 +432,23 @@ __global__ __launch_bounds__(256) void k_march(GridView g, const float* __restri
   }
 }
 
-// List prefetch: the count and first kWave entries of the wave's next ray
+// List prefetch: the count and first 2 kWave entries of the wave's next ray
 // are loaded while the current ray is processed; at the next ray they are
 // copied into the wave's LDS queue, so the shading reads LDS as it does
 // after an in-kernel march.
+// The shading kernels take the lists as separate read-only restrict
+// parameters, so the (wave-uniform) count is a scalar load whose wait is
+// deferred to its first use.
 struct ListPrefetch {
   int n = 0;
-  int2 e = make_int2(0, 0);
-  __device__ void load(const SampleList& L, int M, int64_t r, int64_t R) {
+  int2 e0 = make_int2(0, 0), e1 = make_int2(0, 0);  // entries lane and kWave + lane
+  __device__ void load(const int2* __restrict__ lq, const int32_t* __restrict__ lc, int M,
+                       int64_t r, int64_t R) {
     if (r < R) {
-      n = L.counts[r];
-      if (lane_id() < M) e = L.q[r * M + lane_id()];
+      n = lc[r];
+      const int lane = lane_id();
+      if (lane < M) e0 = lq[r * M + lane];
+      if (kWave + lane < M) e1 = lq[r * M + kWave + lane];
     }
   }
 };
@@ -452,15 +458,18 @@ struct ListPrefetch {
 // marched.  m.ov / m.dv are set whenever n > 0.
 template <bool LIST>
 __device__ __forceinline__ int ray_samples(const GridView& g, const float ray[6], const Params& p,
-                                           const SampleList& L, ListPrefetch& pf, int64_t r,
-                                           int64_t r_next, int64_t R, March& m, int2* q) {
+                                           const int2* __restrict__ lq,
+                                           const int32_t* __restrict__ lc, ListPrefetch& pf,
+                                           int64_t r, int64_t r_next, int64_t R, March& m,
+                                           int2* q) {
   if constexpr (LIST) {
     const int M = p.max_samples;
     const int n = min(max(pf.n, 0), M);  // a stale list cannot overrun its row
     const int lane = lane_id();
-    if (lane < M) q[lane] = pf.e;
-    for (int j = kWave + lane; j < n; j += kWave) q[j] = L.q[r * M + j];
-    pf.load(L, M, r_next, R);
+    if (lane < M) q[lane] = pf.e0;
+    if (kWave + lane < M) q[kWave + lane] = pf.e1;
+    for (int j = 2 * kWave + lane; j < n; j += kWave) q[j] = lq[r * M + j];
+    pf.load(lq, lc, M, r_next, R);
     wave_sync();
     if (n > 0) ray_to_voxel(g, ray, m);
     return n;
@@ -547,7 +556,8 @@ __device__ __forceinline__ void render_ray(const GridView& g, const float* __res
 template <int C, bool LIST>
 __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __restrict__ vox,
                                                     const float* __restrict__ rays, int64_t R,
-                                                    Params p, SampleList L,
+                                                    Params p, const int2* __restrict__ lq,
+                                                    const int32_t* __restrict__ lc,
                                                     float* __restrict__ feat_out,
                                                     float* __restrict__ depth,
                                                     float* __restrict__ normal,
@@ -559,10 +569,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
   int2* const q = lds_q + (int64_t)w * p.max_samples;
   RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   ListPrefetch pf;
-  if (LIST) pf.load(L, p.max_samples, rs.r, R);
+  if (LIST) pf.load(lq, lc, p.max_samples, rs.r, R);
   for (; rs.next(rays); rs.advance()) {
     March m;
-    const int n = ray_samples<LIST>(g, rs.cur, p, L, pf, rs.r, rs.r + rs.stride, R, m, q);
+    const int n = ray_samples<LIST>(g, rs.cur, p, lq, lc, pf, rs.r, rs.r + rs.stride, R, m, q);
     shade_ray<C>(g, vox, p, m, n, q, rs.r, feat_out, depth, normal, wsum, nsamples);
   }
 }
@@ -624,6 +634,11 @@ struct SampleState {
   float w, s, tn, f;  // weight, dL/dw, T_{k+1}, SDF
 };
 
+// Scatter of the adjoint into grad_vox.  Float atomics on device memory are
+// performed past the L2 (each XCD has its own L2), one request per 64-byte
+// piece of memory that an instruction touches, so the number of distinct
+// pieces per instruction is what costs.
+//
 // Per-wave LDS staging of one chunk's scatter.  During staging and merging
 // the arrays are column-major (entry [j][lane]: 64 lanes write 64
 // consecutive words); the merged sums are then compacted, row-major by head
@@ -646,9 +661,8 @@ struct BwdScratch {
 template <int C>
 __device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Cell& cell, float w,
                                               float df, const float gN[3], float inv_h,
-                                              float* __restrict__ grad_vox) {
+                                              const March& m, float* __restrict__ grad_vox) {
   constexpr int V = 1 + C;
-  constexpr int PER = 8 * V;  // scatter values per cell
   const int lane = lane_id();
   int key = -1 - lane;
   if (act) {
@@ -687,6 +701,24 @@ __device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Ce
       for (int j = 0; j < 16; ++j) mv[j] += sc->val[j * kWave + l2];
     }
   }
+  // Base voxel of each cell, relative to the first cell of the chunk and
+  // packed 10 bits per axis (-1: too far to pack; such a cell shares no
+  // corner in the merge below, which is always correct).
+  int packed = -1;
+  {
+    int32_t i[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) i[a] = (int32_t)floorf(lattice_x(m.ov[a], m.dv[a], cell.t));
+    const int first = hm ? __builtin_ctzll(hm) : 0;
+    bool fits = head;
+    int32_t d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      d[a] = i[a] - __builtin_amdgcn_readlane(i[a], first);
+      fits = fits && d[a] > -511 && d[a] < 511;
+    }
+    if (fits) packed = ((d[0] + 512) << 20) | ((d[1] + 512) << 10) | (d[2] + 512);
+  }
   wave_sync();
   // compact: row-major by head rank (all staged reads are done)
   if (head) {
@@ -695,16 +727,69 @@ __device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Ce
     for (int j = 0; j < 16; ++j) sc->val[rk * 16 + j] = mv[j];
 #pragma unroll
     for (int a = 0; a < 8; ++a) sc->off[rk * 8 + a] = mo[a];
+    sc->key[rk] = packed;
   }
   wave_sync();
-#pragma unroll 2
-  for (int idx = lane; idx < H * PER; idx += kWave) {
-    const int hh = idx / PER, rem = idx - hh * PER;
-    const int a = rem / V, ch = rem - a * V;
-    const float v = sc->val[hh * 16 + (ch == 0 ? a : 8 + a)];
-    const float mult = ch == 0 ? 1.0f : sc->gC[ch > 0 ? ch - 1 : 0];
-    const int32_t o = sc->off[hh * 8 + a];
-    unsafeAtomicAdd(grad_vox + (int64_t)o * V + ch, v * mult);
+  // Consecutive cells along a ray share corners.  The cells holding one
+  // voxel are consecutive (each coordinate of the base voxel is monotone
+  // along the ray), at most four.  The first of them takes the sums of the
+  // others (at most three cells on), the others drop that corner, so each
+  // voxel gets one atomic add per chunk.
+  if (lane < H) {
+    float tv[16];
+    bool own[8];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) tv[j] = sc->val[lane * 16 + j];
+    const int pc = sc->key[lane];
+    const int pp = lane > 0 ? sc->key[lane - 1] : -1;
+    int pn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pn[k] = lane + 1 + k < H ? sc->key[lane + 1 + k] : -1;
+    const int cx = pc >> 20, cy = (pc >> 10) & 1023, cz = pc & 1023;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int vx = cx + (a & 1), vy = cy + ((a >> 1) & 1), vz = cz + (a >> 2);
+      // corner index of voxel v in the cell packed as q, or -1
+      auto corner_in = [&](int q) {
+        if (pc < 0 || q < 0) return -1;
+        const int dx = vx - (q >> 20), dy = vy - ((q >> 10) & 1023), dz = vz - (q & 1023);
+        return ((unsigned)dx | (unsigned)dy | (unsigned)dz) <= 1u ? dx + 2 * dy + 4 * dz : -1;
+      };
+      own[a] = corner_in(pp) < 0;
+      if (own[a]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int b = corner_in(pn[k]);
+          if (b < 0) break;
+          tv[a] += sc->val[(lane + 1 + k) * 16 + b];
+          tv[8 + a] += sc->val[(lane + 1 + k) * 16 + 8 + b];
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sc->val[lane * 16 + j] = tv[j];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!own[a]) sc->off[lane * 8 + a] = -1;
+  } else {
+    wave_sync();
+  }
+  wave_sync();
+  // Lanes laid out (row, cell, x corner, channel): an instruction covers the
+  // same row of corners (fixed y and z offsets) of consecutive cells, which
+  // along a ray mostly fall in the same or neighbouring 64-byte pieces.
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    for (int idx = lane; idx < H * 2 * V; idx += kWave) {
+      const int hh = idx / (2 * V), e = idx - hh * (2 * V);
+      const int ax = e / V, ch = e - ax * V;
+      const int a = ax + 2 * t;
+      const float v = sc->val[hh * 16 + (ch == 0 ? a : 8 + a)];
+      const float mult = ch == 0 ? 1.0f : sc->gC[ch > 0 ? ch - 1 : 0];
+      const int32_t o = sc->off[hh * 8 + a];
+      if (o >= 0) unsafeAtomicAdd(grad_vox + (int64_t)o * V + ch, v * mult);
+    }
   }
   wave_sync();  // the staging arrays are rewritten by the next chunk
 }
@@ -822,7 +907,7 @@ __device__ __forceinline__ void write_outputs_and_l2_grad(
 template <int C, bool FUSED, bool LIST>
 __global__ __launch_bounds__(256) void k_render_bwd(
     GridView g, const float* __restrict__ vox, const float* __restrict__ rays, int64_t R, Params p,
-    SampleList L,
+    const int2* __restrict__ lq, const int32_t* __restrict__ lc,
     const float* __restrict__ g_feat, const float* __restrict__ g_depth,
     const float* __restrict__ g_normal, const float* __restrict__ g_wsum, L2Ref ref,
     float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
@@ -843,13 +928,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   const int M = p.max_samples;
   RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   ListPrefetch pf;
-  if (LIST) pf.load(L, M, rs.r, R);
+  if (LIST) pf.load(lq, lc, M, rs.r, R);
   for (; rs.next(rays); rs.advance()) {
     const int64_t r = rs.r;
     Upstream<C> pre, up;
     load_ray_inputs<C, FUSED>(r, g_feat, g_depth, g_normal, g_wsum, ref, pre);
     March m;
-    const int n = ray_samples<LIST>(g, rs.cur, p, L, pf, r, r + rs.stride, R, m, q);
+    const int n = ray_samples<LIST>(g, rs.cur, p, lq, lc, pf, r, r + rs.stride, R, m, q);
     if constexpr (!FUSED) {
       if (n == 0) continue;  // wave-uniform: nothing to scatter
       up = pre;
@@ -898,7 +983,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         const float e = 0.5f * expf(-fabsf(f) * p.inv_beta);
         df = dsig * (-e * p.inv_beta * p.inv_beta);
       }
-      scatter_chunk<C>(sc, act, cell, wt, df, up.gN, g.inv_h, grad_vox);
+      scatter_chunk<C>(sc, act, cell, wt, df, up.gN, g.inv_h, m, grad_vox);
       continue;
     }
     // Several chunks.  Pass 1: recompute the forward quantities of every
@@ -1000,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         const float e = 0.5f * expf(-fabsf(s.f) * p.inv_beta);
         df = dsig * (-e * p.inv_beta * p.inv_beta);
       }
-      scatter_chunk<C>(sc, act, cell, s.w, df, up.gN, g.inv_h, grad_vox);
+      scatter_chunk<C>(sc, act, cell, s.w, df, up.gN, g.inv_h, m, grad_vox);
       carry += total;
     }
   }
@@ -1240,11 +1325,11 @@ int sg_render_forward(const sg_grid* grid, const float* d_vox, int32_t C, const 
   const Launch l = plan(n_rays, sizeof(int2) * p.max_samples);
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_fwd<CC, true>), dim3(l.blocks), dim3(l.threads),
-                                        l.lds, s, g, d_vox, d_rays, n_rays, p, L, d_feat_out,
+                                        l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts, d_feat_out,
                                         d_depth, d_normal, d_wsum, d_nsamples));
   } else {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_fwd<CC, false>), dim3(l.blocks), dim3(l.threads),
-                                        l.lds, s, g, d_vox, d_rays, n_rays, p, L, d_feat_out,
+                                        l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts, d_feat_out,
                                         d_depth, d_normal, d_wsum, d_nsamples));
   }
   SG_HIP_CHECK(hipGetLastError());
@@ -1275,12 +1360,12 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, nullptr};
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, true>), dim3(l.blocks),
-                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts,
                                         d_g_feat, d_g_depth, d_g_normal, d_g_wsum, none, nullptr,
                                         nullptr, nullptr, nullptr, nullptr, d_grad_vox, false));
   } else {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, false>), dim3(l.blocks),
-                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts,
                                         d_g_feat, d_g_depth, d_g_normal, d_g_wsum, none, nullptr,
                                         nullptr, nullptr, nullptr, nullptr, d_grad_vox, false));
   }
@@ -1321,12 +1406,12 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, d_loss_ray};
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true, true>), dim3(l.blocks),
-                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts,
                                         nullptr, nullptr, nullptr, nullptr, ref, d_feat_out,
                                         d_depth, d_normal, d_wsum, d_nsamples, d_grad_vox, keep_v));
   } else {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true, false>), dim3(l.blocks),
-                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L,
+                                        dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts,
                                         nullptr, nullptr, nullptr, nullptr, ref, d_feat_out,
                                         d_depth, d_normal, d_wsum, d_nsamples, d_grad_vox, keep_v));
   }
