@@ -120,8 +120,10 @@ def _check_vox(grid, vox, C):
     want(vox, "vox", torch.float32, (grid.n_blocks, 512, 1 + C), grid.device)
 
 
-# Sample lists up to this size are made by default (memory from torch's
-# caching allocator); beyond it the shading kernels march in place.
+# Sample lists.  A single call marches in its own kernel (lists=None, the
+# default: cheapest when one kernel consumes the samples).  When several
+# calls consume the same rays (a forward and its backward), march() once and
+# pass the buffer; lists="auto" does that for one call, up to this size.
 LISTS_AUTO_MAX = 4 << 30
 
 
@@ -166,7 +168,7 @@ def _lists(lists, grid, rays, params):
 
 
 def render_forward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, out=None,
-                   lists="auto"):
+                   lists=None):
     """Colour/feature, depth, normal, weight sum and sample count per ray."""
     params = RenderParams.of(params)
     C = vox.shape[-1] - 1
@@ -190,7 +192,7 @@ def render_forward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, ou
 
 
 def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g_feat, g_depth,
-                    g_normal, g_wsum=None, grad_vox=None, lists="auto"):
+                    g_normal, g_wsum=None, grad_vox=None, lists=None):
     """Accumulate dL/dvox for upstream gradients of the render outputs."""
     params = RenderParams.of(params)
     C = vox.shape[-1] - 1
@@ -217,7 +219,7 @@ def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g
 
 
 def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, ref, lambda_d=0.1,
-                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False, lists="auto"):
+                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False, lists=None):
     """Fused forward + squared-L2 loss + gradient (accumulated into grad_vox).
 
     ref: dict of reference "feat" [R,C], "depth" [R], "normal" [R,3].
