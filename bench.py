@@ -23,7 +23,10 @@ arrivals of full-frame requests (320x240, 640x480, 1296x968 or 1920x1080,
 uniform), at 0.5x, 0.8x and 1.2x of the plain path's measured capacity,
 served (i) by the plain path, one rays + forward call per request in
 arrival order, and (ii) by packed multi-grid launches replayed from a HIP
-graph with an 8 GiB budget for in-flight outputs.  Latency = GPU completion
+graph with an 8 GiB budget for in-flight outputs, ticks of 2^20 pixels
+filled shortest-remaining-request first (with aging).  The same is repeated
+for a mix of small requests only (320x240 and 640x480), where per-call
+launches weigh more.  Latency = GPU completion
 time - arrival time; p50 / p99 over the requests of each point.
 """
 from __future__ import annotations
@@ -119,10 +122,11 @@ def cpu_baseline(w, n_rays, min_seconds=10.0, max_passes=3):
 
 
 RESOLUTIONS = ((320, 240), (640, 480), (1296, 968), (1920, 1080))
+SMALL_RESOLUTIONS = ((320, 240), (640, 480))
 
 
 def serve_bench(args, dev):
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     import paper_2305_13220_amd as sg
@@ -138,52 +142,61 @@ def serve_bench(args, dev):
         poses.append(list(cams))
         blocks.append(g.n_blocks)
     log(f"serving setup {time.perf_counter() - t0:.1f}s: blocks {blocks}")
-
-    def reqs(n, qps, k):
-        return poisson_requests(n, qps, len(grids), poses, RESOLUTIONS,
-                                seed=[0, scenes.SEED_ARRIVALS, k])
-
     plain = PlainServer(grids, 3, keep_outputs=False)
     packed = PackedServer(grids, 3, hbm_budget_bytes=int(args.serve_budget_gib * (1 << 30)),
                           keep_outputs=False)
-    plain.run(reqs(16, 1e9, 1), realtime=False)  # warm-up: code, allocator, graphs
-    packed.run(reqs(16, 1e9, 1), realtime=False)
 
-    def capacity(server, n):
-        r = reqs(n, 1e9, 2)
-        server.run(r, realtime=False)
-        st = latency_stats(r)
-        span = max(q.done for q in r) - min(q.arrival for q in r)
-        return n / span, st["rays_per_s"]
+    def scenario(name, res, sub):
+        def reqs(n, qps, k):
+            return poisson_requests(n, qps, len(grids), poses, res,
+                                    seed=[0, scenes.SEED_ARRIVALS, sub, k])
 
-    n_cal = max(16, args.serve_requests // 5)
-    cap_plain, rays_plain = capacity(plain, n_cal)
-    cap_packed, rays_packed = capacity(packed, n_cal)
-    log(f"capacity: plain {cap_plain:.1f} req/s, packed {cap_packed:.1f} req/s")
-    points = []
-    for k, load in enumerate((0.5, 0.8, 1.2)):
-        qps = load * cap_plain
-        a = reqs(args.serve_requests, qps, 10 + k)
-        plain.run(a, realtime=True)
-        b = reqs(args.serve_requests, qps, 10 + k)
-        packed.run(b, realtime=True)
-        pt = {"load": load, "qps": round(qps, 2),
-              "plain": {kk: round(v, 3) if isinstance(v, float) else v
-                        for kk, v in latency_stats(a).items()},
-              "packed": {kk: round(v, 3) if isinstance(v, float) else v
-                         for kk, v in latency_stats(b).items()}}
-        log(f"load {load}: plain p50/p99 {pt['plain']['p50_ms']}/{pt['plain']['p99_ms']} ms, "
-            f"packed {pt['packed']['p50_ms']}/{pt['packed']['p99_ms']} ms")
-        points.append(pt)
-    head = points[1]
-    return {"grids": "room 2 cm, room 1 cm, second room 2 cm (C=3)", "blocks": blocks,
-            "resolutions": [f"{w}x{h}" for w, h in RESOLUTIONS],
-            "requests_per_point": args.serve_requests,
-            "capacity_req_per_s": {"plain": round(cap_plain, 2), "packed": round(cap_packed, 2)},
-            "capacity_rays_per_s": {"plain": rays_plain, "packed": rays_packed},
-            "p50_ms_at_0.8": {"plain": head["plain"]["p50_ms"], "packed": head["packed"]["p50_ms"]},
-            "p99_ms_at_0.8": {"plain": head["plain"]["p99_ms"], "packed": head["packed"]["p99_ms"]},
-            "points": points}
+        plain.run(reqs(16, 1e9, 1), realtime=False)  # warm-up: code, allocator, graphs
+        packed.run(reqs(16, 1e9, 1), realtime=False)
+
+        def capacity(server, n):
+            r = reqs(n, 1e9, 2)
+            server.run(r, realtime=False)
+            span = max(q.done for q in r) - min(q.arrival for q in r)
+            return n / span, latency_stats(r)["rays_per_s"]
+
+        n_cal = max(16, args.serve_requests // 5)
+        cap_plain, rays_plain = capacity(plain, n_cal)
+        cap_packed, rays_packed = capacity(packed, n_cal)
+        log(f"{name}: capacity plain {cap_plain:.1f} req/s, packed {cap_packed:.1f} req/s")
+        points = []
+        for k, load in enumerate((0.5, 0.8, 1.2)):
+            qps = load * cap_plain
+            a = reqs(args.serve_requests, qps, 10 + k)
+            plain.run(a, realtime=True)
+            b = reqs(args.serve_requests, qps, 10 + k)
+            packed.run(b, realtime=True)
+            pt = {"load": load, "qps": round(qps, 2),
+                  "plain": {kk: round(v, 3) if isinstance(v, float) else v
+                            for kk, v in latency_stats(a).items()},
+                  "packed": {kk: round(v, 3) if isinstance(v, float) else v
+                             for kk, v in latency_stats(b).items()}}
+            log(f"{name} load {load}: plain p50/p99 {pt['plain']['p50_ms']}/"
+                f"{pt['plain']['p99_ms']} ms, packed {pt['packed']['p50_ms']}/"
+                f"{pt['packed']['p99_ms']} ms")
+            points.append(pt)
+        head = points[1]
+        return {"resolutions": [f"{w}x{h}" for w, h in res],
+                "requests_per_point": args.serve_requests,
+                "capacity_req_per_s": {"plain": round(cap_plain, 2), "packed": round(cap_packed, 2)},
+                "capacity_rays_per_s": {"plain": rays_plain, "packed": rays_packed},
+                "p50_ms_at_0.8": {"plain": head["plain"]["p50_ms"],
+                                  "packed": head["packed"]["p50_ms"]},
+                "p99_ms_at_0.8": {"plain": head["plain"]["p99_ms"],
+                                  "packed": head["packed"]["p99_ms"]},
+                "points": points}
+
+    out = {"grids": "room 2 cm, room 1 cm, second room 2 cm (C=3)", "blocks": blocks,
+           "packed": {"tick_rays": packed.tick_rays, "order": packed.order,
+                      "hbm_budget_gib": args.serve_budget_gib}}
+    out["full_mix"] = scenario("full mix", RESOLUTIONS, 0)
+    out["small_mix"] = scenario("small mix", SMALL_RESOLUTIONS, 1)
+    return out
 
 
 def main():

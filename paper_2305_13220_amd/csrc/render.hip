@@ -21,6 +21,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <cstddef>
+
 #include "common.h"
 
 namespace sg {
@@ -593,6 +595,62 @@ struct PackedGrid {
 };
 static_assert(sizeof(PackedGrid) <= sizeof(sg_packed_grid), "descriptor does not fit");
 
+// The kernel reads the descriptors through these mirrors, whose pointers are
+// typed global: a pointer loaded from memory is otherwise generic, and every
+// access through it would be a flat instruction.
+#define SG_GLOBAL __attribute__((address_space(1)))
+struct GridViewG {
+  const SG_GLOBAL Slot* slots;
+  uint64_t mask;
+  const SG_GLOBAL int32_t* nbr;
+  int64_t n_blocks;
+  int32_t bmin[3], bmax[3];
+  float h, inv_h;
+  float org[3];
+  const SG_GLOBAL int32_t* map;
+  int32_t mdim[3];
+};
+struct PackedGridG {
+  GridViewG view;
+  const SG_GLOBAL float* vox;
+  Params params;
+  int32_t C;
+};
+struct SlotG {
+  int32_t grid, width;
+  int64_t pixel_begin, count, ray_base;
+  float cam[16];
+  SG_GLOBAL float *feat, *depth, *normal, *wsum;
+  SG_GLOBAL int32_t* nsamples;
+};
+static_assert(sizeof(GridViewG) == sizeof(GridView) && sizeof(PackedGridG) == sizeof(PackedGrid) &&
+                  offsetof(PackedGridG, params) == offsetof(PackedGrid, params) &&
+                  offsetof(GridViewG, map) == offsetof(GridView, map),
+              "descriptor mirrors must match");
+static_assert(sizeof(SlotG) == sizeof(sg_render_slot) &&
+                  offsetof(SlotG, feat) == offsetof(sg_render_slot, feat) &&
+                  offsetof(SlotG, nsamples) == offsetof(sg_render_slot, nsamples),
+              "slot mirror must match");
+
+__device__ __forceinline__ GridView view_of(const GridViewG& x) {
+  GridView v;
+  v.slots = (const Slot*)x.slots;
+  v.mask = x.mask;
+  v.nbr = (const int32_t*)x.nbr;
+  v.n_blocks = x.n_blocks;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    v.bmin[a] = x.bmin[a];
+    v.bmax[a] = x.bmax[a];
+    v.org[a] = x.org[a];
+    v.mdim[a] = x.mdim[a];
+  }
+  v.h = x.h;
+  v.inv_h = x.inv_h;
+  v.map = (const int32_t*)x.map;
+  return v;
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_render_packed(const sg_packed_grid* __restrict__ grids,
                                                        int32_t n_grids,
@@ -606,25 +664,29 @@ __global__ __launch_bounds__(256) void k_render_packed(const sg_packed_grid* __r
   const int32_t ns = min(*d_n_slots, max_slots);
   if (ns <= 0) return;
   const int64_t total = slots[ns - 1].ray_base + slots[ns - 1].count;
+  const SlotG* sl = reinterpret_cast<const SlotG*>(slots);
   for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < total; r += (int64_t)gridDim.x * wpb) {
     int32_t lo = 0, hi = ns - 1;  // last slot with ray_base <= r
     while (lo < hi) {
       const int32_t mid = (lo + hi + 1) >> 1;
-      if (slots[mid].ray_base <= r) lo = mid;
+      if (sl[mid].ray_base <= r) lo = mid;
       else hi = mid - 1;
     }
-    const sg_render_slot& S = slots[lo];
+    const SlotG& S = sl[lo];
     const int32_t gi = S.grid;
     // slots whose ranges leave a gap: rays in the gap belong to no slot
     if (gi < 0 || gi >= n_grids || S.width <= 0 || r - S.ray_base >= S.count) continue;
     // descriptors are sg_packed_grid-sized (512 B) records, not PackedGrid-sized
-    const PackedGrid& G = *reinterpret_cast<const PackedGrid*>(grids + gi);
+    const PackedGridG& G = *reinterpret_cast<const PackedGridG*>(grids + gi);
     if (G.C != C || G.params.max_samples > q_cap) continue;
     const int64_t pix = S.pixel_begin + (r - S.ray_base);
+    // a frame has fewer than 2^31 pixels: 32-bit division
+    const uint32_t pu = (uint32_t)pix, wu = (uint32_t)S.width;
+    const uint32_t row = pu / wu;
     float ray[6];
-    pinhole_ray(S.cam, (int32_t)(pix % S.width), (int32_t)(pix / S.width), ray);
-    render_ray<C>(G.view, G.vox, G.params, ray, q, pix, S.feat, S.depth, S.normal, S.wsum,
-                  S.nsamples);
+    pinhole_ray(S.cam, (int32_t)(pu - row * wu), (int32_t)row, ray);
+    render_ray<C>(view_of(G.view), (const float*)G.vox, G.params, ray, q, pix, (float*)S.feat,
+                  (float*)S.depth, (float*)S.normal, (float*)S.wsum, (int32_t*)S.nsamples);
   }
 }
 

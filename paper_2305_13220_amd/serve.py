@@ -4,9 +4,10 @@ batching into packed multi-grid launches replayed from a HIP graph.
 A request asks for a full frame (width x height, pinhole camera) of one of
 the resident grids.  Arriving requests are admitted in order while the
 output buffers of the requests in flight fit a device-memory budget.  Every
-tick packs up to `tick_rays` pixels, taken in admission order from the
-unfinished requests (a large request spans several ticks; several requests
-share a tick), into a slot table that is copied to the device and rendered
+tick packs up to `tick_rays` pixels from the unfinished requests (a large
+request spans several ticks; several requests share a tick; by default the
+request with the fewest remaining pixels goes first, with its waiting time
+counted against its size), into a slot table that is copied to the device and rendered
 by one `sg_render_forward_packed` launch.  Two table buffers and two
 captured graphs alternate, so the host fills one table while the GPU renders
 the other.  A request completes with the tick that renders its last pixels.
@@ -103,9 +104,22 @@ class PackedServer:
     """Continuous batching of render requests into packed, graph-replayed launches."""
 
     def __init__(self, grids, C=3, hbm_budget_bytes=8 << 30, tick_rays=1 << 20, max_slots=256,
-                 use_graph=True, keep_outputs=True):
+                 use_graph=True, keep_outputs=True, order="srpt", aging_px_per_s=2e8,
+                 one_grid_per_tick=False):
         """grids: list of (Grid, vox tensor, RenderParams or dict).  With
-        keep_outputs False a request's outputs are released when it completes."""
+        keep_outputs False a request's outputs are released when it completes.
+
+        order "fifo" packs ticks in admission order; "srpt" packs the
+        admitted request with the fewest remaining pixels first, where every
+        second of waiting counts as aging_px_per_s fewer pixels (so a large
+        request is not starved).  With one_grid_per_tick a tick holds only
+        requests on the grid of its first request, so a launch works on one
+        grid's voxels (better cache reuse than mixing grids)."""
+        if order not in ("fifo", "srpt"):
+            raise ValueError("order must be 'fifo' or 'srpt'")
+        self.order = order
+        self.aging = float(aging_px_per_s)
+        self.one_grid = bool(one_grid_per_tick)
         L = lib()
         self.C = C
         self.dev = grids[0][0].device
@@ -233,18 +247,27 @@ class PackedServer:
                         time.sleep(min(wait, 0.002))
                 continue
             # pack one tick
+            if self.order == "srpt" and len(admitted) > 1:
+                t_now = clock.now()
+                admitted.sort(key=lambda e: (e[0].pixels - e[1]) - self.aging * (t_now - e[0].arrival))
             work, budget, finished, freed = [], self.tick_rays, [], 0
-            while admitted and budget > 0 and len(work) < self.max_slots:
-                req, nxt = admitted[0]
+            g0 = admitted[0][0].grid
+            k = 0
+            while k < len(admitted) and budget > 0 and len(work) < self.max_slots:
+                req, nxt = admitted[k]
+                if self.one_grid and req.grid != g0:
+                    k += 1
+                    continue
                 cnt = min(budget, req.pixels - nxt)
                 work.append((req, nxt, cnt))
                 budget -= cnt
                 if nxt + cnt == req.pixels:
-                    admitted.pop(0)
+                    admitted.pop(k)
                     finished.append(req)
                     freed += req.out_bytes(self.C)
                 else:
-                    admitted[0][1] = nxt + cnt
+                    admitted[k][1] = nxt + cnt
+                    k += 1
             ev = self.tick(work)
             inflight.append((ev, finished, freed))
         torch.cuda.synchronize()
