@@ -408,6 +408,57 @@ struct RayStream {
   __device__ void advance() { r += stride; }
 };
 
+// The same sequence of rays (first, first + stride, ...), set up in batches
+// of up to kWave: lane i loads ray i of the batch and runs march_setup on it
+// (one pass for the whole batch instead of one wave-wide pass per ray);
+// ray i is then read from lane i.
+struct BatchRays {
+  int64_t stride, R, base, r;
+  int i = 0, nb = 0;
+  float ray_l[6];
+  March m_l;
+  uint64_t okm = 0;
+  __device__ BatchRays(int64_t first, int64_t stride_, int64_t R_)
+      : stride(stride_), R(R_), base(first - (int64_t)kWave * stride_), r(first) {}
+  template <bool SETUP>
+  __device__ bool next(const float* __restrict__ rays, const GridView& g, const Params& p) {
+    if (++i >= nb) {
+      base += (int64_t)kWave * stride;
+      i = 0;
+      if (base >= R) return false;
+      nb = (int)min((int64_t)kWave, (R - base + stride - 1) / stride);
+      const int64_t rl = base + (int64_t)lane_id() * stride;
+      bool ok = false;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) ray_l[a] = 0.0f;
+      if (rl < R) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) ray_l[a] = rays[6 * rl + a];
+        if (SETUP) ok = march_setup(g, ray_l, p, m_l);
+      }
+      okm = __ballot(ok);
+    }
+    r = base + (int64_t)i * stride;
+    return true;
+  }
+  // march set-up of the current ray; false if it has no lattice range
+  __device__ bool march_of(March& m) const {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      m.ov[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_l.ov[a]), i));
+      m.dv[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m_l.dv[a]), i));
+    }
+    m.k_lo = __builtin_amdgcn_readlane(m_l.k_lo, i);
+    m.k_hi = __builtin_amdgcn_readlane(m_l.k_hi, i);
+    return (okm >> i) & 1;
+  }
+  __device__ void ray_of(float out[6]) const {
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+      out[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ray_l[a]), i));
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Sample lists.  With a caller workspace the march runs as its own light
 // kernel (few registers, so many waves per SIMD hide the dependent block
@@ -425,11 +476,11 @@ __global__ __launch_bounds__(256) void k_march(GridView g, const float* __restri
                                                Params p, SampleList L) {
   const int wpb = blockDim.x / kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
-  for (; rs.next(rays); rs.advance()) {
+  BatchRays rs((int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  while (rs.next<true>(rays, g, p)) {
     March m;
     int n = 0;
-    if (march_setup(g, rs.cur, p, m)) n = march_collect(g, m, p, L.q + rs.r * p.max_samples);
+    if (rs.march_of(m)) n = march_collect(g, m, p, L.q + rs.r * p.max_samples);
     if (lane_id() == 0) L.counts[rs.r] = n;
   }
 }
@@ -459,7 +510,7 @@ struct ListPrefetch {
 // is one (entries beyond the prefetched first kWave are read here), else
 // marched.  m.ov / m.dv are set whenever n > 0.
 template <bool LIST>
-__device__ __forceinline__ int ray_samples(const GridView& g, const float ray[6], const Params& p,
+__device__ __forceinline__ int ray_samples(const GridView& g, const BatchRays& rs, const Params& p,
                                            const int2* __restrict__ lq,
                                            const int32_t* __restrict__ lc, ListPrefetch& pf,
                                            int64_t r, int64_t r_next, int64_t R, March& m,
@@ -473,10 +524,14 @@ __device__ __forceinline__ int ray_samples(const GridView& g, const float ray[6]
     for (int j = 2 * kWave + lane; j < n; j += kWave) q[j] = lq[r * M + j];
     pf.load(lq, lc, M, r_next, R);
     wave_sync();
-    if (n > 0) ray_to_voxel(g, ray, m);
+    if (n > 0) {
+      float ray[6];
+      rs.ray_of(ray);
+      ray_to_voxel(g, ray, m);
+    }
     return n;
   } else {
-    return march_setup(g, ray, p, m) ? march_collect(g, m, p, q) : 0;
+    return rs.march_of(m) ? march_collect(g, m, p, q) : 0;
   }
 }
 
@@ -569,12 +624,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
   const int wpb = blockDim.x / kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int2* const q = lds_q + (int64_t)w * p.max_samples;
-  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  BatchRays rs((int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   ListPrefetch pf;
   if (LIST) pf.load(lq, lc, p.max_samples, rs.r, R);
-  for (; rs.next(rays); rs.advance()) {
+  while (rs.next<!LIST>(rays, g, p)) {
     March m;
-    const int n = ray_samples<LIST>(g, rs.cur, p, lq, lc, pf, rs.r, rs.r + rs.stride, R, m, q);
+    const int n = ray_samples<LIST>(g, rs, p, lq, lc, pf, rs.r, rs.r + rs.stride, R, m, q);
     shade_ray<C>(g, vox, p, m, n, q, rs.r, feat_out, depth, normal, wsum, nsamples);
   }
 }
@@ -988,15 +1043,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   // the launch has the room; otherwise pass 2 interpolates again.
   float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (4 + C) * p.max_samples;
   const int M = p.max_samples;
-  RayStream rs(rays, (int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  BatchRays rs((int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   ListPrefetch pf;
   if (LIST) pf.load(lq, lc, M, rs.r, R);
-  for (; rs.next(rays); rs.advance()) {
+  while (rs.next<!LIST>(rays, g, p)) {
     const int64_t r = rs.r;
     Upstream<C> pre, up;
     load_ray_inputs<C, FUSED>(r, g_feat, g_depth, g_normal, g_wsum, ref, pre);
     March m;
-    const int n = ray_samples<LIST>(g, rs.cur, p, lq, lc, pf, r, r + rs.stride, R, m, q);
+    const int n = ray_samples<LIST>(g, rs, p, lq, lc, pf, r, r + rs.stride, R, m, q);
     if constexpr (!FUSED) {
       if (n == 0) continue;  // wave-uniform: nothing to scatter
       up = pre;
