@@ -193,7 +193,7 @@ def serve_bench(args, dev):
 
     out = {"grids": "room 2 cm, room 1 cm, second room 2 cm (C=3)", "blocks": blocks,
            "packed": {"tick_rays": packed.tick_rays, "order": packed.order,
-                      "hbm_budget_gib": args.serve_budget_gib}}
+                      "launch": packed.launch_mode, "hbm_budget_gib": args.serve_budget_gib}}
     out["full_mix"] = scenario("full mix", RESOLUTIONS, 0)
     out["small_mix"] = scenario("small mix", SMALL_RESOLUTIONS, 1)
     return out

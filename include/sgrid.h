@@ -336,6 +336,22 @@ int sg_render_forward_packed(const sg_packed_grid* d_grids, int32_t n_grids,
                              int64_t launch_rays, sg_stream stream);
 
 /*
+ * The same over one resident grid known on the host: every slot among the
+ * first min(*d_n_slots, max_slots) is rendered on grid g with voxels d_vox
+ * and params (the slots' `grid` field is ignored).  Each pixel's result is
+ * bit-identical to sg_rays_pinhole + sg_render_forward on that pixel.  With
+ * the grid fixed per launch the kernel keeps its view in registers, which
+ * makes it as fast per ray as sg_render_forward; a server captures one
+ * launch per resident grid.  Asynchronous, allocates nothing,
+ * graph-capturable.  SG_EINVAL for a NULL pointer, an unsupported C or
+ * max_slots / launch_rays < 1.
+ */
+int sg_render_forward_slots(const sg_grid* g, const float* d_vox, int32_t C,
+                            const sg_render_params* params, const sg_render_slot* d_slots,
+                            const int32_t* d_n_slots, int32_t max_slots, int64_t launch_rays,
+                            sg_stream stream);
+
+/*
  * sg_render_footprint -- memory-traffic accounting of the render (integer,
  * exact).  For each ray writes d_counts int32 [R,3] = (S, U, K): kept
  * samples, distinct voxels read by their interpolation cells, distinct

@@ -745,6 +745,75 @@ __global__ __launch_bounds__(256) void k_render_packed(const sg_packed_grid* __r
   }
 }
 
+// Packed launch over one resident grid (the grid is a kernel argument, so
+// its view lives in scalar registers as in k_render_fwd).  Each wave sets up
+// a batch of its rays lane-parallel: slot lookup, pinhole ray and march
+// clip for ray i in lane i; the rays are then marched and shaded one by one
+// exactly as k_render_fwd does, so every pixel gets the same bits.
+template <int C>
+__global__ __launch_bounds__(256) void k_render_slots(GridView g, const float* __restrict__ vox,
+                                                      Params p,
+                                                      const sg_render_slot* __restrict__ slots,
+                                                      const int32_t* __restrict__ d_n_slots,
+                                                      int32_t max_slots) {
+  extern __shared__ int2 lds_q[];
+  const int wpb = blockDim.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int2* q = lds_q + (int64_t)w * p.max_samples;
+  const int32_t ns = min(*d_n_slots, max_slots);
+  if (ns <= 0) return;
+  const SlotG* sl = reinterpret_cast<const SlotG*>(slots);
+  const int64_t total = sl[ns - 1].ray_base + sl[ns - 1].count;
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  const int lane = lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * wpb + w; base < total; base += (int64_t)kWave * stride) {
+    const int64_t rl = base + (int64_t)lane * stride;
+    int32_t lo = 0;
+    int64_t pix = 0;
+    March ml;
+    bool ok = false, in_slot = false;
+    if (rl < total) {
+      int32_t hi = ns - 1;  // last slot with ray_base <= r
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (sl[mid].ray_base <= rl) lo = mid;
+        else hi = mid - 1;
+      }
+      const SlotG& S = sl[lo];
+      // slots whose ranges leave a gap: rays in the gap belong to no slot
+      in_slot = S.width > 0 && rl - S.ray_base < S.count;
+      if (in_slot) {
+        pix = S.pixel_begin + (rl - S.ray_base);
+        // a frame has fewer than 2^31 pixels: 32-bit division
+        const uint32_t pu = (uint32_t)pix, wu = (uint32_t)S.width;
+        const uint32_t row = pu / wu;
+        float ray[6];
+        pinhole_ray(S.cam, (int32_t)(pu - row * wu), (int32_t)row, ray);
+        ok = march_setup(g, ray, p, ml);
+      }
+    }
+    const uint64_t slot_m = __ballot(in_slot), ok_m = __ballot(ok);
+    const int nb = (int)min((int64_t)kWave, (total - base + stride - 1) / stride);
+    for (int i = 0; i < nb; ++i) {
+      if (!((slot_m >> i) & 1)) continue;
+      const SlotG& S = sl[__builtin_amdgcn_readlane(lo, i)];
+      const int64_t pi = ((int64_t)__builtin_amdgcn_readlane((int32_t)(pix >> 32), i) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int32_t)pix, i);
+      March m;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        m.ov[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ml.ov[a]), i));
+        m.dv[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ml.dv[a]), i));
+      }
+      m.k_lo = __builtin_amdgcn_readlane(ml.k_lo, i);
+      m.k_hi = __builtin_amdgcn_readlane(ml.k_hi, i);
+      const int n = ((ok_m >> i) & 1) ? march_collect(g, m, p, q) : 0;
+      shade_ray<C>(g, vox, p, m, n, q, pi, (float*)S.feat, (float*)S.depth, (float*)S.normal,
+                   (float*)S.wsum, (int32_t*)S.nsamples);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Backward.
 struct SampleState {
@@ -1572,6 +1641,27 @@ int sg_render_forward_packed(const sg_packed_grid* d_grids, int32_t n_grids,
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_packed<CC>, dim3(l.blocks), dim3(l.threads), l.lds,
                                       s, d_grids, n_grids, d_slots, d_n_slots, max_slots,
                                       max_samples_cap));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_render_forward_slots(const sg_grid* grid, const float* d_vox, int32_t C,
+                            const sg_render_params* params, const sg_render_slot* d_slots,
+                            const int32_t* d_n_slots, int32_t max_slots, int64_t launch_rays,
+                            sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (!d_vox || !d_slots || !d_n_slots) return fail(SG_EINVAL, "a required pointer is NULL");
+  if (max_slots < 1) return fail(SG_EINVAL, "max_slots must be >= 1");
+  if (launch_rays < 1) return fail(SG_EINVAL, "launch_rays must be >= 1");
+  const GridView g = view_of(grid);
+  const Launch l = plan(launch_rays, sizeof(int2) * p.max_samples);
+  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_slots<CC>, dim3(l.blocks), dim3(l.threads), l.lds,
+                                      (hipStream_t)stream, g, d_vox, p, d_slots, d_n_slots,
+                                      max_slots));
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

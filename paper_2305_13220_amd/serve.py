@@ -105,7 +105,7 @@ class PackedServer:
 
     def __init__(self, grids, C=3, hbm_budget_bytes=8 << 30, tick_rays=1 << 20, max_slots=256,
                  use_graph=True, keep_outputs=True, order="srpt", aging_px_per_s=2e8,
-                 one_grid_per_tick=False):
+                 one_grid_per_tick=False, launch="multi_grid", small_tick_rays=None):
         """grids: list of (Grid, vox tensor, RenderParams or dict).  With
         keep_outputs False a request's outputs are released when it completes.
 
@@ -114,9 +114,23 @@ class PackedServer:
         second of waiting counts as aging_px_per_s fewer pixels (so a large
         request is not starved).  With one_grid_per_tick a tick holds only
         requests on the grid of its first request, so a launch works on one
-        grid's voxels (better cache reuse than mixing grids)."""
+        grid's voxels (better cache reuse than mixing grids).
+
+        With small_tick_rays set, a tick whose first request has at most that
+        many pixels left is limited to that many pixels (and launched with a
+        grid of that size), so small requests are not held up behind a full
+        tick.
+
+        launch "per_grid" (implies one grid per tick) renders a tick with
+        sg_render_forward_slots on that grid (one captured graph per grid and
+        table); "multi_grid" with sg_render_forward_packed over the
+        descriptor table of all grids (one graph per table)."""
         if order not in ("fifo", "srpt"):
             raise ValueError("order must be 'fifo' or 'srpt'")
+        if launch not in ("per_grid", "multi_grid"):
+            raise ValueError("launch must be 'per_grid' or 'multi_grid'")
+        self.launch_mode = launch
+        one_grid_per_tick = one_grid_per_tick or launch == "per_grid"
         self.order = order
         self.aging = float(aging_px_per_s)
         self.one_grid = bool(one_grid_per_tick)
@@ -125,6 +139,8 @@ class PackedServer:
         self.dev = grids[0][0].device
         self.budget = int(hbm_budget_bytes)
         self.tick_rays = int(tick_rays)
+        self.small_tick = self.tick_rays if small_tick_rays is None else min(int(small_tick_rays),
+                                                                             self.tick_rays)
         self.max_slots = int(max_slots)
         descs = (ctypes.c_ubyte * (PACKED_GRID_BYTES * len(grids)))()
         cap = 1
@@ -138,6 +154,7 @@ class PackedServer:
                                         ctypes.byref(descs, PACKED_GRID_BYTES * i)),
                   "sg_packed_grid_desc")
         self.keep = grids  # grids and voxels must outlive the launches
+        self.grid_args = [(g, vox, RenderParams.of(prm).c()) for g, vox, prm in grids]
         self.n_grids = len(grids)
         self.q_cap = cap
         self.d_grids = torch.frombuffer(bytearray(descs), dtype=torch.uint8).to(self.dev)
@@ -148,36 +165,44 @@ class PackedServer:
         self.d_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
                         for _ in range(2)]
         self.d_count = [torch.zeros(1, dtype=torch.int32, device=self.dev) for _ in range(2)]
-        self.graphs = [None, None]
+        self.graphs = {}  # (table, grid or -1) -> captured graph
         self.use_graph = use_graph
         self.busy = [None, None]  # end event of the tick that last used each table
         self.next_b = 0
         self.keep_outputs = keep_outputs
 
-    def _launch(self, b):
+    def _launch(self, b, gi, rays):
+        if self.launch_mode == "per_grid":
+            g, vox, pc = self.grid_args[gi]
+            check(lib().sg_render_forward_slots(g.handle, ptr(vox), self.C, ctypes.byref(pc),
+                                                ptr(self.d_slots[b]), ptr(self.d_count[b]),
+                                                self.max_slots, rays, stream_ptr(self.dev)),
+                  "sg_render_forward_slots")
+            return
         check(lib().sg_render_forward_packed(ptr(self.d_grids), self.n_grids, ptr(self.d_slots[b]),
                                              ptr(self.d_count[b]), self.max_slots, self.C,
-                                             self.q_cap, self.tick_rays, stream_ptr(self.dev)),
+                                             self.q_cap, rays, stream_ptr(self.dev)),
               "sg_render_forward_packed")
 
-    def _render(self, b):
+    def _render(self, b, gi, rays):
         if not self.use_graph:
-            self._launch(b)
+            self._launch(b, gi, rays)
             return
-        if self.graphs[b] is None:
+        key = (b, gi if self.launch_mode == "per_grid" else -1, rays)
+        if key not in self.graphs:
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             s = torch.cuda.Stream(self.dev)
             s.wait_stream(torch.cuda.current_stream(self.dev))
             with torch.cuda.stream(s):
-                self._launch(b)  # warm-up outside capture
+                self._launch(b, gi, rays)  # warm-up outside capture
             torch.cuda.current_stream(self.dev).wait_stream(s)
             torch.cuda.synchronize()
             with torch.cuda.graph(g):
-                self._launch(b)
-            self.graphs[b] = g
+                self._launch(b, gi, rays)
+            self.graphs[key] = g
             torch.cuda.synchronize()
-        self.graphs[b].replay()
+        self.graphs[key].replay()
 
     def tick(self, work):
         """Render one tick: work = list of (request, pixel_begin, count).  Returns its end event."""
@@ -198,7 +223,8 @@ class PackedServer:
         self.h_count[b][0] = len(work)
         self.d_slots[b][: raw.size].copy_(self.h_slots[b][: raw.size], non_blocking=True)
         self.d_count[b].copy_(self.h_count[b], non_blocking=True)
-        self._render(b)
+        total = sum(c for _, _, c in work)
+        self._render(b, work[0][0].grid, self.small_tick if total <= self.small_tick else self.tick_rays)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         self.busy[b] = ev
@@ -221,8 +247,7 @@ class PackedServer:
                 if admitted or inflight:
                     if in_flight_bytes + need > self.budget:
                         break
-                req.out = alloc_outputs(req.pixels, self.C, self.dev)
-                in_flight_bytes += need
+                in_flight_bytes += need  # reserved now, allocated when first packed
                 admitted.append([req, 0])
                 i += 1
             # retire finished ticks
@@ -250,7 +275,9 @@ class PackedServer:
             if self.order == "srpt" and len(admitted) > 1:
                 t_now = clock.now()
                 admitted.sort(key=lambda e: (e[0].pixels - e[1]) - self.aging * (t_now - e[0].arrival))
-            work, budget, finished, freed = [], self.tick_rays, [], 0
+            first_left = admitted[0][0].pixels - admitted[0][1]
+            budget = self.small_tick if first_left <= self.small_tick else self.tick_rays
+            work, finished, freed = [], [], 0
             g0 = admitted[0][0].grid
             k = 0
             while k < len(admitted) and budget > 0 and len(work) < self.max_slots:
@@ -259,6 +286,8 @@ class PackedServer:
                     k += 1
                     continue
                 cnt = min(budget, req.pixels - nxt)
+                if req.out is None:
+                    req.out = alloc_outputs(req.pixels, self.C, self.dev)
                 work.append((req, nxt, cnt))
                 budget -= cnt
                 if nxt + cnt == req.pixels:

@@ -108,6 +108,7 @@ def test_packed_validation(L):
     assert L.sg_render_forward_packed(fake, 0, fake, fake, 4, 3, 128, 100, None) == -1
     assert L.sg_render_forward_packed(fake, 1, fake, fake, 4, 5, 128, 100, None) == -1
     assert L.sg_render_forward_packed(fake, 1, fake, fake, 4, 3, 2000, 100, None) == -1
+    assert L.sg_render_forward_slots(None, fake, 3, ctypes.byref(p), fake, fake, 4, 100, None) == -1
     # the numpy slot record matches the C struct layout
     assert SLOT_DTYPE.itemsize == ctypes.sizeof(SlotC) == 136
     assert SLOT_DTYPE.fields["cam"][1] == 32 and SLOT_DTYPE.fields["nsamples"][1] == 128

@@ -34,14 +34,18 @@ def _requests(poses, n, seed, resolutions=((64, 48), (160, 120), (97, 61))):
                             resolutions=resolutions, seed=seed)
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_packed_mix_equals_alone(resident, use_graph):
+@pytest.mark.parametrize("use_graph,launch,order", [(False, "multi_grid", "fifo"),
+                                                    (True, "multi_grid", "srpt"),
+                                                    (False, "per_grid", "srpt"),
+                                                    (True, "per_grid", "fifo")])
+def test_packed_mix_equals_alone(resident, use_graph, launch, order):
     from paper_2305_13220_amd.serve import PackedServer, PlainServer
     grids, poses = resident
     mixed = _requests(poses, 24, seed=4)
     alone = _requests(poses, 24, seed=4)
     # small ticks: requests split across ticks and share them
-    srv = PackedServer(grids, C=3, tick_rays=7000, max_slots=16, use_graph=use_graph)
+    srv = PackedServer(grids, C=3, tick_rays=7000, max_slots=16, use_graph=use_graph,
+                       launch=launch, order=order)
     srv.run(mixed, realtime=False)
     PlainServer(grids, C=3).run(alone, realtime=False)
     for a, b in zip(mixed, alone):
