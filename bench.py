@@ -199,6 +199,46 @@ def serve_bench(args, dev):
     return out
 
 
+def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
+    """SDF and gradient at the k^3 lattice points of the grid's bounding box
+    (the point-query timing of Sec. 4), one sg_query call per k.  Bytes per
+    point: 12 in, 4 + 4 + 12 out (valid, f, grad); the voxel reads are left
+    out, so the bandwidth figure is a lower bound."""
+    import torch
+    import paper_2305_13220_amd as sg
+    h = grid.voxel_size
+    bmin, bmax = block_coords.min(0), block_coords.max(0)
+    lo = [grid.origin[a] + 8 * h * float(bmin[a]) for a in range(3)]
+    hi = [grid.origin[a] + 8 * h * float(bmax[a] + 1) for a in range(3)]
+    rows = []
+    for k in ks:
+        ax = [torch.linspace(lo[a], hi[a], k, device=dev) for a in range(3)]
+        zz, yy, xx = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        pts = torch.stack([xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)], 1).contiguous()
+        del xx, yy, zz
+        m = pts.shape[0]
+        out = sg.query(grid, vox, pts, features=False)
+        torch.cuda.synchronize()
+        reps = max(3, min(200, int(2e8 // m)))
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        for _ in range(reps):
+            sg.query(grid, vox, pts, features=False, out=out)
+        e[1].record()
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1]) / reps
+        gbs = 32 * m / (ms * 1e-3) / 1e9
+        rows.append({"k": k, "points": m, "ms": round(ms, 4),
+                     "points_per_s": round(m / (ms * 1e-3), 1),
+                     "valid_frac": round(out["valid"].float().mean().item(), 4),
+                     "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        del pts, out
+    torch.cuda.empty_cache()
+    return {"what": "SDF + gradient at k^3 lattice points of the grid's bounding box "
+                    "(room 2 cm, C=3 voxels), one call", "kernel": "k_query<3>",
+            "bytes_per_point": 32, "sizes": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +248,7 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-query", action="store_true", help="skip the k^3 point-query timing")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests per arrival-rate point of the serving measurement")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -387,6 +428,8 @@ def main():
                            "traffic_backward": measured_traffic("k_render_bwd<3, false, true>",
                                                                 "room_2cm_65536")},
     }
+    if not args.no_query:
+        res["query"] = query_bench(grid, vox, w["block_coords"], dev)
     if not args.no_serve:
         res["serving"] = serve_bench(args, dev)
     if not args.no_cpu:

@@ -190,6 +190,24 @@ int sg_rays_pinhole(const float* d_cams, int32_t n_cams, const int32_t* d_pix,
                     int64_t n_rays, float* d_rays, sg_stream stream);
 
 /*
+ * sg_query -- the trilinear SDF, its closed-form gradient and the features
+ * at arbitrary world points (Eq. 17-18), the query the paper times on k^3
+ * points (Sec. 4).  For each point p of d_points float [n,3]:
+ *   x = (p - origin) * fl(1/h) in voxel units (float32, no fused
+ *   multiply-add, as the march computes it; |x| >= 2^24 or NaN: invalid);
+ *   the point is valid iff the blocks of all 8 corners of its cell are
+ *   allocated (the render's sample rule);
+ *   d_valid [n] int32 (nullable): 1 / 0; d_f [n] (nullable): f;
+ *   d_grad [n,3] (nullable): grad f in world units; d_feat [n,C] (nullable):
+ *   features.  Invalid points give 0 everywhere.
+ * Device memory owned by the caller; asynchronous; allocates nothing.
+ * SG_EINVAL for NULL d_vox / d_points, n < 0 or an unsupported C.
+ */
+int sg_query(const sg_grid* g, const float* d_vox, int32_t C, const float* d_points,
+             int64_t n_points, int32_t* d_valid, float* d_f, float* d_grad, float* d_feat,
+             sg_stream stream);
+
+/*
  * Sample lists (optional).  sg_render_march runs the block march of
  * Sec. 3.5.1 for every ray on its own and writes each ray's kept samples to
  * d_lists: [n_rays][max_samples] pairs (lattice index k, block index) in

@@ -285,21 +285,20 @@ struct Cell {
   int32_t off[8];
 };
 
-__device__ __forceinline__ void locate(const GridView& g, const March& m, const Params& p, int2 e,
-                                       Cell& c) {
-  c.t = lattice_t(p, e.x);
+// Cell of the voxel-space point x in block bi (the block of its base voxel).
+__device__ __forceinline__ void cell_at(const GridView& g, const float x[3], int32_t block,
+                                        Cell& c) {
   int32_t i[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float x = lattice_x(m.ov[a], m.dv[a], c.t);
-    const float fl = floorf(x);
+    const float fl = floorf(x[a]);
     i[a] = (int32_t)fl;
-    c.u[a] = x - fl;
+    c.u[a] = x[a] - fl;
   }
-  // Entries come from this call's march or from a caller's list buffer;
+  // Block indices come from a march, a lookup or a caller's list buffer;
   // clamping keeps a stale list from addressing outside the grid (it then
   // renders wrong values, never faults).
-  const int64_t bi = min(max((int64_t)e.y, (int64_t)0), g.n_blocks - 1);
+  const int64_t bi = min(max((int64_t)block, (int64_t)0), g.n_blocks - 1);
   const int4* row = reinterpret_cast<const int4*>(g.nbr + 8 * bi);
   const int4 n0 = row[0], n1 = row[1];
   const int32_t nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
@@ -310,6 +309,15 @@ __device__ __forceinline__ void locate(const GridView& g, const March& m, const 
     const int s = (cx >> 3) | ((cy >> 3) << 1) | ((cz >> 3) << 2);
     c.off[a] = max(nb[s], 0) * SG_BLOCK_VOXELS + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7);
   }
+}
+
+__device__ __forceinline__ void locate(const GridView& g, const March& m, const Params& p, int2 e,
+                                       Cell& c) {
+  c.t = lattice_t(p, e.x);
+  float x[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] = lattice_x(m.ov[a], m.dv[a], c.t);
+  cell_at(g, x, e.y, c);
 }
 
 // Load the 1 + C parameters of one voxel.
@@ -811,6 +819,59 @@ __global__ __launch_bounds__(256) void k_render_slots(GridView g, const float* _
       shade_ray<C>(g, vox, p, m, n, q, pi, (float*)S.feat, (float*)S.depth, (float*)S.normal,
                    (float*)S.wsum, (int32_t*)S.nsamples);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Point query (Eq. 17-18 at arbitrary points): one lane per point.  The
+// voxel-space position, its floor and the validity rule (all 8 corner
+// blocks allocated) are the march's, so a query at a sample's position
+// returns that sample's f, grad f and features.
+template <int C>
+__global__ __launch_bounds__(256) void k_query(GridView g, const float* __restrict__ vox,
+                                               const float* __restrict__ pts, int64_t m,
+                                               int32_t* __restrict__ valid_out,
+                                               float* __restrict__ f_out,
+                                               float* __restrict__ grad_out,
+                                               float* __restrict__ feat_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  float x[3];
+  bool ok = true;
+  int32_t i[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x[a] = to_voxel(pts[3 * q + a], g.org[a], g.inv_h);
+    ok = ok && (fabsf(x[a]) < kPosLimit);
+    i[a] = (int32_t)floorf(fabsf(x[a]) < kPosLimit ? x[a] : 0.0f);
+  }
+  int32_t idx = -1, nm = 0, dist = 0;
+  if (ok) {
+    const int32_t bx = i[0] >> 3, by = i[1] >> 3, bz = i[2] >> 3;
+    if (bx >= g.bmin[0] && bx <= g.bmax[0] && by >= g.bmin[1] && by <= g.bmax[1] &&
+        bz >= g.bmin[2] && bz <= g.bmax[2])
+      block_state(g, bx, by, bz, idx, nm, dist);
+  }
+  const int need = need_mask(i[0] & 7, i[1] & 7, i[2] & 7);
+  const bool valid = ok && idx >= 0 && (nm & need) == need;
+  float f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
+#pragma unroll
+  for (int ch = 0; ch < C; ++ch) col[ch] = 0.0f;
+  if (valid) {
+    Cell cell;
+    cell_at(g, x, idx, cell);
+    interpolate<C>(vox, cell, g.inv_h, f, grad, col);
+  }
+  if (valid_out) valid_out[q] = valid ? 1 : 0;
+  if (f_out) f_out[q] = f;
+  if (grad_out) {
+    grad_out[3 * q] = grad[0];
+    grad_out[3 * q + 1] = grad[1];
+    grad_out[3 * q + 2] = grad[2];
+  }
+  if (feat_out) {
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) feat_out[(int64_t)C * q + ch] = col[ch];
   }
 }
 
@@ -1662,6 +1723,25 @@ int sg_render_forward_slots(const sg_grid* grid, const float* d_vox, int32_t C,
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_slots<CC>, dim3(l.blocks), dim3(l.threads), l.lds,
                                       (hipStream_t)stream, g, d_vox, p, d_slots, d_n_slots,
                                       max_slots));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_query(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_points,
+             int64_t n_points, int32_t* d_valid, float* d_f, float* d_grad, float* d_feat,
+             sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (n_points < 0) return fail(SG_EINVAL, "n_points must be >= 0");
+  if (n_points == 0) return SG_OK;
+  if (!d_vox || !d_points) return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const int64_t blocks = (n_points + 255) / 256;
+  if (blocks > INT_MAX) return fail(SG_ERANGE, "too many points for one launch");
+  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_query<CC>, dim3((unsigned)blocks), dim3(256), 0,
+                                      (hipStream_t)stream, g, d_vox, d_points, n_points, d_valid,
+                                      d_f, d_grad, C > 0 ? d_feat : nullptr));
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

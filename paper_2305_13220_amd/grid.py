@@ -258,6 +258,34 @@ def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, re
     return (out, grad_vox, loss) if with_loss else (out, grad_vox)
 
 
+def query(grid: Grid, vox: torch.Tensor, points: torch.Tensor, features: bool = True, out=None):
+    """f, grad f and (if features) the C features at world points [m,3]
+    (Eq. 17-18), with a validity flag (all 8 corner blocks allocated).
+    Returns a dict; out may hold preallocated tensors of the same keys."""
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    want(points, "points", torch.float32, (None, 3), grid.device)
+    m = points.shape[0]
+    dev = grid.device
+    shapes = {"valid": ((m,), torch.int32), "f": ((m,), torch.float32),
+              "grad": ((m, 3), torch.float32)}
+    if features:
+        shapes["feat"] = ((m, C), torch.float32)
+    res = {}
+    for k, (shape, dt) in shapes.items():
+        t = None if out is None else out.get(k)
+        if t is None:
+            t = torch.empty(shape, dtype=dt, device=dev)
+        else:
+            want(t, k, dt, shape, dev)
+        res[k] = t
+    feat = res.get("feat")
+    check(lib().sg_query(grid.handle, ptr(vox), C, ptr(points), m, ptr(res["valid"]),
+                         ptr(res["f"]), ptr(res["grad"]), ptr(feat) if C and feat is not None
+                         else None, stream_ptr(dev)), "sg_query")
+    return res
+
+
 def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
     """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
     params = RenderParams.of(params)
