@@ -199,6 +199,72 @@ def serve_bench(args, dev):
     return out
 
 
+def frames_bench(dev, n_frames=50):
+    """Full-frame forward renders of the 1 cm room with 16 semantic logits
+    (C = 19) at 1296x968 along a seeded 50-pose trajectory: camera rays and
+    the forward render per frame, timed frame by frame with HIP events."""
+    import numpy as np
+    import torch
+    import paper_2305_13220_amd as sg
+    from synth import workloads
+    t0 = time.perf_counter()
+    w = workloads.room_1cm_sem(n_cams=n_frames)
+    C = w["vox"].shape[-1] - 1
+    W, H = w["W"], w["H"]
+    grid = sg.Grid(torch.from_numpy(w["block_coords"]).to(dev), float(w["h"]),
+                   tuple(float(x) for x in w["origin"]))
+    vox = torch.from_numpy(w["vox"]).to(dev)
+    cams = torch.from_numpy(w["cams"]).to(dev)
+    params = sg.RenderParams.of(w["params"])
+    R = W * H
+    vv, uu = torch.meshgrid(torch.arange(H, device=dev, dtype=torch.int32),
+                            torch.arange(W, device=dev, dtype=torch.int32), indexing="ij")
+    pix = [torch.stack([torch.full_like(uu, i).reshape(-1), uu.reshape(-1), vv.reshape(-1)],
+                       1).contiguous() for i in range(n_frames)]
+    out = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
+           "normal": torch.empty((R, 3), device=dev), "wsum": torch.empty(R, device=dev),
+           "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
+    rays = sg.rays_pinhole(cams, pix[0])
+    fb, S = 0, 0
+    for i in range(n_frames):
+        rays = sg.rays_pinhole(cams, pix[i])
+        c = sg.render_footprint(grid, rays, params).cpu().numpy()
+        fb += algorithmic_bytes(c, C)[0]
+        S += int(c[:, 0].astype(np.int64).sum())
+    log(f"frames setup {time.perf_counter() - t0:.1f}s: {grid.n_blocks} blocks, C={C}")
+    for _ in range(3):
+        sg.render_forward(grid, vox, sg.rays_pinhole(cams, pix[0]), params, out=out)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n_frames)]
+    for i in range(n_frames):
+        ev[i][0].record()
+        rays = sg.rays_pinhole(cams, pix[i])
+        ev[i][1].record()
+        sg.render_forward(grid, vox, rays, params, out=out)
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    frame_ms = np.array([e[0].elapsed_time(e[2]) for e in ev])
+    fwd_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    total = float(frame_ms.sum())
+    ach = fb / (fwd_ms.sum() * 1e-3) / 1e9
+    res = {"workload": "room_1cm_sem_1296x968_50_frames",
+           "scene": "room at h = 1 cm, 16 semantic logits + RGB (C = 19)",
+           "blocks": grid.n_blocks, "frames": n_frames, "rays_per_frame": R,
+           "frames_per_s": round(n_frames / (total * 1e-3), 2),
+           "rays_per_s": n_frames * R / (total * 1e-3), "samples_per_s": S / (total * 1e-3),
+           "ms_per_frame_p50": round(float(np.median(frame_ms)), 4),
+           "ms_per_frame_p99": round(float(np.percentile(frame_ms, 99)), 4),
+           "forward_kernel_ms_mean": round(float(fwd_ms.mean()), 4),
+           "mean_samples_per_ray": S / (n_frames * R),
+           "roofline_forward": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                "kernel": "k_render_fwd<19, false>",
+                                "algorithmic_bytes_per_frame": fb // n_frames}}
+    del vox, grid, out, pix
+    torch.cuda.empty_cache()
+    return res
+
+
 def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
     """SDF and gradient at the k^3 lattice points of the grid's bounding box
     (the point-query timing of Sec. 4), one sg_query call per k.  Bytes per
@@ -249,6 +315,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the k^3 point-query timing")
+    ap.add_argument("--no-frames", action="store_true",
+                    help="skip the 1 cm semantic full-frame render timing")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests per arrival-rate point of the serving measurement")
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -428,6 +496,8 @@ def main():
                            "traffic_backward": measured_traffic("k_render_bwd<3, false, true>",
                                                                 "room_2cm_65536")},
     }
+    if not args.no_frames:
+        res["frames"] = frames_bench(dev)
     if not args.no_query:
         res["query"] = query_bench(grid, vox, w["block_coords"], dev)
     if not args.no_serve:

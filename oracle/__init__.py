@@ -15,6 +15,8 @@ Every function cites the passage of the paper it follows:
     trilinear value and closed-form gradient of Eq. 17-18.
   * ``render_backward``: its adjoint with respect to the voxel parameters.
   * ``query``: SDF, gradient and features at points (Eq. 17-18).
+  * ``eikonal``: the Eikonal regulariser of Eq. 16 at points and its
+    derivative with respect to the SDF voxels.
   * ``density``: VolSDF's Laplace-CDF transform named in Sec. 3.5.1.
   * ``rays_pinhole``: inverse of the pinhole projection used in Eq. 3.
   * ``footprint``: exact counts of the voxels and blocks each ray reads.
@@ -148,6 +150,29 @@ def query(block_coords, vox, C, h, origin, points):
     _check(lib.or_query(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org), _p(pts),
                         _I64(m), _p(valid), _p(f), _p(g), _p(feat)), "query")
     return valid.astype(bool), f, g, feat[:, :C]
+
+
+def eikonal(block_coords, vox, C, h, origin, points, weight, with_mag=False):
+    """Eikonal loss weight * (|grad f| - 1)^2 per point (Eq. 16, with the
+    gradient of Eq. 18) and d(sum of losses)/d vox.
+
+    Returns (loss [m], grad_vox [n,512,1+C]) and, with with_mag, also
+    (mag_vox [n,512], gmag [m]): sums of absolute values of the gradient
+    terms per voxel, and the per-point scale of grad f.
+    """
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    pts = _c(points, np.float32).reshape(-1, 3)
+    m = pts.shape[0]
+    org = _c(origin, np.float32).reshape(3)
+    loss = np.empty(m, np.float64)
+    gv = np.zeros(vx.shape, np.float64)
+    mag = np.zeros(vx.shape[:2], np.float64)
+    gmag = np.empty(m, np.float64)
+    _check(lib.or_eikonal(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org), _p(pts),
+                          _I64(m), _D(weight), _p(loss), _p(gv), _p(mag), _p(gmag)), "eikonal")
+    return (loss, gv, mag, gmag) if with_mag else (loss, gv)
 
 
 def render_forward(block_coords, vox, C, h, origin, rays, params, with_mag=False):

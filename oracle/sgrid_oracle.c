@@ -386,6 +386,69 @@ int or_query(const int32_t* block_coords, int64_t n_blocks, const double* vox, i
   return 0;
 }
 
+/*
+ * Eikonal regulariser (Eq. 16) at points p [m,3], each with weight `weight`:
+ * loss[q] = weight * (|g| - 1)^2 with g = grad f(p) of Eq. 18 (0 for points
+ * that are not valid), and its derivative with respect to the SDF voxels.
+ * g is linear in the SDF values, g = sum_a theta_a (dr_a/du) / h, so
+ *   d loss / d theta_a = weight * 2 (|g| - 1) * (g / |g|) . (dr_a/du) / h.
+ * The direction g / |g| is undefined at g = 0; the term is taken as 0 there.
+ * grad_vox [n,512,1+C] is accumulated in channel 0; mag_vox [n,512]
+ * (nullable) accumulates the absolute values of the same terms and gmag [m]
+ * (nullable) the norm of the per-axis sums sum_a |dr_a/du| |theta_a| / h
+ * (scales for tolerances).
+ */
+int or_eikonal(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
+               float h, const float org[3], const float* p, int64_t m, double weight,
+               double* loss, double* grad_vox, double* mag_vox, double* gmag) {
+  if (C < 0 || !(h > 0)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  float inv_h = 1.0f / h;
+  const double hd = (double)h;
+  for (int64_t q = 0; q < m; ++q) {
+    float xv[3];
+    for (int a = 0; a < 3; ++a) xv[a] = (p[3 * q + a] - org[a]) * inv_h;
+    sample s;
+    loss[q] = 0.0;
+    if (gmag) gmag[q] = 0.0;
+    if (!locate(&tb, xv, &s)) continue;
+    double r[8], dr[8][3], th0[8];
+    corner_weights(s.u, r, dr);
+    for (int a = 0; a < 8; ++a)
+      th0[a] = vox[((size_t)s.blk[a] * VOX_PER_BLOCK + (size_t)s.loc[a]) * (size_t)(1 + C)];
+    /* g and its magnitude scale, from the plain sum over corners */
+    double g[3], gm2 = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+      double acc = 0.0, am = 0.0;
+      for (int a = 0; a < 8; ++a) {
+        acc += dr[a][ax] * th0[a];
+        am += fabs(dr[a][ax] * th0[a]);
+      }
+      g[ax] = acc / hd;
+      gm2 += (am / hd) * (am / hd);
+    }
+    if (gmag) gmag[q] = sqrt(gm2);
+    const double n = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    loss[q] = weight * (n - 1.0) * (n - 1.0);
+    if (!(n > 0.0)) continue;
+    const double coef = weight * 2.0 * (n - 1.0) / n;
+    for (int a = 0; a < 8; ++a) {
+      const size_t v = (size_t)s.blk[a] * VOX_PER_BLOCK + (size_t)s.loc[a];
+      double t = 0.0, tm = 0.0;
+      for (int ax = 0; ax < 3; ++ax) {
+        t += coef * g[ax] * dr[a][ax] / hd;
+        tm += fabs(coef * g[ax] * dr[a][ax] / hd);
+      }
+      grad_vox[v * (size_t)(1 + C)] += t;
+      if (mag_vox) mag_vox[v] += tm;
+    }
+  }
+  table_free(&tb);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Forward render (Eq. 12-15). */
 

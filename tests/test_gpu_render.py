@@ -55,6 +55,29 @@ def test_forward_room_full_batch(room):
     check_forward(out, _oracle_fwd(w, w["rays"]), what="room 2cm 65536 rays")
 
 
+def test_forward_room_1cm_semantic_frame():
+    """A full 1296x968 frame of the 1 cm room with 16 semantic logits (C = 19)
+    in one launch, as the full-frame benchmark renders it; 3,000 seeded rays
+    of the frame checked against the oracle, and every sample count against
+    the footprint kernel's."""
+    from synth import cameras, workloads
+    import paper_2305_13220_amd as sg
+    w = workloads.room_1cm_sem(n_cams=2)
+    W, H = w["W"], w["H"]
+    g = make_grid(w)
+    vox = to_dev(w["vox"])
+    rays_np = cameras.pixel_rays(w["cams"], cameras.frame_pixels(1, W, H))
+    rays = to_dev(rays_np)
+    out = sg.render_forward(g, vox, rays, w["params"])
+    counts = sg.render_footprint(g, rays, w["params"])
+    assert torch.equal(out["nsamples"], counts[:, 0])
+    rows = np.sort(np.random.default_rng(11).choice(H * W, 3000, replace=False))
+    o = oracle.render_forward(w["block_coords"], w["vox"], w["vox"].shape[-1] - 1, w["h"],
+                              w["origin"], rays_np[rows], w["params"], with_mag=True)
+    assert (o["nsamples"] > 0).mean() > 0.5
+    check_forward(out, o, rows=rows, what="room 1cm C=19 frame")
+
+
 @pytest.fixture(scope="module")
 def room_hash_only():
     from synth import workloads

@@ -1,0 +1,82 @@
+"""Pins of the oracle's Eikonal regulariser (Eq. 16 with the gradient of
+Eq. 18) and of its derivative with respect to the SDF voxels.
+
+* Multilinear SDF fields are reproduced exactly by trilinear interpolation,
+  so the loss at a point is weight * (|grad P(p)| - 1)^2 in closed form
+  (checked with the polynomial's own gradient, written here).  A linear field
+  of unit slope gives zero loss and zero gradient.
+* The voxel gradient equals central differences of the summed loss in
+  float64 (a dropped factor, a wrong sign or a transposed axis fails this).
+* Invalid points contribute nothing; feature channels get no gradient.
+"""
+import numpy as np
+import pytest
+
+from synth.scenes import voxel_positions
+from test_oracle_interp import _dense_blocks, _multilinear
+
+
+def _setup(seed, C=0, field=None):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / 16
+    origin = np.zeros(3, np.float32)
+    blocks = _dense_blocks((-2, -2, -2), (1, 1, 1))
+    val, grad = field or _multilinear(rng)
+    pos = voxel_positions(blocks, h, origin)
+    vox = np.empty((blocks.shape[0], 512, 1 + C))
+    vox[..., 0] = val(pos)
+    vox[..., 1:] = rng.normal(size=vox.shape[:2] + (C,))
+    pv = rng.integers(-15 * 64, 14 * 64, size=(500, 3)) / 64.0  # voxel units, exact in float32
+    p = (pv * h).astype(np.float32)
+    return rng, h, origin, blocks, vox, p, pv * h, grad
+
+
+@pytest.mark.parametrize("weight", [1.0, 0.37])
+def test_eikonal_loss_closed_form_multilinear(oracle_lib, weight):
+    _, h, origin, blocks, vox, p, pw, grad = _setup(31, C=2)
+    loss, gv = oracle_lib.eikonal(blocks, vox, 2, np.float32(h), origin, p, weight)
+    want = weight * (np.linalg.norm(grad(pw), axis=-1) - 1.0) ** 2
+    np.testing.assert_allclose(loss, want, rtol=1e-10, atol=1e-12)
+    assert not gv[..., 1:].any(), "feature channels must get no gradient"
+    assert np.abs(gv[..., 0]).sum() > 0
+
+
+def test_unit_slope_linear_field_has_zero_loss_and_gradient(oracle_lib):
+    a = np.array([0.36, -0.48, 0.8])  # |a| = 1
+    field = (lambda q: q @ a + 0.25, lambda q: np.broadcast_to(a, q.shape))
+    _, h, origin, blocks, vox, p, _, _ = _setup(32, field=field)
+    loss, gv = oracle_lib.eikonal(blocks, vox, 0, np.float32(h), origin, p, 2.0)
+    assert np.abs(loss).max() < 1e-24
+    assert np.abs(gv).max() < 1e-10
+
+
+def test_eikonal_gradient_matches_central_differences(oracle_lib):
+    rng, h, origin, blocks, vox, p, _, _ = _setup(33, C=1)
+    vox[..., 0] += 0.3 * rng.normal(size=vox.shape[:2]) * h  # not multilinear any more
+    weight = 0.8
+    _, gv = oracle_lib.eikonal(blocks, vox, 1, np.float32(h), origin, p, weight)
+    touched = np.flatnonzero(np.abs(gv[..., 0]).ravel() > 0)
+    assert touched.size > 100
+    pick = rng.choice(touched, 40, replace=False)
+    eps = 1e-6
+    for flat in pick:
+        b, v = divmod(int(flat), 512)
+        hi, lo = vox.copy(), vox.copy()
+        hi[b, v, 0] += eps
+        lo[b, v, 0] -= eps
+        lp = oracle_lib.eikonal(blocks, hi, 1, np.float32(h), origin, p, weight)[0].sum()
+        lm = oracle_lib.eikonal(blocks, lo, 1, np.float32(h), origin, p, weight)[0].sum()
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - gv[b, v, 0]) <= 1e-6 * max(1.0, abs(fd)), (b, v, fd, gv[b, v, 0])
+
+
+def test_invalid_points_contribute_nothing(oracle_lib):
+    _, h, origin, blocks, vox, p, _, _ = _setup(34)
+    bad = np.array([[np.nan, 0, 0], [5.0, 5.0, 5.0], [0, np.inf, 0]], np.float32)
+    loss, gv = oracle_lib.eikonal(blocks, vox, 0, np.float32(h), origin, bad, 1.0)
+    assert not loss.any() and not gv.any()
+    # appending invalid points changes nothing
+    l1, g1 = oracle_lib.eikonal(blocks, vox, 0, np.float32(h), origin, p, 1.0)
+    l2, g2 = oracle_lib.eikonal(blocks, vox, 0, np.float32(h), origin, np.concatenate([p, bad]), 1.0)
+    np.testing.assert_array_equal(l2[: len(p)], l1)
+    np.testing.assert_array_equal(g2, g1)
