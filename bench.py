@@ -294,10 +294,24 @@ def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
         torch.cuda.synchronize()
         ms = e[0].elapsed_time(e[1]) / reps
         gbs = 32 * m / (ms * 1e-3) / 1e9
-        rows.append({"k": k, "points": m, "ms": round(ms, 4),
-                     "points_per_s": round(m / (ms * 1e-3), 1),
-                     "valid_frac": round(out["valid"].float().mean().item(), 4),
-                     "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        row = {"k": k, "points": m, "ms": round(ms, 4),
+               "points_per_s": round(m / (ms * 1e-3), 1),
+               "valid_frac": round(out["valid"].float().mean().item(), 4),
+               "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if k == 128:
+            # Eikonal regulariser on the same points: loss per point and the
+            # scatter of its gradient into the SDF voxels
+            gv = torch.zeros_like(vox)
+            sg.eikonal(grid, vox, pts, 0.1, grad_vox=gv)
+            torch.cuda.synchronize()
+            e[0].record()
+            for _ in range(reps):
+                sg.eikonal(grid, vox, pts, 0.1, grad_vox=gv)
+            e[1].record()
+            torch.cuda.synchronize()
+            row["eikonal_ms"] = round(e[0].elapsed_time(e[1]) / reps, 4)
+            del gv
+        rows.append(row)
         del pts, out
     torch.cuda.empty_cache()
     return {"what": "SDF + gradient at k^3 lattice points of the grid's bounding box "

@@ -208,6 +208,25 @@ int sg_query(const sg_grid* g, const float* d_vox, int32_t C, const float* d_poi
              sg_stream stream);
 
 /*
+ * sg_eikonal -- the Eikonal regulariser (Eq. 16) at points, the uniform
+ * in-grid samples of the training loss, with its derivative with respect to
+ * the SDF voxels.  For each point p of d_points float [n,3], valid as in
+ * sg_query, with g = grad f(p) of Eq. 18:
+ *   d_loss [n] (nullable): weight * (|g| - 1)^2, 0 for invalid points;
+ *   d_grad_vox [n_blocks,512,1+C] (nullable): accumulates, in channel 0
+ *     only, weight * 2 (|g| - 1) (g / |g|) . grad_x r(p, corner) for each of
+ *     the 8 corners (nothing where |g| = 0, where the direction is
+ *     undefined).  Accumulated with float atomics: the caller zeroes it, the
+ *     summation order (so the last bits) is unspecified.
+ * Device memory owned by the caller; asynchronous; allocates nothing.
+ * SG_EINVAL for NULL d_vox / d_points, n < 0, a non-finite weight or an
+ * unsupported C.
+ */
+int sg_eikonal(const sg_grid* g, const float* d_vox, int32_t C, const float* d_points,
+               int64_t n_points, float weight, float* d_loss, float* d_grad_vox,
+               sg_stream stream);
+
+/*
  * Sample lists (optional).  sg_render_march runs the block march of
  * Sec. 3.5.1 for every ray on its own and writes each ray's kept samples to
  * d_lists: [n_rays][max_samples] pairs (lattice index k, block index) in

@@ -157,8 +157,9 @@ def eikonal(block_coords, vox, C, h, origin, points, weight, with_mag=False):
     gradient of Eq. 18) and d(sum of losses)/d vox.
 
     Returns (loss [m], grad_vox [n,512,1+C]) and, with with_mag, also
-    (mag_vox [n,512], gmag [m]): sums of absolute values of the gradient
-    terms per voxel, and the per-point scale of grad f.
+    (mag_vox [n,512], gmag [m]): per voxel, the summed size its gradient
+    terms can take when |grad f| moves by up to gmag; per point, the scale
+    that bounds the rounding error of grad f.
     """
     lib = _load()
     bc = _c(block_coords, np.int32).reshape(-1, 3)

@@ -393,10 +393,12 @@ int or_query(const int32_t* block_coords, int64_t n_blocks, const double* vox, i
  * g is linear in the SDF values, g = sum_a theta_a (dr_a/du) / h, so
  *   d loss / d theta_a = weight * 2 (|g| - 1) * (g / |g|) . (dr_a/du) / h.
  * The direction g / |g| is undefined at g = 0; the term is taken as 0 there.
- * grad_vox [n,512,1+C] is accumulated in channel 0; mag_vox [n,512]
- * (nullable) accumulates the absolute values of the same terms and gmag [m]
- * (nullable) the norm of the per-axis sums sum_a |dr_a/du| |theta_a| / h
- * (scales for tolerances).
+ * grad_vox [n,512,1+C] is accumulated in channel 0.  Two scales for
+ * tolerances: gmag [m] (nullable), the norm of the per-axis sums
+ * sum_a |dr_a/du| |theta_a| / h (what bounds the rounding error of g), and
+ * mag_vox [n,512] (nullable), which accumulates per term
+ * 2 weight (|(|g| - 1)| + gmag) sum_axes |dr_a/du| / h, the size the term
+ * can take when |g| moves by up to gmag (|g| - 1 cancels where |g| is near 1).
  */
 int or_eikonal(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
                float h, const float org[3], const float* p, int64_t m, double weight,
@@ -439,7 +441,7 @@ int or_eikonal(const int32_t* block_coords, int64_t n_blocks, const double* vox,
       double t = 0.0, tm = 0.0;
       for (int ax = 0; ax < 3; ++ax) {
         t += coef * g[ax] * dr[a][ax] / hd;
-        tm += fabs(coef * g[ax] * dr[a][ax] / hd);
+        tm += 2.0 * fabs(weight) * (fabs(n - 1.0) + sqrt(gm2)) * fabs(dr[a][ax]) / hd;
       }
       grad_vox[v * (size_t)(1 + C)] += t;
       if (mag_vox) mag_vox[v] += tm;

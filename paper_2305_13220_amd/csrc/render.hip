@@ -827,21 +827,14 @@ __global__ __launch_bounds__(256) void k_render_slots(GridView g, const float* _
 // voxel-space position, its floor and the validity rule (all 8 corner
 // blocks allocated) are the march's, so a query at a sample's position
 // returns that sample's f, grad f and features.
-template <int C>
-__global__ __launch_bounds__(256) void k_query(GridView g, const float* __restrict__ vox,
-                                               const float* __restrict__ pts, int64_t m,
-                                               int32_t* __restrict__ valid_out,
-                                               float* __restrict__ f_out,
-                                               float* __restrict__ grad_out,
-                                               float* __restrict__ feat_out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
+__device__ __forceinline__ bool point_cell(const GridView& g, const float* __restrict__ p,
+                                           Cell& cell) {
   float x[3];
   bool ok = true;
   int32_t i[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    x[a] = to_voxel(pts[3 * q + a], g.org[a], g.inv_h);
+    x[a] = to_voxel(p[a], g.org[a], g.inv_h);
     ok = ok && (fabsf(x[a]) < kPosLimit);
     i[a] = (int32_t)floorf(fabsf(x[a]) < kPosLimit ? x[a] : 0.0f);
   }
@@ -854,14 +847,25 @@ __global__ __launch_bounds__(256) void k_query(GridView g, const float* __restri
   }
   const int need = need_mask(i[0] & 7, i[1] & 7, i[2] & 7);
   const bool valid = ok && idx >= 0 && (nm & need) == need;
+  if (valid) cell_at(g, x, idx, cell);
+  return valid;
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_query(GridView g, const float* __restrict__ vox,
+                                               const float* __restrict__ pts, int64_t m,
+                                               int32_t* __restrict__ valid_out,
+                                               float* __restrict__ f_out,
+                                               float* __restrict__ grad_out,
+                                               float* __restrict__ feat_out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  Cell cell;
+  const bool valid = point_cell(g, pts + 3 * q, cell);
   float f = 0.0f, grad[3] = {0.0f, 0.0f, 0.0f}, col[C > 0 ? C : 1];
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) col[ch] = 0.0f;
-  if (valid) {
-    Cell cell;
-    cell_at(g, x, idx, cell);
-    interpolate<C>(vox, cell, g.inv_h, f, grad, col);
-  }
+  if (valid) interpolate<C>(vox, cell, g.inv_h, f, grad, col);
   if (valid_out) valid_out[q] = valid ? 1 : 0;
   if (f_out) f_out[q] = f;
   if (grad_out) {
@@ -873,6 +877,68 @@ __global__ __launch_bounds__(256) void k_query(GridView g, const float* __restri
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) feat_out[(int64_t)C * q + ch] = col[ch];
   }
+}
+
+// Eikonal regulariser (Eq. 16) at points: loss = weight (|g| - 1)^2 with g
+// the closed-form gradient of Eq. 18, and its derivative with respect to the
+// SDF of the 8 corners.  g is linear in the corner SDFs, one difference per
+// cell edge, so its adjoint a = weight 2 (|g| - 1) g / |g| reaches the upper
+// end of an x edge as + a_x w_y w_z / h and the lower end as the negative
+// (likewise for y and z).  Where |g| = 0 the direction is undefined and
+// nothing is scattered.  V = 1 + C floats per voxel; only the SDF channel is
+// read and written.
+__global__ __launch_bounds__(256) void k_eikonal(GridView g, const float* __restrict__ vox,
+                                                 int32_t V, const float* __restrict__ pts,
+                                                 int64_t m, float weight,
+                                                 float* __restrict__ loss_out,
+                                                 float* __restrict__ grad_vox) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  Cell cell;
+  float l = 0.0f;
+  if (point_cell(g, pts + 3 * q, cell)) {
+    const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
+                wz[2] = {1.0f - cell.u[2], cell.u[2]};
+    float sdf[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) sdf[a] = vox[(int64_t)cell.off[a] * V];
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int lo = e & 1, hi = e >> 1;
+      const int c0x = 2 * lo + 4 * hi, c0y = lo + 4 * hi, c0z = lo + 2 * hi;
+      gx += wy[lo] * wz[hi] * (sdf[c0x | 1] - sdf[c0x]);
+      gy += wx[lo] * wz[hi] * (sdf[c0y | 2] - sdf[c0y]);
+      gz += wx[lo] * wy[hi] * (sdf[c0z | 4] - sdf[c0z]);
+    }
+    gx *= g.inv_h;
+    gy *= g.inv_h;
+    gz *= g.inv_h;
+    const float n = sqrtf(gx * gx + gy * gy + gz * gz);
+    l = weight * (n - 1.0f) * (n - 1.0f);
+    if (grad_vox && n > 0.0f) {
+      const float coef = weight * 2.0f * (n - 1.0f) / n * g.inv_h;
+      const float ax = coef * gx, ay = coef * gy, az = coef * gz;
+      float d[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) d[a] = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int lo = e & 1, hi = e >> 1;
+        const int c0x = 2 * lo + 4 * hi, c0y = lo + 4 * hi, c0z = lo + 2 * hi;
+        const float ex = ax * wy[lo] * wz[hi], ey = ay * wx[lo] * wz[hi], ez = az * wx[lo] * wy[hi];
+        d[c0x | 1] += ex;
+        d[c0x] -= ex;
+        d[c0y | 2] += ey;
+        d[c0y] -= ey;
+        d[c0z | 4] += ez;
+        d[c0z] -= ez;
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a) unsafeAtomicAdd(grad_vox + (int64_t)cell.off[a] * V, d[a]);
+    }
+  }
+  if (loss_out) loss_out[q] = l;
 }
 
 // ---------------------------------------------------------------------------
@@ -1742,6 +1808,25 @@ int sg_query(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_query<CC>, dim3((unsigned)blocks), dim3(256), 0,
                                       (hipStream_t)stream, g, d_vox, d_points, n_points, d_valid,
                                       d_f, d_grad, C > 0 ? d_feat : nullptr));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_eikonal(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_points,
+               int64_t n_points, float weight, float* d_loss, float* d_grad_vox,
+               sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (!std::isfinite(weight)) return fail(SG_EINVAL, "weight must be finite");
+  if (n_points < 0) return fail(SG_EINVAL, "n_points must be >= 0");
+  if (n_points == 0) return SG_OK;
+  if (!d_vox || !d_points) return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const int64_t blocks = (n_points + 255) / 256;
+  if (blocks > INT_MAX) return fail(SG_ERANGE, "too many points for one launch");
+  hipLaunchKernelGGL(k_eikonal, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, g,
+                     d_vox, 1 + C, d_points, n_points, weight, d_loss, d_grad_vox);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

@@ -286,6 +286,23 @@ def query(grid: Grid, vox: torch.Tensor, points: torch.Tensor, features: bool = 
     return res
 
 
+def eikonal(grid: Grid, vox: torch.Tensor, points: torch.Tensor, weight: float = 1.0,
+            grad_vox=None, loss: bool = True):
+    """Eikonal loss weight * (|grad f| - 1)^2 per point (Eq. 16) and its
+    gradient accumulated into grad_vox (SDF channel).  Returns
+    (loss [m] or None, grad_vox or None)."""
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    want(points, "points", torch.float32, (None, 3), grid.device)
+    if grad_vox is not None:
+        want(grad_vox, "grad_vox", torch.float32, tuple(vox.shape), grid.device)
+    m = points.shape[0]
+    out = torch.empty(m, dtype=torch.float32, device=grid.device) if loss else None
+    check(lib().sg_eikonal(grid.handle, ptr(vox), C, ptr(points), m, ctypes.c_float(weight),
+                           ptr(out), ptr(grad_vox), stream_ptr(grid.device)), "sg_eikonal")
+    return out, grad_vox
+
+
 def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
     """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
     params = RenderParams.of(params)

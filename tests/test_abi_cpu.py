@@ -78,6 +78,7 @@ def test_render_validation(L):
                                 fake, None, 0, None) == -1
     assert L.sg_render_footprint(None, fake, 10, ctypes.byref(p), fake, None, None) == -1
     assert L.sg_query(None, fake, 3, fake, 10, None, None, None, None, None) == -1
+    assert L.sg_eikonal(None, fake, 3, fake, 10, ctypes.c_float(1.0), None, None, None) == -1
     f = ctypes.c_float
     assert L.sg_render_l2_step(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, f(0.1),
                                f(0.05), fake, fake, fake, fake, None, None, fake, None, 0,

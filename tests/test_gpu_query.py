@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import make_grid, to_dev
+from gpu_helpers import assert_close_mag, make_grid, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -123,3 +123,68 @@ def test_query_lattice_room_full_and_options():
     assert empty["f"].numel() == 0
     with pytest.raises(ValueError):
         sg.query(g, vox, pts[:10], out={"f": torch.empty(11, device="cuda")})
+
+
+def _eikonal_check(w, vox_np, C, pts, weight, what):
+    """Eikonal loss per point and the accumulated SDF gradient against the
+    oracle.  Points where |grad f| is below 1e-3 of its rounding scale are
+    dropped first (there the direction g/|g| is ill-conditioned in float32).
+    Loss: within w (2 |n - 1| d + d^2) with d = 4e-5 of that scale; voxel
+    gradient: 1e-4 of the oracle's per-voxel term scale."""
+    sg = _sg()
+    valid, _, grad, _ = oracle.query(w["block_coords"], vox_np, C, w["h"], w["origin"], pts)
+    loss_o, gv_o, mag_o, gmag = oracle.eikonal(w["block_coords"], vox_np, C, w["h"], w["origin"],
+                                               pts, weight, with_mag=True)
+    n = np.linalg.norm(grad, axis=-1)
+    keep = ~valid | (n >= 1e-3 * gmag)
+    pts, valid, n, gmag = pts[keep], valid[keep], n[keep], gmag[keep]
+    loss_o, gv_o, mag_o, _ = oracle.eikonal(w["block_coords"], vox_np, C, w["h"], w["origin"],
+                                            pts, weight, with_mag=True)
+    g = make_grid(w)
+    vox = to_dev(vox_np)
+    gv = torch.zeros_like(vox)
+    loss, _ = sg.eikonal(g, vox, to_dev(pts), weight, grad_vox=gv)
+    loss = loss.cpu().numpy()
+    d = 4e-5 * gmag
+    bound = abs(weight) * (2 * np.abs(n - 1) * d + d * d) + 1e-30
+    bad = np.abs(loss - loss_o) > bound
+    assert not bad.any(), f"{what}: {bad.sum()} losses out of tolerance"
+    assert not loss[~valid].any(), f"{what}: loss of an invalid point"
+    gv = gv.cpu().numpy()
+    assert not gv[..., 1:].any(), f"{what}: feature channels touched"
+    assert_close_mag(gv[..., 0], gv_o[..., 0], mag_o, 1e-4, f"{what}: grad_vox")
+    assert np.abs(gv_o[..., 0]).sum() > 0
+    # loss only, gradient only
+    l2, none = sg.eikonal(g, vox, to_dev(pts), weight)
+    assert none is None and torch.equal(l2.cpu(), torch.from_numpy(loss))
+    gv2 = torch.zeros_like(vox)
+    nl, _ = sg.eikonal(g, vox, to_dev(pts), weight, grad_vox=gv2, loss=False)
+    assert nl is None and gv2.abs().sum().item() > 0
+
+
+def test_eikonal_sphere():
+    from synth import workloads, scenes
+    w = workloads.sphere_tiny()
+    vox = scenes.perturb(w["vox"], w["h"], seed=3)  # not a distance field any more
+    _eikonal_check(w, vox, 3, _points(w, 30000, 4, -0.7, 0.7), 0.1, "sphere, perturbed")
+
+
+def test_eikonal_room():
+    from synth import workloads
+    w = workloads.room_2cm()
+    _eikonal_check(w, w["vox"], 3, _points(w, 60000, 5, -0.2, 6.2), 1.0, "room")
+
+
+def test_eikonal_invalid_arguments():
+    from synth import workloads
+    sg = _sg()
+    w = workloads.sphere_tiny()
+    g = make_grid(w)
+    vox = to_dev(w["vox"])
+    with pytest.raises(sg.SgridError):
+        sg.eikonal(g, vox, to_dev(np.zeros((4, 3), np.float32)), float("nan"))
+    with pytest.raises(ValueError):
+        sg.eikonal(g, vox, to_dev(np.zeros((4, 3), np.float32)),
+                   grad_vox=torch.zeros(3, device="cuda"))
+    l0, _ = sg.eikonal(g, vox, to_dev(np.zeros((0, 3), np.float32)))
+    assert l0.numel() == 0
