@@ -15,8 +15,9 @@ Every function cites the passage of the paper it follows:
     trilinear value and closed-form gradient of Eq. 17-18.
   * ``render_backward``: its adjoint with respect to the voxel parameters.
   * ``query``: SDF, gradient and features at points (Eq. 17-18).
-  * ``eikonal``: the Eikonal regulariser of Eq. 16 at points and its
-    derivative with respect to the SDF voxels.
+  * ``eikonal`` / ``eikonal_rays``: the Eikonal regulariser of Eq. 16 at
+    points or on the render's ray samples, and its derivative with respect
+    to the SDF voxels.
   * ``density``: VolSDF's Laplace-CDF transform named in Sec. 3.5.1.
   * ``rays_pinhole``: inverse of the pinhole projection used in Eq. 3.
   * ``footprint``: exact counts of the voxels and blocks each ray reads.
@@ -174,6 +175,26 @@ def eikonal(block_coords, vox, C, h, origin, points, weight, with_mag=False):
     _check(lib.or_eikonal(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org), _p(pts),
                           _I64(m), _D(weight), _p(loss), _p(gv), _p(mag), _p(gmag)), "eikonal")
     return (loss, gv, mag, gmag) if with_mag else (loss, gv)
+
+
+def eikonal_rays(block_coords, vox, C, h, origin, rays, params, weight, with_mag=False):
+    """The Eikonal term on every kept ray sample (Sec. 3.5.2 with the samples
+    of Sec. 3.5.1): loss_ray [R] = sum_k weight (|grad f(x_k)| - 1)^2 and
+    d(sum of losses)/d vox; with with_mag also the per-voxel scale of
+    ``eikonal``."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    ry = _c(rays, np.float32).reshape(-1, 6)
+    R = ry.shape[0]
+    org, gp = _geom_args(h, origin, params)
+    loss = np.empty(R, np.float64)
+    gv = np.zeros(vx.shape, np.float64)
+    mag = np.zeros(vx.shape[:2], np.float64)
+    _check(lib.or_eikonal_rays(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org),
+                               _p(ry), _I64(R), *gp, _D(weight), _p(loss), _p(gv), _p(mag)),
+           "eikonal_rays")
+    return (loss, gv, mag) if with_mag else (loss, gv)
 
 
 def render_forward(block_coords, vox, C, h, origin, rays, params, with_mag=False):

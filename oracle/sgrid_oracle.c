@@ -400,44 +400,31 @@ int or_query(const int32_t* block_coords, int64_t n_blocks, const double* vox, i
  * 2 weight (|(|g| - 1)| + gmag) sum_axes |dr_a/du| / h, the size the term
  * can take when |g| moves by up to gmag (|g| - 1 cancels where |g| is near 1).
  */
-int or_eikonal(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
-               float h, const float org[3], const float* p, int64_t m, double weight,
-               double* loss, double* grad_vox, double* mag_vox, double* gmag) {
-  if (C < 0 || !(h > 0)) return -1;
-  table tb;
-  int rc = table_make(&tb, block_coords, n_blocks);
-  if (rc) return rc;
-  float inv_h = 1.0f / h;
-  const double hd = (double)h;
-  for (int64_t q = 0; q < m; ++q) {
-    float xv[3];
-    for (int a = 0; a < 3; ++a) xv[a] = (p[3 * q + a] - org[a]) * inv_h;
-    sample s;
-    loss[q] = 0.0;
-    if (gmag) gmag[q] = 0.0;
-    if (!locate(&tb, xv, &s)) continue;
-    double r[8], dr[8][3], th0[8];
-    corner_weights(s.u, r, dr);
-    for (int a = 0; a < 8; ++a)
-      th0[a] = vox[((size_t)s.blk[a] * VOX_PER_BLOCK + (size_t)s.loc[a]) * (size_t)(1 + C)];
-    /* g and its magnitude scale, from the plain sum over corners */
-    double g[3], gm2 = 0.0;
-    for (int ax = 0; ax < 3; ++ax) {
-      double acc = 0.0, am = 0.0;
-      for (int a = 0; a < 8; ++a) {
-        acc += dr[a][ax] * th0[a];
-        am += fabs(dr[a][ax] * th0[a]);
-      }
-      g[ax] = acc / hd;
-      gm2 += (am / hd) * (am / hd);
+/* The Eikonal term of one located sample: returns weight (|g| - 1)^2 and
+ * accumulates its voxel gradient and scales (see or_eikonal). */
+static double eik_sample(const sample* s, const double* vox, int C, double hd, double weight,
+                         double* grad_vox, double* mag_vox, double* gmag) {
+  double r[8], dr[8][3], th0[8];
+  corner_weights(s->u, r, dr);
+  for (int a = 0; a < 8; ++a)
+    th0[a] = vox[((size_t)s->blk[a] * VOX_PER_BLOCK + (size_t)s->loc[a]) * (size_t)(1 + C)];
+  /* g and its magnitude scale, from the plain sum over corners */
+  double g[3], gm2 = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    double acc = 0.0, am = 0.0;
+    for (int a = 0; a < 8; ++a) {
+      acc += dr[a][ax] * th0[a];
+      am += fabs(dr[a][ax] * th0[a]);
     }
-    if (gmag) gmag[q] = sqrt(gm2);
-    const double n = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    loss[q] = weight * (n - 1.0) * (n - 1.0);
-    if (!(n > 0.0)) continue;
+    g[ax] = acc / hd;
+    gm2 += (am / hd) * (am / hd);
+  }
+  if (gmag) *gmag = sqrt(gm2);
+  const double n = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  if (n > 0.0 && grad_vox) {
     const double coef = weight * 2.0 * (n - 1.0) / n;
     for (int a = 0; a < 8; ++a) {
-      const size_t v = (size_t)s.blk[a] * VOX_PER_BLOCK + (size_t)s.loc[a];
+      const size_t v = (size_t)s->blk[a] * VOX_PER_BLOCK + (size_t)s->loc[a];
       double t = 0.0, tm = 0.0;
       for (int ax = 0; ax < 3; ++ax) {
         t += coef * g[ax] * dr[a][ax] / hd;
@@ -447,6 +434,59 @@ int or_eikonal(const int32_t* block_coords, int64_t n_blocks, const double* vox,
       if (mag_vox) mag_vox[v] += tm;
     }
   }
+  return weight * (n - 1.0) * (n - 1.0);
+}
+
+int or_eikonal(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
+               float h, const float org[3], const float* p, int64_t m, double weight,
+               double* loss, double* grad_vox, double* mag_vox, double* gmag) {
+  if (C < 0 || !(h > 0)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  float inv_h = 1.0f / h;
+  for (int64_t q = 0; q < m; ++q) {
+    float xv[3];
+    for (int a = 0; a < 3; ++a) xv[a] = (p[3 * q + a] - org[a]) * inv_h;
+    sample s;
+    loss[q] = 0.0;
+    if (gmag) gmag[q] = 0.0;
+    if (!locate(&tb, xv, &s)) continue;
+    loss[q] = eik_sample(&s, vox, C, (double)h, weight, grad_vox, mag_vox, gmag ? &gmag[q] : NULL);
+  }
+  table_free(&tb);
+  return 0;
+}
+
+/*
+ * The Eikonal term on the ray samples of the render (the "ray-based samples
+ * around surfaces" of Sec. 3.5.2): for each ray, loss_ray[r] = sum over its
+ * kept samples (the samples the render uses, Sec. 3.5.1) of
+ * weight * (|grad f(x_k)| - 1)^2, with the voxel gradient and scales of
+ * or_eikonal accumulated over all samples.
+ */
+int or_eikonal_rays(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
+                    float h, const float org[3], const float* rays, int64_t R, float step,
+                    float t_near, float t_far, float beta, int32_t max_samples, double weight,
+                    double* loss_ray, double* grad_vox, double* mag_vox) {
+  if (C < 0 || R < 0) return -1;
+  geom g;
+  if (geom_make(&g, h, org, step, t_near, t_far, beta, max_samples)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  sample* smp = (sample*)malloc((size_t)max_samples * sizeof(sample));
+  if (!smp) {
+    table_free(&tb);
+    return -3;
+  }
+  for (int64_t r = 0; r < R; ++r) {
+    int n = ray_samples(&tb, &g, rays + 6 * r, smp);
+    double l = 0.0;
+    for (int q = 0; q < n; ++q) l += eik_sample(&smp[q], vox, C, (double)h, weight, grad_vox, mag_vox, NULL);
+    loss_ray[r] = l;
+  }
+  free(smp);
   table_free(&tb);
   return 0;
 }

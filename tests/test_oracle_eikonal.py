@@ -80,3 +80,55 @@ def test_invalid_points_contribute_nothing(oracle_lib):
     l2, g2 = oracle_lib.eikonal(blocks, vox, 0, np.float32(h), origin, np.concatenate([p, bad]), 1.0)
     np.testing.assert_array_equal(l2[: len(p)], l1)
     np.testing.assert_array_equal(g2, g1)
+
+
+def _axis_rays(rng, h, n=40):
+    """Rays along +z (and -x) whose origins and samples are dyadic, so every
+    float32 sample position equals o + t d exactly."""
+    o = rng.integers(-14 * 16, 13 * 16, size=(n, 2)) / 16.0 * h
+    rz = np.zeros((n, 6), np.float32)
+    rz[:, 0], rz[:, 1], rz[:, 2], rz[:, 5] = o[:, 0], o[:, 1], -1.0, 1.0
+    rx = np.zeros((n, 6), np.float32)
+    rx[:, 1], rx[:, 2], rx[:, 0], rx[:, 3] = o[:, 0], o[:, 1], 1.0, -1.0
+    return np.concatenate([rz, rx])
+
+
+def test_ray_samples_eikonal_is_point_eikonal_at_the_samples(oracle_lib):
+    rng, h, origin, blocks, vox, _, _, _ = _setup(35, C=1)
+    vox[..., 0] += 0.3 * rng.normal(size=vox.shape[:2]) * h
+    rays = _axis_rays(rng, h)
+    params = {"step": h / 2, "t_near": 0.0, "t_far": 2.0, "beta": h, "max_samples": 200}
+    loss_r, gv_r = oracle_lib.eikonal_rays(blocks, vox, 1, np.float32(h), origin, rays, params, 0.6)
+    total = np.zeros_like(vox)
+    n_s = 0
+    for r, ray in enumerate(rays):
+        s = oracle_lib.ray_samples(blocks, np.float32(h), origin, ray, params)
+        pts = (ray[:3].astype(np.float64) + s["t"][:, None].astype(np.float64) * ray[3:]).astype(np.float32)
+        assert np.array_equal(pts.astype(np.float64),
+                              ray[:3].astype(np.float64) + s["t"][:, None] * ray[3:].astype(np.float64))
+        l, g = oracle_lib.eikonal(blocks, vox, 1, np.float32(h), origin, pts, 0.6)
+        np.testing.assert_allclose(loss_r[r], l.sum(), rtol=1e-12, atol=1e-15)
+        total += g
+        n_s += len(pts)
+    assert n_s > 1000
+    np.testing.assert_allclose(gv_r, total, rtol=1e-10, atol=1e-12)
+
+
+def test_ray_samples_eikonal_gradient_matches_central_differences(oracle_lib):
+    rng, h, origin, blocks, vox, _, _, _ = _setup(36)
+    vox[..., 0] += 0.3 * rng.normal(size=vox.shape[:2]) * h
+    rays = _axis_rays(rng, h, n=8)
+    params = {"step": h / 2, "t_near": 0.0, "t_far": 2.0, "beta": h, "max_samples": 200}
+    _, gv = oracle_lib.eikonal_rays(blocks, vox, 0, np.float32(h), origin, rays, params, 1.3)
+    touched = np.flatnonzero(np.abs(gv[..., 0]).ravel() > 0)
+    pick = rng.choice(touched, 30, replace=False)
+    eps = 1e-6
+    for flat in pick:
+        b, v = divmod(int(flat), 512)
+        hi, lo = vox.copy(), vox.copy()
+        hi[b, v, 0] += eps
+        lo[b, v, 0] -= eps
+        lp = oracle_lib.eikonal_rays(blocks, hi, 0, np.float32(h), origin, rays, params, 1.3)[0].sum()
+        lm = oracle_lib.eikonal_rays(blocks, lo, 0, np.float32(h), origin, rays, params, 1.3)[0].sum()
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - gv[b, v, 0]) <= 1e-6 * max(1.0, abs(fd)), (b, v, fd, gv[b, v, 0])
