@@ -435,6 +435,15 @@ def main():
 
     ms = run(step_fused)
     ms_sep = run(step_separate)
+
+    def step_eikonal(timed):
+        """the fused step with the Eikonal term on the ray samples (weight 0.1)"""
+        rr = sg.rays_pinhole(cams, pix)
+        grad.zero_()
+        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out,
+                          lambda_e=0.1)
+
+    ms_eik = run(step_eikonal)
     fused_each = np.array([e[0].elapsed_time(e[1]) for e in fused_ev])
     fused_ms = float(fused_each.mean())
     fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sep_ev]))
@@ -498,6 +507,7 @@ def main():
         "samples_per_s": S / (ms * 1e-3),
         "mean_samples_per_ray": S / R,
         "fused_kernel_ms": round(fused_ms, 4),
+        "ms_per_step_with_eikonal": round(ms_eik, 4),
         "roofline": roof,
         "separate_calls": {"ms_per_step": round(ms_sep, 4), "rays_per_s": R / (ms_sep * 1e-3),
                            "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),

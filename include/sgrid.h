@@ -192,7 +192,7 @@ int sg_rays_pinhole(const float* d_cams, int32_t n_cams, const int32_t* d_pix,
 /*
  * sg_query -- the trilinear SDF, its closed-form gradient and the features
  * at arbitrary world points (Eq. 17-18), the query the paper times on k^3
- * points (Sec. 4).  For each point p of d_points float [n,3]:
+ * points (Sec. 4.2).  For each point p of d_points float [n,3]:
  *   x = (p - origin) * fl(1/h) in voxel units (float32, no fused
  *   multiply-add, as the march computes it; |x| >= 2^24 or NaN: invalid);
  *   the point is valid iff the blocks of all 8 corners of its cell are
@@ -299,23 +299,29 @@ int sg_render_backward(const sg_grid* g, const float* d_vox, int32_t C,
 /*
  * sg_render_l2_step -- one training step of the rendering losses, fused:
  * forward render, squared-L2 losses of Eq. 12-14 against reference values,
- * and their gradient with respect to the voxels (Sec. 3.5.1, 3.5.4), with
+ * the Eikonal regulariser of Eq. 16 on the ray samples (Sec. 3.5.2), and
+ * their gradient with respect to the voxels (Sec. 3.5.1, 3.5.4), with
  *   L = (1/R) sum_r ( |C_r - C*_r|^2 + lambda_d (D_r - D*_r)^2
- *                     + lambda_n |N_r - N*_r|^2 ).
+ *                     + lambda_n |N_r - N*_r|^2
+ *                     + lambda_e sum_k (|grad f(x_rk)| - 1)^2 ),
+ * the last sum over the ray's kept samples.
  * Writes the forward outputs exactly as sg_render_forward does (bit for
  * bit), d_loss_ray[r] (nullable, [R]) = ray r's term of L (so L is their
- * sum), and ACCUMULATES dL/dvox into d_grad_vox [n_blocks,512,1+C] exactly as
- * sg_l2_loss_grad followed by sg_render_backward would (up to the order of
- * the float32 atomic adds).  Each ray is marched and its corners gathered
- * once.  d_ref_feat [R,C] (nullable iff C == 0), d_ref_depth [R],
- * d_ref_normal [R,3].
+ * sum), and ACCUMULATES dL/dvox into d_grad_vox [n_blocks,512,1+C] as
+ * sg_l2_loss_grad followed by sg_render_backward would, plus, for
+ * lambda_e != 0, the gradient of the Eikonal term as sg_eikonal gives it at
+ * each sample (up to rounding and the order of the float32 atomic adds).
+ * Each ray is marched and its corners gathered once.  d_ref_feat [R,C]
+ * (nullable iff C == 0), d_ref_depth [R], d_ref_normal [R,3].  SG_EINVAL
+ * also for a non-finite lambda.
  */
 int sg_render_l2_step(const sg_grid* g, const float* d_vox, int32_t C, const float* d_rays,
                       int64_t n_rays, const sg_render_params* params, const float* d_ref_feat,
                       const float* d_ref_depth, const float* d_ref_normal, float lambda_d,
-                      float lambda_n, float* d_feat_out, float* d_depth, float* d_normal,
-                      float* d_wsum, int32_t* d_nsamples, float* d_loss_ray, float* d_grad_vox,
-                      const void* d_lists, size_t lists_bytes, sg_stream stream);
+                      float lambda_n, float lambda_e, float* d_feat_out, float* d_depth,
+                      float* d_normal, float* d_wsum, int32_t* d_nsamples, float* d_loss_ray,
+                      float* d_grad_vox, const void* d_lists, size_t lists_bytes,
+                      sg_stream stream);
 
 /*
  * Packed multi-grid rendering for a render server.  A launch renders the

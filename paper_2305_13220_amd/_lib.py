@@ -62,7 +62,7 @@ _SIGNATURES = {
     "sg_packed_grid_desc": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "sg_render_forward_packed": ([_vp, _i32, _vp, _vp, _i32, _i32, _i32, _i64, _vp], ctypes.c_int),
     "sg_render_forward_slots": ([_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i64, _vp], ctypes.c_int),
-    "sg_render_l2_step": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _f, _f, _vp, _vp, _vp,
+    "sg_render_l2_step": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _f, _f, _f, _vp, _vp, _vp,
                            _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "sg_l2_loss_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _f, _f, _vp, _vp, _vp, _vp, _vp],
                         ctypes.c_int),

@@ -964,8 +964,9 @@ struct BwdScratch {
 };
 
 // Adjoint scatter of one chunk.  Lane holds a sample (act) with its cell,
-// weight w and dL/df; the per-corner terms
-//   dL/dtheta_d[a] += r_a dL/df + w (dr_a/du . g_N) / h      (Eq. 17-18)
+// weight w, dL/df and gA = dL/d(grad f) of the sample (w g_N from the normal
+// output, plus the Eikonal term where it is on); the per-corner terms
+//   dL/dtheta_d[a] += r_a dL/df + (dr_a/du . gA) / h      (Eq. 17-18)
 //   dL/dtheta_c[a] += w r_a g_C
 // are staged in LDS, runs of lanes in one cell are merged (positions are
 // monotone per axis, so a cell's samples are adjacent in either lane
@@ -973,7 +974,7 @@ struct BwdScratch {
 // corner, channel) so that each atomic instruction covers few lines.
 template <int C>
 __device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Cell& cell, float w,
-                                              float df, const float gN[3], float inv_h,
+                                              float df, const float gA[3], float inv_h,
                                               const March& m, float* __restrict__ grad_vox) {
   constexpr int V = 1 + C;
   const int lane = lane_id();
@@ -981,15 +982,15 @@ __device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Ce
   if (act) {
     const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
                 wz[2] = {1.0f - cell.u[2], cell.u[2]};
-    const float wih = w * inv_h;
+    const float gx = gA[0] * inv_h, gy = gA[1] * inv_h, gz = gA[2] * inv_h;
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       const float ra = wx[ax] * wy[ay] * wz[az];
-      const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gN[0] +
-                       (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gN[1] +
-                       (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gN[2];
-      sc->val[a * kWave + lane] = ra * df + wih * gn;
+      const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gx +
+                       (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gy +
+                       (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gz;
+      sc->val[a * kWave + lane] = ra * df + gn;
       sc->val[(8 + a) * kWave + lane] = w * ra;
       sc->off[a * kWave + lane] = cell.off[a];
     }
@@ -1118,14 +1119,24 @@ __device__ __forceinline__ float wave_exclusive_suffix_sum(float v) {
 
 // Reference values of the squared-L2 rendering losses (Eq. 12-14) for the
 // fused training step; L = (1/R) sum_r |C - C*|^2 + lambda_d (D - D*)^2 +
-// lambda_n |N - N*|^2.
+// lambda_n |N - N*|^2 + lambda_e sum_k (|grad f(x_k)| - 1)^2 (the Eikonal
+// term of Eq. 16 on the ray's samples).
 struct L2Ref {
   const float* feat;    // [R,C]
   const float* depth;   // [R]
   const float* normal;  // [R,3]
-  float lambda_d, lambda_n;
+  float lambda_d, lambda_n, lambda_e;
   float* loss_ray;      // [R] nullable: each ray's term of L
 };
+
+// Eikonal term of one sample with gradient g: adds (|g| - 1)^2 to eik and
+// returns the factor c of its adjoint, dL/dg = c g, for weight lam (0 where
+// |g| = 0: the direction is undefined there).
+__device__ __forceinline__ float eikonal_sample(const float g[3], float lam, float& eik) {
+  const float n = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  eik += (n - 1.0f) * (n - 1.0f);
+  return n > 0.0f ? lam * 2.0f * (n - 1.0f) / n : 0.0f;
+}
 
 // Upstream gradients g = dL/d(feat, depth, normal, wsum) of one ray.
 template <int C>
@@ -1172,7 +1183,7 @@ __device__ __forceinline__ void write_outputs_and_l2_grad(
     int64_t r, int64_t R, int n, float accC[C > 0 ? C : 1], float accD, float accN[3], float accW,
     float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
     float* __restrict__ wsum, int32_t* __restrict__ nsamples, const L2Ref& ref,
-    const Upstream<C>& refv, Upstream<C>& up, BwdScratch* sc) {
+    const Upstream<C>& refv, Upstream<C>& up, BwdScratch* sc, float eik) {
   const int lane = lane_id();
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
@@ -1198,6 +1209,7 @@ __device__ __forceinline__ void write_outputs_and_l2_grad(
     up.gN[a] = s2 * ref.lambda_n * dn;
     loss += ref.lambda_n * dn * dn;
   }
+  if (ref.lambda_e != 0.0f) loss += ref.lambda_e * wave_sum(eik);
   up.gW = 0.0f;
   stage_gC<C>(up, sc);
   if (lane == 0) {
@@ -1274,15 +1286,17 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         wt = expf(-excl) * -expm1f(-sd);
         tn = expf(-incl);
       }
+      float ce = 0.0f;  // Eikonal adjoint factor of this sample
       if constexpr (FUSED) {
-        float accC[C > 0 ? C : 1], accN[3];
+        float accC[C > 0 ? C : 1], accN[3], eik = 0.0f;
 #pragma unroll
         for (int ch = 0; ch < C; ++ch) accC[ch] = wt * col[ch];
         accN[0] = wt * grad[0];
         accN[1] = wt * grad[1];
         accN[2] = wt * grad[2];
+        if (ref.lambda_e != 0.0f && act) ce = eikonal_sample(grad, ref.lambda_e * (1.0f / (float)R), eik);
         write_outputs_and_l2_grad<C>(r, R, n, accC, wt * cell.t, accN, wt, feat_out, depth, normal,
-                                     wsum, nsamples, ref, pre, up, sc);
+                                     wsum, nsamples, ref, pre, up, sc, eik);
         if (n == 0) continue;
       }
       float s = up.gD * cell.t + up.gW + up.gN[0] * grad[0] + up.gN[1] * grad[1] +
@@ -1296,7 +1310,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         const float e = 0.5f * expf(-fabsf(f) * p.inv_beta);
         df = dsig * (-e * p.inv_beta * p.inv_beta);
       }
-      scatter_chunk<C>(sc, act, cell, wt, df, up.gN, g.inv_h, m, grad_vox);
+      const float gA[3] = {wt * up.gN[0] + ce * grad[0], wt * up.gN[1] + ce * grad[1],
+                           wt * up.gN[2] + ce * grad[2]};
+      scatter_chunk<C>(sc, act, cell, wt, df, gA, g.inv_h, m, grad_vox);
       continue;
     }
     // Several chunks.  Pass 1: recompute the forward quantities of every
@@ -1304,7 +1320,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
     float accC[C > 0 ? C : 1], accD = 0.0f, accN[3] = {0.0f, 0.0f, 0.0f}, accW = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
-    float tau = 0.0f;
+    float tau = 0.0f, eik = 0.0f;
     for (int c0 = 0; c0 < n; c0 += kWave) {
       const int j = c0 + lane;
       const bool act = j < n;
@@ -1340,6 +1356,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
           accN[1] += s.w * grad[1];
           accN[2] += s.w * grad[2];
           accW += s.w;
+          if (ref.lambda_e != 0.0f) eikonal_sample(grad, 0.0f, eik);
           s.s = 0.0f;  // formed in pass 2, once the outputs are known
         } else {
           float dw = up.gD * cell.t + up.gW + up.gN[0] * grad[0] + up.gN[1] * grad[1] +
@@ -1354,7 +1371,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
     }
     if constexpr (FUSED)
       write_outputs_and_l2_grad<C>(r, R, n, accC, accD, accN, accW, feat_out, depth, normal, wsum,
-                                   nsamples, ref, pre, up, sc);
+                                   nsamples, ref, pre, up, sc, eik);
     wave_sync();
     // Pass 2: chunks in reverse with lanes in reverse sample order (lane l
     // holds sample c0 + 63 - l), so sum_{j>k} w_j s_j is an exclusive prefix
@@ -1367,9 +1384,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       SampleState s = {0.0f, 0.0f, 0.0f, 0.0f};
       Cell cell;
       cell.t = 0.0f;
+      float gA[3] = {0.0f, 0.0f, 0.0f};
       if (act) {
         s = st[j];
         locate(g, m, p, q[j], cell);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gA[a] = s.w * up.gN[a];
         if constexpr (FUSED) {
           float f, grad[3], col[C > 0 ? C : 1];
           if (keep_v) {
@@ -1386,6 +1406,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(
 #pragma unroll
           for (int ch = 0; ch < C; ++ch) dw += up.gC[ch] * col[ch];
           s.s = dw;
+          if (ref.lambda_e != 0.0f) {
+            float unused = 0.0f;
+            const float ce = eikonal_sample(grad, ref.lambda_e * (1.0f / (float)R), unused);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gA[a] += ce * grad[a];
+          }
         }
       }
       const float ws = s.w * s.s;
@@ -1398,7 +1424,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         const float e = 0.5f * expf(-fabsf(s.f) * p.inv_beta);
         df = dsig * (-e * p.inv_beta * p.inv_beta);
       }
-      scatter_chunk<C>(sc, act, cell, s.w, df, up.gN, g.inv_h, m, grad_vox);
+      scatter_chunk<C>(sc, act, cell, s.w, df, gA, g.inv_h, m, grad_vox);
       carry += total;
     }
   }
@@ -1670,7 +1696,7 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
   const Launch l =
       plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch));
-  const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, nullptr};
+  const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f, nullptr};
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, true>), dim3(l.blocks),
                                         dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts,
@@ -1689,9 +1715,10 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
 int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
                       int64_t n_rays, const sg_render_params* params, const float* d_ref_feat,
                       const float* d_ref_depth, const float* d_ref_normal, float lambda_d,
-                      float lambda_n, float* d_feat_out, float* d_depth, float* d_normal,
-                      float* d_wsum, int32_t* d_nsamples, float* d_loss_ray, float* d_grad_vox,
-                      const void* d_lists, size_t lists_bytes, sg_stream stream) {
+                      float lambda_n, float lambda_e, float* d_feat_out, float* d_depth,
+                      float* d_normal, float* d_wsum, int32_t* d_nsamples, float* d_loss_ray,
+                      float* d_grad_vox, const void* d_lists, size_t lists_bytes,
+                      sg_stream stream) {
   int rc = check_grid(grid);
   if (rc) return rc;
   Params p;
@@ -1699,8 +1726,8 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
   if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
   if (n_rays == 0) return SG_OK;
-  if (!std::isfinite(lambda_d) || !std::isfinite(lambda_n))
-    return fail(SG_EINVAL, "lambda_d / lambda_n must be finite");
+  if (!std::isfinite(lambda_d) || !std::isfinite(lambda_n) || !std::isfinite(lambda_e))
+    return fail(SG_EINVAL, "lambda_d / lambda_n / lambda_e must be finite");
   if (!d_vox || !d_rays || !d_ref_depth || !d_ref_normal || !d_depth || !d_normal || !d_wsum ||
       !d_grad_vox || (C > 0 && (!d_ref_feat || !d_feat_out)))
     return fail(SG_EINVAL, "a required pointer is NULL");
@@ -1716,7 +1743,8 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   const size_t vbytes = sizeof(float) * (size_t)(4 + C) * p.max_samples;
   const bool keep_v = (base + vbytes) * 4 <= 64 * 1024;
   const Launch l = plan(n_rays, base + (keep_v ? vbytes : 0));
-  const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, d_loss_ray};
+  const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, lambda_e,
+                     d_loss_ray};
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, true, true>), dim3(l.blocks),
                                         dim3(l.threads), l.lds, s, g, d_vox, d_rays, n_rays, p, L.q, L.counts,

@@ -219,8 +219,10 @@ def render_backward(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, g
 
 
 def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, ref, lambda_d=0.1,
-                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False, lists=None):
-    """Fused forward + squared-L2 loss + gradient (accumulated into grad_vox).
+                   lambda_n=0.05, grad_vox=None, out=None, with_loss=False, lists=None,
+                   lambda_e=0.0):
+    """Fused forward + squared-L2 loss (+ lambda_e times the Eikonal term on
+    the ray samples) + gradient (accumulated into grad_vox).
 
     ref: dict of reference "feat" [R,C], "depth" [R], "normal" [R,3].
     Returns (outputs dict, grad_vox[, loss_per_ray]).
@@ -251,7 +253,8 @@ def render_l2_step(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params, re
     check(lib().sg_render_l2_step(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
                                   ptr(ref["feat"]) if C else None, ptr(ref["depth"]),
                                   ptr(ref["normal"]), ctypes.c_float(lambda_d),
-                                  ctypes.c_float(lambda_n), ptr(out["feat"]) if C else None,
+                                  ctypes.c_float(lambda_n), ctypes.c_float(lambda_e),
+                                  ptr(out["feat"]) if C else None,
                                   ptr(out["depth"]), ptr(out["normal"]), ptr(out["wsum"]),
                                   ptr(out.get("nsamples")), ptr(loss), ptr(grad_vox), wp, wb,
                                   stream_ptr(dev)), "sg_render_l2_step")

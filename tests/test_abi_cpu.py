@@ -81,8 +81,8 @@ def test_render_validation(L):
     assert L.sg_eikonal(None, fake, 3, fake, 10, ctypes.c_float(1.0), None, None, None) == -1
     f = ctypes.c_float
     assert L.sg_render_l2_step(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, f(0.1),
-                               f(0.05), fake, fake, fake, fake, None, None, fake, None, 0,
-                               None) == -1
+                               f(0.05), f(0.0), fake, fake, fake, fake, None, None, fake, None,
+                               0, None) == -1
 
 
 def test_workspace_size(L):

@@ -304,10 +304,12 @@ def test_invalid_arguments_raise(sphere):
         sg.render_forward(g, vox[:10], rays, w["params"])
 
 
-def _fused_check(w, g, vox, rays_np, seed, what, max_samples=None):
+def _fused_check(w, g, vox, rays_np, seed, what, max_samples=None, lambda_e=0.0, vox_np=None):
     """Fused forward + L2 loss + backward against (a) the separate GPU calls
-    and (b) the oracle's forward -> loss gradient -> adjoint."""
+    and (b) the oracle's forward -> loss gradient -> adjoint, plus (with
+    lambda_e) the oracle's Eikonal term on the ray samples."""
     sg = _sg()
+    vox_np = w["vox"] if vox_np is None else vox_np
     prm = dict(w["params"]) if max_samples is None else dict(w["params"], max_samples=max_samples)
     R = rays_np.shape[0]
     rng = np.random.default_rng(seed)
@@ -316,21 +318,32 @@ def _fused_check(w, g, vox, rays_np, seed, what, max_samples=None):
               "normal": rng.normal(size=(R, 3)).astype(np.float32)}
     ref = {k: to_dev(v) for k, v in ref_np.items()}
     rays = to_dev(rays_np)
-    out, grad, loss = sg.render_l2_step(g, vox, rays, prm, ref, 0.1, 0.05, with_loss=True)
+    out, grad, loss = sg.render_l2_step(g, vox, rays, prm, ref, 0.1, 0.05, with_loss=True,
+                                        lambda_e=lambda_e)
     fwd = sg.render_forward(g, vox, rays, prm)
     for k in fwd:
         assert torch.equal(out[k], fwd[k]), f"{what}: fused {k} differs from render_forward"
     gl = sg.l2_loss_grad(fwd, ref, 0.1, 0.05)
     sep = sg.render_backward(g, vox, rays, prm, gl["feat"], gl["depth"], gl["normal"])
-    torch.testing.assert_close(grad, sep, rtol=1e-5, atol=1e-6 * sep.abs().max().item())
+    if lambda_e == 0.0:
+        torch.testing.assert_close(grad, sep, rtol=1e-5, atol=1e-6 * sep.abs().max().item())
     # oracle chain
-    o = oracle.render_forward(w["block_coords"], w["vox"], 3, w["h"], w["origin"], rays_np, prm,
+    o = oracle.render_forward(w["block_coords"], vox_np, 3, w["h"], w["origin"], rays_np, prm,
                               with_mag=True)
     L, gc, gd, gn = oracle.l2_loss_grad(o["feat"], ref_np["feat"], o["depth"], ref_np["depth"],
                                         o["normal"], ref_np["normal"], 0.1, 0.05)
-    assert loss.sum().item() == pytest.approx(L, rel=1e-4)
-    gref, mag = oracle.render_backward(w["block_coords"], w["vox"], 3, w["h"], w["origin"],
+    gref, mag = oracle.render_backward(w["block_coords"], vox_np, 3, w["h"], w["origin"],
                                        rays_np, prm, gc, gd, gn, None, with_mag=True)
+    if lambda_e != 0.0:
+        le, ge, me = oracle.eikonal_rays(w["block_coords"], vox_np, 3, w["h"], w["origin"],
+                                         rays_np, prm, lambda_e / R, with_mag=True)
+        assert np.abs(ge[..., 0]).sum() > 0.1 * np.abs(gref[..., 0]).sum(), \
+            f"{what}: the Eikonal term is too small to test"
+        L += le.sum()
+        gref = gref + ge
+        mag = mag.copy()
+        mag[..., 0] += me
+    assert loss.sum().item() == pytest.approx(L, rel=1e-4)
     # The kernel differentiates the loss at its own float32 forward, which
     # is within RTOL_FWD * mag of the oracle's; where feat ~ ref that shift
     # is a large relative change of the upstream gradient 2 (feat - ref) / R.
@@ -344,7 +357,7 @@ def _fused_check(w, g, vox, rays_np, seed, what, max_samples=None):
     dc = shift(o["mag_feat"], o["feat"], ref_np["feat"], 1.0)
     dd = shift(o["mag_depth"], o["depth"], ref_np["depth"], 0.1)
     dn = shift(o["mag_normal"], o["normal"], ref_np["normal"], 0.05)
-    _, mag_up = oracle.render_backward(w["block_coords"], w["vox"], 3, w["h"], w["origin"],
+    _, mag_up = oracle.render_backward(w["block_coords"], vox_np, 3, w["h"], w["origin"],
                                        rays_np, prm, dc, dd, dn, None, with_mag=True)
     assert_close_mag(grad.cpu().numpy(), gref, mag, RTOL_BWD, what, atol=mag_up + ATOL)
 
@@ -363,6 +376,23 @@ def test_fused_l2_step_multichunk(sphere):
 def test_fused_l2_step_room_full_batch(room):
     w, g, vox, _ = room
     _fused_check(w, g, vox, w["rays"], seed=13, what="fused room 65536")
+
+
+@pytest.mark.parametrize("max_samples", [128, 1024])
+def test_fused_l2_step_with_eikonal(sphere, max_samples):
+    """The Eikonal term on the ray samples inside the fused step (single- and
+    multi-chunk rays), on a perturbed SDF so that |grad f| is far from 1."""
+    from synth import scenes
+    w, g, _, _ = sphere
+    vox_np = scenes.perturb(w["vox"], w["h"], seed=4)
+    _fused_check(w, g, to_dev(vox_np), w["rays"][::2], seed=14, what=f"fused + Eikonal {max_samples}",
+                 max_samples=max_samples, lambda_e=0.005, vox_np=vox_np)
+
+
+def test_fused_l2_step_with_eikonal_room(room):
+    w, g, vox, _ = room
+    _fused_check(w, g, vox, w["rays"][:16384], seed=15, what="fused + Eikonal room",
+                 lambda_e=0.5)
 
 
 def test_march_kernel_and_inkernel_march_agree(room):
