@@ -21,6 +21,8 @@ Every function cites the passage of the paper it follows:
   * ``density``: VolSDF's Laplace-CDF transform named in Sec. 3.5.1.
   * ``rays_pinhole``: inverse of the pinhole projection used in Eq. 3.
   * ``footprint``: exact counts of the voxels and blocks each ray reads.
+  * ``alloc_blocks`` / ``fuse``: block allocation from depth maps (Sec.
+    3.4.1) and the depth, colour and semantic fusion of Sec. 3.4.2.
 """
 from __future__ import annotations
 
@@ -327,3 +329,46 @@ def optim_step(kind, p, g, m, v, lr, b1, b2, eps, t):
         v = b2 * v + (1 - b2) * g * g
         p = p - lr * g / (np.sqrt(v) + eps)
     return p, m, v
+
+
+def alloc_blocks(cams, depth, h, origin, dilate=1, depth_max=np.inf):
+    """Blocks allocated from depth maps (Sec. 3.4.1): the dilated blocks of
+    every unprojected pixel, in order of first occurrence.  cams [F,16],
+    depth [F,H,W].  Returns int32 [n,3]."""
+    lib = _load()
+    cm = _c(cams, np.float32).reshape(-1, 16)
+    dp = _c(depth, np.float32)
+    F, H, W = dp.shape
+    org = _c(origin, np.float32).reshape(3)
+    n = ctypes.c_int64(0)
+    cap = max(1, F * H * W * (2 * dilate + 1) ** 3)
+    cap = min(cap, 1 << 26)
+    while True:
+        out = np.empty((cap, 3), np.int32)
+        rc = lib.or_alloc_blocks(_p(cm), _I32(F), _p(dp), _I32(W), _I32(H), _F(h), _p(org),
+                                 _I32(dilate), _F(depth_max), _p(out), _I64(cap), ctypes.byref(n))
+        if rc == -2:
+            cap = n.value
+            continue
+        _check(rc, "alloc_blocks")
+        return out[: n.value].copy()
+
+
+def fuse(block_coords, h, origin, cams, depth, feat, trunc, n_sem=0):
+    """Fused SDF and features of every voxel of the given blocks (Sec.
+    3.4.2).  feat [F,H,W,C].  Returns (vox [n,512,1+C] float64,
+    weight [n,512] float64 = number of associations)."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    cm = _c(cams, np.float32).reshape(-1, 16)
+    dp = _c(depth, np.float32)
+    F, H, W = dp.shape
+    ft = _c(feat, np.float32).reshape(F, H, W, -1)
+    C = ft.shape[-1]
+    org = _c(origin, np.float32).reshape(3)
+    vox = np.empty((bc.shape[0], 512, 1 + C), np.float64)
+    wt = np.empty((bc.shape[0], 512), np.float64)
+    _check(lib.or_fuse(_p(bc), _I64(bc.shape[0]), _F(h), _p(org), _p(cm), _I32(F), _p(dp),
+                       _p(ft), _I32(C), _I32(W), _I32(H), _F(trunc), _I32(n_sem), _p(vox), _p(wt)),
+           "fuse")
+    return vox, wt

@@ -804,3 +804,229 @@ int or_rays_pinhole(const float* cams, int32_t n_cams, const int32_t* pix, int64
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Block allocation from depth (Sec. 3.4.1) and fusion (Sec. 3.4.2).         */
+
+#define COORD_LIMIT 1048576 /* block coordinates lie in [-2^20, 2^20) */
+
+typedef struct {
+  uint64_t key;
+  int64_t pos;
+} keyed;
+
+static int cmp_keyed(const void* a, const void* b) {
+  const keyed* x = (const keyed*)a;
+  const keyed* y = (const keyed*)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->pos < y->pos ? -1 : (x->pos > y->pos);
+}
+
+static int cmp_pos(const void* a, const void* b) {
+  const keyed* x = (const keyed*)a;
+  const keyed* y = (const keyed*)b;
+  return x->pos < y->pos ? -1 : (x->pos > y->pos);
+}
+
+static uint64_t coord_key(const int32_t* c) {
+  return ((uint64_t)(uint32_t)(c[0] + COORD_LIMIT) << 42) |
+         ((uint64_t)(uint32_t)(c[1] + COORD_LIMIT) << 21) | (uint64_t)(uint32_t)(c[2] + COORD_LIMIT);
+}
+
+/* Keep the first occurrence of every coordinate of c [n,3], in order; returns
+ * the number kept (c is compacted in place), or -3 on allocation failure. */
+static int64_t unique_first(int32_t* c, int64_t n) {
+  if (n == 0) return 0;
+  keyed* k = (keyed*)malloc((size_t)n * sizeof(keyed));
+  if (!k) return -3;
+  for (int64_t i = 0; i < n; ++i) {
+    k[i].key = coord_key(c + 3 * i);
+    k[i].pos = i;
+  }
+  qsort(k, (size_t)n, sizeof(keyed), cmp_keyed);
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (i == 0 || k[i].key != k[i - 1].key) k[m++] = k[i];
+  qsort(k, (size_t)m, sizeof(keyed), cmp_pos);
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t p = k[i].pos; /* p >= i: copying forward is safe */
+    c[3 * i] = c[3 * p];
+    c[3 * i + 1] = c[3 * p + 1];
+    c[3 * i + 2] = c[3 * p + 2];
+  }
+  free(k);
+  return m;
+}
+
+/*
+ * Blocks allocated from depth maps (Sec. 3.4.1): every pixel (u, v) of
+ * frame f with a depth D (finite, 0 < D <= depth_max) is lifted to the
+ * camera point (x D, y D, D), x = (u + 1/2 - cx) / fx, y = (v + 1/2 - cy) / fy
+ * (the inverse projection of the pinhole model, depth along the optical
+ * axis), moved to the world by [R | t], and its block floor(X / (8h)) taken
+ * (through the voxel floor(X / h), as the march does); each such block is
+ * dilated to the (2r+1)^3 blocks around it.  float32, one rounding per
+ * operation, in the order written.  Output: the block coordinates in order of
+ * first occurrence (frames, rows, columns, then dilation offsets z, y, x
+ * from -r to r), duplicates removed.  cams [F,16] as in or_rays_pinhole;
+ * depth [F,H,W].  Pixels whose blocks (dilated) would leave [-2^20, 2^20)
+ * are skipped.  out [cap,3]; *n_out = number written; -2 if cap is too small.
+ */
+int or_alloc_blocks(const float* cams, int32_t F, const float* depth, int32_t W, int32_t H,
+                    float h, const float org[3], int32_t r, float depth_max, int32_t* out,
+                    int64_t cap, int64_t* n_out) {
+  if (F < 0 || W < 0 || H < 0 || r < 0 || !(h > 0)) return -1;
+  const float inv_h = 1.0f / h;
+  const int64_t P = (int64_t)F * W * H;
+  int32_t* b = (int32_t*)malloc((size_t)(P > 0 ? P : 1) * 3 * sizeof(int32_t));
+  if (!b) return -3;
+  int64_t nb = 0;
+  for (int32_t f = 0; f < F; ++f) {
+    const float* K = cams + 16 * (size_t)f;
+    for (int32_t v = 0; v < H; ++v)
+      for (int32_t u = 0; u < W; ++u) {
+        const float D = depth[((size_t)f * H + v) * W + u];
+        if (!(isfinite(D) && D > 0.0f && D <= depth_max)) continue;
+        const float x = ((float)u + 0.5f - K[2]) / K[0];
+        const float y = ((float)v + 0.5f - K[3]) / K[1];
+        const float xc[3] = {x * D, y * D, D};
+        int ok = 1;
+        int32_t bb[3];
+        for (int a = 0; a < 3; ++a) {
+          const float* M = K + 4 + 4 * a;
+          const float p0 = M[0] * xc[0];
+          const float p1 = M[1] * xc[1];
+          const float p2 = M[2] * xc[2];
+          const float X = ((p0 + p1) + p2) + M[3];
+          const float xv = (X - org[a]) * inv_h;
+          if (!(fabsf(xv) < POS_LIMIT)) {
+            ok = 0;
+            break;
+          }
+          bb[a] = floor_div8((int32_t)floorf(xv));
+          if (bb[a] - r < -COORD_LIMIT || bb[a] + r >= COORD_LIMIT) ok = 0;
+        }
+        if (!ok) continue;
+        b[3 * nb] = bb[0];
+        b[3 * nb + 1] = bb[1];
+        b[3 * nb + 2] = bb[2];
+        ++nb;
+      }
+  }
+  int64_t nu = unique_first(b, nb);
+  if (nu < 0) {
+    free(b);
+    return -3;
+  }
+  const int64_t side = 2 * (int64_t)r + 1, nd = nu * side * side * side;
+  int32_t* d = (int32_t*)malloc((size_t)(nd > 0 ? nd : 1) * 3 * sizeof(int32_t));
+  if (!d) {
+    free(b);
+    return -3;
+  }
+  int64_t m = 0;
+  for (int64_t i = 0; i < nu; ++i)
+    for (int32_t dz = -r; dz <= r; ++dz)
+      for (int32_t dy = -r; dy <= r; ++dy)
+        for (int32_t dx = -r; dx <= r; ++dx) {
+          d[3 * m] = b[3 * i] + dx;
+          d[3 * m + 1] = b[3 * i + 1] + dy;
+          d[3 * m + 2] = b[3 * i + 2] + dz;
+          ++m;
+        }
+  free(b);
+  const int64_t no = unique_first(d, m);
+  if (no < 0) {
+    free(d);
+    return -3;
+  }
+  *n_out = no;
+  if (no > cap) {
+    free(d);
+    return -2;
+  }
+  memcpy(out, d, (size_t)no * 3 * sizeof(int32_t));
+  free(d);
+  return 0;
+}
+
+/*
+ * Fusion (Sec. 3.4.2): every voxel v (world position origin + i h, float32)
+ * is projected into every frame f: camera point c = R^T (X - t), pixel
+ * (floor(fx c_x / c_z + cx), floor(fy c_y / c_z + cy)) (the pixel whose
+ * centre ray the voxel is nearest to), and associated when c_z > 0, the
+ * pixel lies in the image, its depth D is finite and > 0, and the
+ * projective SDF D - c_z is within the truncation bound (|D - c_z| < trunc).
+ * The least-squares solutions are averages over the associations:
+ *   vox[v,0]   = mean of (D - c_z),   vox[v,1+ch] = mean of feat[f,pixel,ch],
+ * and the last n_sem feature channels (semantic logits) are divided by
+ * their L2 norm.  A voxel with no association gets SDF = trunc and zero
+ * features.  weight[v] = number of associations.  The decisions (pixel,
+ * association) are taken in float32 in the order written, the averages in
+ * double.  feat [F,H,W,C]; vox [n,512,1+C]; weight [n,512].
+ */
+int or_fuse(const int32_t* block_coords, int64_t n_blocks, float h, const float org[3],
+            const float* cams, int32_t F, const float* depth, const float* feat, int32_t C,
+            int32_t W, int32_t H, float trunc, int32_t n_sem, double* vox, double* weight) {
+  if (n_blocks < 0 || F < 0 || C < 0 || n_sem < 0 || n_sem > C || !(h > 0) || !(trunc > 0))
+    return -1;
+  double* acc = (double*)malloc((size_t)(C > 0 ? C : 1) * sizeof(double));
+  if (!acc) return -3;
+  for (int64_t bi = 0; bi < n_blocks; ++bi)
+    for (int l = 0; l < VOX_PER_BLOCK; ++l) {
+      const int32_t li[3] = {l & 7, (l >> 3) & 7, l >> 6};
+      float X[3];
+      for (int a = 0; a < 3; ++a) {
+        const float fi = (float)(8 * block_coords[3 * bi + a] + li[a]);
+        const float step = fi * h;
+        X[a] = org[a] + step;
+      }
+      double sd = 0.0;
+      int64_t cnt = 0;
+      for (int ch = 0; ch < C; ++ch) acc[ch] = 0.0;
+      for (int32_t f = 0; f < F; ++f) {
+        const float* K = cams + 16 * (size_t)f;
+        float dd[3];
+        for (int a = 0; a < 3; ++a) dd[a] = X[a] - K[4 + 4 * a + 3];
+        float c[3];
+        for (int j = 0; j < 3; ++j) {
+          const float p0 = K[4 + j] * dd[0];     /* R[0][j] */
+          const float p1 = K[8 + j] * dd[1];     /* R[1][j] */
+          const float p2 = K[12 + j] * dd[2];    /* R[2][j] */
+          c[j] = (p0 + p1) + p2;
+        }
+        const float z = c[2];
+        if (!(z > 0.0f)) continue;
+        const float qx = c[0] / z, qy = c[1] / z;
+        const float uf = K[0] * qx + K[2];
+        const float vf = K[1] * qy + K[3];
+        if (!(uf >= 0.0f && uf < (float)W && vf >= 0.0f && vf < (float)H)) continue;
+        const int32_t pu = (int32_t)floorf(uf), pv = (int32_t)floorf(vf);
+        const size_t pix = ((size_t)f * H + pv) * W + pu;
+        const float D = depth[pix];
+        if (!(isfinite(D) && D > 0.0f)) continue;
+        const float s = D - z;
+        if (!(fabsf(s) < trunc)) continue;
+        sd += (double)D - (double)z;
+        for (int ch = 0; ch < C; ++ch) acc[ch] += feat[pix * C + ch];
+        ++cnt;
+      }
+      double* o = vox + ((size_t)bi * VOX_PER_BLOCK + l) * (size_t)(1 + C);
+      weight[(size_t)bi * VOX_PER_BLOCK + l] = (double)cnt;
+      if (cnt == 0) {
+        o[0] = trunc;
+        for (int ch = 0; ch < C; ++ch) o[1 + ch] = 0.0;
+        continue;
+      }
+      o[0] = sd / (double)cnt;
+      for (int ch = 0; ch < C; ++ch) o[1 + ch] = acc[ch] / (double)cnt;
+      if (n_sem > 0) {
+        double nrm = 0.0;
+        for (int ch = C - n_sem; ch < C; ++ch) nrm += o[1 + ch] * o[1 + ch];
+        nrm = sqrt(nrm);
+        for (int ch = C - n_sem; ch < C; ++ch) o[1 + ch] = nrm > 0.0 ? o[1 + ch] / nrm : 0.0;
+      }
+    }
+  free(acc);
+  return 0;
+}

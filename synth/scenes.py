@@ -199,6 +199,54 @@ def room_sdf(p, objs):
     return _room_min(p, objs)[0]
 
 
+def part_features(pos, near, meta, n_sem=0):
+    """RGB (+ n_sem one-hot semantic logits) of room part `near` at points pos."""
+    out = np.empty(pos.shape[:-1] + (3 + n_sem,), np.float32)
+    for ch in range(3):
+        f = meta["tex_f"][near, ch]
+        ph = 2 * np.pi * (pos[..., 0] * f[..., 0] + pos[..., 1] * f[..., 1]
+                          + pos[..., 2] * f[..., 2]) + meta["tex_p"][near, ch]
+        out[..., ch] = np.clip(meta["base"][near, ch] + 0.2 * np.sin(ph), 0.0, 1.0)
+    if n_sem:
+        out[..., 3:] = (meta["labels"][near][..., None] == np.arange(n_sem)).astype(np.float32)
+    return out
+
+
+def room_frames(meta, cams, W, H, n_sem=0, max_depth=20.0):
+    """Depth and feature images of the analytic room seen by cams [F,16]:
+    depth [F,H,W] float32 (z in the camera frame of the first surface,
+    found by sphere tracing the exact SDF in float64; NaN where nothing is
+    hit) and features [F,H,W,3+n_sem] (RGB, one-hot semantics) of the part
+    hit."""
+    from .cameras import frame_pixels, pixel_rays
+    objs = meta["objects"]
+    F = cams.shape[0]
+    depth = np.full((F, H, W), np.nan, np.float32)
+    feat = np.zeros((F, H, W, 3 + n_sem), np.float32)
+    for i in range(F):
+        r = pixel_rays(cams, frame_pixels(i, W, H)).astype(np.float64)
+        o, d = r[:, :3], r[:, 3:]
+        t = np.zeros(len(r))
+        act = np.ones(len(r), bool)
+        hit = np.zeros(len(r), bool)
+        for _ in range(400):
+            idx = np.flatnonzero(act)
+            if idx.size == 0:
+                break
+            sd = room_sdf(o[idx] + t[idx, None] * d[idx], objs)
+            t[idx] += sd
+            done = sd < 1e-6
+            hit[idx[done]] = True
+            act[idx[done | (t[idx] > max_depth)]] = False
+        R = cams[i, 4:].astype(np.float64).reshape(3, 4)[:, :3]
+        z = t * (d @ R[:, 2])
+        pts = o + t[:, None] * d
+        _, near = _room_min(pts, objs)
+        depth[i].reshape(-1)[hit] = z[hit].astype(np.float32)
+        feat[i].reshape(-1, 3 + n_sem)[hit] = part_features(pts[hit], near[hit], meta, n_sem)
+    return depth, feat
+
+
 def room_scene(h=0.02, band_vox=3, seed=0, n_objects=20, n_sem=0, texture_seed=None):
     """6 x 6 x 3 m box room with seeded furniture, exact union SDF.
 
@@ -232,14 +280,7 @@ def room_scene(h=0.02, band_vox=3, seed=0, n_objects=20, n_sem=0, texture_seed=N
         bc, pos, sdf, near = bc[keep], pos[keep], sdf[keep], near[keep]
         v = np.empty((bc.shape[0], 512, 1 + C), np.float32)
         v[..., 0] = sdf
-        for ch in range(3):
-            f = meta["tex_f"][near, ch]  # [n,512,3]
-            ph = 2 * np.pi * (pos[..., 0] * f[..., 0] + pos[..., 1] * f[..., 1]
-                              + pos[..., 2] * f[..., 2]) + meta["tex_p"][near, ch]
-            v[..., 1 + ch] = np.clip(meta["base"][near, ch] + 0.2 * np.sin(ph), 0.0, 1.0)
-        if n_sem:
-            lab = meta["labels"][near]
-            v[..., 4:] = (lab[..., None] == np.arange(n_sem)).astype(np.float32)
+        v[..., 1:] = part_features(pos, near, meta, n_sem)
         blocks.append(bc.astype(np.int32))
         chunks.append(v)
     bc = np.concatenate(blocks, axis=0)

@@ -101,3 +101,16 @@ def serving_grids(seed=0):
             out.append((sc, params(h / 2, 0.0, 12.0, h, 128), cams))
         _CACHE[key] = out
     return _CACHE[key]
+
+
+def room_depth_frames(seed=0, n_frames=10, W=640, H=480, n_sem=0):
+    """Depth and RGB(+semantic) images of the 2 cm room from seeded poses
+    (the input of block allocation and fusion)."""
+    key = ("room_frames", seed, n_frames, W, H, n_sem)
+    if key not in _CACHE:
+        base = _room(seed, 0.02, 0)
+        cams = cameras.room_cams(base["meta"]["objects"], seed=seed + 7, n=n_frames, W=W, H=H)
+        depth, feat = scenes.room_frames(base["meta"], cams, W, H, n_sem=n_sem)
+        _CACHE[key] = {"cams": cams, "depth": depth, "feat": feat, "W": W, "H": H,
+                       "h": np.float32(0.02), "origin": np.zeros(3, np.float32), "room": base}
+    return _CACHE[key]
