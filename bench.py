@@ -265,6 +265,56 @@ def frames_bench(dev, n_frames=50):
     return res
 
 
+def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5):
+    """Block allocation from depth maps, grid build and fusion of ten seeded
+    640x480 depth + RGB frames of the 2 cm room (Sec. 3.4): the set-up of
+    the grid that the render then refines."""
+    import numpy as np
+    import torch
+    import paper_2305_13220_amd as sg
+    from synth import workloads
+    t0 = time.perf_counter()
+    fr = workloads.room_depth_frames(n_frames=n_frames, W=640, H=480)
+    cams, depth, feat = (torch.from_numpy(fr[k]).to(dev) for k in ("cams", "depth", "feat"))
+    log(f"fusion setup {time.perf_counter() - t0:.1f}s")
+    h = float(fr["h"])
+    blocks = sg.alloc_blocks(cams, depth, h, dilate=1)
+    grid = sg.Grid(blocks, h)
+    vox, wt = sg.fuse(grid, cams, depth, feat, trunc)
+    torch.cuda.synchronize()
+    t_alloc, t_build, t_fuse = [], [], []
+    for _ in range(reps):
+        a = time.perf_counter()
+        blocks = sg.alloc_blocks(cams, depth, h, dilate=1)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        grid = sg.Grid(blocks, h)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        sg.fuse(grid, cams, depth, feat, trunc, vox=vox, weight=False)
+        e[1].record()
+        torch.cuda.synchronize()
+        t_alloc.append(b - a)
+        t_build.append(c - b)
+        t_fuse.append(e[0].elapsed_time(e[1]) * 1e-3)
+    n_vox = grid.n_blocks * 512
+    fuse_s = float(np.median(t_fuse))
+    total = float(np.median(t_alloc)) + float(np.median(t_build)) + fuse_s
+    res = {"workload": "room_2cm_fusion_10x640x480", "frames": n_frames, "blocks": grid.n_blocks,
+           "alloc_ms": round(float(np.median(t_alloc)) * 1e3, 3),
+           "build_ms": round(float(np.median(t_build)) * 1e3, 3),
+           "fuse_ms": round(fuse_s * 1e3, 3),
+           "fuse_voxel_frames_per_s": n_vox * n_frames / fuse_s,
+           "frames_per_s_end_to_end": round(n_frames / total, 1),
+           "associated_frac": round(float((wt > 0).float().mean().item()), 4),
+           "kernel": "k_fuse<3>"}
+    del vox, wt, grid, cams, depth, feat
+    torch.cuda.empty_cache()
+    return res
+
+
 def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
     """SDF and gradient at the k^3 lattice points of the grid's bounding box
     (the point-query timing of Sec. 4), one sg_query call per k.  Bytes per
@@ -329,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the k^3 point-query timing")
+    ap.add_argument("--no-fusion", action="store_true",
+                    help="skip the allocation + fusion timing")
     ap.add_argument("--no-frames", action="store_true",
                     help="skip the 1 cm semantic full-frame render timing")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -524,6 +576,8 @@ def main():
         res["frames"] = frames_bench(dev)
     if not args.no_query:
         res["query"] = query_bench(grid, vox, w["block_coords"], dev)
+    if not args.no_fusion:
+        res["fusion"] = fusion_bench(dev)
     if not args.no_serve:
         res["serving"] = serve_bench(args, dev)
     if not args.no_cpu:

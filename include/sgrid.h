@@ -169,6 +169,54 @@ int sg_grid_neighbors(const sg_grid* g, int32_t* d_out, sg_stream stream);
 int sg_grid_lookup(const sg_grid* g, const int32_t* d_coords, int64_t n,
                    int32_t* d_idx, sg_stream stream);
 
+/*
+ * sg_alloc_blocks -- the blocks to allocate for depth maps (Sec. 3.4.1):
+ * every pixel (u, v) of frame f whose depth D is finite, > 0 and
+ * <= depth_max is lifted to the camera point (x D, y D, D),
+ * x = (u + 1/2 - cx) / fx, y = (v + 1/2 - cy) / fy (D is the depth along the
+ * optical axis), moved to the world by the frame's [R | t], and its block
+ * floor(floor((X - origin) / h) / 8) taken; each such block is dilated to the
+ * (2 dilate + 1)^3 blocks around it.  float32 without fused multiply-add, in
+ * the order written.  Pixels whose dilated blocks would leave [-2^20, 2^20)
+ * are skipped.
+ *   d_cams   float [n_frames,16], the layout of sg_rays_pinhole;
+ *   d_depth  float [n_frames,H,W];
+ *   d_out    int32 [cap,3] output: the block coordinates in order of first
+ *            occurrence (frames, rows, columns, then dilation offsets z, y, x
+ *            from -dilate to dilate), without duplicates: the input of
+ *            sg_grid_build;
+ *   *n_out   the number of blocks (also when cap is too small: SG_EINVAL
+ *            then, with nothing written, so a caller can size d_out).
+ * Allocates temporary device memory and synchronises the stream (a set-up
+ * call, like sg_grid_build).  dilate in [0, 8].
+ */
+int sg_alloc_blocks(const float* d_cams, int32_t n_frames, const float* d_depth, int32_t W,
+                    int32_t H, float voxel_size, const float origin[3], int32_t dilate,
+                    float depth_max, int32_t* d_out, int64_t cap, int64_t* n_out,
+                    sg_stream stream);
+
+/*
+ * sg_fuse -- depth, colour and semantic fusion (Sec. 3.4.2): every voxel
+ * (world position origin + i h) of the grid is projected into every frame
+ * (camera point c = R^T (X - t); pixel (floor(fx c_x / c_z + cx),
+ * floor(fy c_y / c_z + cy))) and associated when c_z > 0, the pixel lies in
+ * the image, its depth D is finite and > 0 and |D - c_z| < trunc.  The
+ * per-voxel least-squares solutions are the averages over its associations:
+ *   d_vox [n_blocks,512,1+C] (output): SDF = mean of D - c_z, features =
+ *     mean of d_feat at the pixel; the last n_sem feature channels
+ *     (semantic logits) are then divided by their L2 norm.  Voxels with no
+ *     association: SDF = trunc, features 0.
+ *   d_weight [n_blocks,512] float (nullable): number of associations.
+ * d_cams [n_frames,16], d_depth [n_frames,H,W], d_feat [n_frames,H,W,C]
+ * (nullable iff C == 0).  Decisions in float32 without fused multiply-add;
+ * frames are summed in order, so the output is deterministic.  Device
+ * memory owned by the caller; asynchronous; allocates nothing.  C as for
+ * rendering; 0 <= n_sem <= C; trunc finite and > 0.
+ */
+int sg_fuse(const sg_grid* g, const float* d_cams, int32_t n_frames, const float* d_depth,
+            const float* d_feat, int32_t C, int32_t W, int32_t H, float trunc, int32_t n_sem,
+            float* d_vox, float* d_weight, sg_stream stream);
+
 /* Free the grid's device memory (waits for nothing; the caller makes sure no
  * launched work still uses the grid).  NULL is accepted. */
 int sg_grid_destroy(sg_grid* g);

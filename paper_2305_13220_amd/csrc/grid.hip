@@ -98,6 +98,7 @@ __global__ void k_insert_first(const uint64_t* __restrict__ keys, int64_t n, Bui
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t key = keys[i];
+  if (key == kEmptyKey) return;  // a masked-out entry
   uint64_t p = mix64(key) & mask;
   for (;;) {
     unsigned long long prev =
@@ -115,7 +116,7 @@ __global__ void k_mark_first(const uint64_t* __restrict__ keys, int64_t n, const
                              uint64_t mask, int32_t* __restrict__ flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  flags[i] = (s[find_build(s, mask, keys[i])].first == (int32_t)i) ? 1 : 0;
+  flags[i] = (keys[i] != kEmptyKey && s[find_build(s, mask, keys[i])].first == (int32_t)i) ? 1 : 0;
 }
 
 __global__ void k_assign(const uint64_t* __restrict__ keys, const int32_t* __restrict__ coords,
@@ -345,9 +346,111 @@ struct DevFree {
     }                                                                             \
   } while (0)
 
+
+// ---------------------------------------------------------------------------
+// Block allocation from depth maps (Sec. 3.4.1).
+
+// Key and block of pixel p of a frame: the pixel is lifted to the camera
+// point (x D, y D, D) with x = (u + 1/2 - cx) / fx, y = (v + 1/2 - cy) / fy,
+// moved to the world by [R | t], and its block taken through the voxel
+// floor((X - origin) / h).  float32, no fused multiply-add, in this order.
+// kEmptyKey for an invalid depth or a block (dilated by r) out of range.
+__global__ void k_unproject(const float* __restrict__ cams, const float* __restrict__ depth,
+                            int32_t W, int32_t H, int64_t P, float inv_h, float ox, float oy,
+                            float oz, int32_t r, float depth_max, uint64_t* __restrict__ keys,
+                            int32_t* __restrict__ coords) {
+#pragma clang fp contract(off)
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int64_t f = p / ((int64_t)W * H);
+  const int32_t rem = (int32_t)(p - f * (int64_t)W * H);
+  const int32_t v = rem / W, u = rem - v * W;
+  const float* K = cams + 16 * f;
+  const float D = depth[p];
+  uint64_t key = kEmptyKey;
+  int32_t b[3] = {0, 0, 0};
+  if (isfinite(D) && D > 0.0f && D <= depth_max) {
+    const float x = ((float)u + 0.5f - K[2]) / K[0];
+    const float y = ((float)v + 0.5f - K[3]) / K[1];
+    const float xc[3] = {x * D, y * D, D};
+    const float org[3] = {ox, oy, oz};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float* M = K + 4 + 4 * a;
+      const float p0 = M[0] * xc[0];
+      const float p1 = M[1] * xc[1];
+      const float p2 = M[2] * xc[2];
+      const float X = ((p0 + p1) + p2) + M[3];
+      const float xv = (X - org[a]) * inv_h;
+      const bool fin = fabsf(xv) < 16777216.0f;
+      ok = ok && fin;
+      b[a] = ((int32_t)floorf(fin ? xv : 0.0f)) >> 3;  // arithmetic shift: floor division
+      ok = ok && b[a] - r >= -kCoordLimit && b[a] + r < kCoordLimit;
+    }
+    if (ok) key = pack_key(b[0], b[1], b[2]);
+  }
+  keys[p] = key;
+  coords[3 * p] = b[0];
+  coords[3 * p + 1] = b[1];
+  coords[3 * p + 2] = b[2];
+}
+
+// The (2r+1)^3 blocks around each block, offsets z, y, x from -r to r.
+__global__ void k_dilate(const int32_t* __restrict__ in, int64_t n, int32_t r,
+                         int32_t* __restrict__ out, uint64_t* __restrict__ keys) {
+  const int64_t side = 2 * r + 1, per = side * side * side;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * per) return;
+  const int64_t src = i / per;
+  const int32_t o = (int32_t)(i - src * per);
+  const int32_t dz = o / (int32_t)(side * side), dy = (o / (int32_t)side) % (int32_t)side,
+                dx = o % (int32_t)side;
+  const int32_t c[3] = {in[3 * src] + dx - r, in[3 * src + 1] + dy - r, in[3 * src + 2] + dz - r};
+  out[3 * i] = c[0];
+  out[3 * i + 1] = c[1];
+  out[3 * i + 2] = c[2];
+  keys[i] = pack_key(c[0], c[1], c[2]);
+}
+
 }  // namespace sg
 
 using namespace sg;
+
+// First occurrence of every valid key (kEmptyKey entries skipped), in input
+// order: coords of the kept entries to out (capacity n), their count to nu.
+static int unique_first(const uint64_t* d_keys, const int32_t* d_coords, int64_t n,
+                        int32_t* d_out, int64_t& nu, hipStream_t s) {
+  nu = 0;
+  if (n == 0) return SG_OK;
+  DevFree tmp;
+  int32_t *d_flags, *d_offs, *d_sums;
+  BuildSlot* d_bslots;
+  const uint64_t cap = pow2_at_least(2 * (uint64_t)n);
+  const int64_t n_tiles = (n + kScanTile - 1) / kScanTile;
+  SG_ALLOC(tmp, d_flags, sizeof(int32_t) * n);
+  SG_ALLOC(tmp, d_offs, sizeof(int32_t) * n);
+  SG_ALLOC(tmp, d_sums, sizeof(int32_t) * n_tiles);
+  SG_ALLOC(tmp, d_bslots, sizeof(BuildSlot) * cap);
+  const int T = 256;
+  k_fill_build<<<grid1d((int64_t)cap, T), T, 0, s>>>(d_bslots, cap);
+  k_insert_first<<<grid1d(n, T), T, 0, s>>>(d_keys, n, d_bslots, cap - 1);
+  k_mark_first<<<grid1d(n, T), T, 0, s>>>(d_keys, n, d_bslots, cap - 1, d_flags);
+  k_scan_tiles<<<(unsigned)n_tiles, kScanThreads, 0, s>>>(d_flags, n, d_offs, d_sums);
+  k_scan_sums<<<1, kScanThreads, 0, s>>>(d_sums, n_tiles);
+  k_scan_add<<<(unsigned)n_tiles, kScanThreads, 0, s>>>(d_offs, n, d_sums);
+  k_assign<<<grid1d(n, T), T, 0, s>>>(d_keys, d_coords, n, d_bslots, cap - 1, d_flags, d_offs,
+                                      d_out);
+  int32_t last_off = 0, last_flag = 0;
+  SG_HIP_CHECK(hipMemcpyAsync(&last_off, d_offs + (n - 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+  SG_HIP_CHECK(hipMemcpyAsync(&last_flag, d_flags + (n - 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+  SG_HIP_CHECK(hipGetLastError());
+  SG_HIP_CHECK(hipStreamSynchronize(s));
+  nu = (int64_t)last_off + last_flag;
+  return SG_OK;
+}
 
 extern "C" {
 
@@ -475,6 +578,58 @@ int sg_grid_build_ex(const int32_t* d_block_coords, int64_t n, float voxel_size,
   keep.ptrs.clear();  // ownership moves to the grid
   guard.g = nullptr;
   *out = g;
+  return SG_OK;
+}
+
+int sg_alloc_blocks(const float* d_cams, int32_t n_frames, const float* d_depth, int32_t W,
+                    int32_t H, float voxel_size, const float origin[3], int32_t dilate,
+                    float depth_max, int32_t* d_out, int64_t cap, int64_t* n_out,
+                    sg_stream stream) {
+  if (!n_out) return fail(SG_EINVAL, "n_out is NULL");
+  *n_out = 0;
+  if (n_frames < 0 || W < 0 || H < 0) return fail(SG_EINVAL, "sizes must be >= 0");
+  if (dilate < 0 || dilate > 8) return fail(SG_EINVAL, "dilate must be in [0, 8]");
+  if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size))
+    return fail(SG_EINVAL, "voxel_size must be finite and > 0");
+  if (!origin) return fail(SG_EINVAL, "origin is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(SG_EINVAL, "origin must be finite");
+  if (std::isnan(depth_max)) return fail(SG_EINVAL, "depth_max is NaN");
+  if (cap < 0) return fail(SG_EINVAL, "cap must be >= 0");
+  const int64_t P = (int64_t)n_frames * W * H;
+  if (P > (int64_t)INT_MAX) return fail(SG_EINVAL, "more than 2^31-1 pixels in one call");
+  if (P == 0) return SG_OK;
+  if (!d_cams || !d_depth) return fail(SG_EINVAL, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  DevFree tmp;
+  uint64_t* d_keys;
+  int32_t *d_coords, *d_unique;
+  SG_ALLOC(tmp, d_keys, sizeof(uint64_t) * P);
+  SG_ALLOC(tmp, d_coords, sizeof(int32_t) * 3 * P);
+  SG_ALLOC(tmp, d_unique, sizeof(int32_t) * 3 * P);
+  const int T = 256;
+  k_unproject<<<grid1d(P, T), T, 0, s>>>(d_cams, d_depth, W, H, P, 1.0f / voxel_size, origin[0],
+                                         origin[1], origin[2], dilate, depth_max, d_keys,
+                                         d_coords);
+  int64_t nu = 0;
+  int rc = unique_first(d_keys, d_coords, P, d_unique, nu, s);
+  if (rc) return rc;
+  const int64_t side = 2 * (int64_t)dilate + 1, nd = nu * side * side * side;
+  if (nd > (int64_t)INT_MAX) return fail(SG_EINVAL, "too many dilated blocks");
+  if (nd == 0) return SG_OK;
+  uint64_t* d_dkeys;
+  int32_t *d_dil, *d_res;
+  SG_ALLOC(tmp, d_dkeys, sizeof(uint64_t) * nd);
+  SG_ALLOC(tmp, d_dil, sizeof(int32_t) * 3 * nd);
+  SG_ALLOC(tmp, d_res, sizeof(int32_t) * 3 * nd);
+  k_dilate<<<grid1d(nd, T), T, 0, s>>>(d_unique, nu, dilate, d_dil, d_dkeys);
+  int64_t no = 0;
+  if ((rc = unique_first(d_dkeys, d_dil, nd, d_res, no, s))) return rc;
+  *n_out = no;
+  if (no > cap) return fail(SG_EINVAL, "cap is smaller than the number of blocks (in *n_out)");
+  if (!d_out) return fail(SG_EINVAL, "d_out is NULL");
+  SG_HIP_CHECK(hipMemcpyAsync(d_out, d_res, sizeof(int32_t) * 3 * no, hipMemcpyDeviceToDevice, s));
+  SG_HIP_CHECK(hipStreamSynchronize(s));
   return SG_OK;
 }
 

@@ -306,6 +306,51 @@ def eikonal(grid: Grid, vox: torch.Tensor, points: torch.Tensor, weight: float =
     return out, grad_vox
 
 
+def alloc_blocks(cams: torch.Tensor, depth: torch.Tensor, voxel_size: float, origin=(0.0, 0.0, 0.0),
+                 dilate: int = 1, depth_max: float = float("inf")):
+    """Block coordinates [n,3] int32 allocated for depth maps [F,H,W] seen by
+    cams [F,16] (Sec. 3.4.1), in order of first occurrence."""
+    want(cams, "cams", torch.float32, (None, 16))
+    want(depth, "depth", torch.float32, (cams.shape[0], None, None), cams.device)
+    F, H, W = depth.shape
+    org = (ctypes.c_float * 3)(*[float(x) for x in origin])
+    n = ctypes.c_int64(0)
+    dev = cams.device
+    with torch.cuda.device(dev):
+        rc = lib().sg_alloc_blocks(ptr(cams), F, ptr(depth), W, H, ctypes.c_float(voxel_size), org,
+                                   dilate, ctypes.c_float(depth_max), None, 0, ctypes.byref(n),
+                                   stream_ptr(dev))
+        if rc != 0 and n.value == 0:
+            check(rc, "sg_alloc_blocks")
+        out = torch.empty((n.value, 3), dtype=torch.int32, device=dev)
+        if n.value:
+            check(lib().sg_alloc_blocks(ptr(cams), F, ptr(depth), W, H, ctypes.c_float(voxel_size),
+                                        org, dilate, ctypes.c_float(depth_max), ptr(out), n.value,
+                                        ctypes.byref(n), stream_ptr(dev)), "sg_alloc_blocks")
+    return out
+
+
+def fuse(grid: Grid, cams: torch.Tensor, depth: torch.Tensor, feat: torch.Tensor, trunc: float,
+         n_sem: int = 0, vox=None, weight: bool = True):
+    """Fused voxels [n,512,1+C] (and association counts [n,512]) of depth
+    [F,H,W] and features [F,H,W,C] seen by cams [F,16] (Sec. 3.4.2)."""
+    want(cams, "cams", torch.float32, (None, 16), grid.device)
+    F = cams.shape[0]
+    want(depth, "depth", torch.float32, (F, None, None), grid.device)
+    H, W = depth.shape[1], depth.shape[2]
+    want(feat, "feat", torch.float32, (F, H, W, None), grid.device)
+    C = feat.shape[-1]
+    if vox is None:
+        vox = torch.empty((grid.n_blocks, 512, 1 + C), dtype=torch.float32, device=grid.device)
+    else:
+        want(vox, "vox", torch.float32, (grid.n_blocks, 512, 1 + C), grid.device)
+    wt = torch.empty((grid.n_blocks, 512), dtype=torch.float32, device=grid.device) if weight else None
+    check(lib().sg_fuse(grid.handle, ptr(cams), F, ptr(depth), ptr(feat) if C else None, C, W, H,
+                        ctypes.c_float(trunc), n_sem, ptr(vox), ptr(wt), stream_ptr(grid.device)),
+          "sg_fuse")
+    return vox, wt
+
+
 def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
     """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
     params = RenderParams.of(params)

@@ -79,6 +79,17 @@ def test_render_validation(L):
     assert L.sg_render_footprint(None, fake, 10, ctypes.byref(p), fake, None, None) == -1
     assert L.sg_query(None, fake, 3, fake, 10, None, None, None, None, None) == -1
     assert L.sg_eikonal(None, fake, 3, fake, 10, ctypes.c_float(1.0), None, None, None) == -1
+    assert L.sg_fuse(None, fake, 1, fake, fake, 3, 4, 4, ctypes.c_float(0.1), 0, fake, None,
+                     None) == -1
+    n = ctypes.c_int64(5)
+    org = (ctypes.c_float * 3)(0, 0, 0)
+    assert L.sg_alloc_blocks(fake, 1, fake, 4, 4, ctypes.c_float(0.02), org, -1, ctypes.c_float(1),
+                             None, 0, ctypes.byref(n), None) == -1 and n.value == 0
+    assert L.sg_alloc_blocks(fake, 1, fake, 4, 4, ctypes.c_float(0.0), org, 1, ctypes.c_float(1),
+                             None, 0, ctypes.byref(n), None) == -1
+    # zero pixels: nothing to do, no GPU call
+    assert L.sg_alloc_blocks(None, 0, None, 4, 4, ctypes.c_float(0.02), org, 1, ctypes.c_float(1),
+                             None, 0, ctypes.byref(n), None) == 0 and n.value == 0
     f = ctypes.c_float
     assert L.sg_render_l2_step(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, fake, f(0.1),
                                f(0.05), f(0.0), fake, fake, fake, fake, None, None, fake, None,
