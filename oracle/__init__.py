@@ -23,6 +23,7 @@ Every function cites the passage of the paper it follows:
   * ``footprint``: exact counts of the voxels and blocks each ray reads.
   * ``alloc_blocks`` / ``fuse``: block allocation from depth maps (Sec.
     3.4.1) and the depth, colour and semantic fusion of Sec. 3.4.2.
+  * ``denoise``: the Gaussian blur of Sec. 3.4.3 over allocated voxels.
 """
 from __future__ import annotations
 
@@ -372,3 +373,17 @@ def fuse(block_coords, h, origin, cams, depth, feat, trunc, n_sem=0):
                        _p(ft), _I32(C), _I32(W), _I32(H), _F(trunc), _I32(n_sem), _p(vox), _p(wt)),
            "fuse")
     return vox, wt
+
+
+def denoise(block_coords, vox, C, radius=1, sigma=1.0, with_mag=False):
+    """Gaussian blur of every channel over the allocated voxels of each
+    voxel's (2 radius + 1)^3 neighbourhood, weights renormalised (Sec.
+    3.4.3).  Returns out [n,512,1+C] (and the scale sum w|theta| / sum w)."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    out = np.empty(vx.shape, np.float64)
+    mag = np.empty(vx.shape, np.float64)
+    _check(lib.or_denoise(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _I32(radius), _D(sigma),
+                          _p(out), _p(mag)), "denoise")
+    return (out, mag) if with_mag else out

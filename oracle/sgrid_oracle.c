@@ -1030,3 +1030,57 @@ int or_fuse(const int32_t* block_coords, int64_t n_blocks, float h, const float 
   free(acc);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* De-noising (Sec. 3.4.3).                                                  */
+
+/*
+ * Gaussian blur of every property of every voxel over the allocated voxels
+ * of its (2 radius + 1)^3 neighbourhood:
+ *   out(v) = sum_d w(d) theta(v + d) / sum_d w(d),  w(d) = exp(-|d|^2 / (2 sigma^2)),
+ * both sums over the offsets d whose voxel v + d lies in an allocated block
+ * (the weights are renormalised where the neighbourhood leaves the grid).
+ * vox, out [n,512,1+C]; mag (nullable) [n,512,1+C] receives
+ * sum_d w(d) |theta(v + d)| / sum_d w(d) (the tolerance scale).
+ */
+int or_denoise(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
+               int32_t radius, double sigma, double* out, double* mag) {
+  if (n_blocks < 0 || C < 0 || radius < 0 || !(sigma > 0)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  const int V = 1 + C;
+  for (int64_t b = 0; b < n_blocks; ++b)
+    for (int l = 0; l < VOX_PER_BLOCK; ++l) {
+      const int32_t gi[3] = {8 * block_coords[3 * b] + (l & 7), 8 * block_coords[3 * b + 1] + ((l >> 3) & 7),
+                             8 * block_coords[3 * b + 2] + (l >> 6)};
+      double* o = out + ((size_t)b * VOX_PER_BLOCK + l) * V;
+      double* m = mag ? mag + ((size_t)b * VOX_PER_BLOCK + l) * V : NULL;
+      double wsum = 0.0;
+      for (int ch = 0; ch < V; ++ch) {
+        o[ch] = 0.0;
+        if (m) m[ch] = 0.0;
+      }
+      for (int dz = -radius; dz <= radius; ++dz)
+        for (int dy = -radius; dy <= radius; ++dy)
+          for (int dx = -radius; dx <= radius; ++dx) {
+            const int32_t j[3] = {gi[0] + dx, gi[1] + dy, gi[2] + dz};
+            const int64_t nb = table_find(&tb, floor_div8(j[0]), floor_div8(j[1]), floor_div8(j[2]));
+            if (nb < 0) continue;
+            const double w = exp(-(double)(dx * dx + dy * dy + dz * dz) / (2.0 * sigma * sigma));
+            const double* th =
+                vox + ((size_t)nb * VOX_PER_BLOCK + mod8(j[0]) + 8 * mod8(j[1]) + 64 * mod8(j[2])) * V;
+            wsum += w;
+            for (int ch = 0; ch < V; ++ch) {
+              o[ch] += w * th[ch];
+              if (m) m[ch] += w * fabs(th[ch]);
+            }
+          }
+      for (int ch = 0; ch < V; ++ch) {
+        o[ch] /= wsum; /* wsum > 0: the voxel itself is allocated */
+        if (m) m[ch] /= wsum;
+      }
+    }
+  table_free(&tb);
+  return 0;
+}
