@@ -217,6 +217,19 @@ int sg_fuse(const sg_grid* g, const float* d_cams, int32_t n_frames, const float
             const float* d_feat, int32_t C, int32_t W, int32_t H, float trunc, int32_t n_sem,
             float* d_vox, float* d_weight, sg_stream stream);
 
+/*
+ * sg_denoise -- Gaussian de-noising of the fused voxels (Sec. 3.4.3): every
+ * channel of every voxel v becomes
+ *   sum_d w(d) theta(v + d) / sum_d w(d),  w(d) = exp(-|d|^2 / (2 sigma^2)),
+ * over the offsets d in [-radius, radius]^3 (voxel units) whose voxel lies
+ * in an allocated block (the weights renormalise at the border of the
+ * grid).  d_vox, d_out [n_blocks,512,1+C]; d_out must not overlap d_vox.
+ * radius in [0, 8], sigma finite and > 0.  Device memory owned by the
+ * caller; asynchronous; allocates nothing.
+ */
+int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, float sigma,
+               float* d_out, sg_stream stream);
+
 /* Free the grid's device memory (waits for nothing; the caller makes sure no
  * launched work still uses the grid).  NULL is accepted. */
 int sg_grid_destroy(sg_grid* g);

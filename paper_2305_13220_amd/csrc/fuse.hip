@@ -1,6 +1,7 @@
-// Depth, colour and semantic fusion into the voxels of a grid (Sec. 3.4.2):
-// each voxel is projected into every frame and the associated observations
-// are averaged (the closed-form minimisers of the per-voxel squared losses).
+// Producing the voxels of a grid: depth, colour and semantic fusion
+// (Sec. 3.4.2) -- each voxel is projected into every frame and the
+// associated observations are averaged (the closed-form minimisers of the
+// per-voxel squared losses) -- and the Gaussian de-noising of Sec. 3.4.3.
 #include <climits>
 #include <cmath>
 
@@ -92,6 +93,55 @@ __global__ __launch_bounds__(256) void k_fuse(const int32_t* __restrict__ coords
   }
 }
 
+// Gaussian blur over allocated voxels (Sec. 3.4.3): one workgroup per block,
+// one lane per voxel.  The 27 blocks around the block (radius <= 8 keeps
+// every neighbourhood within them) are resolved once into LDS; each voxel
+// then sums w(d) theta(v + d) and w(d) over the offsets whose block exists
+// and divides (the weights renormalise where the neighbourhood leaves the
+// grid).  Reads of neighbouring voxels are shared through the caches.
+template <int C>
+__global__ __launch_bounds__(512) void k_denoise(GridView g, const int32_t* __restrict__ coords,
+                                                 const float* __restrict__ vox, int32_t radius,
+                                                 float inv_2s2, float* __restrict__ out) {
+  constexpr int V = 1 + C;
+  __shared__ int32_t nb[27];
+  const int64_t b = blockIdx.x;
+  const int t = threadIdx.x;
+  const int32_t bc[3] = {coords[3 * b], coords[3 * b + 1], coords[3 * b + 2]};
+  if (t < 27) {
+    const int32_t x = bc[0] + t % 3 - 1, y = bc[1] + (t / 3) % 3 - 1, z = bc[2] + t / 9 - 1;
+    int32_t idx = -1, nm = 0, dist = 0;
+    if (x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] && y <= g.bmax[1] && z >= g.bmin[2] &&
+        z <= g.bmax[2])
+      block_state(g, x, y, z, idx, nm, dist);
+    nb[t] = idx;
+  }
+  __syncthreads();
+  const int l[3] = {t & 7, (t >> 3) & 7, t >> 6};
+  float acc[V], wsum = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < V; ++ch) acc[ch] = 0.0f;
+  for (int dz = -radius; dz <= radius; ++dz)
+    for (int dy = -radius; dy <= radius; ++dy)
+      for (int dx = -radius; dx <= radius; ++dx) {
+        const int jx = l[0] + dx, jy = l[1] + dy, jz = l[2] + dz;
+        // block offset in {-1, 0, 1} per axis (floor division by 8)
+        const int ox = (jx >> 3) + 1, oy = (jy >> 3) + 1, oz = (jz >> 3) + 1;
+        const int32_t n = nb[ox + 3 * oy + 9 * oz];
+        if (n < 0) continue;
+        const float w = expf(-(float)(dx * dx + dy * dy + dz * dz) * inv_2s2);
+        const float* th = vox + ((int64_t)n * SG_BLOCK_VOXELS + (jx & 7) + 8 * (jy & 7) +
+                                 64 * (jz & 7)) * V;
+        wsum += w;
+#pragma unroll
+        for (int ch = 0; ch < V; ++ch) acc[ch] += w * th[ch];
+      }
+  float* o = out + (b * SG_BLOCK_VOXELS + t) * V;
+  const float inv = 1.0f / wsum;  // > 0: the voxel itself is allocated
+#pragma unroll
+  for (int ch = 0; ch < V; ++ch) o[ch] = acc[ch] * inv;
+}
+
 static bool fuse_C(int C) {
   return C == 0 || C == 1 || C == 2 || C == 3 || C == 4 || C == 8 || C == 16 || C == 19 ||
          C == 32;
@@ -138,6 +188,43 @@ int sg_fuse(const sg_grid* grid, const float* d_cams, int32_t n_frames, const fl
     SG_FUSE_CASE(19)
     SG_FUSE_CASE(32)
 #undef SG_FUSE_CASE
+    default:
+      break;
+  }
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_denoise(const sg_grid* grid, const float* d_vox, int32_t C, int32_t radius, float sigma,
+               float* d_out, sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!fuse_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (radius < 0 || radius > 8) return fail(SG_EINVAL, "radius must be in [0, 8]");
+  if (!(sigma > 0.0f) || !std::isfinite(sigma)) return fail(SG_EINVAL, "sigma must be finite and > 0");
+  if (!d_vox || !d_out) return fail(SG_EINVAL, "a required pointer is NULL");
+  if (d_vox == d_out) return fail(SG_EINVAL, "d_out must not be d_vox (the blur is not in place)");
+  if (grid->n_blocks == 0) return SG_OK;
+  if (grid->n_blocks > INT_MAX) return fail(SG_EINVAL, "too many blocks for one launch");
+  const GridView g = view_of(grid);
+  const float inv_2s2 = (float)(1.0 / (2.0 * (double)sigma * (double)sigma));
+  hipStream_t s = (hipStream_t)stream;
+  switch (C) {
+#define SG_DENOISE_CASE(CC)                                                                 \
+  case CC:                                                                                  \
+    hipLaunchKernelGGL(k_denoise<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, g,    \
+                       grid->d_coords, d_vox, radius, inv_2s2, d_out);                      \
+    break;
+    SG_DENOISE_CASE(0)
+    SG_DENOISE_CASE(1)
+    SG_DENOISE_CASE(2)
+    SG_DENOISE_CASE(3)
+    SG_DENOISE_CASE(4)
+    SG_DENOISE_CASE(8)
+    SG_DENOISE_CASE(16)
+    SG_DENOISE_CASE(19)
+    SG_DENOISE_CASE(32)
+#undef SG_DENOISE_CASE
     default:
       break;
   }

@@ -351,6 +351,19 @@ def fuse(grid: Grid, cams: torch.Tensor, depth: torch.Tensor, feat: torch.Tensor
     return vox, wt
 
 
+def denoise(grid: Grid, vox: torch.Tensor, radius: int = 1, sigma: float = 1.0, out=None):
+    """Gaussian blur of every channel over allocated voxels (Sec. 3.4.3)."""
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    if out is None:
+        out = torch.empty_like(vox)
+    else:
+        want(out, "out", torch.float32, tuple(vox.shape), grid.device)
+    check(lib().sg_denoise(grid.handle, ptr(vox), C, radius, ctypes.c_float(sigma), ptr(out),
+                           stream_ptr(grid.device)), "sg_denoise")
+    return out
+
+
 def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
     """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
     params = RenderParams.of(params)

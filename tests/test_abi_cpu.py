@@ -81,6 +81,7 @@ def test_render_validation(L):
     assert L.sg_eikonal(None, fake, 3, fake, 10, ctypes.c_float(1.0), None, None, None) == -1
     assert L.sg_fuse(None, fake, 1, fake, fake, 3, 4, 4, ctypes.c_float(0.1), 0, fake, None,
                      None) == -1
+    assert L.sg_denoise(None, fake, 3, 1, ctypes.c_float(1.0), fake, None) == -1
     n = ctypes.c_int64(5)
     org = (ctypes.c_float * 3)(0, 0, 0)
     assert L.sg_alloc_blocks(fake, 1, fake, 4, 4, ctypes.c_float(0.02), org, -1, ctypes.c_float(1),

@@ -107,3 +107,35 @@ def test_fuse_invalid_arguments():
         sg.alloc_blocks(cams, dep, 0.02, dilate=9)
     empty = sg.alloc_blocks(cams, torch.full_like(dep, float("nan")), 0.02)
     assert empty.shape == (0, 3)
+
+
+@pytest.mark.parametrize("radius,sigma,C", [(1, 1.0, 3), (2, 0.8, 0), (1, 1.5, 19)])
+def test_denoise_matches_oracle(radius, sigma, C):
+    """Gaussian de-noising (Sec. 3.4.3) within 1e-5 of sum w|theta| / sum w."""
+    sg = _sg()
+    from synth import workloads, scenes
+    from gpu_helpers import assert_close_mag, make_grid
+    if C == 3:
+        w = workloads.room_2cm()
+        vox = scenes.perturb(w["vox"], w["h"], seed=2)
+    else:
+        w = workloads.sphere_tiny()
+        rng = np.random.default_rng(8)
+        vox = np.concatenate([w["vox"][..., :1], rng.normal(size=w["vox"].shape[:2] + (C,))],
+                             -1).astype(np.float32)
+    g = make_grid(w)
+    out = sg.denoise(g, to_dev(vox), radius=radius, sigma=sigma).cpu().numpy()
+    want, mag = oracle.denoise(w["block_coords"], vox, C, radius=radius, sigma=sigma, with_mag=True)
+    assert_close_mag(out, want, mag, 1e-5, f"denoise r={radius} C={C}")
+
+
+def test_denoise_invalid_arguments():
+    sg = _sg()
+    from synth import workloads
+    from gpu_helpers import make_grid
+    w = workloads.sphere_tiny()
+    g = make_grid(w)
+    vox = to_dev(w["vox"])
+    for kw in ({"radius": 9}, {"sigma": 0.0}, {"out": vox}):
+        with pytest.raises(sg.SgridError):
+            sg.denoise(g, vox, **kw)
