@@ -99,6 +99,10 @@ __global__ void k_insert_first(const uint64_t* __restrict__ keys, int64_t n, Bui
   if (i >= n) return;
   const uint64_t key = keys[i];
   if (key == kEmptyKey) return;  // a masked-out entry
+  // An entry equal to its predecessor is not a first occurrence: skipping
+  // it leaves the minimum unchanged and spares the contended slot (runs of
+  // equal keys are common, e.g. neighbouring pixels in one block).
+  if (i > 0 && keys[i - 1] == key) return;
   uint64_t p = mix64(key) & mask;
   for (;;) {
     unsigned long long prev =
