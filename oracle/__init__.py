@@ -24,6 +24,9 @@ Every function cites the passage of the paper it follows:
   * ``alloc_blocks`` / ``fuse``: block allocation from depth maps (Sec.
     3.4.1) and the depth, colour and semantic fusion of Sec. 3.4.2.
   * ``denoise``: the Gaussian blur of Sec. 3.4.3 over allocated voxels.
+  * ``lattice_simplex`` / ``lattice_filter`` / ``crf_meanfield``: the
+    permutohedral-lattice Gaussian filter and the mean-field update of the
+    continuous CRF (Sec. 3.5.3).
 """
 from __future__ import annotations
 
@@ -387,3 +390,41 @@ def denoise(block_coords, vox, C, radius=1, sigma=1.0, with_mag=False):
     _check(lib.or_denoise(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _I32(radius), _D(sigma),
                           _p(out), _p(mag)), "denoise")
     return (out, mag) if with_mag else out
+
+
+def lattice_simplex(pos):
+    """Enclosing lattice simplex of each scaled position [N,d]: vertex keys
+    [N,d+1,d] (first d coordinates) and barycentric weights [N,d+1]."""
+    lib = _load()
+    ps = _c(pos, np.float32)
+    N, d = ps.shape
+    keys = np.empty((N, d + 1, d), np.int32)
+    w = np.empty((N, d + 1), np.float64)
+    _check(lib.or_lattice_simplex(_p(ps), _I64(N), _I32(d), _p(keys), _p(w)), "lattice_simplex")
+    return keys, w
+
+
+def lattice_filter(pos, val):
+    """Permutohedral-lattice Gaussian filter (splat, blur, slice) of values
+    [N,vd] at scaled positions [N,d].  Returns (out [N,vd], n_vertices)."""
+    lib = _load()
+    ps = _c(pos, np.float32)
+    N, d = ps.shape
+    v = _c(val, np.float64).reshape(N, -1)
+    out = np.empty_like(v)
+    nv = ctypes.c_int64(0)
+    _check(lib.or_lattice_filter(_p(ps), _I64(N), _I32(d), _p(v), _I32(v.shape[1]), _p(out),
+                                 ctypes.byref(nv)), "lattice_filter")
+    return out, nv.value
+
+
+def crf_meanfield(pos, unary, w_p, iters):
+    """Label marginals [N,L] after `iters` mean-field updates (Sec. 3.5.3)."""
+    lib = _load()
+    ps = _c(pos, np.float32)
+    N, d = ps.shape
+    u = _c(unary, np.float64).reshape(N, -1)
+    Q = np.empty_like(u)
+    _check(lib.or_crf_meanfield(_p(ps), _I64(N), _I32(d), _p(u), _I32(u.shape[1]), _D(w_p),
+                                _I32(iters), _p(Q)), "crf_meanfield")
+    return Q

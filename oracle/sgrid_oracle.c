@@ -1084,3 +1084,226 @@ int or_denoise(const int32_t* block_coords, int64_t n_blocks, const double* vox,
   table_free(&tb);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Permutohedral-lattice Gaussian filtering and a mean-field step of the     */
+/* continuous CRF (Sec. 3.5.3).                                              */
+
+#define LAT_MAX_D 16
+
+/* Enclosing simplex of a d-dimensional (already scaled) feature position in
+ * the permutohedral lattice A*_d: the position is lifted onto the plane
+ * sum x = 0 of R^{d+1}, the nearest lattice point of remainder 0 is found
+ * by rounding each coordinate to a multiple of d+1 and repairing the
+ * coordinate sum through the ranks of the residuals; the d+1 vertices are
+ * the remainder-0 point shifted by the canonical simplex of each remainder,
+ * with barycentric weights from the sorted residuals.  float32, in the
+ * order written (the vertices are integers decided in float32).
+ * keys [(d+1) x d] (the first d coordinates of each vertex), w [d+1]. */
+static void lattice_simplex(const float* pos, int d, int32_t* keys, double* w) {
+  float el[LAT_MAX_D + 1];
+  float sm = 0.0f;
+  for (int i = d; i >= 1; --i) {
+    const float scale = (float)(d + 1) * sqrtf(2.0f / 3.0f) / sqrtf((float)(i * (i + 1)));
+    const float cf = pos[i - 1] * scale;
+    el[i] = sm - (float)i * cf;
+    sm += cf;
+  }
+  el[0] = sm;
+  int32_t rem0[LAT_MAX_D + 1], rank[LAT_MAX_D + 1];
+  int sum = 0;
+  const float inv = 1.0f / (float)(d + 1);
+  for (int i = 0; i <= d; ++i) {
+    const float v = el[i] * inv;
+    const float up = ceilf(v) * (float)(d + 1), dn = floorf(v) * (float)(d + 1);
+    rem0[i] = (int32_t)((up - el[i] < el[i] - dn) ? up : dn);
+    sum += rem0[i] / (d + 1);
+    rank[i] = 0;
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = i + 1; j <= d; ++j) {
+      const float di = el[i] - (float)rem0[i], dj = el[j] - (float)rem0[j];
+      if (di < dj) ++rank[i];
+      else ++rank[j];
+    }
+  for (int i = 0; i <= d; ++i) {
+    if (sum > 0) {
+      if (rank[i] >= d + 1 - sum) {
+        rank[i] -= d + 1 - sum;
+        rem0[i] -= d + 1;
+      } else {
+        rank[i] += sum;
+      }
+    } else if (sum < 0) {
+      if (rank[i] < -sum) {
+        rank[i] += d + 1 + sum;
+        rem0[i] += d + 1;
+      } else {
+        rank[i] += sum;
+      }
+    }
+  }
+  double b[LAT_MAX_D + 2];
+  for (int i = 0; i <= d + 1; ++i) b[i] = 0.0;
+  for (int i = 0; i <= d; ++i) {
+    const double t = ((double)el[i] - (double)rem0[i]) / (double)(d + 1);
+    b[d - rank[i]] += t;
+    b[d + 1 - rank[i]] -= t;
+  }
+  b[0] += 1.0 + b[d + 1];
+  for (int r = 0; r <= d; ++r) {
+    w[r] = b[r];
+    for (int i = 0; i < d; ++i)
+      keys[r * d + i] = rank[i] <= d - r ? rem0[i] + r : rem0[i] + r - (d + 1);
+  }
+}
+
+typedef struct {
+  int d, vd;
+  int64_t cap, n;
+  int32_t* keys; /* [cap][d] */
+  uint8_t* used;
+  double* val;   /* [cap][vd] */
+} lattice;
+
+static uint64_t lat_hash(const int32_t* k, int d) {
+  uint64_t h = 1469598103934665603ull;
+  for (int i = 0; i < d; ++i) {
+    h ^= (uint64_t)(uint32_t)k[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+/* index of key k, inserting it if absent and insert != 0; -1 if absent */
+static int64_t lat_find(lattice* L, const int32_t* k, int insert) {
+  uint64_t s = lat_hash(k, L->d) & (uint64_t)(L->cap - 1);
+  for (;;) {
+    if (!L->used[s]) {
+      if (!insert) return -1;
+      L->used[s] = 1;
+      memcpy(L->keys + s * L->d, k, (size_t)L->d * sizeof(int32_t));
+      ++L->n;
+      return (int64_t)s;
+    }
+    if (memcmp(L->keys + s * L->d, k, (size_t)L->d * sizeof(int32_t)) == 0) return (int64_t)s;
+    s = (s + 1) & (uint64_t)(L->cap - 1);
+  }
+}
+
+/*
+ * Gaussian filtering of values [N,vd] at feature positions pos [N,d]
+ * (scaled so that the Gaussian has unit standard deviation per axis, as in
+ * the permutohedral-lattice method the paper uses for the message passing):
+ * splat each value onto the d+1 vertices of its simplex with its
+ * barycentric weights, blur the lattice along each of its d+1 directions
+ * with the [1/4, 1/2, 1/4] kernel (missing neighbours count as zero), and
+ * slice back with the same weights.  out [N,vd] is that (unnormalised)
+ * filter response; n_vertices (nullable) the number of lattice points.
+ * Returns -1 for bad sizes, -3 if out of memory.
+ */
+int or_lattice_filter(const float* pos, int64_t N, int32_t d, const double* val, int32_t vd,
+                      double* out, int64_t* n_vertices) {
+  if (d < 1 || d > LAT_MAX_D || vd < 1 || N < 0) return -1;
+  lattice L;
+  L.d = d;
+  L.vd = vd;
+  L.n = 0;
+  L.cap = 1;
+  while (L.cap < 2 * (N * (d + 1) + 1)) L.cap <<= 1;
+  L.keys = (int32_t*)malloc((size_t)L.cap * d * sizeof(int32_t));
+  L.used = (uint8_t*)calloc((size_t)L.cap, 1);
+  L.val = (double*)calloc((size_t)L.cap * vd, sizeof(double));
+  double* tmp = (double*)calloc((size_t)L.cap * vd, sizeof(double));
+  int64_t* vid = (int64_t*)malloc((size_t)(N > 0 ? N : 1) * (d + 1) * sizeof(int64_t));
+  double* bw = (double*)malloc((size_t)(N > 0 ? N : 1) * (d + 1) * sizeof(double));
+  if (!L.keys || !L.used || !L.val || !tmp || !vid || !bw) {
+    free(L.keys); free(L.used); free(L.val); free(tmp); free(vid); free(bw);
+    return -3;
+  }
+  int32_t keys[(LAT_MAX_D + 1) * LAT_MAX_D];
+  double w[LAT_MAX_D + 1];
+  for (int64_t i = 0; i < N; ++i) { /* splat */
+    lattice_simplex(pos + i * d, d, keys, w);
+    for (int r = 0; r <= d; ++r) {
+      const int64_t s = lat_find(&L, keys + r * d, 1);
+      vid[i * (d + 1) + r] = s;
+      bw[i * (d + 1) + r] = w[r];
+      for (int c = 0; c < vd; ++c) L.val[s * vd + c] += w[r] * val[i * vd + c];
+    }
+  }
+  int32_t nk[LAT_MAX_D];
+  for (int j = 0; j <= d; ++j) { /* blur along direction j */
+    for (int64_t s = 0; s < L.cap; ++s) {
+      if (!L.used[s]) continue;
+      const int32_t* k = L.keys + s * d;
+      double* o = tmp + s * vd;
+      for (int c = 0; c < vd; ++c) o[c] = 0.5 * L.val[s * vd + c];
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        /* neighbour: +/- ((1,...,1) - (d+1) e_j), first d coordinates */
+        for (int i = 0; i < d; ++i) nk[i] = k[i] + sgn * (i == j ? -d : 1);
+        const int64_t t = lat_find(&L, nk, 0);
+        if (t < 0) continue;
+        for (int c = 0; c < vd; ++c) o[c] += 0.25 * L.val[t * vd + c];
+      }
+    }
+    double* sw = L.val;
+    L.val = tmp;
+    tmp = sw;
+  }
+  for (int64_t i = 0; i < N; ++i) /* slice */
+    for (int c = 0; c < vd; ++c) {
+      double acc = 0.0;
+      for (int r = 0; r <= d; ++r) acc += bw[i * (d + 1) + r] * L.val[vid[i * (d + 1) + r] * vd + c];
+      out[i * vd + c] = acc;
+    }
+  if (n_vertices) *n_vertices = L.n;
+  free(L.keys); free(L.used); free(L.val); free(tmp); free(vid); free(bw);
+  return 0;
+}
+
+/* The simplex of each position (see lattice_simplex): keys [N][d+1][d],
+ * weights [N][d+1]. */
+int or_lattice_simplex(const float* pos, int64_t N, int32_t d, int32_t* keys, double* w) {
+  if (d < 1 || d > LAT_MAX_D || N < 0) return -1;
+  for (int64_t i = 0; i < N; ++i)
+    lattice_simplex(pos + i * d, d, keys + i * (int64_t)(d + 1) * d, w + i * (d + 1));
+  return 0;
+}
+
+/*
+ * Mean-field inference of the CRF's label distribution (Sec. 3.5.3, after
+ * Krahenbuhl and Koltun): Q = softmax(-unary), then T times
+ *   Q(x_i) <- softmax_l( -unary_i(l) + w_p * m_i(l) ),  m = lattice filter of Q,
+ * the update of the mean-field equation with a Potts compatibility of
+ * weight w_p (the sum over the other labels differs from -m_i(l) by a
+ * per-point constant, which the softmax removes).  The message includes
+ * each point's own contribution.  unary, Q [N,L].
+ */
+int or_crf_meanfield(const float* pos, int64_t N, int32_t d, const double* unary, int32_t L,
+                     double w_p, int32_t T, double* Q) {
+  if (L < 1 || T < 0) return -1;
+  double* m = (double*)malloc((size_t)(N > 0 ? N : 1) * L * sizeof(double));
+  if (!m) return -3;
+  for (int64_t i = 0; i < N; ++i) {
+    double mx = -INFINITY, s = 0.0;
+    for (int l = 0; l < L; ++l) mx = fmax(mx, -unary[i * L + l]);
+    for (int l = 0; l < L; ++l) s += exp(-unary[i * L + l] - mx);
+    for (int l = 0; l < L; ++l) Q[i * L + l] = exp(-unary[i * L + l] - mx) / s;
+  }
+  for (int it = 0; it < T; ++it) {
+    int rc = or_lattice_filter(pos, N, d, Q, L, m, NULL);
+    if (rc) {
+      free(m);
+      return rc;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      double mx = -INFINITY, s = 0.0;
+      for (int l = 0; l < L; ++l) mx = fmax(mx, -unary[i * L + l] + w_p * m[i * L + l]);
+      for (int l = 0; l < L; ++l) s += exp(-unary[i * L + l] + w_p * m[i * L + l] - mx);
+      for (int l = 0; l < L; ++l) Q[i * L + l] = exp(-unary[i * L + l] + w_p * m[i * L + l] - mx) / s;
+    }
+  }
+  free(m);
+  return 0;
+}

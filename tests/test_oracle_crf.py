@@ -1,0 +1,143 @@
+"""Pins of the oracle's permutohedral-lattice filter and mean-field update
+(the message passing of the continuous CRF, Sec. 3.5.3).
+
+* Simplex: the d+1 vertices lie on the lattice (coordinates sum to zero,
+  all congruent mod d+1 after the canonical shift), the barycentric weights
+  are in [0,1] and sum to 1, and the weighted vertices reproduce the lifted
+  position (lifting written here from the definition of the lattice scale).
+* Splat / blur / slice against the same steps written with a Python dict
+  over full lattice coordinates, the blur directions taken from the lattice
+  definition; d = 1 against linear splatting, two [1,2,1]/4 passes and
+  linear slicing on the integer line (numpy); far clusters do not interact.
+* Mean field: zero pairwise weight gives softmax(-unary); with a Potts
+  weight, the update equals softmax(-unary + w F(Q)) computed here from the
+  oracle's own filter (one step), and distributions stay normalised.
+"""
+import numpy as np
+import pytest
+
+
+def _lift(p):
+    """Position on the plane sum x = 0 of R^{d+1}, lattice scale of the method."""
+    N, d = p.shape
+    el = np.zeros((N, d + 1))
+    sm = np.zeros(N)
+    for i in range(d, 0, -1):
+        scale = (d + 1) * np.sqrt(2.0 / 3.0) / np.sqrt(i * (i + 1))
+        cf = p[:, i - 1] * scale
+        el[:, i] = sm - i * cf
+        sm += cf
+    el[:, 0] = sm
+    return el
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8])
+def test_simplex_reproduces_the_lifted_position(oracle_lib, d):
+    rng = np.random.default_rng(d)
+    p = rng.normal(scale=3.0, size=(500, d)).astype(np.float32)
+    keys, w = oracle_lib.lattice_simplex(p)
+    full = np.concatenate([keys, -keys.sum(-1, keepdims=True)], -1).astype(np.float64)  # [N,d+1,d+1]
+    # every vertex: coordinates congruent to each other mod d+1 (a lattice point)
+    m = np.mod(full, d + 1)
+    assert (m == m[..., :1]).all()
+    assert (w >= -1e-6).all() and (w <= 1 + 1e-6).all()
+    np.testing.assert_allclose(w.sum(-1), 1.0, atol=1e-9)
+    rec = (w[..., None] * full).sum(1)
+    np.testing.assert_allclose(rec, _lift(p.astype(np.float64)), atol=2e-5 * (1 + np.abs(p).max()))
+    # the d+1 vertices are distinct and pairwise adjacent (differ by a 0/1 pattern times d+1 shift)
+    for i in range(0, 500, 50):
+        assert len({tuple(v) for v in keys[i]}) == d + 1
+
+
+def _dict_filter(keys, w, v):
+    """Splat / blur / slice written with a Python dict over full lattice
+    coordinates (d+1 of them, summing to zero); blur direction j moves by
+    +-((1,...,1) - (d+1) e_j), vertices that were never splatted stay absent."""
+    N, d1, d = keys.shape
+    full = np.concatenate([keys, -keys.sum(-1, keepdims=True)], -1)
+    lat = {}
+    for i in range(N):
+        for r in range(d1):
+            k = tuple(full[i, r])
+            lat[k] = lat.get(k, 0.0) + w[i, r] * v[i]
+    for j in range(d1):
+        step = np.ones(d1, int)
+        step[j] -= d1
+        new = {}
+        for k, val in lat.items():
+            kk = np.array(k)
+            acc = 0.5 * val
+            for sgn in (-1, 1):
+                nb = tuple(kk + sgn * step)
+                if nb in lat:
+                    acc = acc + 0.25 * lat[nb]
+            new[k] = acc
+        lat = new
+    out = np.zeros_like(v)
+    for i in range(N):
+        for r in range(d1):
+            out[i] += w[i, r] * lat[tuple(full[i, r])]
+    return out, len(lat)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_filter_matches_dict_lattice(oracle_lib, d):
+    rng = np.random.default_rng(20 + d)
+    p = rng.normal(scale=1.5, size=(250, d)).astype(np.float32)
+    v = rng.normal(size=(250, 2))
+    out, nv = oracle_lib.lattice_filter(p, v)
+    keys, w = oracle_lib.lattice_simplex(p)
+    want, n_want = _dict_filter(keys, w, v)
+    np.testing.assert_allclose(out, want, rtol=1e-10, atol=1e-12)
+    assert nv == n_want
+
+
+def test_d1_filter_is_linear_splat_blur_slice(oracle_lib):
+    """d = 1: the lattice is the integer line (coordinate 2/sqrt(3) p); the
+    filter is linear splatting, two [1,2,1]/4 passes over the splatted
+    points, and linear slicing."""
+    rng = np.random.default_rng(7)
+    p = rng.uniform(-2.0, 2.0, size=(400, 1)).astype(np.float32)
+    v = rng.normal(size=(400, 2))
+    out, nv = oracle_lib.lattice_filter(p, v)
+    y = p[:, 0].astype(np.float64) * 2.0 / np.sqrt(3.0)
+    lo = np.floor(y).astype(int)
+    fr = y - lo
+    base = lo.min() - 3
+    size = lo.max() - base + 5
+    grid = np.zeros((size, 2))
+    np.add.at(grid, lo - base, (1 - fr)[:, None] * v)
+    np.add.at(grid, lo + 1 - base, fr[:, None] * v)
+    mask = np.zeros(size)
+    mask[lo - base] = 1
+    mask[lo + 1 - base] = 1
+    k = np.array([1, 2, 1]) / 4.0
+    for _ in range(2):
+        grid = np.stack([np.convolve(grid[:, c], k, mode="same") for c in range(2)], -1) * mask[:, None]
+    want = (1 - fr)[:, None] * grid[lo - base] + fr[:, None] * grid[lo + 1 - base]
+    np.testing.assert_allclose(out, want, atol=1e-6)
+    assert nv == int(mask.sum())
+
+
+def test_far_clusters_do_not_interact(oracle_lib):
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(50, 4)).astype(np.float32)
+    b = (rng.normal(size=(50, 4)) + 100.0).astype(np.float32)
+    va, vb = rng.normal(size=(50, 1)), rng.normal(size=(50, 1))
+    both, _ = oracle_lib.lattice_filter(np.concatenate([a, b]), np.concatenate([va, vb]))
+    np.testing.assert_allclose(both[:50], oracle_lib.lattice_filter(a, va)[0], rtol=1e-12)
+    np.testing.assert_allclose(both[50:], oracle_lib.lattice_filter(b, vb)[0], rtol=1e-12)
+
+
+def test_meanfield_update(oracle_lib):
+    rng = np.random.default_rng(3)
+    N, d, L = 200, 3, 4
+    p = rng.normal(scale=1.5, size=(N, d)).astype(np.float32)
+    U = rng.normal(size=(N, L))
+    sm = lambda a: np.exp(a - a.max(1, keepdims=True)) / np.exp(a - a.max(1, keepdims=True)).sum(1, keepdims=True)
+    np.testing.assert_allclose(oracle_lib.crf_meanfield(p, U, 0.0, 3), sm(-U), rtol=1e-12)
+    Q1 = oracle_lib.crf_meanfield(p, U, 0.7, 1)
+    F, _ = oracle_lib.lattice_filter(p, sm(-U))
+    np.testing.assert_allclose(Q1, sm(-U + 0.7 * F), rtol=1e-12)
+    Q3 = oracle_lib.crf_meanfield(p, U, 0.7, 3)
+    np.testing.assert_allclose(Q3.sum(1), 1.0, atol=1e-12)
