@@ -328,6 +328,58 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5):
     return res
 
 
+def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
+    """Continuous-CRF message passing (Sec. 3.5.3) on 2^18 surface samples of
+    the room: lattice build over 6-D features (xyz / 20 cm, rgb / 0.3), one
+    16-channel lattice filter, and 5 mean-field updates of 16 labels."""
+    import numpy as np
+    import torch
+    import paper_2305_13220_amd as sg
+    from synth import cameras, workloads
+    t0 = time.perf_counter()
+    fr = workloads.room_depth_frames(n_frames=10, W=640, H=480, n_sem=n_sem)
+    pix = np.concatenate([cameras.frame_pixels(i, 640, 480) for i in range(10)])
+    d = fr["depth"].reshape(-1)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(np.flatnonzero(np.isfinite(d)), n, replace=False)
+    rays = cameras.pixel_rays(fr["cams"], pix[idx]).astype(np.float64)
+    Rz = fr["cams"][pix[idx, 0], 4:].astype(np.float64).reshape(-1, 3, 4)[:, :, 2]
+    t = d[idx] / np.einsum("ij,ij->i", rays[:, 3:], Rz)
+    xyz = rays[:, :3] + t[:, None] * rays[:, 3:]
+    feat = fr["feat"].reshape(-1, 3 + n_sem)[idx]
+    pos = torch.from_numpy(np.concatenate([xyz / 0.2, feat[:, :3] / 0.3], 1).astype(np.float32)).to(dev)
+    unary = torch.from_numpy((-np.log(feat[:, 3:] * 0.7 + 0.3 / n_sem)).astype(np.float32)).to(dev)
+    log(f"crf setup {time.perf_counter() - t0:.1f}s")
+    sg.Lattice(pos, max_values=n_sem)
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        lat = sg.Lattice(pos, max_values=n_sem)
+        tb.append(time.perf_counter() - a)
+    Q = lat.meanfield(unary, 5.0, 1)
+    out = lat.filter(Q)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        lat.filter(Q, out=out)
+    e[1].record()
+    for _ in range(reps):
+        lat.meanfield(unary, 5.0, iters, out=Q)
+    e[2].record()
+    torch.cuda.synchronize()
+    f_ms = e[0].elapsed_time(e[1]) / reps
+    mf_ms = e[1].elapsed_time(e[2]) / reps
+    res = {"workload": "room_surface_2^18_samples_d6_16labels", "points": n, "d": 6,
+           "lattice_vertices": lat.n_vertices,
+           "build_ms": round(float(np.median(tb)) * 1e3, 3), "filter_ms": round(f_ms, 4),
+           "meanfield_ms": round(mf_ms, 4), "meanfield_iters": iters,
+           "points_per_s_per_update": n * iters / (mf_ms * 1e-3)}
+    del lat, pos, unary, Q, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
     """SDF and gradient at the k^3 lattice points of the grid's bounding box
     (the point-query timing of Sec. 4), one sg_query call per k.  Bytes per
@@ -392,6 +444,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the k^3 point-query timing")
+    ap.add_argument("--no-crf", action="store_true", help="skip the CRF message-passing timing")
     ap.add_argument("--no-fusion", action="store_true",
                     help="skip the allocation + fusion timing")
     ap.add_argument("--no-frames", action="store_true",
@@ -591,6 +644,8 @@ def main():
         res["query"] = query_bench(grid, vox, w["block_coords"], dev)
     if not args.no_fusion:
         res["fusion"] = fusion_bench(dev)
+    if not args.no_crf:
+        res["crf"] = crf_bench(dev)
     if not args.no_serve:
         res["serving"] = serve_bench(args, dev)
     if not args.no_cpu:

@@ -230,6 +230,44 @@ int sg_fuse(const sg_grid* g, const float* d_cams, int32_t n_frames, const float
 int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, float sigma,
                float* d_out, sg_stream stream);
 
+/*
+ * Continuous CRF message passing (Sec. 3.5.3): the mean-field update of the
+ * CRF is a high-dimensional Gaussian filter over the feature vectors of the
+ * surface samples, evaluated on a permutohedral lattice held in a
+ * collision-free hash of lattice points.
+ *
+ * sg_lattice_build -- the lattice of n_points feature positions d_pos
+ *   float [n,d], 1 <= d <= 16, already divided by the per-feature standard
+ *   deviations (finite, |p| < 2^20): each position's enclosing simplex (d+1
+ *   vertices and barycentric weights; float32 without fused multiply-add,
+ *   so the vertices are the same integers for any evaluation of the same
+ *   steps) and the hash of all vertices.  max_values (1..32) bounds the
+ *   value channels of later filters.  Allocates device memory and
+ *   synchronises the stream.  SG_ERANGE if two lattice keys share a 64-bit
+ *   fingerprint (checked, never silently merged).
+ * sg_lattice_filter -- d_out [n, n_values] = slice(blur(splat(d_val))):
+ *   values splatted onto the simplex vertices with the barycentric weights,
+ *   blurred with [1/4, 1/2, 1/4] along each of the d+1 lattice directions
+ *   (absent neighbours add nothing), and sliced back with the same weights
+ *   (unnormalised; filter a channel of ones to normalise).  Splatting uses
+ *   float atomics: the last bits depend on their order.  Asynchronous;
+ *   allocates nothing.
+ * sg_crf_meanfield -- label marginals d_Q [n, n_labels] after `iters`
+ *   mean-field updates Q <- softmax(-unary + w_p * filter(Q)) from
+ *   Q = softmax(-unary) (a Potts compatibility of weight w_p; the message
+ *   includes each point's own contribution).  d_unary [n, n_labels].
+ *   Asynchronous; allocates nothing.
+ */
+typedef struct sg_lattice sg_lattice;
+int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
+                     sg_stream stream, sg_lattice** out);
+int sg_lattice_num_vertices(const sg_lattice* lat, int64_t* n_vertices);
+int sg_lattice_filter(const sg_lattice* lat, const float* d_val, int32_t n_values, float* d_out,
+                      sg_stream stream);
+int sg_crf_meanfield(const sg_lattice* lat, const float* d_unary, int32_t n_labels, float w_p,
+                     int32_t iters, float* d_Q, sg_stream stream);
+int sg_lattice_destroy(sg_lattice* lat);
+
 /* Free the grid's device memory (waits for nothing; the caller makes sure no
  * launched work still uses the grid).  NULL is accepted. */
 int sg_grid_destroy(sg_grid* g);

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsgrid.so")
-SOURCES = ["grid.hip", "render.hip", "aux.hip", "fuse.hip"]
+SOURCES = ["grid.hip", "render.hip", "aux.hip", "fuse.hip", "lattice.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

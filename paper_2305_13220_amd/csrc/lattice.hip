@@ -1,0 +1,430 @@
+// Permutohedral-lattice Gaussian filtering on a collision-free hash of
+// lattice points, and the mean-field update of the continuous CRF
+// (Sec. 3.5.3): the message passing of the mean-field equation is a
+// high-dimensional Gaussian filter, evaluated by splatting onto the
+// vertices of each point's enclosing simplex, blurring along the d+1
+// lattice directions and slicing back.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace sg {
+
+constexpr int kLatMaxD = 16;
+constexpr int kLatMaxV = 32;
+
+// Enclosing simplex of one scaled position (float32, no fused multiply-add,
+// in this order, so the integer vertices match any other evaluation of the
+// same steps): the position is lifted onto the plane sum x = 0 of R^{d+1},
+// rounded to the nearest remainder-0 lattice point through the ranks of the
+// residuals, and the barycentric weights follow from the sorted residuals.
+// Vertex r has coordinates rem0[i] + r (rank[i] <= d - r) or
+// rem0[i] + r - (d+1) otherwise; only the first d are stored.
+struct Simplex {
+  int32_t rem0[kLatMaxD + 1], rank[kLatMaxD + 1];
+  float w[kLatMaxD + 2];
+};
+
+__device__ inline void lattice_simplex(const float* __restrict__ pos, int d, Simplex& s) {
+#pragma clang fp contract(off)
+  float el[kLatMaxD + 1];
+  float sm = 0.0f;
+  for (int i = d; i >= 1; --i) {
+    const float scale = (float)(d + 1) * sqrtf(2.0f / 3.0f) / sqrtf((float)(i * (i + 1)));
+    const float cf = pos[i - 1] * scale;
+    el[i] = sm - (float)i * cf;
+    sm += cf;
+  }
+  el[0] = sm;
+  int sum = 0;
+  const float inv = 1.0f / (float)(d + 1);
+  for (int i = 0; i <= d; ++i) {
+    const float v = el[i] * inv;
+    const float up = ceilf(v) * (float)(d + 1), dn = floorf(v) * (float)(d + 1);
+    s.rem0[i] = (int32_t)((up - el[i] < el[i] - dn) ? up : dn);
+    sum += s.rem0[i] / (d + 1);
+    s.rank[i] = 0;
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = i + 1; j <= d; ++j) {
+      const float di = el[i] - (float)s.rem0[i], dj = el[j] - (float)s.rem0[j];
+      if (di < dj) ++s.rank[i];
+      else ++s.rank[j];
+    }
+  for (int i = 0; i <= d; ++i) {
+    if (sum > 0) {
+      if (s.rank[i] >= d + 1 - sum) {
+        s.rank[i] -= d + 1 - sum;
+        s.rem0[i] -= d + 1;
+      } else {
+        s.rank[i] += sum;
+      }
+    } else if (sum < 0) {
+      if (s.rank[i] < -sum) {
+        s.rank[i] += d + 1 + sum;
+        s.rem0[i] += d + 1;
+      } else {
+        s.rank[i] += sum;
+      }
+    }
+  }
+  for (int i = 0; i <= d + 1; ++i) s.w[i] = 0.0f;
+  for (int i = 0; i <= d; ++i) {
+    const float t = (el[i] - (float)s.rem0[i]) * inv;
+    s.w[d - s.rank[i]] += t;
+    s.w[d + 1 - s.rank[i]] -= t;
+  }
+  s.w[0] += 1.0f + s.w[d + 1];
+}
+
+__device__ inline int32_t vertex_coord(const Simplex& s, int d, int r, int i) {
+  return s.rank[i] <= d - r ? s.rem0[i] + r : s.rem0[i] + r - (d + 1);
+}
+
+// 64-bit fingerprint of a key (never the empty marker).
+__device__ inline uint64_t key_fp(const int32_t* k, int d) {
+  uint64_t h = 0x9e3779b97f4a7c15ull;
+  for (int i = 0; i < d; ++i) h = mix64(h ^ ((uint64_t)(uint32_t)k[i] + 0x632be59bd9b4e019ull * (i + 1)));
+  return h == kEmptyKey ? h - 1 : h;
+}
+
+struct LatView {
+  uint64_t* fp;    // [cap] fingerprints (kEmptyKey: free)
+  int32_t* keys;   // [cap][d]
+  uint64_t mask;   // cap - 1
+  int d;
+};
+
+// Slot of a key: insert (the CAS winner writes the full key) or find.
+__device__ inline int64_t lat_slot(const LatView& L, const int32_t* k, bool insert) {
+  const uint64_t f = key_fp(k, L.d);
+  uint64_t s = mix64(f) & L.mask;
+  for (;;) {
+    const uint64_t cur = insert ? (uint64_t)atomicCAS((unsigned long long*)&L.fp[s],
+                                                      (unsigned long long)kEmptyKey,
+                                                      (unsigned long long)f)
+                                : L.fp[s];
+    if (cur == kEmptyKey) {
+      if (!insert) return -1;
+      for (int i = 0; i < L.d; ++i) L.keys[s * L.d + i] = k[i];
+      return (int64_t)s;
+    }
+    if (cur == f) return (int64_t)s;
+    s = (s + 1) & L.mask;
+  }
+}
+
+// Per point: simplex, insertion of its d+1 vertices (mode 0), or the check
+// that every vertex's slot holds its full key (mode 1: a fingerprint
+// collision raises the error flag).
+__global__ void k_lat_simplex(const float* __restrict__ pos, int64_t N, LatView L, int mode,
+                              int32_t* __restrict__ vid, float* __restrict__ bw,
+                              int* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int d = L.d;
+  // Positions must be finite and moderate (|p| < 2^20), so that the lifted
+  // coordinates and the vertex keys stay within int32 and the ranks form a
+  // permutation; otherwise the build fails (error bit 2).
+  for (int c = 0; c < d; ++c)
+    if (!(fabsf(pos[i * d + c]) < 1048576.0f)) {
+      atomicOr(err, 2);
+      return;
+    }
+  Simplex s;
+  lattice_simplex(pos + i * d, d, s);
+  int32_t k[kLatMaxD];
+  for (int r = 0; r <= d; ++r) {
+    for (int c = 0; c < d; ++c) k[c] = vertex_coord(s, d, r, c);
+    if (mode == 0) {
+      const int64_t slot = lat_slot(L, k, true);
+      vid[i * (d + 1) + r] = (int32_t)slot;
+      bw[i * (d + 1) + r] = s.w[r];
+    } else {
+      const int64_t slot = vid[i * (d + 1) + r];
+      bool same = true;
+      for (int c = 0; c < d; ++c) same = same && L.keys[slot * d + c] == k[c];
+      if (!same) atomicOr(err, 1);
+    }
+  }
+}
+
+__global__ void k_lat_count(const uint64_t* __restrict__ fp, int64_t cap, int64_t* __restrict__ n) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool used = s < cap && fp[s] != kEmptyKey;
+  const uint64_t b = __ballot(used);
+  if (lane_id() == 0 && b) atomicAdd((unsigned long long*)n, (unsigned long long)__popcll(b));
+}
+
+__global__ void k_lat_zero(float* __restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = 0.0f;
+}
+
+__global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __restrict__ bw,
+                            int64_t N, int d, const float* __restrict__ val, int vd,
+                            float* __restrict__ lv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * (d + 1)) return;
+  const int64_t i = t / (d + 1);
+  const int64_t slot = vid[t];
+  const float w = bw[t];
+  for (int c = 0; c < vd; ++c) unsafeAtomicAdd(lv + slot * vd + c, w * val[i * vd + c]);
+}
+
+// Blur along direction j: new = v/2 + (v(n-) + v(n+))/4, n+- = key +-
+// ((1,...,1) - (d+1) e_j) (first d coordinates); absent neighbours add 0.
+__global__ void k_lat_blur(LatView L, int64_t cap, int j, const float* __restrict__ src, int vd,
+                           float* __restrict__ dst) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= cap || L.fp[s] == kEmptyKey) return;
+  const int d = L.d;
+  // fixed-size loops with guards keep the arrays in registers
+  float acc[kLatMaxV];
+#pragma unroll
+  for (int c = 0; c < kLatMaxV; ++c) acc[c] = c < vd ? 0.5f * src[s * vd + c] : 0.0f;
+  int32_t nk[kLatMaxD];
+#pragma unroll
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+#pragma unroll
+    for (int c = 0; c < kLatMaxD; ++c)
+      nk[c] = c < d ? L.keys[s * d + c] + sgn * (c == j ? -d : 1) : 0;
+    const int64_t t = lat_slot(L, nk, false);
+    if (t < 0) continue;
+    bool same = true;
+#pragma unroll
+    for (int c = 0; c < kLatMaxD; ++c) same = same && (c >= d || L.keys[t * d + c] == nk[c]);
+    if (!same) continue;  // a fingerprint alias of an absent key: no neighbour
+#pragma unroll
+    for (int c = 0; c < kLatMaxV; ++c)
+      if (c < vd) acc[c] += 0.25f * src[t * vd + c];
+  }
+#pragma unroll
+  for (int c = 0; c < kLatMaxV; ++c)
+    if (c < vd) dst[s * vd + c] = acc[c];
+}
+
+__global__ void k_lat_slice(const int32_t* __restrict__ vid, const float* __restrict__ bw,
+                            int64_t N, int d, const float* __restrict__ lv, int vd,
+                            float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float acc[kLatMaxV];
+#pragma unroll
+  for (int c = 0; c < kLatMaxV; ++c) acc[c] = 0.0f;
+  for (int r = 0; r <= d; ++r) {
+    const int64_t slot = vid[i * (d + 1) + r];
+    const float w = bw[i * (d + 1) + r];
+#pragma unroll
+    for (int c = 0; c < kLatMaxV; ++c)
+      if (c < vd) acc[c] += w * lv[slot * vd + c];
+  }
+#pragma unroll
+  for (int c = 0; c < kLatMaxV; ++c)
+    if (c < vd) out[i * vd + c] = acc[c];
+}
+
+// Q = softmax(-unary + w_p * m) per point (m may be null: w_p ignored).
+__global__ void k_softmax(const float* __restrict__ unary, const float* __restrict__ m, float w_p,
+                          int64_t N, int Lb, float* __restrict__ Q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float a[kLatMaxV];
+  float mx = -INFINITY;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    a[l] = l < Lb ? -unary[i * Lb + l] + (m ? w_p * m[i * Lb + l] : 0.0f) : -INFINITY;
+    mx = fmaxf(mx, a[l]);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    a[l] = l < Lb ? expf(a[l] - mx) : 0.0f;
+    s += a[l];
+  }
+  const float inv = 1.0f / s;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l)
+    if (l < Lb) Q[i * Lb + l] = a[l] * inv;
+}
+
+static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace sg
+
+struct sg_lattice {
+  uint32_t magic;
+  int d, vmax;
+  int64_t N, cap, n_vertices;
+  uint64_t* fp;
+  int32_t* keys;
+  int32_t* vid;
+  float* bw;
+  float* v0;
+  float* v1;
+  float* m;  // [N, vmax] message buffer of the mean-field update
+};
+
+namespace sg {
+constexpr uint32_t kLatMagic = 0x4c415454u;  // "LATT"
+static int check_lat(const sg_lattice* L) {
+  if (!L) return fail(SG_EINVAL, "lattice is NULL");
+  if (L->magic != kLatMagic) return fail(SG_ESTATE, "lattice handle is not a live lattice");
+  return SG_OK;
+}
+static void free_lat(sg_lattice* L) {
+  (void)hipFree(L->fp);
+  (void)hipFree(L->keys);
+  (void)hipFree(L->vid);
+  (void)hipFree(L->bw);
+  (void)hipFree(L->v0);
+  (void)hipFree(L->v1);
+  (void)hipFree(L->m);
+  delete L;
+}
+static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_out, hipStream_t s) {
+  const int T = 256;
+  const int d = L->d;
+  const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d};
+  k_lat_zero<<<grid_of(L->cap * vd, T), T, 0, s>>>(L->v0, L->cap * vd);
+  k_lat_splat<<<grid_of(L->N * (d + 1), T), T, 0, s>>>(L->vid, L->bw, L->N, d, d_val, vd, L->v0);
+  float* a = L->v0;
+  float* b = L->v1;
+  for (int j = 0; j <= d; ++j) {
+    k_lat_blur<<<grid_of(L->cap, T), T, 0, s>>>(V, L->cap, j, a, vd, b);
+    float* t = a;
+    a = b;
+    b = t;
+  }
+  k_lat_slice<<<grid_of(L->N, T), T, 0, s>>>(L->vid, L->bw, L->N, d, a, vd, d_out);
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
+                     sg_stream stream, sg_lattice** out) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > kLatMaxD) return fail(SG_EINVAL, "d must be in [1, 16]");
+  if (max_values < 1 || max_values > kLatMaxV) return fail(SG_EINVAL, "max_values must be in [1, 32]");
+  if (n_points < 1 || n_points * (d + 1) > (int64_t)INT_MAX / 2)
+    return fail(SG_EINVAL, "n_points must be >= 1 and n_points * (d+1) < 2^30");
+  if (!d_pos) return fail(SG_EINVAL, "d_pos is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  sg_lattice* L = new sg_lattice();
+  memset(L, 0, sizeof(*L));
+  L->d = d;
+  L->vmax = max_values;
+  L->N = n_points;
+  L->cap = 1;
+  while (L->cap < 2 * n_points * (d + 1)) L->cap <<= 1;
+  const size_t sz[7] = {sizeof(uint64_t) * L->cap, sizeof(int32_t) * L->cap * d,
+                        sizeof(int32_t) * n_points * (d + 1), sizeof(float) * n_points * (d + 1),
+                        sizeof(float) * L->cap * max_values, sizeof(float) * L->cap * max_values,
+                        sizeof(float) * n_points * max_values};
+  void** ptrs[7] = {(void**)&L->fp, (void**)&L->keys, (void**)&L->vid, (void**)&L->bw,
+                    (void**)&L->v0, (void**)&L->v1, (void**)&L->m};
+  for (int k = 0; k < 7; ++k)
+    if (hipMalloc(ptrs[k], sz[k]) != hipSuccess) {
+      (void)hipGetLastError();
+      free_lat(L);
+      return fail(SG_ENOMEM, "device allocation for the lattice failed");
+    }
+  int* d_err = nullptr;
+  int64_t* d_n = nullptr;
+  if (hipMalloc((void**)&d_err, sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&d_n, sizeof(int64_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(d_err);
+    free_lat(L);
+    return fail(SG_ENOMEM, "device allocation for the lattice failed");
+  }
+  const int T = 256;
+  const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d};
+  int rc = SG_OK;
+  int err = 0;
+  int64_t nv = 0;
+  if (hipMemsetAsync(L->fp, 0xff, sz[0], s) != hipSuccess ||
+      hipMemsetAsync(d_err, 0, sizeof(int), s) != hipSuccess ||
+      hipMemsetAsync(d_n, 0, sizeof(int64_t), s) != hipSuccess) {
+    rc = fail(SG_EHIP, "hipMemsetAsync failed");
+  } else {
+    k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 0, L->vid, L->bw, d_err);
+    k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 1, L->vid, L->bw, d_err);
+    k_lat_count<<<grid_of(L->cap, T), T, 0, s>>>(L->fp, L->cap, d_n);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nv, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "lattice build");
+    else if (err & 2) rc = fail(SG_EINVAL, "a position is not finite or |p| >= 2^20");
+    else if (err) rc = fail(SG_ERANGE, "lattice key fingerprint collision");
+  }
+  (void)hipFree(d_err);
+  (void)hipFree(d_n);
+  if (rc) {
+    free_lat(L);
+    return rc;
+  }
+  L->n_vertices = nv;
+  L->magic = kLatMagic;
+  *out = L;
+  return SG_OK;
+}
+
+int sg_lattice_num_vertices(const sg_lattice* L, int64_t* n) {
+  int rc = check_lat(L);
+  if (rc) return rc;
+  if (!n) return fail(SG_EINVAL, "n is NULL");
+  *n = L->n_vertices;
+  return SG_OK;
+}
+
+int sg_lattice_filter(const sg_lattice* L, const float* d_val, int32_t n_values, float* d_out,
+                      sg_stream stream) {
+  int rc = check_lat(L);
+  if (rc) return rc;
+  if (n_values < 1 || n_values > L->vmax)
+    return fail(SG_EINVAL, "n_values must be in [1, max_values of the build]");
+  if (!d_val || !d_out) return fail(SG_EINVAL, "a required pointer is NULL");
+  return lat_filter(L, d_val, n_values, d_out, (hipStream_t)stream);
+}
+
+int sg_crf_meanfield(const sg_lattice* L, const float* d_unary, int32_t n_labels, float w_p,
+                     int32_t iters, float* d_Q, sg_stream stream) {
+  int rc = check_lat(L);
+  if (rc) return rc;
+  if (n_labels < 1 || n_labels > L->vmax)
+    return fail(SG_EINVAL, "n_labels must be in [1, max_values of the build]");
+  if (iters < 0) return fail(SG_EINVAL, "iters must be >= 0");
+  if (!std::isfinite(w_p)) return fail(SG_EINVAL, "w_p must be finite");
+  if (!d_unary || !d_Q) return fail(SG_EINVAL, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int T = 256;
+  k_softmax<<<grid_of(L->N, T), T, 0, s>>>(d_unary, nullptr, 0.0f, L->N, n_labels, d_Q);
+  for (int it = 0; it < iters; ++it) {
+    if ((rc = lat_filter(L, d_Q, n_labels, L->m, s))) return rc;
+    k_softmax<<<grid_of(L->N, T), T, 0, s>>>(d_unary, L->m, w_p, L->N, n_labels, d_Q);
+  }
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_lattice_destroy(sg_lattice* L) {
+  if (!L) return SG_OK;
+  if (L->magic != kLatMagic) return fail(SG_ESTATE, "lattice handle is not a live lattice");
+  L->magic = 0;
+  free_lat(L);
+  return SG_OK;
+}
+
+}  // extern "C"

@@ -364,6 +364,52 @@ def denoise(grid: Grid, vox: torch.Tensor, radius: int = 1, sigma: float = 1.0, 
     return out
 
 
+class Lattice:
+    """Permutohedral lattice of scaled feature positions [n,d] (Sec. 3.5.3)."""
+
+    def __init__(self, pos: torch.Tensor, max_values: int = 32):
+        want(pos, "pos", torch.float32, (None, None))
+        self.device = pos.device
+        self.n, self.d = pos.shape
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().sg_lattice_build(ptr(pos), self.n, self.d, max_values,
+                                         stream_ptr(self.device), ctypes.byref(handle)),
+                  "sg_lattice_build")
+        self._h = handle
+        nv = ctypes.c_int64()
+        check(lib().sg_lattice_num_vertices(self._h, ctypes.byref(nv)), "sg_lattice_num_vertices")
+        self.n_vertices = nv.value
+
+    def filter(self, val: torch.Tensor, out=None):
+        """Unnormalised lattice Gaussian filter of values [n,vd]."""
+        want(val, "val", torch.float32, (self.n, None), self.device)
+        if out is None:
+            out = torch.empty_like(val)
+        check(lib().sg_lattice_filter(self._h, ptr(val), val.shape[1], ptr(out),
+                                      stream_ptr(self.device)), "sg_lattice_filter")
+        return out
+
+    def meanfield(self, unary: torch.Tensor, w_p: float, iters: int, out=None):
+        """Label marginals [n,L] after `iters` mean-field updates."""
+        want(unary, "unary", torch.float32, (self.n, None), self.device)
+        if out is None:
+            out = torch.empty_like(unary)
+        check(lib().sg_crf_meanfield(self._h, ptr(unary), unary.shape[1], ctypes.c_float(w_p),
+                                     iters, ptr(out), stream_ptr(self.device)), "sg_crf_meanfield")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+                lib().sg_lattice_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
 def render_footprint(grid: Grid, rays: torch.Tensor, params, touched: bool = False):
     """Per-ray (samples, distinct voxels, distinct blocks) and the touched map."""
     params = RenderParams.of(params)

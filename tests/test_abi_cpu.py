@@ -82,6 +82,12 @@ def test_render_validation(L):
     assert L.sg_fuse(None, fake, 1, fake, fake, 3, 4, 4, ctypes.c_float(0.1), 0, fake, None,
                      None) == -1
     assert L.sg_denoise(None, fake, 3, 1, ctypes.c_float(1.0), fake, None) == -1
+    lat = ctypes.c_void_p()
+    assert L.sg_lattice_build(fake, 10, 17, 4, None, ctypes.byref(lat)) == -1 and not lat.value
+    assert L.sg_lattice_build(fake, 10, 3, 33, None, ctypes.byref(lat)) == -1
+    assert L.sg_lattice_filter(None, fake, 1, fake, None) == -1
+    assert L.sg_crf_meanfield(None, fake, 2, ctypes.c_float(1.0), 1, fake, None) == -1
+    assert L.sg_lattice_destroy(None) == 0
     n = ctypes.c_int64(5)
     org = (ctypes.c_float * 3)(0, 0, 0)
     assert L.sg_alloc_blocks(fake, 1, fake, 4, 4, ctypes.c_float(0.02), org, -1, ctypes.c_float(1),
