@@ -265,22 +265,22 @@ def frames_bench(dev, n_frames=50):
     return res
 
 
-def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5):
+def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
     """Block allocation from depth maps, grid build and fusion of ten seeded
-    640x480 depth + RGB frames of the 2 cm room (Sec. 3.4): the set-up of
-    the grid that the render then refines."""
+    640x480 depth + RGB + 16 semantic-logit frames of the 2 cm room (Sec.
+    3.4): the set-up of the grid that the render then refines."""
     import numpy as np
     import torch
     import paper_2305_13220_amd as sg
     from synth import workloads
     t0 = time.perf_counter()
-    fr = workloads.room_depth_frames(n_frames=n_frames, W=640, H=480)
+    fr = workloads.room_depth_frames(n_frames=n_frames, W=640, H=480, n_sem=n_sem)
     cams, depth, feat = (torch.from_numpy(fr[k]).to(dev) for k in ("cams", "depth", "feat"))
     log(f"fusion setup {time.perf_counter() - t0:.1f}s")
     h = float(fr["h"])
     blocks = sg.alloc_blocks(cams, depth, h, dilate=1)
     grid = sg.Grid(blocks, h)
-    vox, wt = sg.fuse(grid, cams, depth, feat, trunc)
+    vox, wt = sg.fuse(grid, cams, depth, feat, trunc, n_sem=n_sem)
     torch.cuda.synchronize()
     t_alloc, t_build, t_fuse = [], [], []
     for _ in range(reps):
@@ -293,7 +293,7 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5):
         c = time.perf_counter()
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         e[0].record()
-        sg.fuse(grid, cams, depth, feat, trunc, vox=vox, weight=False)
+        sg.fuse(grid, cams, depth, feat, trunc, n_sem=n_sem, vox=vox, weight=False)
         e[1].record()
         torch.cuda.synchronize()
         t_alloc.append(b - a)
@@ -322,7 +322,7 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5):
            "fuse_voxel_frames_per_s": n_vox * n_frames / fuse_s,
            "frames_per_s_end_to_end": round(n_frames / total, 1),
            "associated_frac": round(float((wt > 0).float().mean().item()), 4),
-           "kernel": "k_fuse<3>"}
+           "kernel": "k_fuse<19>", "C": 3 + n_sem}
     del vox, wt, grid, cams, depth, feat, dn
     torch.cuda.empty_cache()
     return res

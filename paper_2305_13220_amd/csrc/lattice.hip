@@ -153,35 +153,49 @@ __global__ void k_lat_simplex(const float* __restrict__ pos, int64_t N, LatView 
   }
 }
 
-__global__ void k_lat_count(const uint64_t* __restrict__ fp, int64_t cap, int64_t* __restrict__ n) {
+// List of the occupied slots (in no particular order) and their number.
+__global__ void k_lat_compact(const uint64_t* __restrict__ fp, int64_t cap,
+                              unsigned long long* __restrict__ n, int32_t* __restrict__ list) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool used = s < cap && fp[s] != kEmptyKey;
   const uint64_t b = __ballot(used);
-  if (lane_id() == 0 && b) atomicAdd((unsigned long long*)n, (unsigned long long)__popcll(b));
+  unsigned long long base = 0;
+  if (lane_id() == 0 && b) base = atomicAdd(n, (unsigned long long)__popcll(b));
+  base = __shfl(base, 0);
+  if (used) list[base + rank_below(b)] = (int32_t)s;
 }
 
-__global__ void k_lat_zero(float* __restrict__ v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = 0.0f;
+// Zero the value rows of the occupied slots.
+__global__ void k_lat_zero(const int32_t* __restrict__ list, int64_t nv, int vd,
+                           float* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nv * vd) return;
+  const int64_t k = t / vd;
+  v[(int64_t)list[k] * vd + (t - k * vd)] = 0.0f;
 }
 
+// Lanes laid out (point-vertex pair, channel): the channels of one vertex
+// are consecutive, so an atomic instruction touches a few vertex rows
+// rather than 64 (device float atomics are performed past the L2, one
+// request per 64-byte piece an instruction touches).
 __global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __restrict__ bw,
                             int64_t N, int d, const float* __restrict__ val, int vd,
                             float* __restrict__ lv) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N * (d + 1)) return;
-  const int64_t i = t / (d + 1);
-  const int64_t slot = vid[t];
-  const float w = bw[t];
-  for (int c = 0; c < vd; ++c) unsafeAtomicAdd(lv + slot * vd + c, w * val[i * vd + c]);
+  if (t >= N * (d + 1) * vd) return;
+  const int64_t pr = t / vd;
+  const int c = (int)(t - pr * vd);
+  const int64_t i = pr / (d + 1);
+  unsafeAtomicAdd(lv + (int64_t)vid[pr] * vd + c, bw[pr] * val[i * vd + c]);
 }
 
 // Blur along direction j: new = v/2 + (v(n-) + v(n+))/4, n+- = key +-
 // ((1,...,1) - (d+1) e_j) (first d coordinates); absent neighbours add 0.
-__global__ void k_lat_blur(LatView L, int64_t cap, int j, const float* __restrict__ src, int vd,
-                           float* __restrict__ dst) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= cap || L.fp[s] == kEmptyKey) return;
+__global__ void k_lat_blur(LatView L, const int32_t* __restrict__ list, int64_t nv, int j,
+                           const float* __restrict__ src, int vd, float* __restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nv) return;
+  const int64_t s = list[k];
   const int d = L.d;
   // fixed-size loops with guards keep the arrays in registers
   float acc[kLatMaxV];
@@ -208,24 +222,20 @@ __global__ void k_lat_blur(LatView L, int64_t cap, int j, const float* __restric
     if (c < vd) dst[s * vd + c] = acc[c];
 }
 
+// Lanes laid out (point, channel): consecutive lanes read one vertex row.
 __global__ void k_lat_slice(const int32_t* __restrict__ vid, const float* __restrict__ bw,
                             int64_t N, int d, const float* __restrict__ lv, int vd,
                             float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  float acc[kLatMaxV];
-#pragma unroll
-  for (int c = 0; c < kLatMaxV; ++c) acc[c] = 0.0f;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * vd) return;
+  const int64_t i = t / vd;
+  const int c = (int)(t - i * vd);
+  float acc = 0.0f;
   for (int r = 0; r <= d; ++r) {
-    const int64_t slot = vid[i * (d + 1) + r];
-    const float w = bw[i * (d + 1) + r];
-#pragma unroll
-    for (int c = 0; c < kLatMaxV; ++c)
-      if (c < vd) acc[c] += w * lv[slot * vd + c];
+    const int64_t pr = i * (d + 1) + r;
+    acc += bw[pr] * lv[(int64_t)vid[pr] * vd + c];
   }
-#pragma unroll
-  for (int c = 0; c < kLatMaxV; ++c)
-    if (c < vd) out[i * vd + c] = acc[c];
+  out[t] = acc;
 }
 
 // Q = softmax(-unary + w_p * m) per point (m may be null: w_p ignored).
@@ -262,6 +272,7 @@ struct sg_lattice {
   int64_t N, cap, n_vertices;
   uint64_t* fp;
   int32_t* keys;
+  int32_t* list;  // [cap] occupied slots, n_vertices of them
   int32_t* vid;
   float* bw;
   float* v0;
@@ -279,6 +290,7 @@ static int check_lat(const sg_lattice* L) {
 static void free_lat(sg_lattice* L) {
   (void)hipFree(L->fp);
   (void)hipFree(L->keys);
+  (void)hipFree(L->list);
   (void)hipFree(L->vid);
   (void)hipFree(L->bw);
   (void)hipFree(L->v0);
@@ -290,17 +302,19 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   const int T = 256;
   const int d = L->d;
   const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d};
-  k_lat_zero<<<grid_of(L->cap * vd, T), T, 0, s>>>(L->v0, L->cap * vd);
-  k_lat_splat<<<grid_of(L->N * (d + 1), T), T, 0, s>>>(L->vid, L->bw, L->N, d, d_val, vd, L->v0);
+  const int64_t nv = L->n_vertices;
+  k_lat_zero<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, nv, vd, L->v0);
+  k_lat_splat<<<grid_of(L->N * (d + 1) * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, d_val, vd,
+                                                              L->v0);
   float* a = L->v0;
   float* b = L->v1;
   for (int j = 0; j <= d; ++j) {
-    k_lat_blur<<<grid_of(L->cap, T), T, 0, s>>>(V, L->cap, j, a, vd, b);
+    k_lat_blur<<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
     float* t = a;
     a = b;
     b = t;
   }
-  k_lat_slice<<<grid_of(L->N, T), T, 0, s>>>(L->vid, L->bw, L->N, d, a, vd, d_out);
+  k_lat_slice<<<grid_of(L->N * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, a, vd, d_out);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }
@@ -327,13 +341,13 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
   L->N = n_points;
   L->cap = 1;
   while (L->cap < 2 * n_points * (d + 1)) L->cap <<= 1;
-  const size_t sz[7] = {sizeof(uint64_t) * L->cap, sizeof(int32_t) * L->cap * d,
+  const size_t sz[8] = {sizeof(uint64_t) * L->cap, sizeof(int32_t) * L->cap * d,
                         sizeof(int32_t) * n_points * (d + 1), sizeof(float) * n_points * (d + 1),
                         sizeof(float) * L->cap * max_values, sizeof(float) * L->cap * max_values,
-                        sizeof(float) * n_points * max_values};
-  void** ptrs[7] = {(void**)&L->fp, (void**)&L->keys, (void**)&L->vid, (void**)&L->bw,
-                    (void**)&L->v0, (void**)&L->v1, (void**)&L->m};
-  for (int k = 0; k < 7; ++k)
+                        sizeof(float) * n_points * max_values, sizeof(int32_t) * L->cap};
+  void** ptrs[8] = {(void**)&L->fp, (void**)&L->keys, (void**)&L->vid, (void**)&L->bw,
+                    (void**)&L->v0, (void**)&L->v1, (void**)&L->m, (void**)&L->list};
+  for (int k = 0; k < 8; ++k)
     if (hipMalloc(ptrs[k], sz[k]) != hipSuccess) {
       (void)hipGetLastError();
       free_lat(L);
@@ -360,7 +374,8 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
   } else {
     k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 0, L->vid, L->bw, d_err);
     k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 1, L->vid, L->bw, d_err);
-    k_lat_count<<<grid_of(L->cap, T), T, 0, s>>>(L->fp, L->cap, d_n);
+    k_lat_compact<<<grid_of(L->cap, T), T, 0, s>>>(L->fp, L->cap, (unsigned long long*)d_n,
+                                                   L->list);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&nv, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
