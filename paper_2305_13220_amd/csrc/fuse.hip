@@ -142,6 +142,85 @@ __global__ __launch_bounds__(512) void k_denoise(GridView g, const int32_t* __re
   for (int ch = 0; ch < V; ++ch) o[ch] = acc[ch] * inv;
 }
 
+// The same blur through an LDS tile (radius <= kTileR): the block and its
+// halo, (8 + 2 radius)^3 voxels, four channels at a time, loaded once with
+// consecutive lanes on consecutive voxels, together with an allocated flag;
+// each lane then sums its neighbourhood from LDS.  The weights are taken
+// from a small LDS table.  Results equal k_denoise's up to summation order.
+constexpr int kTileR = 2;
+constexpr int kTileSide = 8 + 2 * kTileR;
+constexpr int kTileMax = kTileSide * kTileSide * kTileSide;
+
+template <int C>
+__global__ __launch_bounds__(512) void k_denoise_tile(GridView g, const int32_t* __restrict__ coords,
+                                                      const float* __restrict__ vox, int32_t radius,
+                                                      float inv_2s2, float* __restrict__ out) {
+  constexpr int V = 1 + C;
+  __shared__ int32_t nb[27];
+  __shared__ float4 tile[kTileMax];
+  __shared__ float present[kTileMax];
+  __shared__ float wtab[(2 * kTileR + 1) * (2 * kTileR + 1) * (2 * kTileR + 1)];
+  const int64_t b = blockIdx.x;
+  const int t = threadIdx.x;
+  const int32_t bc[3] = {coords[3 * b], coords[3 * b + 1], coords[3 * b + 2]};
+  const int side = 8 + 2 * radius, n_tile = side * side * side, kw = 2 * radius + 1;
+  if (t < 27) {
+    const int32_t x = bc[0] + t % 3 - 1, y = bc[1] + (t / 3) % 3 - 1, z = bc[2] + t / 9 - 1;
+    int32_t idx = -1, nm = 0, dist = 0;
+    if (x >= g.bmin[0] && x <= g.bmax[0] && y >= g.bmin[1] && y <= g.bmax[1] && z >= g.bmin[2] &&
+        z <= g.bmax[2])
+      block_state(g, x, y, z, idx, nm, dist);
+    nb[t] = idx;
+  }
+  if (t < kw * kw * kw) {
+    const int dx = t % kw - radius, dy = (t / kw) % kw - radius, dz = t / (kw * kw) - radius;
+    wtab[t] = expf(-(float)(dx * dx + dy * dy + dz * dz) * inv_2s2);
+  }
+  __syncthreads();
+  const int l[3] = {t & 7, (t >> 3) & 7, t >> 6};
+  float* o = out + (b * SG_BLOCK_VOXELS + t) * V;
+  for (int c0 = 0; c0 < V; c0 += 4) {
+    for (int e = t; e < n_tile; e += 512) {
+      // tile voxel e = (x, y, z), x fastest, at voxel offset -radius
+      const int x = e % side - radius, y = (e / side) % side - radius, z = e / (side * side) - radius;
+      const int ox = (x >> 3) + 1, oy = (y >> 3) + 1, oz = (z >> 3) + 1;
+      const int32_t n = nb[ox + 3 * oy + 9 * oz];
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (n >= 0) {
+        const float* th = vox + ((int64_t)n * SG_BLOCK_VOXELS + (x & 7) + 8 * (y & 7) + 64 * (z & 7)) * V;
+        v.x = th[c0];
+        if (c0 + 1 < V) v.y = th[c0 + 1];
+        if (c0 + 2 < V) v.z = th[c0 + 2];
+        if (c0 + 3 < V) v.w = th[c0 + 3];
+      }
+      tile[e] = v;
+      present[e] = n >= 0 ? 1.0f : 0.0f;
+    }
+    __syncthreads();
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float wsum = 0.0f;
+    int wi = 0;
+    for (int dz = 0; dz < kw; ++dz)
+      for (int dy = 0; dy < kw; ++dy)
+        for (int dx = 0; dx < kw; ++dx, ++wi) {
+          const int e = (l[0] + dx) + side * ((l[1] + dy) + side * (l[2] + dz));
+          const float w = wtab[wi] * present[e];
+          const float4 v = tile[e];
+          acc.x += w * v.x;
+          acc.y += w * v.y;
+          acc.z += w * v.z;
+          acc.w += w * v.w;
+          wsum += w;
+        }
+    const float inv = 1.0f / wsum;  // > 0: the voxel itself is allocated
+    o[c0] = acc.x * inv;
+    if (c0 + 1 < V) o[c0 + 1] = acc.y * inv;
+    if (c0 + 2 < V) o[c0 + 2] = acc.z * inv;
+    if (c0 + 3 < V) o[c0 + 3] = acc.w * inv;
+    __syncthreads();  // the tile is reloaded for the next channels
+  }
+}
+
 static bool fuse_C(int C) {
   return C == 0 || C == 1 || C == 2 || C == 3 || C == 4 || C == 8 || C == 16 || C == 19 ||
          C == 32;
@@ -212,8 +291,12 @@ int sg_denoise(const sg_grid* grid, const float* d_vox, int32_t C, int32_t radiu
   switch (C) {
 #define SG_DENOISE_CASE(CC)                                                                 \
   case CC:                                                                                  \
-    hipLaunchKernelGGL(k_denoise<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, g,    \
-                       grid->d_coords, d_vox, radius, inv_2s2, d_out);                      \
+    if (radius <= kTileR)                                                                   \
+      hipLaunchKernelGGL(k_denoise_tile<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, \
+                         g, grid->d_coords, d_vox, radius, inv_2s2, d_out);                 \
+    else                                                                                    \
+      hipLaunchKernelGGL(k_denoise<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, g,  \
+                         grid->d_coords, d_vox, radius, inv_2s2, d_out);                    \
     break;
     SG_DENOISE_CASE(0)
     SG_DENOISE_CASE(1)

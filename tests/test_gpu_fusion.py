@@ -139,3 +139,19 @@ def test_denoise_invalid_arguments():
     for kw in ({"radius": 9}, {"sigma": 0.0}, {"out": vox}):
         with pytest.raises(sg.SgridError):
             sg.denoise(g, vox, **kw)
+
+
+def test_denoise_wide_radius_direct_path():
+    """radius 3 takes the kernel without the LDS tile (the tiled one covers
+    radius <= 2): both against the oracle on the perturbed sphere."""
+    sg = _sg()
+    from synth import workloads, scenes
+    from gpu_helpers import assert_close_mag, make_grid
+    w = workloads.sphere_tiny()
+    vox = scenes.perturb(w["vox"], w["h"], seed=6)
+    g = make_grid(w)
+    for radius, sigma in ((3, 1.2), (2, 1.0), (0, 1.0)):
+        out = sg.denoise(g, to_dev(vox), radius=radius, sigma=sigma).cpu().numpy()
+        want, mag = oracle.denoise(w["block_coords"], vox, 3, radius=radius, sigma=sigma,
+                                   with_mag=True)
+        assert_close_mag(out, want, mag, 1e-5, f"denoise r={radius}")
