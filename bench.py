@@ -380,6 +380,64 @@ def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
     return res
 
 
+def train_bench(dev, steps=20):
+    """Optimisation at scale: the 2 cm room with seeded noise on SDF and RGB,
+    batches of 2^18 rays against renders of the clean grid (photometric,
+    depth and normal L2), each step = rays + gradient zeroing + fused
+    forward/loss/backward + Adam over every voxel; Adam also timed alone."""
+    import numpy as np
+    import torch
+    import paper_2305_13220_amd as sg
+    from synth import workloads
+    w = workloads.room_2cm_noisy(n_rays=1 << 18)
+    grid = sg.Grid(torch.from_numpy(w["block_coords"]).to(dev), float(w["h"]),
+                   tuple(float(x) for x in w["origin"]))
+    vox = torch.from_numpy(w["vox"]).to(dev)
+    clean = torch.from_numpy(w["clean_vox"]).to(dev)
+    cams = torch.from_numpy(w["cams"]).to(dev)
+    pix = torch.from_numpy(w["pix"]).to(dev)
+    params = sg.RenderParams.of(w["params"])
+    R = pix.shape[0]
+    rays = sg.rays_pinhole(cams, pix)
+    target = {k: v.clone() for k, v in sg.render_forward(grid, clean, rays, params).items()}
+    grad = torch.zeros_like(vox)
+    m = torch.zeros_like(vox)
+    v = torch.zeros_like(vox)
+    C = vox.shape[-1] - 1
+    out = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
+           "normal": torch.empty((R, 3), device=dev), "wsum": torch.empty(R, device=dev),
+           "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
+
+    def step(t):
+        rr = sg.rays_pinhole(cams, pix)
+        grad.zero_()
+        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
+        sg.optim_step(0, vox, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, t)
+
+    for t in range(1, 4):
+        step(t)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for t in range(4, 4 + steps):
+        step(t)
+    e[1].record()
+    for t in range(steps):
+        sg.optim_step(0, vox, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, 100 + t)
+    e[2].record()
+    torch.cuda.synchronize()
+    ms = e[0].elapsed_time(e[1]) / steps
+    adam_ms = e[1].elapsed_time(e[2]) / steps
+    adam_bytes = 7 * vox.numel() * 4  # read p, g, m, v; write p, m, v
+    res = {"workload": "room_2cm_noisy_262144_adam", "rays_per_step": R, "ms_per_step": round(ms, 4),
+           "rays_per_s": R / (ms * 1e-3), "adam_ms": round(adam_ms, 4),
+           "adam_hbm_frac": round(adam_bytes / (adam_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "params": int(vox.numel())}
+    del grid, vox, clean, grad, m, v, out, target
+    torch.cuda.empty_cache()
+    return res
+
+
 def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
     """SDF and gradient at the k^3 lattice points of the grid's bounding box
     (the point-query timing of Sec. 4), one sg_query call per k.  Bytes per
@@ -445,6 +503,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the k^3 point-query timing")
     ap.add_argument("--no-crf", action="store_true", help="skip the CRF message-passing timing")
+    ap.add_argument("--no-train", action="store_true",
+                    help="skip the 2^18-ray noisy-room training timing")
     ap.add_argument("--no-fusion", action="store_true",
                     help="skip the allocation + fusion timing")
     ap.add_argument("--no-frames", action="store_true",
@@ -640,6 +700,8 @@ def main():
     }
     if not args.no_frames:
         res["frames"] = frames_bench(dev)
+    if not args.no_train:
+        res["training"] = train_bench(dev)
     if not args.no_query:
         res["query"] = query_bench(grid, vox, w["block_coords"], dev)
     if not args.no_fusion:
