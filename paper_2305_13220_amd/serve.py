@@ -105,7 +105,7 @@ class PackedServer:
 
     def __init__(self, grids, C=3, hbm_budget_bytes=8 << 30, tick_rays=1 << 20, max_slots=256,
                  use_graph=True, keep_outputs=True, order="srpt", aging_px_per_s=2e8,
-                 one_grid_per_tick=False, launch="multi_grid", small_tick_rays=None):
+                 one_grid_per_tick=False, launch="multi_grid", small_tick_rays=None, n_tables=2):
         """grids: list of (Grid, vox tensor, RenderParams or dict).  With
         keep_outputs False a request's outputs are released when it completes.
 
@@ -120,6 +120,9 @@ class PackedServer:
         many pixels left is limited to that many pixels (and launched with a
         grid of that size), so small requests are not held up behind a full
         tick.
+
+        n_tables slot tables are used in turn: up to n_tables ticks can be
+        queued on the GPU while the host fills the next table.
 
         launch "per_grid" (implies one grid per tick) renders a tick with
         sg_render_forward_slots on that grid (one captured graph per grid and
@@ -159,15 +162,17 @@ class PackedServer:
         self.q_cap = cap
         self.d_grids = torch.frombuffer(bytearray(descs), dtype=torch.uint8).to(self.dev)
         n = self.max_slots
+        self.n_tables = max(2, int(n_tables))
+        nt = self.n_tables
         self.h_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8).pin_memory()
-                        for _ in range(2)]
-        self.h_count = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(2)]
+                        for _ in range(nt)]
+        self.h_count = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(nt)]
         self.d_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
-                        for _ in range(2)]
-        self.d_count = [torch.zeros(1, dtype=torch.int32, device=self.dev) for _ in range(2)]
-        self.graphs = {}  # (table, grid or -1) -> captured graph
+                        for _ in range(nt)]
+        self.d_count = [torch.zeros(1, dtype=torch.int32, device=self.dev) for _ in range(nt)]
+        self.graphs = {}  # (table, grid or -1, rays) -> captured graph
         self.use_graph = use_graph
-        self.busy = [None, None]  # end event of the tick that last used each table
+        self.busy = [None] * nt  # end event of the tick that last used each table
         self.next_b = 0
         self.keep_outputs = keep_outputs
 
@@ -207,7 +212,7 @@ class PackedServer:
     def tick(self, work):
         """Render one tick: work = list of (request, pixel_begin, count).  Returns its end event."""
         b = self.next_b
-        self.next_b ^= 1
+        self.next_b = (b + 1) % self.n_tables
         if self.busy[b] is not None:
             self.busy[b].synchronize()  # the table is free once its tick has finished
         slots = np.zeros(len(work), dtype=SLOT_DTYPE)
