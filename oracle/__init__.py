@@ -14,7 +14,8 @@ Every function cites the passage of the paper it follows:
   * ``render_forward``: volume rendering, Sec. 3.5.1, Eq. 12-15, with the
     trilinear value and closed-form gradient of Eq. 17-18.
   * ``render_backward``: its adjoint with respect to the voxel parameters.
-  * ``query``: SDF, gradient and features at points (Eq. 17-18).
+  * ``query`` / ``query_backward``: SDF, gradient and features at points
+    (Eq. 17-18), and the adjoint of that query with respect to the voxels.
   * ``eikonal`` / ``eikonal_rays``: the Eikonal regulariser of Eq. 16 at
     points or on the render's ray samples, and its derivative with respect
     to the SDF voxels.
@@ -201,6 +202,26 @@ def eikonal_rays(block_coords, vox, C, h, origin, rays, params, weight, with_mag
                                _p(ry), _I64(R), *gp, _D(weight), _p(loss), _p(gv), _p(mag)),
            "eikonal_rays")
     return (loss, gv, mag) if with_mag else (loss, gv)
+
+
+def query_backward(block_coords, C, h, origin, points, g_f=None, g_grad=None, g_feat=None,
+                   n_blocks=None):
+    """Adjoint of ``query`` with respect to the voxels (Eq. 17-18): returns
+    (grad_vox [n,512,1+C], mag [n,512,1+C])."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    pts = _c(points, np.float32).reshape(-1, 3)
+    m = pts.shape[0]
+    org = _c(origin, np.float32).reshape(3)
+    gv = np.zeros((bc.shape[0], 512, 1 + C), np.float64)
+    mag = np.zeros_like(gv)
+    gf = None if g_f is None else _c(g_f, np.float64).reshape(m)
+    gg = None if g_grad is None else _c(g_grad, np.float64).reshape(m, 3)
+    gc = None if g_feat is None else _c(g_feat, np.float64).reshape(m, C)
+    _check(lib.or_query_backward(_p(bc), _I64(bc.shape[0]), _I32(C), _F(h), _p(org), _p(pts),
+                                 _I64(m), _p(gf), _p(gg), _p(gc), _p(gv), _p(mag)),
+           "query_backward")
+    return gv, mag
 
 
 def render_forward(block_coords, vox, C, h, origin, rays, params, with_mag=False):

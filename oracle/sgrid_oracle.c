@@ -1307,3 +1307,54 @@ int or_crf_meanfield(const float* pos, int64_t N, int32_t d, const double* unary
   free(m);
   return 0;
 }
+
+/*
+ * Adjoint of the point query (Eq. 17-18) with respect to the voxels: for
+ * upstream gradients g_f [m], g_grad [m,3], g_feat [m,C] (each nullable) of
+ * a scalar loss, accumulates into grad_vox [n,512,1+C]
+ *   channel 0:   r_a g_f + (dr_a/du . g_grad) / h
+ *   channel 1+c: r_a g_feat[c]
+ * for the 8 corners a of every valid point; mag_vox (nullable, same shape)
+ * accumulates the absolute values of the terms.
+ */
+int or_query_backward(const int32_t* block_coords, int64_t n_blocks, int32_t C, float h,
+                      const float org[3], const float* p, int64_t m, const double* g_f,
+                      const double* g_grad, const double* g_feat, double* grad_vox,
+                      double* mag_vox) {
+  if (C < 0 || !(h > 0)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  const float inv_h = 1.0f / h;
+  const size_t V = (size_t)(1 + C);
+  for (int64_t q = 0; q < m; ++q) {
+    float xv[3];
+    for (int a = 0; a < 3; ++a) xv[a] = (p[3 * q + a] - org[a]) * inv_h;
+    sample s;
+    if (!locate(&tb, xv, &s)) continue;
+    double r[8], dr[8][3];
+    corner_weights(s.u, r, dr);
+    for (int a = 0; a < 8; ++a) {
+      const size_t v = ((size_t)s.blk[a] * VOX_PER_BLOCK + (size_t)s.loc[a]) * V;
+      double t0 = 0.0, m0 = 0.0;
+      if (g_f) {
+        t0 += r[a] * g_f[q];
+        m0 += fabs(r[a] * g_f[q]);
+      }
+      if (g_grad)
+        for (int ax = 0; ax < 3; ++ax) {
+          t0 += dr[a][ax] * g_grad[3 * q + ax] / (double)h;
+          m0 += fabs(dr[a][ax] * g_grad[3 * q + ax] / (double)h);
+        }
+      grad_vox[v] += t0;
+      if (mag_vox) mag_vox[v] += m0;
+      if (g_feat)
+        for (int c = 0; c < C; ++c) {
+          grad_vox[v + 1 + c] += r[a] * g_feat[(size_t)C * q + c];
+          if (mag_vox) mag_vox[v + 1 + c] += fabs(r[a] * g_feat[(size_t)C * q + c]);
+        }
+    }
+  }
+  table_free(&tb);
+  return 0;
+}

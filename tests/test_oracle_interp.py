@@ -160,3 +160,35 @@ def test_ray_samples_cap_and_t_far_inclusive(oracle_lib):
     prm["max_samples"] = 4
     s = oracle_lib.ray_samples(blocks, h, np.zeros(3, np.float32), ray, prm)
     np.testing.assert_array_equal(s["k"], np.arange(4))
+
+
+def test_query_backward_is_the_adjoint_of_query(oracle_lib):
+    """<g, J theta> = <J^T g, theta> for random upstream gradients, with the
+    forward from or_query (f, grad f and features are linear in theta), and
+    central differences of a loss on the query outputs."""
+    rng = np.random.default_rng(51)
+    h = np.float32(0.05)
+    origin = np.array([0.1, -0.2, 0.05], np.float32)
+    blocks = _dense_blocks((-1, -1, -1), (1, 0, 1))
+    C = 2
+    vox = rng.normal(size=(blocks.shape[0], 512, 1 + C))
+    lo = origin + h * (8 * blocks.min(0) + 0.5)
+    hi = origin + h * (8 * blocks.max(0) + 6.5)
+    p = rng.uniform(lo, hi, size=(400, 3)).astype(np.float32)
+    p[:5] = [1e3, 0, 0]  # invalid points contribute nothing
+    gf, gg, gc = rng.normal(size=400), rng.normal(size=(400, 3)), rng.normal(size=(400, C))
+    gv, _ = oracle_lib.query_backward(blocks, C, h, origin, p, gf, gg, gc)
+    valid, f, g, feat = oracle_lib.query(blocks, vox, C, h, origin, p)
+    lhs = (gf * f).sum() + (gg * g).sum() + (gc * feat).sum()
+    assert float((gv * vox).sum()) == pytest.approx(float(lhs), rel=1e-10)
+    assert valid[5:].all() and not valid[:5].any()
+    # central differences on a few voxels
+    loss = lambda vx: float(sum((w * o).sum() for w, o in zip(
+        (gf, gg, gc), oracle_lib.query(blocks, vx, C, h, origin, p)[1:])))
+    touched = np.argwhere(np.abs(gv) > 0)
+    for b, v, c in touched[rng.choice(len(touched), 12, replace=False)]:
+        hi_, lo_ = vox.copy(), vox.copy()
+        hi_[b, v, c] += 1e-6
+        lo_[b, v, c] -= 1e-6
+        fd = (loss(hi_) - loss(lo_)) / 2e-6
+        assert fd == pytest.approx(gv[b, v, c], rel=1e-5, abs=1e-8)
