@@ -307,6 +307,20 @@ int sg_query(const sg_grid* g, const float* d_vox, int32_t C, const float* d_poi
              sg_stream stream);
 
 /*
+ * sg_query_backward -- adjoint of sg_query with respect to the voxels, for
+ * losses on queried values (e.g. the CRF's losses on surface samples,
+ * Sec. 3.5.3): for upstream gradients d_g_f [n], d_g_grad [n,3] (world
+ * units) and d_g_feat [n,C] (each nullable) it ACCUMULATES into d_grad_vox
+ * [n_blocks,512,1+C], for the 8 corners a of every valid point,
+ *   channel 0: r_a g_f + (grad_x r_a . g_grad),  channel 1+c: r_a g_feat[c].
+ * Float atomics: the caller zeroes d_grad_vox; the summation order (so the
+ * last bits) is unspecified.  Asynchronous; allocates nothing.
+ */
+int sg_query_backward(const sg_grid* g, int32_t C, const float* d_points, int64_t n_points,
+                      const float* d_g_f, const float* d_g_grad, const float* d_g_feat,
+                      float* d_grad_vox, sg_stream stream);
+
+/*
  * sg_eikonal -- the Eikonal regulariser (Eq. 16) at points, the uniform
  * in-grid samples of the training loss, with its derivative with respect to
  * the SDF voxels.  For each point p of d_points float [n,3], valid as in

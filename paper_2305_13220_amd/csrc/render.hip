@@ -879,6 +879,45 @@ __global__ __launch_bounds__(256) void k_query(GridView g, const float* __restri
   }
 }
 
+// Adjoint of the point query with respect to the voxels: for upstream
+// gradients of f, grad f and the features at each valid point, corner a
+// receives r_a g_f + (dr_a/du . g_grad) / h in the SDF channel and
+// r_a g_feat[c] in feature channel c (float atomics).
+template <int C>
+__global__ __launch_bounds__(256) void k_query_backward(GridView g, const float* __restrict__ pts,
+                                                        int64_t m, const float* __restrict__ g_f,
+                                                        const float* __restrict__ g_grad,
+                                                        const float* __restrict__ g_feat,
+                                                        float* __restrict__ grad_vox) {
+  constexpr int V = 1 + C;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  Cell cell;
+  if (!point_cell(g, pts + 3 * q, cell)) return;
+  const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
+              wz[2] = {1.0f - cell.u[2], cell.u[2]};
+  const float gf = g_f ? g_f[q] : 0.0f;
+  float gg[3] = {0.0f, 0.0f, 0.0f};
+  if (g_grad) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gg[a] = g_grad[3 * q + a] * g.inv_h;
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const float ra = wx[ax] * wy[ay] * wz[az];
+    const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gg[0] +
+                     (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gg[1] +
+                     (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gg[2];
+    float* dst = grad_vox + (int64_t)cell.off[a] * V;
+    if (g_f || g_grad) unsafeAtomicAdd(dst, ra * gf + gn);
+    if (g_feat) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) unsafeAtomicAdd(dst + 1 + c, ra * g_feat[(int64_t)C * q + c]);
+    }
+  }
+}
+
 // Eikonal regulariser (Eq. 16) at points: loss = weight (|g| - 1)^2 with g
 // the closed-form gradient of Eq. 18, and its derivative with respect to the
 // SDF of the 8 corners.  g is linear in the corner SDFs, one difference per
@@ -1839,6 +1878,25 @@ int sg_query(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_query<CC>, dim3((unsigned)blocks), dim3(256), 0,
                                       (hipStream_t)stream, g, d_vox, d_points, n_points, d_valid,
                                       d_f, d_grad, C > 0 ? d_feat : nullptr));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_query_backward(const sg_grid* grid, int32_t C, const float* d_points, int64_t n_points,
+                      const float* d_g_f, const float* d_g_grad, const float* d_g_feat,
+                      float* d_grad_vox, sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!supported_C(C)) return fail(SG_EINVAL, "unsupported feature count C");
+  if (n_points < 0) return fail(SG_EINVAL, "n_points must be >= 0");
+  if (n_points == 0) return SG_OK;
+  if (!d_points || !d_grad_vox) return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const int64_t blocks = (n_points + 255) / 256;
+  if (blocks > INT_MAX) return fail(SG_ERANGE, "too many points for one launch");
+  SG_DISPATCH_C(C, hipLaunchKernelGGL(k_query_backward<CC>, dim3((unsigned)blocks), dim3(256), 0,
+                                      (hipStream_t)stream, g, d_points, n_points, d_g_f, d_g_grad,
+                                      C > 0 ? d_g_feat : nullptr, d_grad_vox));
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

@@ -289,6 +289,25 @@ def query(grid: Grid, vox: torch.Tensor, points: torch.Tensor, features: bool = 
     return res
 
 
+def query_backward(grid: Grid, vox_shape, points: torch.Tensor, g_f=None, g_grad=None, g_feat=None,
+                   grad_vox=None):
+    """Accumulate the adjoint of ``query`` into grad_vox (zeros of vox_shape
+    if None) for upstream gradients of f [m], grad f [m,3], features [m,C]."""
+    C = vox_shape[-1] - 1
+    want(points, "points", torch.float32, (None, 3), grid.device)
+    m = points.shape[0]
+    if grad_vox is None:
+        grad_vox = torch.zeros(tuple(vox_shape), dtype=torch.float32, device=grid.device)
+    _check_vox(grid, grad_vox, C)
+    for t, name, shape in ((g_f, "g_f", (m,)), (g_grad, "g_grad", (m, 3)), (g_feat, "g_feat", (m, C))):
+        if t is not None:
+            want(t, name, torch.float32, shape, grid.device)
+    check(lib().sg_query_backward(grid.handle, C, ptr(points), m, ptr(g_f), ptr(g_grad),
+                                  ptr(g_feat), ptr(grad_vox), stream_ptr(grid.device)),
+          "sg_query_backward")
+    return grad_vox
+
+
 def eikonal(grid: Grid, vox: torch.Tensor, points: torch.Tensor, weight: float = 1.0,
             grad_vox=None, loss: bool = True):
     """Eikonal loss weight * (|grad f| - 1)^2 per point (Eq. 16) and its

@@ -188,3 +188,37 @@ def test_eikonal_invalid_arguments():
                    grad_vox=torch.zeros(3, device="cuda"))
     l0, _ = sg.eikonal(g, vox, to_dev(np.zeros((0, 3), np.float32)))
     assert l0.numel() == 0
+
+
+@pytest.mark.parametrize("which", ["room", "sphere19"])
+def test_query_backward_matches_oracle(which):
+    """Adjoint of the query against the oracle's, within 1e-4 of the sum of
+    absolute values of the terms (the gradient bar)."""
+    sg = _sg()
+    from synth import workloads
+    if which == "room":
+        w = workloads.room_2cm()
+        vox, C = w["vox"], 3
+        pts = _points(w, 60000, 7, -0.2, 6.2)
+    else:
+        w = workloads.sphere_tiny()
+        rng0 = np.random.default_rng(4)
+        vox = np.concatenate([w["vox"][..., :1], rng0.normal(size=w["vox"].shape[:2] + (19,))],
+                             -1).astype(np.float32)
+        C = 19
+        pts = _points(w, 30000, 8, -0.7, 0.7)
+    rng = np.random.default_rng(12)
+    m = len(pts)
+    gf = rng.normal(size=m).astype(np.float32)
+    gg = rng.normal(size=(m, 3)).astype(np.float32)
+    gc = rng.normal(size=(m, C)).astype(np.float32)
+    g = make_grid(w)
+    got = sg.query_backward(g, vox.shape, to_dev(pts), to_dev(gf), to_dev(gg), to_dev(gc))
+    want, mag = oracle.query_backward(w["block_coords"], C, w["h"], w["origin"], pts, gf, gg, gc)
+    assert_close_mag(got.cpu().numpy(), want, mag, 1e-4, f"query backward {which}")
+    assert np.abs(want).sum() > 0
+    # only the SDF-side gradients
+    got0 = sg.query_backward(g, vox.shape, to_dev(pts), g_f=to_dev(gf)).cpu().numpy()
+    want0, mag0 = oracle.query_backward(w["block_coords"], C, w["h"], w["origin"], pts, g_f=gf)
+    assert_close_mag(got0, want0, mag0, 1e-4, f"query backward {which}, g_f only")
+    assert not got0[..., 1:].any()
