@@ -257,6 +257,10 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   Q = softmax(-unary) (a Potts compatibility of weight w_p; the message
  *   includes each point's own contribution).  d_unary [n, n_labels].
  *   Asynchronous; allocates nothing.
+ * Filters and updates on one lattice share its value buffers: calls on the
+ * same lattice must not overlap (issue them on one stream).
+ * sg_lattice_destroy frees the lattice (waits for nothing: the caller makes
+ * sure no launched work still uses it); NULL is accepted.
  */
 typedef struct sg_lattice sg_lattice;
 int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
