@@ -25,9 +25,9 @@ Every function cites the passage of the paper it follows:
   * ``alloc_blocks`` / ``fuse``: block allocation from depth maps (Sec.
     3.4.1) and the depth, colour and semantic fusion of Sec. 3.4.2.
   * ``denoise``: the Gaussian blur of Sec. 3.4.3 over allocated voxels.
-  * ``lattice_simplex`` / ``lattice_filter`` / ``crf_meanfield``: the
-    permutohedral-lattice Gaussian filter and the mean-field update of the
-    continuous CRF (Sec. 3.5.3).
+  * ``lattice_simplex`` / ``lattice_filter`` / ``crf_meanfield`` /
+    ``crf_label_loss``: the permutohedral-lattice Gaussian filter, the
+    mean-field update and the label loss of the continuous CRF (Sec. 3.5.3).
 """
 from __future__ import annotations
 
@@ -449,3 +449,17 @@ def crf_meanfield(pos, unary, w_p, iters):
     _check(lib.or_crf_meanfield(_p(ps), _I64(N), _I32(d), _p(u), _I32(u.shape[1]), _D(w_p),
                                 _I32(iters), _p(Q)), "crf_meanfield")
     return Q
+
+
+def crf_label_loss(logits, Q, weight=1.0):
+    """KL(softmax(logits) || Q) per node times weight, and its gradient with
+    respect to the logits (Q fixed) (Sec. 3.5.3).  Returns (loss [N], g [N,L])."""
+    lib = _load()
+    lg = _c(logits, np.float64)
+    N, L = lg.shape
+    q = _c(Q, np.float64).reshape(N, L)
+    loss = np.empty(N, np.float64)
+    g = np.empty((N, L), np.float64)
+    _check(lib.or_crf_label_loss(_p(lg), _p(q), _I64(N), _I32(L), _D(weight), _p(loss), _p(g)),
+           "crf_label_loss")
+    return loss, g

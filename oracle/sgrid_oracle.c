@@ -1358,3 +1358,33 @@ int or_query_backward(const int32_t* block_coords, int64_t n_blocks, int32_t C, 
   table_free(&tb);
   return 0;
 }
+
+/*
+ * Label loss of the continuous CRF (Sec. 3.5.3, Eq. 22), the f-divergence
+ * taken as the Kullback-Leibler divergence: for each node, x = softmax of
+ * its label logits [L] and Q its mean-field marginals (a fixed target),
+ *   loss[i] = weight * sum_l x_l log(x_l / Q_l),
+ *   g[i,k]  = d loss[i] / d logit_k = weight * x_k (a_k - sum_l x_l a_l),
+ *             a_l = log x_l - log Q_l.
+ */
+int or_crf_label_loss(const double* logits, const double* Q, int64_t N, int32_t L, double weight,
+                      double* loss, double* g) {
+  if (L < 1 || N < 0) return -1;
+  for (int64_t i = 0; i < N; ++i) {
+    const double* s = logits + i * L;
+    double mx = -INFINITY, z = 0.0;
+    for (int l = 0; l < L; ++l) mx = fmax(mx, s[l]);
+    for (int l = 0; l < L; ++l) z += exp(s[l] - mx);
+    double kl = 0.0;
+    for (int l = 0; l < L; ++l) {
+      const double lx = s[l] - mx - log(z);
+      kl += exp(lx) * (lx - log(Q[i * L + l]));
+    }
+    loss[i] = weight * kl;
+    for (int k = 0; k < L; ++k) {
+      const double lx = s[k] - mx - log(z);
+      g[i * L + k] = weight * exp(lx) * ((lx - log(Q[i * L + k])) - kl);
+    }
+  }
+  return 0;
+}

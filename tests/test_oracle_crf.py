@@ -141,3 +141,27 @@ def test_meanfield_update(oracle_lib):
     np.testing.assert_allclose(Q1, sm(-U + 0.7 * F), rtol=1e-12)
     Q3 = oracle_lib.crf_meanfield(p, U, 0.7, 3)
     np.testing.assert_allclose(Q3.sum(1), 1.0, atol=1e-12)
+
+
+def test_label_loss_kl_and_gradient(oracle_lib):
+    """KL >= 0, zero iff softmax(logits) = Q; the gradient equals central
+    differences of the loss and sums to zero over the labels (softmax is
+    invariant to a common shift of the logits)."""
+    rng = np.random.default_rng(9)
+    N, L = 50, 6
+    s = rng.normal(size=(N, L))
+    Q = rng.dirichlet(np.ones(L), size=N)
+    loss, g = oracle_lib.crf_label_loss(s, Q, 0.7)
+    assert (loss >= 0).all()
+    x = np.exp(s - s.max(1, keepdims=True))
+    x /= x.sum(1, keepdims=True)
+    np.testing.assert_allclose(loss, 0.7 * (x * np.log(x / Q)).sum(1), rtol=1e-12)
+    z, _ = oracle_lib.crf_label_loss(np.log(Q) + 3.0, Q, 1.0)
+    assert np.abs(z).max() < 1e-12
+    np.testing.assert_allclose(g.sum(1), 0.0, atol=1e-12)
+    for i, k in [(0, 0), (3, 5), (17, 2), (49, 4)]:
+        hi, lo = s.copy(), s.copy()
+        hi[i, k] += 1e-6
+        lo[i, k] -= 1e-6
+        fd = (oracle_lib.crf_label_loss(hi, Q, 0.7)[0][i] - oracle_lib.crf_label_loss(lo, Q, 0.7)[0][i]) / 2e-6
+        assert fd == pytest.approx(g[i, k], rel=1e-6, abs=1e-9)
