@@ -263,6 +263,21 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  * sure no launched work still uses it); NULL is accepted.
  */
 typedef struct sg_lattice sg_lattice;
+/*
+ * sg_crf_label_loss -- the CRF's label loss (Eq. 22, the f-divergence taken
+ * as Kullback-Leibler): per node i, x = softmax(logits_i) and Q_i its
+ * mean-field marginals (a fixed target, entries > 0):
+ *   d_loss [n] (nullable) = weight * sum_l x_l log(x_l / Q_l),
+ *   d_g (nullable) row i, columns 0..L-1 = weight * x_k (a_k - KL_i),
+ *     a = log x - log Q (the gradient with respect to the logits).
+ * d_logits rows of stride ld_logits, d_Q [n,L], d_g rows of stride ld_g
+ * (so the logits can be the semantic columns of sg_query's feature output
+ * and the gradient written into the same columns of sg_query_backward's
+ * d_g_feat).  Asynchronous; allocates nothing.  1 <= L <= 32.
+ */
+int sg_crf_label_loss(const float* d_logits, int64_t ld_logits, const float* d_Q, int64_t n,
+                      int32_t n_labels, float weight, float* d_loss, float* d_g, int64_t ld_g,
+                      sg_stream stream);
 int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
                      sg_stream stream, sg_lattice** out);
 int sg_lattice_num_vertices(const sg_lattice* lat, int64_t* n_vertices);

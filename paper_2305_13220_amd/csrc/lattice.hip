@@ -262,6 +262,44 @@ __global__ void k_softmax(const float* __restrict__ unary, const float* __restri
     if (l < Lb) Q[i * Lb + l] = a[l] * inv;
 }
 
+// Label loss of the CRF per node: x = softmax(logits), loss = weight *
+// KL(x || Q), gradient weight * x_k (a_k - KL) with a = log x - log Q
+// (Q a fixed target).  Row strides ld_s / ld_g (elements) let the logits
+// be a column range of a feature array and the gradient be written into
+// the matching columns of an upstream-gradient array.
+__global__ void k_crf_label_loss(const float* __restrict__ logits, int64_t ld_s,
+                                 const float* __restrict__ Q, int64_t N, int Lb, float weight,
+                                 float* __restrict__ loss, float* __restrict__ g, int64_t ld_g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float lx[kLatMaxV];
+  float mx = -INFINITY;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    lx[l] = l < Lb ? logits[i * ld_s + l] : -INFINITY;
+    mx = fmaxf(mx, lx[l]);
+  }
+  float z = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) z += l < Lb ? expf(lx[l] - mx) : 0.0f;
+  const float lz = logf(z);
+  float kl = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    if (l < Lb) {
+      lx[l] = lx[l] - mx - lz;                       // log x_l
+      const float a = lx[l] - logf(Q[i * Lb + l]);   // log x_l - log Q_l
+      kl += expf(lx[l]) * a;
+    }
+  }
+  if (loss) loss[i] = weight * kl;
+  if (g) {
+#pragma unroll
+    for (int l = 0; l < kLatMaxV; ++l)
+      if (l < Lb) g[i * ld_g + l] = weight * expf(lx[l]) * ((lx[l] - logf(Q[i * Lb + l])) - kl);
+  }
+}
+
 static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace sg
@@ -430,6 +468,22 @@ int sg_crf_meanfield(const sg_lattice* L, const float* d_unary, int32_t n_labels
     if ((rc = lat_filter(L, d_Q, n_labels, L->m, s))) return rc;
     k_softmax<<<grid_of(L->N, T), T, 0, s>>>(d_unary, L->m, w_p, L->N, n_labels, d_Q);
   }
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_crf_label_loss(const float* d_logits, int64_t ld_logits, const float* d_Q, int64_t n,
+                      int32_t n_labels, float weight, float* d_loss, float* d_g, int64_t ld_g,
+                      sg_stream stream) {
+  if (n < 0) return fail(SG_EINVAL, "n must be >= 0");
+  if (n_labels < 1 || n_labels > kLatMaxV) return fail(SG_EINVAL, "n_labels must be in [1, 32]");
+  if (ld_logits < n_labels || (d_g && ld_g < n_labels))
+    return fail(SG_EINVAL, "row strides must be >= n_labels");
+  if (!std::isfinite(weight)) return fail(SG_EINVAL, "weight must be finite");
+  if (n == 0) return SG_OK;
+  if (!d_logits || !d_Q) return fail(SG_EINVAL, "a required pointer is NULL");
+  k_crf_label_loss<<<grid_of(n, 256), 256, 0, (hipStream_t)stream>>>(
+      d_logits, ld_logits, d_Q, n, n_labels, weight, d_loss, d_g, ld_g);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

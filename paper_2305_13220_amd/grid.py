@@ -383,6 +383,29 @@ def denoise(grid: Grid, vox: torch.Tensor, radius: int = 1, sigma: float = 1.0, 
     return out
 
 
+def crf_label_loss(feat: torch.Tensor, Q: torch.Tensor, col0: int = 0, weight: float = 1.0,
+                   g_feat=None):
+    """KL(softmax(feat[:, col0:col0+L]) || Q) per node times weight (Sec.
+    3.5.3), and its gradient written into g_feat[:, col0:col0+L] (a zero
+    array shaped like feat if None).  Returns (loss [n], g_feat)."""
+    want(feat, "feat", torch.float32, (None, None))
+    n, Cf = feat.shape
+    want(Q, "Q", torch.float32, (n, None), feat.device)
+    L = Q.shape[1]
+    if col0 < 0 or col0 + L > Cf:
+        raise ValueError("the label columns lie outside feat")
+    if g_feat is None:
+        g_feat = torch.zeros_like(feat)
+    else:
+        want(g_feat, "g_feat", torch.float32, (n, Cf), feat.device)
+    loss = torch.empty(n, dtype=torch.float32, device=feat.device)
+    base = ctypes.c_void_p(feat.data_ptr() + 4 * col0) if n else None
+    gbase = ctypes.c_void_p(g_feat.data_ptr() + 4 * col0) if n else None
+    check(lib().sg_crf_label_loss(base, Cf, ptr(Q), n, L, ctypes.c_float(weight), ptr(loss), gbase,
+                                  Cf, stream_ptr(feat.device)), "sg_crf_label_loss")
+    return loss, g_feat
+
+
 class Lattice:
     """Permutohedral lattice of scaled feature positions [n,d] (Sec. 3.5.3)."""
 

@@ -87,3 +87,58 @@ def test_lattice_invalid_inputs():
     with pytest.raises(sg.SgridError):
         lat.filter(to_dev(np.zeros((10, 3), np.float32)))
     assert lat.n_vertices == 4
+
+
+def test_crf_label_loss_matches_oracle():
+    sg = _sg()
+    rng = np.random.default_rng(21)
+    n, L, Cf, col0 = 5000, 16, 19, 3
+    feat = rng.normal(scale=2.0, size=(n, Cf)).astype(np.float32)
+    Q = rng.dirichlet(np.ones(L) * 0.5, size=n).astype(np.float32) + 1e-6
+    Q = (Q / Q.sum(1, keepdims=True)).astype(np.float32)
+    loss, g = sg.crf_label_loss(to_dev(feat), to_dev(Q), col0, 0.3)
+    want_l, want_g = oracle.crf_label_loss(feat[:, col0:col0 + L], Q, 0.3)
+    loss, g = loss.cpu().numpy(), g.cpu().numpy()
+    scale = 0.3 * (1.0 + np.abs(np.log(Q)).max(1) + np.abs(feat[:, col0:col0 + L]).max(1))
+    assert (np.abs(loss - want_l) <= 1e-5 * scale).all()
+    assert (np.abs(g[:, col0:col0 + L] - want_g) <= 1e-5 * scale[:, None]).all()
+    assert not g[:, :col0].any() and not g[:, col0 + L:].any()
+
+
+def test_crf_label_loss_into_voxels_chain():
+    """Surface samples of the 2 cm room with 16 semantic channels: query the
+    logits, mean field on (xyz, rgb) features, label loss, and its gradient
+    through the query adjoint into the voxels; the GPU chain against the
+    oracle's, within 1e-3 of the largest gradient (float32 queries shift the
+    unaries slightly and the shift propagates through three updates)."""
+    sg = _sg()
+    from synth import scenes
+    from gpu_helpers import make_grid
+    room = scenes.room_scene(h=0.02, band_vox=3, seed=0, n_sem=16)
+    pos, _ = _surface_features()
+    xyz = (pos[:, :3] * 0.2).astype(np.float32)  # world points of the nodes
+    g = make_grid(room)
+    vox = to_dev(room["vox"])
+    q = sg.query(g, vox, to_dev(xyz))
+    valid = q["valid"].cpu().numpy().astype(bool)
+    assert valid.mean() > 0.9
+    keep = np.flatnonzero(valid)
+    xyz, pos = xyz[keep], pos[keep]
+    feat = sg.query(g, vox, to_dev(xyz))["feat"]
+    logits = feat[:, 3:].contiguous()
+    unary = -torch.log_softmax(logits, 1)
+    lat = sg.Lattice(to_dev(pos), max_values=16)
+    Q = lat.meanfield(unary.contiguous(), 5.0, 3)
+    _, g_feat = sg.crf_label_loss(feat, Q, 3, 0.1)
+    gv = sg.query_backward(g, room["vox"].shape, to_dev(xyz), g_feat=g_feat).cpu().numpy()
+    # oracle chain
+    _, _, _, ofeat = oracle.query(room["block_coords"], room["vox"], 19, room["h"], room["origin"], xyz)
+    ol = ofeat[:, 3:]
+    ou = -(ol - ol.max(1, keepdims=True) - np.log(np.exp(ol - ol.max(1, keepdims=True)).sum(1, keepdims=True)))
+    oQ = oracle.crf_meanfield(pos, ou, 5.0, 3)
+    _, og = oracle.crf_label_loss(ol, oQ, 0.1)
+    ogf = np.concatenate([np.zeros((len(xyz), 3)), og], 1)
+    want, _ = oracle.query_backward(room["block_coords"], 19, room["h"], room["origin"], xyz,
+                                    g_feat=ogf)
+    assert np.abs(want).max() > 0
+    assert np.abs(gv - want).max() <= 1e-3 * np.abs(want).max()
