@@ -26,8 +26,9 @@ Every function cites the passage of the paper it follows:
     3.4.1) and the depth, colour and semantic fusion of Sec. 3.4.2.
   * ``denoise``: the Gaussian blur of Sec. 3.4.3 over allocated voxels.
   * ``lattice_simplex`` / ``lattice_filter`` / ``crf_meanfield`` /
-    ``crf_label_loss``: the permutohedral-lattice Gaussian filter, the
-    mean-field update and the label loss of the continuous CRF (Sec. 3.5.3).
+    ``crf_label_loss`` / ``crf_property_loss``: the permutohedral-lattice
+    Gaussian filter, the mean-field update and the label, colour and normal
+    losses of the continuous CRF (Sec. 3.5.3).
 """
 from __future__ import annotations
 
@@ -462,4 +463,18 @@ def crf_label_loss(logits, Q, weight=1.0):
     g = np.empty((N, L), np.float64)
     _check(lib.or_crf_label_loss(_p(lg), _p(q), _I64(N), _I32(L), _D(weight), _p(loss), _p(g)),
            "crf_label_loss")
+    return loss, g
+
+
+def crf_property_loss(x, filt, weight=1.0):
+    """|x - F(x)/F(1)|^2 per node times weight and its gradient (Q fixed)
+    (Sec. 3.5.3); filt = lattice filter of [x, 1].  Returns (loss, g)."""
+    lib = _load()
+    xx = _c(x, np.float64)
+    N, P = xx.shape
+    f = _c(filt, np.float64).reshape(N, P + 1)
+    loss = np.empty(N, np.float64)
+    g = np.empty((N, P), np.float64)
+    _check(lib.or_crf_property_loss(_p(xx), _p(f), _I64(N), _I32(P), _D(weight), _p(loss), _p(g)),
+           "crf_property_loss")
     return loss, g

@@ -1388,3 +1388,27 @@ int or_crf_label_loss(const double* logits, const double* Q, int64_t N, int32_t 
   }
   return 0;
 }
+
+/*
+ * Colour / normal loss of the continuous CRF (Sec. 3.5.3, Eq. 22) for a
+ * continuous property x [n,P]: its mean-field estimate is the normalised
+ * Gaussian filter of the property over the other features,
+ * Q_i = F(x)_i / F(1)_i (filt [n,P+1] holds F applied to [x, 1]), a fixed
+ * target; loss[i] = weight |x_i - Q_i|^2, g[i] = 2 weight (x_i - Q_i).
+ */
+int or_crf_property_loss(const double* x, const double* filt, int64_t N, int32_t P,
+                         double weight, double* loss, double* g) {
+  if (P < 1 || N < 0) return -1;
+  for (int64_t i = 0; i < N; ++i) {
+    const double den = filt[i * (P + 1) + P];
+    double l = 0.0;
+    for (int k = 0; k < P; ++k) {
+      const double q = filt[i * (P + 1) + k] / den;
+      const double d = x[i * P + k] - q;
+      l += d * d;
+      g[i * P + k] = 2.0 * weight * d;
+    }
+    loss[i] = weight * l;
+  }
+  return 0;
+}

@@ -165,3 +165,21 @@ def test_label_loss_kl_and_gradient(oracle_lib):
         lo[i, k] -= 1e-6
         fd = (oracle_lib.crf_label_loss(hi, Q, 0.7)[0][i] - oracle_lib.crf_label_loss(lo, Q, 0.7)[0][i]) / 2e-6
         assert fd == pytest.approx(g[i, k], rel=1e-6, abs=1e-9)
+
+
+def test_property_loss(oracle_lib):
+    """A constant property is its own filtered estimate (zero loss); for a
+    random property the loss is |x - F(x)/F(1)|^2 with F the pinned filter,
+    and the gradient 2 w (x - Q)."""
+    rng = np.random.default_rng(4)
+    p = rng.normal(scale=2.0, size=(300, 4)).astype(np.float32)
+    const = np.tile([0.2, -0.5, 0.7], (300, 1))
+    f, _ = oracle_lib.lattice_filter(p, np.concatenate([const, np.ones((300, 1))], 1))
+    l0, g0 = oracle_lib.crf_property_loss(const, f, 2.0)
+    assert np.abs(l0).max() < 1e-20 and np.abs(g0).max() < 1e-10
+    x = rng.normal(size=(300, 3))
+    f, _ = oracle_lib.lattice_filter(p, np.concatenate([x, np.ones((300, 1))], 1))
+    loss, g = oracle_lib.crf_property_loss(x, f, 0.5)
+    Q = f[:, :3] / f[:, 3:]
+    np.testing.assert_allclose(loss, 0.5 * ((x - Q) ** 2).sum(1), rtol=1e-12)
+    np.testing.assert_allclose(g, (x - Q), rtol=1e-12)
