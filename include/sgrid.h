@@ -278,6 +278,19 @@ typedef struct sg_lattice sg_lattice;
 int sg_crf_label_loss(const float* d_logits, int64_t ld_logits, const float* d_Q, int64_t n,
                       int32_t n_labels, float weight, float* d_loss, float* d_g, int64_t ld_g,
                       sg_stream stream);
+/*
+ * sg_crf_property_loss -- the CRF's colour or normal loss (Eq. 22) for a
+ * continuous property x (P values per node, rows of stride ld_x): its
+ * mean-field estimate is the normalised Gaussian filter over the other
+ * features, Q = F(x) / F(1), read from d_filtered [n, P+1] = sg_lattice_filter
+ * of [x, 1] (a fixed target):
+ *   d_loss [n] (nullable) = weight |x - Q|^2,
+ *   d_g (nullable) row i (stride ld_g) = 2 weight (x_i - Q_i).
+ * Asynchronous; allocates nothing.  1 <= P <= 31.
+ */
+int sg_crf_property_loss(const float* d_x, int64_t ld_x, const float* d_filtered, int64_t n,
+                         int32_t n_props, float weight, float* d_loss, float* d_g, int64_t ld_g,
+                         sg_stream stream);
 int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
                      sg_stream stream, sg_lattice** out);
 int sg_lattice_num_vertices(const sg_lattice* lat, int64_t* n_vertices);

@@ -64,6 +64,8 @@ _SIGNATURES = {
     "sg_crf_meanfield": ([_vp, _vp, _i32, ctypes.c_float, _i32, _vp, _vp], ctypes.c_int),
     "sg_crf_label_loss": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_float, _vp, _vp, _i64, _vp],
                           ctypes.c_int),
+    "sg_crf_property_loss": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_float, _vp, _vp, _i64, _vp],
+                             ctypes.c_int),
     "sg_lattice_destroy": ([_vp], ctypes.c_int),
     "sg_render_list_bytes": ([_i64, _vp], ctypes.c_size_t),
     "sg_render_march": ([_vp, _vp, _i64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),

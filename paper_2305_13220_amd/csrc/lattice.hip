@@ -300,6 +300,23 @@ __global__ void k_crf_label_loss(const float* __restrict__ logits, int64_t ld_s,
   }
 }
 
+// Colour / normal loss per node: Q = F(x) / F(1) from the filter of [x, 1]
+// (a fixed target), loss = weight |x - Q|^2, gradient 2 weight (x - Q).
+__global__ void k_crf_property_loss(const float* __restrict__ x, int64_t ld_x,
+                                    const float* __restrict__ filt, int64_t N, int P, float weight,
+                                    float* __restrict__ loss, float* __restrict__ g, int64_t ld_g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const float inv = 1.0f / filt[i * (P + 1) + P];
+  float l = 0.0f;
+  for (int k = 0; k < P; ++k) {
+    const float d = x[i * ld_x + k] - filt[i * (P + 1) + k] * inv;
+    l += d * d;
+    if (g) g[i * ld_g + k] = 2.0f * weight * d;
+  }
+  if (loss) loss[i] = weight * l;
+}
+
 static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace sg
@@ -484,6 +501,22 @@ int sg_crf_label_loss(const float* d_logits, int64_t ld_logits, const float* d_Q
   if (!d_logits || !d_Q) return fail(SG_EINVAL, "a required pointer is NULL");
   k_crf_label_loss<<<grid_of(n, 256), 256, 0, (hipStream_t)stream>>>(
       d_logits, ld_logits, d_Q, n, n_labels, weight, d_loss, d_g, ld_g);
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_crf_property_loss(const float* d_x, int64_t ld_x, const float* d_filtered, int64_t n,
+                         int32_t n_props, float weight, float* d_loss, float* d_g, int64_t ld_g,
+                         sg_stream stream) {
+  if (n < 0) return fail(SG_EINVAL, "n must be >= 0");
+  if (n_props < 1 || n_props >= kLatMaxV) return fail(SG_EINVAL, "n_props must be in [1, 31]");
+  if (ld_x < n_props || (d_g && ld_g < n_props))
+    return fail(SG_EINVAL, "row strides must be >= n_props");
+  if (!std::isfinite(weight)) return fail(SG_EINVAL, "weight must be finite");
+  if (n == 0) return SG_OK;
+  if (!d_x || !d_filtered) return fail(SG_EINVAL, "a required pointer is NULL");
+  k_crf_property_loss<<<grid_of(n, 256), 256, 0, (hipStream_t)stream>>>(
+      d_x, ld_x, d_filtered, n, n_props, weight, d_loss, d_g, ld_g);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

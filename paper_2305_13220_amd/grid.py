@@ -406,6 +406,31 @@ def crf_label_loss(feat: torch.Tensor, Q: torch.Tensor, col0: int = 0, weight: f
     return loss, g_feat
 
 
+def crf_property_loss(feat: torch.Tensor, filtered: torch.Tensor, col0: int, weight: float = 1.0,
+                      g_feat=None):
+    """|x - F(x)/F(1)|^2 per node times weight for the property
+    x = feat[:, col0:col0+P] (Sec. 3.5.3), filtered = lattice filter of
+    [x, 1] [n, P+1]; the gradient goes into g_feat[:, col0:col0+P].
+    Returns (loss [n], g_feat)."""
+    want(feat, "feat", torch.float32, (None, None))
+    n, Cf = feat.shape
+    want(filtered, "filtered", torch.float32, (n, None), feat.device)
+    P = filtered.shape[1] - 1
+    if P < 1 or col0 < 0 or col0 + P > Cf:
+        raise ValueError("the property columns lie outside feat")
+    if g_feat is None:
+        g_feat = torch.zeros_like(feat)
+    else:
+        want(g_feat, "g_feat", torch.float32, (n, Cf), feat.device)
+    loss = torch.empty(n, dtype=torch.float32, device=feat.device)
+    base = ctypes.c_void_p(feat.data_ptr() + 4 * col0) if n else None
+    gbase = ctypes.c_void_p(g_feat.data_ptr() + 4 * col0) if n else None
+    check(lib().sg_crf_property_loss(base, Cf, ptr(filtered), n, P, ctypes.c_float(weight),
+                                     ptr(loss), gbase, Cf, stream_ptr(feat.device)),
+          "sg_crf_property_loss")
+    return loss, g_feat
+
+
 class Lattice:
     """Permutohedral lattice of scaled feature positions [n,d] (Sec. 3.5.3)."""
 

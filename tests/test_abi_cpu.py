@@ -92,6 +92,10 @@ def test_render_validation(L):
     assert L.sg_crf_label_loss(fake, 2, fake, 10, 4, ctypes.c_float(1.0), None, None, 4, None) == -1
     assert L.sg_crf_label_loss(fake, 4, fake, 10, 33, ctypes.c_float(1.0), None, None, 33, None) == -1
     assert L.sg_crf_label_loss(None, 4, None, 0, 4, ctypes.c_float(1.0), None, None, 4, None) == 0
+    assert L.sg_crf_property_loss(fake, 2, fake, 10, 3, ctypes.c_float(1.0), None, None, 3,
+                                  None) == -1
+    assert L.sg_crf_property_loss(None, 3, None, 0, 3, ctypes.c_float(1.0), None, None, 3,
+                                  None) == 0
     n = ctypes.c_int64(5)
     org = (ctypes.c_float * 3)(0, 0, 0)
     assert L.sg_alloc_blocks(fake, 1, fake, 4, 4, ctypes.c_float(0.02), org, -1, ctypes.c_float(1),

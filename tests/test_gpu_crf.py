@@ -142,3 +142,27 @@ def test_crf_label_loss_into_voxels_chain():
                                     g_feat=ogf)
     assert np.abs(want).max() > 0
     assert np.abs(gv - want).max() <= 1e-3 * np.abs(want).max()
+
+
+def test_crf_property_loss_matches_oracle():
+    """Colour loss of room surface samples: the lattice over (xyz, semantic
+    one-hot) features, the filter of [rgb, 1], the loss against the oracle's
+    on the same filter inputs (filter within the filter bar, loss and
+    gradient within 1e-4 relative plus 1e-6)."""
+    sg = _sg()
+    from synth import workloads
+    fr = workloads.room_depth_frames(n_frames=2, W=160, H=120, n_sem=16)
+    pos, _ = _surface_features()
+    rng = np.random.default_rng(2)
+    rgb = np.clip(rng.normal(0.5, 0.2, size=(len(pos), 3)), 0, 1).astype(np.float32)
+    feats = np.concatenate([pos[:, :3], rng.normal(size=(len(pos), 2)).astype(np.float32)], 1)
+    vals = np.concatenate([rgb, np.ones((len(pos), 1), np.float32)], 1)
+    lat = sg.Lattice(to_dev(feats), max_values=4)
+    filt = lat.filter(to_dev(vals))
+    feat = np.concatenate([np.zeros((len(pos), 1), np.float32), rgb], 1)  # [sdf, rgb]
+    loss, g = sg.crf_property_loss(to_dev(feat), filt, 1, 0.4)
+    ofilt, _ = oracle.lattice_filter(feats, vals)
+    ol, og = oracle.crf_property_loss(rgb, ofilt, 0.4)
+    np.testing.assert_allclose(loss.cpu().numpy(), ol, rtol=1e-4, atol=1e-6)
+    np.testing.assert_allclose(g.cpu().numpy()[:, 1:], og, rtol=1e-4, atol=1e-6)
+    assert not g.cpu().numpy()[:, 0].any()
