@@ -28,7 +28,8 @@ Every function cites the passage of the paper it follows:
   * ``lattice_simplex`` / ``lattice_filter`` / ``crf_meanfield`` /
     ``crf_label_loss`` / ``crf_property_loss``: the permutohedral-lattice
     Gaussian filter, the mean-field update and the label, colour and normal
-    losses of the continuous CRF (Sec. 3.5.3).
+    losses of the continuous CRF (Sec. 3.5.3); ``surface_points``: its
+    nodes, the zero crossings of the SDF along rays.
 """
 from __future__ import annotations
 
@@ -478,3 +479,21 @@ def crf_property_loss(x, filt, weight=1.0):
     _check(lib.or_crf_property_loss(_p(xx), _p(f), _I64(N), _I32(P), _D(weight), _p(loss), _p(g)),
            "crf_property_loss")
     return loss, g
+
+
+def surface_points(block_coords, vox, C, h, origin, rays, params):
+    """First entering zero crossing of the SDF along each ray's kept samples
+    (Sec. 3.5.3's surface nodes).  Returns (hit [R] bool, points [R,3],
+    fmin [R] = margin of the sign decisions)."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    vx = _c(vox, np.float64)
+    ry = _c(rays, np.float32).reshape(-1, 6)
+    R = ry.shape[0]
+    org, gp = _geom_args(h, origin, params)
+    hit = np.empty(R, np.int32)
+    pts = np.empty((R, 3), np.float64)
+    fm = np.empty(R, np.float64)
+    _check(lib.or_surface_points(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org),
+                                 _p(ry), _I64(R), *gp, _p(hit), _p(pts), _p(fm)), "surface_points")
+    return hit.astype(bool), pts, fm

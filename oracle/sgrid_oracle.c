@@ -1412,3 +1412,55 @@ int or_crf_property_loss(const double* x, const double* filt, int64_t N, int32_t
   }
   return 0;
 }
+
+/*
+ * Surface points of rays (the nodes of the continuous CRF are zero
+ * crossings of the SDF seen from random viewpoints, Sec. 3.5.3): along the
+ * kept samples of each ray (Sec. 3.5.1), the first pair of lattice-adjacent
+ * samples with f_j > 0 >= f_{j+1} (entering the surface); the crossing is
+ * placed by linear interpolation of f, t* = t_j + step f_j / (f_j - f_{j+1}),
+ * at o + t* d.  hit [R] (1 / 0), points [R,3] (0 where no hit), and
+ * margin [R] (nullable) = min(|f_j|, |f_{j+1}|) of the pair (how far the
+ * sign decisions are from zero).
+ */
+int or_surface_points(const int32_t* block_coords, int64_t n_blocks, const double* vox, int32_t C,
+                      float h, const float org[3], const float* rays, int64_t R, float step,
+                      float t_near, float t_far, float beta, int32_t max_samples, int32_t* hit,
+                      double* points, double* margin) {
+  if (C < 0 || R < 0) return -1;
+  geom g;
+  if (geom_make(&g, h, org, step, t_near, t_far, beta, max_samples)) return -1;
+  table tb;
+  int rc = table_make(&tb, block_coords, n_blocks);
+  if (rc) return rc;
+  sample* smp = (sample*)malloc((size_t)max_samples * sizeof(sample));
+  double* f = (double*)malloc((size_t)max_samples * sizeof(double));
+  double* feat = (double*)malloc((size_t)(C > 0 ? C : 1) * sizeof(double));
+  if (!smp || !f || !feat) {
+    free(smp); free(f); free(feat);
+    table_free(&tb);
+    return -3;
+  }
+  for (int64_t r = 0; r < R; ++r) {
+    const int n = ray_samples(&tb, &g, rays + 6 * r, smp);
+    for (int j = 0; j < n; ++j) {
+      double gr[3];
+      interpolate(&smp[j], vox, C, (double)h, &f[j], gr, feat);
+    }
+    hit[r] = 0;
+    points[3 * r] = points[3 * r + 1] = points[3 * r + 2] = 0.0;
+    if (margin) margin[r] = 0.0;
+    for (int j = 0; j + 1 < n; ++j) {
+      if (smp[j + 1].k != smp[j].k + 1) continue;
+      if (!(f[j] > 0.0 && f[j + 1] <= 0.0)) continue;
+      const double ts = (double)smp[j].t + (double)step * f[j] / (f[j] - f[j + 1]);
+      for (int a = 0; a < 3; ++a) points[3 * r + a] = (double)rays[6 * r + a] + ts * (double)rays[6 * r + 3 + a];
+      hit[r] = 1;
+      if (margin) margin[r] = fmin(fabs(f[j]), fabs(f[j + 1]));
+      break;
+    }
+  }
+  free(smp); free(f); free(feat);
+  table_free(&tb);
+  return 0;
+}

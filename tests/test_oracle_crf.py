@@ -183,3 +183,30 @@ def test_property_loss(oracle_lib):
     Q = f[:, :3] / f[:, 3:]
     np.testing.assert_allclose(loss, 0.5 * ((x - Q) ** 2).sum(1), rtol=1e-12)
     np.testing.assert_allclose(g, (x - Q), rtol=1e-12)
+
+
+def test_surface_points_on_a_plane_and_sphere(oracle_lib):
+    """A linear SDF (plane z = 0.3, f = 0.3 - z) is interpolated exactly, so
+    the crossing lies on the plane; on the sphere grid the crossing of the
+    central ray is within the interpolation error of radius 0.5; a ray that
+    misses the grid reports no hit."""
+    from synth import workloads
+    from synth.scenes import voxel_positions
+    from test_oracle_interp import _dense_blocks
+    h = np.float32(1.0 / 16)
+    blocks = _dense_blocks((-1, -1, -1), (0, 0, 0))
+    pos = voxel_positions(blocks, float(h), np.zeros(3))
+    vox = (-0.2 - pos[..., 2])[..., None]  # positive below the plane z = -0.2
+    rays = np.array([[-0.2, 0.1, -0.8, 0.0, 0.0, 1.0], [0.1, -0.3, -0.9, 0.3, 0.2, 0.9327379],
+                     [5.0, 5.0, 5.0, 1.0, 0.0, 0.0]], np.float32)
+    params = {"step": float(h) / 2, "t_near": 0.0, "t_far": 3.0, "beta": float(h), "max_samples": 256}
+    hit, pts, margin = oracle_lib.surface_points(blocks, vox, 0, h, np.zeros(3, np.float32), rays,
+                                                 params)
+    assert hit.tolist() == [True, True, False]
+    np.testing.assert_allclose(pts[:2, 2], -0.2, atol=1e-6)
+    assert (margin[:2] >= 0).all() and not pts[2].any()
+    w = workloads.sphere_tiny()
+    ray = w["rays"][(w["H"] // 2) * w["W"] + w["W"] // 2][None]
+    hit, pts, _ = oracle_lib.surface_points(w["block_coords"], w["vox"], 3, w["h"], w["origin"], ray,
+                                            w["params"])
+    assert hit[0] and abs(np.linalg.norm(pts[0]) - 0.5) < 2e-3
