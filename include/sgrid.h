@@ -339,6 +339,21 @@ int sg_query(const sg_grid* g, const float* d_vox, int32_t C, const float* d_poi
              sg_stream stream);
 
 /*
+ * sg_surface_points -- surface points along rays (the nodes of the
+ * continuous CRF are zero crossings of the SDF seen from random viewpoints,
+ * Sec. 3.5.3): along each ray's kept samples (as sg_render_forward takes
+ * them), the first pair of lattice-adjacent samples with f_j > 0 >= f_{j+1}
+ * (entering the surface), placed by linear interpolation of f:
+ * t* = t_j + step f_j / (f_j - f_{j+1}).  d_points [R,3] = o + t* d and
+ * d_hit [R] = 1, or zeros and 0 where the ray crosses no surface.
+ * d_vox [n_blocks,512,1+C] (only the SDF channel is read), 0 <= C <= 64.
+ * Asynchronous; allocates nothing.
+ */
+int sg_surface_points(const sg_grid* g, const float* d_vox, int32_t C, const float* d_rays,
+                      int64_t n_rays, const sg_render_params* params, float* d_points,
+                      int32_t* d_hit, sg_stream stream);
+
+/*
  * sg_query_backward -- adjoint of sg_query with respect to the voxels, for
  * losses on queried values (e.g. the CRF's losses on surface samples,
  * Sec. 3.5.3): for upstream gradients d_g_f [n], d_g_grad [n,3] (world

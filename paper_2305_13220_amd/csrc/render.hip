@@ -642,6 +642,70 @@ __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __r
   }
 }
 
+// Surface points (the nodes of the continuous CRF are zero crossings of the
+// SDF seen from random viewpoints): along the kept samples of each ray, the
+// first pair of lattice-adjacent samples with f_j > 0 >= f_{j+1}, placed by
+// linear interpolation of f, t* = t_j + step f_j / (f_j - f_{j+1}), at
+// o + t* d.  Lanes test consecutive pairs of a chunk; the lowest candidate
+// writes the ray's point.
+__device__ __forceinline__ float sdf_at(const float* __restrict__ vox, const Cell& c, int V) {
+  const float wx[2] = {1.0f - c.u[0], c.u[0]}, wy[2] = {1.0f - c.u[1], c.u[1]},
+              wz[2] = {1.0f - c.u[2], c.u[2]};
+  float f = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    f += wx[a & 1] * wy[(a >> 1) & 1] * wz[(a >> 2) & 1] * vox[(int64_t)c.off[a] * V];
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_surface(GridView g, const float* __restrict__ vox, int V,
+                                                 const float* __restrict__ rays, int64_t R,
+                                                 Params p, float* __restrict__ points,
+                                                 int32_t* __restrict__ hit) {
+  extern __shared__ int2 lds_q[];
+  const int wpb = blockDim.x / kWave, lane = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int2* const q = lds_q + (int64_t)w * p.max_samples;
+  BatchRays rs((int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
+  ListPrefetch pf;
+  while (rs.next<true>(rays, g, p)) {
+    const int64_t r = rs.r;
+    March m;
+    const int n = ray_samples<false>(g, rs, p, nullptr, nullptr, pf, r, r + rs.stride, R, m, q);
+    bool found = false;
+    for (int c0 = 0; c0 + 1 < n && !found; c0 += kWave) {
+      const int j = c0 + lane;
+      bool cand = false;
+      float fj = 0.0f, fn = 0.0f, tj = 0.0f;
+      if (j + 1 < n && q[j + 1].x == q[j].x + 1) {
+        Cell a, b;
+        locate(g, m, p, q[j], a);
+        locate(g, m, p, q[j + 1], b);
+        fj = sdf_at(vox, a, V);
+        fn = sdf_at(vox, b, V);
+        tj = a.t;
+        cand = fj > 0.0f && fn <= 0.0f;
+      }
+      const uint64_t bal = __ballot(cand);
+      if (bal) {
+        found = true;
+        if (lane == __builtin_ctzll(bal)) {
+          float ray[6];
+          rs.ray_of(ray);
+          const float ts = tj + p.step * (fj / (fj - fn));
+#pragma unroll
+          for (int a = 0; a < 3; ++a) points[3 * r + a] = ray[a] + ts * ray[3 + a];
+          hit[r] = 1;
+        }
+      }
+    }
+    if (!found && lane == 0) {
+      points[3 * r] = points[3 * r + 1] = points[3 * r + 2] = 0.0f;
+      hit[r] = 0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Packed multi-grid render for serving: one launch renders the pixel ranges
 // ("slots") of several requests over several resident grids.  Rays are made
@@ -1878,6 +1942,25 @@ int sg_query(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_query<CC>, dim3((unsigned)blocks), dim3(256), 0,
                                       (hipStream_t)stream, g, d_vox, d_points, n_points, d_valid,
                                       d_f, d_grad, C > 0 ? d_feat : nullptr));
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_surface_points(const sg_grid* grid, const float* d_vox, int32_t C, const float* d_rays,
+                      int64_t n_rays, const sg_render_params* params, float* d_points,
+                      int32_t* d_hit, sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  Params p;
+  if ((rc = check_params(params, p))) return rc;
+  if (C < 0 || C > 64) return fail(SG_EINVAL, "C must be in [0, 64]");
+  if (n_rays < 0) return fail(SG_EINVAL, "n_rays must be >= 0");
+  if (n_rays == 0) return SG_OK;
+  if (!d_vox || !d_rays || !d_points || !d_hit) return fail(SG_EINVAL, "a required pointer is NULL");
+  const GridView g = view_of(grid);
+  const Launch l = plan(n_rays, sizeof(int2) * p.max_samples, 4, 4);
+  hipLaunchKernelGGL(k_surface, dim3(l.blocks), dim3(l.threads), l.lds, (hipStream_t)stream, g,
+                     d_vox, 1 + C, d_rays, n_rays, p, d_points, d_hit);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

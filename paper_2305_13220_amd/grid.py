@@ -289,6 +289,22 @@ def query(grid: Grid, vox: torch.Tensor, points: torch.Tensor, features: bool = 
     return res
 
 
+def surface_points(grid: Grid, vox: torch.Tensor, rays: torch.Tensor, params):
+    """First entering zero crossing of the SDF along each ray (the CRF's
+    surface nodes, Sec. 3.5.3).  Returns (points [R,3], hit [R] int32)."""
+    params = RenderParams.of(params)
+    C = vox.shape[-1] - 1
+    _check_vox(grid, vox, C)
+    want(rays, "rays", torch.float32, (None, 6), grid.device)
+    R = rays.shape[0]
+    pts = torch.empty((R, 3), dtype=torch.float32, device=grid.device)
+    hit = torch.empty(R, dtype=torch.int32, device=grid.device)
+    prm = params.c()
+    check(lib().sg_surface_points(grid.handle, ptr(vox), C, ptr(rays), R, ctypes.byref(prm),
+                                  ptr(pts), ptr(hit), stream_ptr(grid.device)), "sg_surface_points")
+    return pts, hit
+
+
 def query_backward(grid: Grid, vox_shape, points: torch.Tensor, g_f=None, g_grad=None, g_feat=None,
                    grad_vox=None):
     """Accumulate the adjoint of ``query`` into grad_vox (zeros of vox_shape

@@ -80,6 +80,7 @@ def test_render_validation(L):
     assert L.sg_query(None, fake, 3, fake, 10, None, None, None, None, None) == -1
     assert L.sg_eikonal(None, fake, 3, fake, 10, ctypes.c_float(1.0), None, None, None) == -1
     assert L.sg_query_backward(None, 3, fake, 10, None, None, None, fake, None) == -1
+    assert L.sg_surface_points(None, fake, 3, fake, 10, ctypes.byref(p), fake, fake, None) == -1
     assert L.sg_fuse(None, fake, 1, fake, fake, 3, 4, 4, ctypes.c_float(0.1), 0, fake, None,
                      None) == -1
     assert L.sg_denoise(None, fake, 3, 1, ctypes.c_float(1.0), fake, None) == -1

@@ -166,3 +166,28 @@ def test_crf_property_loss_matches_oracle():
     np.testing.assert_allclose(loss.cpu().numpy(), ol, rtol=1e-4, atol=1e-6)
     np.testing.assert_allclose(g.cpu().numpy()[:, 1:], og, rtol=1e-4, atol=1e-6)
     assert not g.cpu().numpy()[:, 0].any()
+
+
+@pytest.mark.parametrize("which", ["sphere", "room"])
+def test_surface_points_match_oracle(which):
+    """Hit flags equal except where a sign decision is within float32
+    rounding of zero (at most 1 in 1,000 rays); points, where the decisions
+    have a margin above 1e-5 h, within 1e-4 of the step plus 1e-5 of the
+    coordinates."""
+    sg = _sg()
+    from synth import workloads
+    from gpu_helpers import make_grid
+    w = workloads.sphere_tiny() if which == "sphere" else workloads.room_2cm()
+    rays_np = w["rays"] if which == "sphere" else w["rays"][:16384]
+    g = make_grid(w)
+    pts, hit = sg.surface_points(g, to_dev(w["vox"]), to_dev(rays_np), w["params"])
+    pts, hit = pts.cpu().numpy(), hit.cpu().numpy().astype(bool)
+    ohit, opts, margin = oracle.surface_points(w["block_coords"], w["vox"], 3, w["h"], w["origin"],
+                                               rays_np, w["params"])
+    assert ohit.mean() > 0.3
+    differ = hit != ohit
+    assert differ.sum() <= max(2, int(1e-3 * len(hit)))
+    both = hit & ohit & (margin > 1e-5 * float(w["h"]))
+    err = np.abs(pts[both] - opts[both]).max()
+    assert err <= 1e-4 * float(w["params"]["step"]) + 1e-5 * np.abs(opts[both]).max()
+    assert not pts[~hit].any()
