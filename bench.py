@@ -517,7 +517,7 @@ def main():
                          "(reads and writes it once: a reference for memory counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(rays are independent; a multi-GPU step would shard the batch and all-reduce the "
               "voxel gradients). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
