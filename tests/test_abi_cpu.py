@@ -168,3 +168,16 @@ def test_binding_rejects_cpu_tensors():
     import paper_2305_13220_amd as sg
     with pytest.raises(ValueError, match="GPU tensor"):
         sg.Grid(torch.zeros((4, 3), dtype=torch.int32), 0.02)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says why,
+    before touching a GPU."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
