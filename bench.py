@@ -299,6 +299,12 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
         t_alloc.append(b - a)
         t_build.append(c - b)
         t_fuse.append(e[0].elapsed_time(e[1]) * 1e-3)
+    t_fd = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        sg.Grid.from_depth(cams, depth, h, dilate=1)
+        torch.cuda.synchronize()
+        t_fd.append(time.perf_counter() - a)
     n_vox = grid.n_blocks * 512
     fuse_s = float(np.median(t_fuse))
     total = float(np.median(t_alloc)) + float(np.median(t_build)) + fuse_s
@@ -318,6 +324,7 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
            "denoise_hbm_frac": round(dn_bytes / (dn_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "alloc_ms": round(float(np.median(t_alloc)) * 1e3, 3),
            "build_ms": round(float(np.median(t_build)) * 1e3, 3),
+           "grid_from_depth_ms": round(float(np.median(t_fd)) * 1e3, 3),
            "fuse_ms": round(fuse_s * 1e3, 3),
            "fuse_voxel_frames_per_s": n_vox * n_frames / fuse_s,
            "frames_per_s_end_to_end": round(n_frames / total, 1),

@@ -196,6 +196,18 @@ int sg_alloc_blocks(const float* d_cams, int32_t n_frames, const float* d_depth,
                     sg_stream stream);
 
 /*
+ * sg_grid_from_depth -- sg_alloc_blocks and sg_grid_build_ex in one call:
+ * the grid of the blocks allocated for the depth maps (same arguments and
+ * order of block indices), without the caller sizing an intermediate
+ * buffer.  SG_EINVAL if no pixel has a valid depth.  Allocates device
+ * memory and synchronises the stream.
+ */
+int sg_grid_from_depth(const float* d_cams, int32_t n_frames, const float* d_depth, int32_t W,
+                       int32_t H, float voxel_size, const float origin[3], int32_t dilate,
+                       float depth_max, sg_stream stream, sg_grid** out,
+                       const sg_build_options* options);
+
+/*
  * sg_fuse -- depth, colour and semantic fusion (Sec. 3.4.2): every voxel
  * (world position origin + i h) of the grid is projected into every frame
  * (camera point c = R^T (X - t); pixel (floor(fx c_x / c_z + cx),

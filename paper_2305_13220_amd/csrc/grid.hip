@@ -456,6 +456,52 @@ static int unique_first(const uint64_t* d_keys, const int32_t* d_coords, int64_t
   return SG_OK;
 }
 
+// The allocated block coordinates for depth maps (shared by sg_alloc_blocks
+// and sg_grid_from_depth), in first-occurrence order, in device memory
+// owned by `keep`; synchronises the stream.
+static int alloc_blocks_dev(const float* d_cams, int32_t n_frames, const float* d_depth,
+                            int32_t W, int32_t H, float voxel_size, const float origin[3],
+                            int32_t dilate, float depth_max, hipStream_t s, DevFree& keep,
+                            int32_t*& d_res, int64_t& no) {
+  no = 0;
+  d_res = nullptr;
+  if (n_frames < 0 || W < 0 || H < 0) return fail(SG_EINVAL, "sizes must be >= 0");
+  if (dilate < 0 || dilate > 8) return fail(SG_EINVAL, "dilate must be in [0, 8]");
+  if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size))
+    return fail(SG_EINVAL, "voxel_size must be finite and > 0");
+  if (!origin) return fail(SG_EINVAL, "origin is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(SG_EINVAL, "origin must be finite");
+  if (std::isnan(depth_max)) return fail(SG_EINVAL, "depth_max is NaN");
+  const int64_t P = (int64_t)n_frames * W * H;
+  if (P > (int64_t)INT_MAX) return fail(SG_EINVAL, "more than 2^31-1 pixels in one call");
+  if (P == 0) return SG_OK;
+  if (!d_cams || !d_depth) return fail(SG_EINVAL, "a required pointer is NULL");
+  DevFree tmp;
+  uint64_t* d_keys;
+  int32_t *d_coords, *d_unique;
+  SG_ALLOC(tmp, d_keys, sizeof(uint64_t) * P);
+  SG_ALLOC(tmp, d_coords, sizeof(int32_t) * 3 * P);
+  SG_ALLOC(tmp, d_unique, sizeof(int32_t) * 3 * P);
+  const int T = 256;
+  k_unproject<<<grid1d(P, T), T, 0, s>>>(d_cams, d_depth, W, H, P, 1.0f / voxel_size, origin[0],
+                                         origin[1], origin[2], dilate, depth_max, d_keys,
+                                         d_coords);
+  int64_t nu = 0;
+  int rc = unique_first(d_keys, d_coords, P, d_unique, nu, s);
+  if (rc) return rc;
+  const int64_t side = 2 * (int64_t)dilate + 1, nd = nu * side * side * side;
+  if (nd > (int64_t)INT_MAX) return fail(SG_EINVAL, "too many dilated blocks");
+  if (nd == 0) return SG_OK;
+  uint64_t* d_dkeys;
+  int32_t* d_dil;
+  SG_ALLOC(tmp, d_dkeys, sizeof(uint64_t) * nd);
+  SG_ALLOC(tmp, d_dil, sizeof(int32_t) * 3 * nd);
+  SG_ALLOC(keep, d_res, sizeof(int32_t) * 3 * nd);
+  k_dilate<<<grid1d(nd, T), T, 0, s>>>(d_unique, nu, dilate, d_dil, d_dkeys);
+  return unique_first(d_dkeys, d_dil, nd, d_res, no, s);  // synchronises the stream
+}
+
 extern "C" {
 
 const char* sg_last_error(void) { return g_last_error.c_str(); }
@@ -591,51 +637,40 @@ int sg_alloc_blocks(const float* d_cams, int32_t n_frames, const float* d_depth,
                     sg_stream stream) {
   if (!n_out) return fail(SG_EINVAL, "n_out is NULL");
   *n_out = 0;
-  if (n_frames < 0 || W < 0 || H < 0) return fail(SG_EINVAL, "sizes must be >= 0");
-  if (dilate < 0 || dilate > 8) return fail(SG_EINVAL, "dilate must be in [0, 8]");
-  if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size))
-    return fail(SG_EINVAL, "voxel_size must be finite and > 0");
-  if (!origin) return fail(SG_EINVAL, "origin is NULL");
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(origin[a])) return fail(SG_EINVAL, "origin must be finite");
-  if (std::isnan(depth_max)) return fail(SG_EINVAL, "depth_max is NaN");
   if (cap < 0) return fail(SG_EINVAL, "cap must be >= 0");
-  const int64_t P = (int64_t)n_frames * W * H;
-  if (P > (int64_t)INT_MAX) return fail(SG_EINVAL, "more than 2^31-1 pixels in one call");
-  if (P == 0) return SG_OK;
-  if (!d_cams || !d_depth) return fail(SG_EINVAL, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
-  DevFree tmp;
-  uint64_t* d_keys;
-  int32_t *d_coords, *d_unique;
-  SG_ALLOC(tmp, d_keys, sizeof(uint64_t) * P);
-  SG_ALLOC(tmp, d_coords, sizeof(int32_t) * 3 * P);
-  SG_ALLOC(tmp, d_unique, sizeof(int32_t) * 3 * P);
-  const int T = 256;
-  k_unproject<<<grid1d(P, T), T, 0, s>>>(d_cams, d_depth, W, H, P, 1.0f / voxel_size, origin[0],
-                                         origin[1], origin[2], dilate, depth_max, d_keys,
-                                         d_coords);
-  int64_t nu = 0;
-  int rc = unique_first(d_keys, d_coords, P, d_unique, nu, s);
-  if (rc) return rc;
-  const int64_t side = 2 * (int64_t)dilate + 1, nd = nu * side * side * side;
-  if (nd > (int64_t)INT_MAX) return fail(SG_EINVAL, "too many dilated blocks");
-  if (nd == 0) return SG_OK;
-  uint64_t* d_dkeys;
-  int32_t *d_dil, *d_res;
-  SG_ALLOC(tmp, d_dkeys, sizeof(uint64_t) * nd);
-  SG_ALLOC(tmp, d_dil, sizeof(int32_t) * 3 * nd);
-  SG_ALLOC(tmp, d_res, sizeof(int32_t) * 3 * nd);
-  k_dilate<<<grid1d(nd, T), T, 0, s>>>(d_unique, nu, dilate, d_dil, d_dkeys);
+  DevFree keep;
+  int32_t* d_res = nullptr;
   int64_t no = 0;
-  if ((rc = unique_first(d_dkeys, d_dil, nd, d_res, no, s))) return rc;
+  int rc = alloc_blocks_dev(d_cams, n_frames, d_depth, W, H, voxel_size, origin, dilate, depth_max,
+                            s, keep, d_res, no);
+  if (rc) return rc;
   *n_out = no;
+  if (no == 0) return SG_OK;
   if (no > cap) return fail(SG_EINVAL, "cap is smaller than the number of blocks (in *n_out)");
   if (!d_out) return fail(SG_EINVAL, "d_out is NULL");
   SG_HIP_CHECK(hipMemcpyAsync(d_out, d_res, sizeof(int32_t) * 3 * no, hipMemcpyDeviceToDevice, s));
   SG_HIP_CHECK(hipStreamSynchronize(s));
   return SG_OK;
 }
+
+int sg_grid_from_depth(const float* d_cams, int32_t n_frames, const float* d_depth, int32_t W,
+                       int32_t H, float voxel_size, const float origin[3], int32_t dilate,
+                       float depth_max, sg_stream stream, sg_grid** out,
+                       const sg_build_options* options) {
+  if (!out) return fail(SG_EINVAL, "out is NULL");
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  DevFree keep;
+  int32_t* d_res = nullptr;
+  int64_t no = 0;
+  int rc = alloc_blocks_dev(d_cams, n_frames, d_depth, W, H, voxel_size, origin, dilate, depth_max,
+                            s, keep, d_res, no);
+  if (rc) return rc;
+  if (no == 0) return fail(SG_EINVAL, "no pixel has a valid depth: nothing to allocate");
+  return sg_grid_build_ex(d_res, no, voxel_size, origin, stream, out, nullptr, options);
+}
+
 
 int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks) {
   int rc = check_grid(g);

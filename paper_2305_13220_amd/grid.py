@@ -40,21 +40,26 @@ class Grid:
     """Hash of allocated 8^3 blocks (collision-free, first-occurrence indices)."""
 
     def __init__(self, block_coords: torch.Tensor, voxel_size: float, origin=(0.0, 0.0, 0.0),
-                 return_index: bool = False, dense_map_max_cells: int = -1):
+                 return_index: bool = False, dense_map_max_cells: int = -1, _handle=None):
         """dense_map_max_cells: 0 = hash only; < 0 = library default."""
-        want(block_coords, "block_coords", torch.int32, (None, 3))
-        self.device = block_coords.device
-        n = block_coords.shape[0]
-        org = (ctypes.c_float * 3)(*[float(x) for x in origin])
-        handle = ctypes.c_void_p()
-        idx = torch.empty(n, dtype=torch.int32, device=self.device) if return_index else None
-        opts = _lib.BuildOptionsC(int(dense_map_max_cells))
-        with torch.cuda.device(self.device):
-            check(lib().sg_grid_build_ex(ptr(block_coords), n, ctypes.c_float(voxel_size), org,
-                                         stream_ptr(self.device), ctypes.byref(handle), ptr(idx),
-                                         ctypes.byref(opts)), "sg_grid_build_ex")
-        self._h = handle
-        self.index_of_input = idx
+        if _handle is not None:  # a grid the library already built (see from_depth)
+            self.device = block_coords
+            self._h = _handle
+            self.index_of_input = None
+        else:
+            want(block_coords, "block_coords", torch.int32, (None, 3))
+            self.device = block_coords.device
+            n = block_coords.shape[0]
+            org = (ctypes.c_float * 3)(*[float(x) for x in origin])
+            handle = ctypes.c_void_p()
+            idx = torch.empty(n, dtype=torch.int32, device=self.device) if return_index else None
+            opts = _lib.BuildOptionsC(int(dense_map_max_cells))
+            with torch.cuda.device(self.device):
+                check(lib().sg_grid_build_ex(ptr(block_coords), n, ctypes.c_float(voxel_size), org,
+                                             stream_ptr(self.device), ctypes.byref(handle), ptr(idx),
+                                             ctypes.byref(opts)), "sg_grid_build_ex")
+            self._h = handle
+            self.index_of_input = idx
         nb = ctypes.c_int64()
         check(lib().sg_grid_num_blocks(self._h, ctypes.byref(nb)), "sg_grid_num_blocks")
         self.n_blocks = nb.value
@@ -63,6 +68,26 @@ class Grid:
         check(lib().sg_grid_geometry(self._h, ctypes.byref(vs), o), "sg_grid_geometry")
         self.voxel_size = vs.value
         self.origin = tuple(o)
+
+    @classmethod
+    def from_depth(cls, cams: torch.Tensor, depth: torch.Tensor, voxel_size: float,
+                   origin=(0.0, 0.0, 0.0), dilate: int = 1, depth_max: float = float("inf"),
+                   dense_map_max_cells: int = -1):
+        """The grid of the blocks allocated for depth maps [F,H,W] seen by
+        cams [F,16] (Sec. 3.4.1), built in one library call."""
+        want(cams, "cams", torch.float32, (None, 16))
+        want(depth, "depth", torch.float32, (cams.shape[0], None, None), cams.device)
+        F, H, W = depth.shape
+        org = (ctypes.c_float * 3)(*[float(x) for x in origin])
+        handle = ctypes.c_void_p()
+        opts = _lib.BuildOptionsC(int(dense_map_max_cells))
+        with torch.cuda.device(cams.device):
+            check(lib().sg_grid_from_depth(ptr(cams), F, ptr(depth), W, H,
+                                           ctypes.c_float(voxel_size), org, dilate,
+                                           ctypes.c_float(depth_max), stream_ptr(cams.device),
+                                           ctypes.byref(handle), ctypes.byref(opts)),
+                  "sg_grid_from_depth")
+        return cls(cams.device, voxel_size, origin, _handle=handle)
 
     @property
     def handle(self):

@@ -155,3 +155,17 @@ def test_denoise_wide_radius_direct_path():
         want, mag = oracle.denoise(w["block_coords"], vox, 3, radius=radius, sigma=sigma,
                                    with_mag=True)
         assert_close_mag(out, want, mag, 1e-5, f"denoise r={radius}")
+
+
+def test_grid_from_depth_is_alloc_then_build():
+    """One call: the grid's block coordinates are the allocation's, in the
+    same order (so the block indices are those sg_grid_build gives)."""
+    sg = _sg()
+    fr, depth = _frames(3, 160, 120)
+    cams, dep = to_dev(fr["cams"]), to_dev(depth)
+    g = sg.Grid.from_depth(cams, dep, float(fr["h"]), dilate=1, depth_max=20.0)
+    want = oracle.alloc_blocks(fr["cams"], depth, fr["h"], fr["origin"], dilate=1, depth_max=20.0)
+    np.testing.assert_array_equal(g.block_coords().cpu().numpy(), want)
+    assert g.dense_map()[0] is not None
+    with pytest.raises(sg.SgridError, match="valid depth"):
+        sg.Grid.from_depth(cams, torch.full_like(dep, float("nan")), float(fr["h"]))
