@@ -312,6 +312,18 @@ int sg_crf_meanfield(const sg_lattice* lat, const float* d_unary, int32_t n_labe
                      int32_t iters, float* d_Q, sg_stream stream);
 int sg_lattice_destroy(sg_lattice* lat);
 
+/*
+ * sg_grid_extend -- add blocks to a grid (new frames' allocations, Sec.
+ * 3.4.1): the grid is rebuilt from its own block coordinates followed by
+ * d_new_coords [n_new,3], so existing blocks keep their indices and new
+ * ones get the next indices in order of first occurrence (the caller grows
+ * its voxel arrays accordingly).  The handle stays valid.  Allocates device
+ * memory and synchronises the stream; the caller makes sure no launched work
+ * still uses the grid.  On error the grid is unchanged.
+ */
+int sg_grid_extend(sg_grid* g, const int32_t* d_new_coords, int64_t n_new, sg_stream stream,
+                   const sg_build_options* options);
+
 /* Free the grid's device memory (waits for nothing; the caller makes sure no
  * launched work still uses the grid).  NULL is accepted. */
 int sg_grid_destroy(sg_grid* g);

@@ -672,6 +672,39 @@ int sg_grid_from_depth(const float* d_cams, int32_t n_frames, const float* d_dep
 }
 
 
+int sg_grid_extend(sg_grid* grid, const int32_t* d_new_coords, int64_t n_new, sg_stream stream,
+                   const sg_build_options* options) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (n_new < 0) return fail(SG_EINVAL, "n_new must be >= 0");
+  if (n_new == 0) return SG_OK;
+  if (!d_new_coords) return fail(SG_EINVAL, "d_new_coords is NULL");
+  const int64_t n = grid->n_blocks + n_new;
+  if (n > (int64_t)INT_MAX) return fail(SG_EINVAL, "more than 2^31-1 blocks");
+  hipStream_t s = (hipStream_t)stream;
+  DevFree tmp;
+  int32_t* d_all;
+  SG_ALLOC(tmp, d_all, sizeof(int32_t) * 3 * n);
+  // existing blocks first, so they keep their indices; new ones follow in
+  // order of first occurrence
+  SG_HIP_CHECK(hipMemcpyAsync(d_all, grid->d_coords, sizeof(int32_t) * 3 * grid->n_blocks,
+                              hipMemcpyDeviceToDevice, s));
+  SG_HIP_CHECK(hipMemcpyAsync(d_all + 3 * grid->n_blocks, d_new_coords, sizeof(int32_t) * 3 * n_new,
+                              hipMemcpyDeviceToDevice, s));
+  sg_grid* fresh = nullptr;
+  const float org[3] = {grid->org[0], grid->org[1], grid->org[2]};
+  if ((rc = sg_grid_build_ex(d_all, n, grid->h, org, stream, &fresh, nullptr, options))) return rc;
+  // the handle stays valid: its contents move to the new structure
+  (void)hipFree(grid->d_slots);
+  (void)hipFree(grid->d_nbr);
+  (void)hipFree(grid->d_coords);
+  if (grid->d_map) (void)hipFree(grid->d_map);
+  *grid = *fresh;
+  fresh->magic = 0;
+  delete fresh;
+  return SG_OK;
+}
+
 int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks) {
   int rc = check_grid(g);
   if (rc) return rc;

@@ -89,6 +89,21 @@ class Grid:
                   "sg_grid_from_depth")
         return cls(cams.device, voxel_size, origin, _handle=handle)
 
+    def extend(self, new_coords: torch.Tensor, dense_map_max_cells: int = -1):
+        """Add blocks: existing blocks keep their indices, new ones follow in
+        order of first occurrence.  Returns the new number of blocks."""
+        want(new_coords, "new_coords", torch.int32, (None, 3), self.device)
+        opts = _lib.BuildOptionsC(int(dense_map_max_cells))
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize(self.device)
+            check(lib().sg_grid_extend(self.handle, ptr(new_coords), new_coords.shape[0],
+                                       stream_ptr(self.device), ctypes.byref(opts)),
+                  "sg_grid_extend")
+        nb = ctypes.c_int64()
+        check(lib().sg_grid_num_blocks(self._h, ctypes.byref(nb)), "sg_grid_num_blocks")
+        self.n_blocks = nb.value
+        return self.n_blocks
+
     @property
     def handle(self):
         if self._h is None or not self._h.value:

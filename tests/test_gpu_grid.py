@@ -100,3 +100,27 @@ def test_hash_only_grid_has_no_map():
     m, _ = g.dense_map()
     assert m is None
     g.destroy()
+
+
+def test_extend_keeps_indices_and_appends_new_blocks():
+    """Extending a grid equals building it from the concatenated input: the
+    old blocks keep their indices, new ones follow in first-occurrence
+    order; neighbours, the dense map and lookups follow."""
+    rng = np.random.default_rng(31)
+    a = rng.integers(-6, 6, size=(3000, 3)).astype(np.int32)
+    b = rng.integers(-9, 9, size=(4000, 3)).astype(np.int32)
+    g = _build(a)
+    n_old = g.n_blocks
+    old = g.block_coords().cpu().numpy()
+    n = g.extend(to_dev(b))
+    blocks_or, _ = oracle.build_grid(np.concatenate([a, b]))
+    assert n == blocks_or.shape[0] > n_old
+    got = g.block_coords().cpu().numpy()
+    np.testing.assert_array_equal(got, blocks_or)
+    np.testing.assert_array_equal(got[:n_old], old)
+    np.testing.assert_array_equal(g.neighbors().cpu().numpy(), oracle.neighbors(blocks_or))
+    q = rng.integers(-11, 11, size=(5000, 3)).astype(np.int32)
+    np.testing.assert_array_equal(g.lookup(to_dev(q)).cpu().numpy(), oracle.lookup(blocks_or, q))
+    assert g.dense_map()[0] is not None
+    assert g.extend(to_dev(np.zeros((0, 3), np.int32))) == n
+    g.destroy()
