@@ -105,7 +105,8 @@ class PackedServer:
 
     def __init__(self, grids, C=3, hbm_budget_bytes=8 << 30, tick_rays=1 << 20, max_slots=256,
                  use_graph=True, keep_outputs=True, order="srpt", aging_px_per_s=2e8,
-                 one_grid_per_tick=False, launch="multi_grid", small_tick_rays=None, n_tables=2):
+                 one_grid_per_tick=False, launch="multi_grid", small_tick_rays=None, n_tables=2,
+                 max_inflight=None):
         """grids: list of (Grid, vox tensor, RenderParams or dict).  With
         keep_outputs False a request's outputs are released when it completes.
 
@@ -122,7 +123,11 @@ class PackedServer:
         tick.
 
         n_tables slot tables are used in turn: up to n_tables ticks can be
-        queued on the GPU while the host fills the next table.
+        queued on the GPU while the host fills the next table.  max_inflight
+        (default n_tables) bounds the ticks queued on the GPU: with 1 the
+        next tick is packed only when the previous one has finished, so a
+        request arriving meanwhile joins it (lower latency, at the cost of
+        the GPU idling while the host packs).
 
         launch "per_grid" (implies one grid per tick) renders a tick with
         sg_render_forward_slots on that grid (one captured graph per grid and
@@ -173,6 +178,7 @@ class PackedServer:
         self.graphs = {}  # (table, grid or -1, rays) -> captured graph
         self.use_graph = use_graph
         self.busy = [None] * nt  # end event of the tick that last used each table
+        self.max_inflight = nt if max_inflight is None else max(1, int(max_inflight))
         self.next_b = 0
         self.keep_outputs = keep_outputs
 
@@ -268,9 +274,9 @@ class PackedServer:
                 else:
                     keep.append((ev, finished, freed))
             inflight = keep
-            if not admitted:
+            if not admitted or len(inflight) >= self.max_inflight:
                 if inflight:
-                    time.sleep(0.0002)
+                    time.sleep(0.0002 if not admitted else 0.00005)
                 elif i < len(pending):
                     wait = pending[i].arrival - clock.now()
                     if wait > 0:
