@@ -275,6 +275,15 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  * sure no launched work still uses it); NULL is accepted.
  */
 typedef struct sg_lattice sg_lattice;
+int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
+                     sg_stream stream, sg_lattice** out);
+int sg_lattice_num_vertices(const sg_lattice* lat, int64_t* n_vertices);
+int sg_lattice_filter(const sg_lattice* lat, const float* d_val, int32_t n_values, float* d_out,
+                      sg_stream stream);
+int sg_crf_meanfield(const sg_lattice* lat, const float* d_unary, int32_t n_labels, float w_p,
+                     int32_t iters, float* d_Q, sg_stream stream);
+int sg_lattice_destroy(sg_lattice* lat);
+
 /*
  * sg_crf_label_loss -- the CRF's label loss (Eq. 22, the f-divergence taken
  * as Kullback-Leibler): per node i, x = softmax(logits_i) and Q_i its
@@ -303,14 +312,6 @@ int sg_crf_label_loss(const float* d_logits, int64_t ld_logits, const float* d_Q
 int sg_crf_property_loss(const float* d_x, int64_t ld_x, const float* d_filtered, int64_t n,
                          int32_t n_props, float weight, float* d_loss, float* d_g, int64_t ld_g,
                          sg_stream stream);
-int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
-                     sg_stream stream, sg_lattice** out);
-int sg_lattice_num_vertices(const sg_lattice* lat, int64_t* n_vertices);
-int sg_lattice_filter(const sg_lattice* lat, const float* d_val, int32_t n_values, float* d_out,
-                      sg_stream stream);
-int sg_crf_meanfield(const sg_lattice* lat, const float* d_unary, int32_t n_labels, float w_p,
-                     int32_t iters, float* d_Q, sg_stream stream);
-int sg_lattice_destroy(sg_lattice* lat);
 
 /*
  * sg_grid_extend -- add blocks to a grid (new frames' allocations, Sec.
