@@ -16,6 +16,7 @@ Every function cites the passage of the paper it follows:
   * ``render_backward``: its adjoint with respect to the voxel parameters.
   * ``query`` / ``query_backward``: SDF, gradient and features at points
     (Eq. 17-18), and the adjoint of that query with respect to the voxels.
+  * ``uniform_points``: uniform samples in the allocated blocks (SplitMix64).
   * ``eikonal`` / ``eikonal_rays``: the Eikonal regulariser of Eq. 16 at
     points or on the render's ray samples, and its derivative with respect
     to the SDF voxels.
@@ -497,3 +498,23 @@ def surface_points(block_coords, vox, C, h, origin, rays, params):
     _check(lib.or_surface_points(_p(bc), _I64(bc.shape[0]), _p(vx), _I32(C), _F(h), _p(org),
                                  _p(ry), _I64(R), *gp, _p(hit), _p(pts), _p(fm)), "surface_points")
     return hit.astype(bool), pts, fm
+
+
+def splitmix64(c):
+    """SplitMix64 output for counter c (a published counter-based generator)."""
+    lib = _load()
+    lib.or_splitmix64.restype = ctypes.c_uint64
+    lib.or_splitmix64.argtypes = [ctypes.c_uint64]
+    return int(lib.or_splitmix64(ctypes.c_uint64(c)))
+
+
+def uniform_points(block_coords, h, origin, n, seed):
+    """n points uniform over the allocated blocks (counter-based SplitMix64
+    draws), the Eikonal term's uniform in-grid samples (Sec. 3.5.2)."""
+    lib = _load()
+    bc = _c(block_coords, np.int32).reshape(-1, 3)
+    org = _c(origin, np.float32).reshape(3)
+    out = np.empty((n, 3), np.float32)
+    _check(lib.or_uniform_points(_p(bc), _I64(bc.shape[0]), _F(h), _p(org), _I64(n),
+                                 ctypes.c_uint64(seed), _p(out)), "uniform_points")
+    return out

@@ -1464,3 +1464,40 @@ int or_surface_points(const int32_t* block_coords, int64_t n_blocks, const doubl
   table_free(&tb);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Uniform samples in the sparse grid (the Eikonal term's "uniform samples  */
+/* in the sparse grids", Sec. 3.5.2).                                        */
+
+/* SplitMix64 (Steele, Lea and Flood, 2014) as a counter-based generator:
+ * output for counter c = the mix of c + 0x9e3779b97f4a7c15. */
+uint64_t or_splitmix64(uint64_t c) {
+  uint64_t z = c + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+/*
+ * n points uniform over the allocated blocks: point i draws x_k =
+ * splitmix64(seed + 4 i + k), k = 0..3; block = x_0 mod n_blocks, and
+ * u_a = (x_{1+a} >> 40) 2^-24 in [0,1) places it in the block: voxel
+ * coordinate v_a = 8 b_a + 8 u_a, world position origin_a + v_a h (float32,
+ * one rounding per operation in this order).  out [n,3].
+ */
+int or_uniform_points(const int32_t* block_coords, int64_t n_blocks, float h, const float org[3],
+                      int64_t n, uint64_t seed, float* out) {
+  if (n_blocks < 1 || n < 0 || !(h > 0)) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t base = seed + 4ull * (uint64_t)i;
+    const int64_t b = (int64_t)(or_splitmix64(base) % (uint64_t)n_blocks);
+    for (int a = 0; a < 3; ++a) {
+      const float u = (float)(or_splitmix64(base + 1 + a) >> 40) * 5.9604644775390625e-8f; /* 2^-24 */
+      const float v0 = (float)(8 * block_coords[3 * b + a]);
+      const float v = v0 + 8.0f * u;
+      const float d = v * h;
+      out[3 * i + a] = org[a] + d;
+    }
+  }
+  return 0;
+}

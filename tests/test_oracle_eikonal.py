@@ -132,3 +132,36 @@ def test_ray_samples_eikonal_gradient_matches_central_differences(oracle_lib):
         lm = oracle_lib.eikonal_rays(blocks, lo, 0, np.float32(h), origin, rays, params, 1.3)[0].sum()
         fd = (lp - lm) / (2 * eps)
         assert abs(fd - gv[b, v, 0]) <= 1e-6 * max(1.0, abs(fd)), (b, v, fd, gv[b, v, 0])
+
+
+def test_splitmix64_reference_outputs(oracle_lib):
+    """The generator's first two outputs from state 0 (the published sequence)."""
+    assert oracle_lib.splitmix64(0) == 0xE220A8397B1DCDAF
+    assert oracle_lib.splitmix64(0x9E3779B97F4A7C15) == 0x6E789E6AA1B965F4
+
+
+def test_uniform_points_cover_the_blocks(oracle_lib):
+    rng = np.random.default_rng(0)
+    blocks = np.unique(rng.integers(-5, 5, size=(40, 3)), axis=0).astype(np.int32)
+    h = np.float32(0.02)
+    origin = np.array([0.5, -0.25, 1.0], np.float32)
+    n = 200000
+    p = oracle_lib.uniform_points(blocks, h, origin, n, seed=12345)
+    # every point lies in one of the blocks (cell coordinates in [8b, 8b+8))
+    v = (p.astype(np.float64) - origin) / float(h)
+    b = np.floor(v / 8.0).astype(np.int64)
+    keys = {tuple(x) for x in blocks}
+    inside = np.array([tuple(x) in keys for x in b[:5000]])
+    assert inside.mean() > 0.999
+    # blocks and positions inside them are uniform (5-sigma bounds)
+    idx = {tuple(x): i for i, x in enumerate(blocks)}
+    counts = np.bincount([idx.get(tuple(x), 0) for x in b], minlength=len(blocks))
+    exp = n / len(blocks)
+    assert np.abs(counts - exp).max() < 5 * np.sqrt(exp)
+    frac = v / 8.0 - b
+    for a in range(3):
+        hist = np.histogram(frac[:, a], bins=10, range=(0, 1))[0]
+        assert np.abs(hist - n / 10).max() < 5 * np.sqrt(n / 10)
+    # reproducible, and the seed matters
+    np.testing.assert_array_equal(p[:100], oracle_lib.uniform_points(blocks, h, origin, 100, 12345))
+    assert not np.array_equal(p[:100], oracle_lib.uniform_points(blocks, h, origin, 100, 12346))
