@@ -393,6 +393,20 @@ int sg_query_backward(const sg_grid* g, int32_t C, const float* d_points, int64_
                       float* d_grad_vox, sg_stream stream);
 
 /*
+ * sg_uniform_points -- n points uniform over the grid's allocated blocks,
+ * the uniform in-grid samples of the Eikonal term (Sec. 3.5.2): point i
+ * draws x_k = splitmix64(seed + 4 i + k), k = 0..3 (SplitMix64 used as a
+ * counter-based generator), takes block x_0 mod n_blocks (in index order)
+ * and the offsets u_a = (x_{1+a} >> 40) 2^-24 in [0,1): world position
+ * origin_a + (8 b_a + 8 u_a) h, float32 in that order (bit-reproducible).
+ * d_points float [n,3].  Asynchronous; allocates nothing.  Points near the
+ * border of the allocated region can be invalid for sg_query / sg_eikonal
+ * (a corner block missing); those calls skip them.
+ */
+int sg_uniform_points(const sg_grid* g, int64_t n, uint64_t seed, float* d_points,
+                      sg_stream stream);
+
+/*
  * sg_eikonal -- the Eikonal regulariser (Eq. 16) at points, the uniform
  * in-grid samples of the training loss, with its derivative with respect to
  * the SDF voxels.  For each point p of d_points float [n,3], valid as in

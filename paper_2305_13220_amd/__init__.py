@@ -10,9 +10,9 @@ Python binding plus the training / serving loops around it.
 from ._lib import SgridError, lib  # noqa: F401
 from .grid import (  # noqa: F401
     Grid, Lattice, RenderParams, SdfRender, crf_label_loss, crf_property_loss, l2_loss_grad, optim_step, rays_pinhole, render,
-    alloc_blocks, denoise, eikonal, fuse, list_bytes, march, query, query_backward, render_backward, surface_points, render_footprint, render_forward, render_l2_step,
+    alloc_blocks, denoise, eikonal, fuse, list_bytes, march, query, query_backward, render_backward, surface_points, uniform_points, render_footprint, render_forward, render_l2_step,
 )
 
 __all__ = ["Grid", "Lattice", "RenderParams", "SdfRender", "SgridError", "l2_loss_grad", "optim_step",
            "rays_pinhole", "render", "render_backward", "render_footprint", "render_forward",
-           "render_l2_step", "list_bytes", "march", "query", "query_backward", "surface_points", "eikonal", "alloc_blocks", "fuse", "denoise", "crf_label_loss", "crf_property_loss", "lib"]
+           "render_l2_step", "list_bytes", "march", "query", "query_backward", "surface_points", "uniform_points", "eikonal", "alloc_blocks", "fuse", "denoise", "crf_label_loss", "crf_property_loss", "lib"]

@@ -53,6 +53,7 @@ _SIGNATURES = {
     "sg_query": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "sg_surface_points": ([_vp, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp], ctypes.c_int),
     "sg_query_backward": ([_vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "sg_uniform_points": ([_vp, _i64, ctypes.c_uint64, _vp, _vp], ctypes.c_int),
     "sg_eikonal": ([_vp, _vp, _i32, _vp, _i64, ctypes.c_float, _vp, _vp, _vp], ctypes.c_int),
     "sg_grid_extend": ([_vp, _vp, _i64, _vp, _vp], ctypes.c_int),
     "sg_grid_from_depth": ([_vp, _i32, _vp, _i32, _i32, ctypes.c_float, _vp, _i32, ctypes.c_float,

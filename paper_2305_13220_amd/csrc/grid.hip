@@ -456,6 +456,37 @@ static int unique_first(const uint64_t* d_keys, const int32_t* d_coords, int64_t
   return SG_OK;
 }
 
+// Uniform samples in the allocated blocks (the Eikonal term's uniform
+// in-grid samples): point i draws x_k = splitmix64(seed + 4 i + k) (the
+// counter-based form of Steele, Lea and Flood's SplitMix64), block
+// x_0 mod n, and offsets (x_{1+a} >> 40) 2^-24 inside it; float32 in the
+// order written, so the points are the same bits on any device.
+__device__ inline uint64_t splitmix64(uint64_t c) {
+  uint64_t z = c + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_uniform_points(const int32_t* __restrict__ coords, int64_t n_blocks, float h,
+                                 float ox, float oy, float oz, int64_t n, uint64_t seed,
+                                 float* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t base = seed + 4ull * (uint64_t)i;
+  const int64_t b = (int64_t)(splitmix64(base) % (uint64_t)n_blocks);
+  const float org[3] = {ox, oy, oz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float u = (float)(splitmix64(base + 1 + a) >> 40) * 5.9604644775390625e-8f;  // 2^-24
+    const float v0 = (float)(8 * coords[3 * b + a]);
+    const float v = v0 + 8.0f * u;
+    const float d = v * h;
+    out[3 * i + a] = org[a] + d;
+  }
+}
+
 // The allocated block coordinates for depth maps (shared by sg_alloc_blocks
 // and sg_grid_from_depth), in first-occurrence order, in device memory
 // owned by `keep`; synchronises the stream.
@@ -702,6 +733,21 @@ int sg_grid_extend(sg_grid* grid, const int32_t* d_new_coords, int64_t n_new, sg
   *grid = *fresh;
   fresh->magic = 0;
   delete fresh;
+  return SG_OK;
+}
+
+int sg_uniform_points(const sg_grid* grid, int64_t n, uint64_t seed, float* d_points,
+                      sg_stream stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (n < 0) return fail(SG_EINVAL, "n must be >= 0");
+  if (n == 0) return SG_OK;
+  if (!d_points) return fail(SG_EINVAL, "d_points is NULL");
+  if ((n + 255) / 256 > INT_MAX) return fail(SG_EINVAL, "too many points for one launch");
+  k_uniform_points<<<grid1d(n, 256), 256, 0, (hipStream_t)stream>>>(
+      grid->d_coords, grid->n_blocks, grid->h, grid->org[0], grid->org[1], grid->org[2], n, seed,
+      d_points);
+  SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }
 

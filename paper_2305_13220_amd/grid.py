@@ -364,6 +364,15 @@ def query_backward(grid: Grid, vox_shape, points: torch.Tensor, g_f=None, g_grad
     return grad_vox
 
 
+def uniform_points(grid: Grid, n: int, seed: int = 0):
+    """n points uniform over the allocated blocks [n,3] (Sec. 3.5.2's uniform
+    in-grid samples; counter-based SplitMix64 draws, reproducible)."""
+    out = torch.empty((n, 3), dtype=torch.float32, device=grid.device)
+    check(lib().sg_uniform_points(grid.handle, n, ctypes.c_uint64(seed & ((1 << 64) - 1)), ptr(out),
+                                  stream_ptr(grid.device)), "sg_uniform_points")
+    return out
+
+
 def eikonal(grid: Grid, vox: torch.Tensor, points: torch.Tensor, weight: float = 1.0,
             grad_vox=None, loss: bool = True):
     """Eikonal loss weight * (|grad f| - 1)^2 per point (Eq. 16) and its

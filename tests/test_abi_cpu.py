@@ -104,6 +104,7 @@ def test_render_validation(L):
     assert L.sg_alloc_blocks(fake, 1, fake, 4, 4, ctypes.c_float(0.0), org, 1, ctypes.c_float(1),
                              None, 0, ctypes.byref(n), None) == -1
     assert L.sg_grid_extend(None, fake, 3, None, None) == -1
+    assert L.sg_uniform_points(None, 10, 0, fake, None) == -1
     gh = ctypes.c_void_p()
     assert L.sg_grid_from_depth(fake, 1, fake, 4, 4, ctypes.c_float(0.02), org, 9, ctypes.c_float(1),
                                 None, ctypes.byref(gh), None) == -1 and not gh.value

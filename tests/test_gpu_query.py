@@ -222,3 +222,18 @@ def test_query_backward_matches_oracle(which):
     want0, mag0 = oracle.query_backward(w["block_coords"], C, w["h"], w["origin"], pts, g_f=gf)
     assert_close_mag(got0, want0, mag0, 1e-4, f"query backward {which}, g_f only")
     assert not got0[..., 1:].any()
+
+
+def test_uniform_points_bit_exact_and_eikonal_on_them():
+    """The uniform in-grid samples are the oracle's bit for bit (integer
+    draws, float32 placement in a fixed order), and the Eikonal term on them
+    matches the oracle."""
+    sg = _sg()
+    from synth import workloads
+    w = workloads.room_2cm()
+    g = make_grid(w)
+    for seed in (7, (1 << 63) + 5):
+        got = sg.uniform_points(g, 100000, seed).cpu().numpy()
+        want = oracle.uniform_points(w["block_coords"], w["h"], w["origin"], 100000, seed)
+        np.testing.assert_array_equal(got, want)
+    _eikonal_check(w, w["vox"], 3, want[:40000], 0.5, "uniform in-grid samples")
