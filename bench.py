@@ -265,10 +265,11 @@ def frames_bench(dev, n_frames=50):
     return res
 
 
-def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
+def fusion_bench(dev, n_frames=10, dilate=2, reps=5, n_sem=16):
     """Block allocation from depth maps, grid build and fusion of ten seeded
     640x480 depth + RGB + 16 semantic-logit frames of the 2 cm room (Sec.
-    3.4): the set-up of the grid that the render then refines."""
+    3.4): the set-up of the grid that the render then refines.  Dilation
+    radius R = 2 blocks and truncation mu = 8 h R, the supplement's values."""
     import numpy as np
     import torch
     import paper_2305_13220_amd as sg
@@ -278,14 +279,15 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
     cams, depth, feat = (torch.from_numpy(fr[k]).to(dev) for k in ("cams", "depth", "feat"))
     log(f"fusion setup {time.perf_counter() - t0:.1f}s")
     h = float(fr["h"])
-    blocks = sg.alloc_blocks(cams, depth, h, dilate=1)
+    trunc = 8 * h * dilate
+    blocks = sg.alloc_blocks(cams, depth, h, dilate=dilate)
     grid = sg.Grid(blocks, h)
     vox, wt = sg.fuse(grid, cams, depth, feat, trunc, n_sem=n_sem)
     torch.cuda.synchronize()
     t_alloc, t_build, t_fuse = [], [], []
     for _ in range(reps):
         a = time.perf_counter()
-        blocks = sg.alloc_blocks(cams, depth, h, dilate=1)
+        blocks = sg.alloc_blocks(cams, depth, h, dilate=dilate)
         torch.cuda.synchronize()
         b = time.perf_counter()
         grid = sg.Grid(blocks, h)
@@ -302,7 +304,7 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
     t_fd = []
     for _ in range(reps):
         a = time.perf_counter()
-        sg.Grid.from_depth(cams, depth, h, dilate=1)
+        sg.Grid.from_depth(cams, depth, h, dilate=dilate)
         torch.cuda.synchronize()
         t_fd.append(time.perf_counter() - a)
     n_vox = grid.n_blocks * 512
@@ -320,6 +322,7 @@ def fusion_bench(dev, n_frames=10, trunc=0.06, reps=5, n_sem=16):
     dn_ms = e[0].elapsed_time(e[1]) / reps
     dn_bytes = 2 * vox.numel() * 4  # each voxel read once and written once
     res = {"workload": "room_2cm_fusion_10x640x480", "frames": n_frames, "blocks": grid.n_blocks,
+           "dilate": dilate, "trunc_m": round(trunc, 4),
            "denoise_ms": round(dn_ms, 4),
            "denoise_hbm_frac": round(dn_bytes / (dn_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "alloc_ms": round(float(np.median(t_alloc)) * 1e3, 3),

@@ -212,10 +212,12 @@ int sg_grid_from_depth(const float* d_cams, int32_t n_frames, const float* d_dep
  * (world position origin + i h) of the grid is projected into every frame
  * (camera point c = R^T (X - t); pixel (floor(fx c_x / c_z + cx),
  * floor(fy c_y / c_z + cy))) and associated when c_z > 0, the pixel lies in
- * the image, its depth D is finite and > 0 and |D - c_z| < trunc.  The
+ * the image, its depth D is finite and > 0 and D - c_z >= -trunc (more
+ * than trunc behind the surface is occluded; the truncation psi(x, mu) =
+ * min(x, mu) of the supplement's Volumetric Fusion, mu = trunc).  The
  * per-voxel least-squares solutions are the averages over its associations:
- *   d_vox [n_blocks,512,1+C] (output): SDF = mean of D - c_z, features =
- *     mean of d_feat at the pixel; the last n_sem feature channels
+ *   d_vox [n_blocks,512,1+C] (output): SDF = mean of min(D - c_z, trunc),
+ *     features = mean of d_feat at the pixel; the last n_sem feature channels
  *     (semantic logits) are then divided by their L2 norm.  Voxels with no
  *     association: SDF = trunc, features 0.
  *   d_weight [n_blocks,512] float (nullable): number of associations.

@@ -359,7 +359,7 @@ def optim_step(kind, p, g, m, v, lr, b1, b2, eps, t):
     return p, m, v
 
 
-def alloc_blocks(cams, depth, h, origin, dilate=1, depth_max=np.inf):
+def alloc_blocks(cams, depth, h, origin, dilate=2, depth_max=np.inf):
     """Blocks allocated from depth maps (Sec. 3.4.1): the dilated blocks of
     every unprojected pixel, in order of first occurrence.  cams [F,16],
     depth [F,H,W].  Returns int32 [n,3]."""

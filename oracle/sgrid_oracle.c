@@ -955,10 +955,12 @@ int or_alloc_blocks(const float* cams, int32_t F, const float* depth, int32_t W,
  * is projected into every frame f: camera point c = R^T (X - t), pixel
  * (floor(fx c_x / c_z + cx), floor(fy c_y / c_z + cy)) (the pixel whose
  * centre ray the voxel is nearest to), and associated when c_z > 0, the
- * pixel lies in the image, its depth D is finite and > 0, and the
- * projective SDF D - c_z is within the truncation bound (|D - c_z| < trunc).
- * The least-squares solutions are averages over the associations:
- *   vox[v,0]   = mean of (D - c_z),   vox[v,1+ch] = mean of feat[f,pixel,ch],
+ * pixel lies in the image, its depth D is finite and > 0, and the voxel is
+ * not more than trunc behind the surface (D - c_z >= -trunc; the truncation
+ * of the supplement's Volumetric Fusion).  The least-squares solutions are
+ * averages over the associations of the truncated projective SDF:
+ *   vox[v,0]   = mean of min(D - c_z, trunc),
+ *   vox[v,1+ch] = mean of feat[f,pixel,ch],
  * and the last n_sem feature channels (semantic logits) are divided by
  * their L2 norm.  A voxel with no association gets SDF = trunc and zero
  * features.  weight[v] = number of associations.  The decisions (pixel,
@@ -1005,9 +1007,15 @@ int or_fuse(const int32_t* block_coords, int64_t n_blocks, float h, const float 
         const size_t pix = ((size_t)f * H + pv) * W + pu;
         const float D = depth[pix];
         if (!(isfinite(D) && D > 0.0f)) continue;
+        /* Truncation of the supplement's Volumetric Fusion: an association
+           more than trunc behind the surface is rejected (occluded); in
+           front of it the projective SDF is clipped to min(D - z, trunc). */
         const float s = D - z;
-        if (!(fabsf(s) < trunc)) continue;
-        sd += (double)D - (double)z;
+        if (!(s >= -trunc)) continue;
+        {
+          const double sdv = (double)D - (double)z;
+          sd += sdv < (double)trunc ? sdv : (double)trunc;
+        }
         for (int ch = 0; ch < C; ++ch) acc[ch] += feat[pix * C + ch];
         ++cnt;
       }

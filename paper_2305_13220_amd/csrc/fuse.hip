@@ -62,8 +62,8 @@ __global__ __launch_bounds__(256) void k_fuse(const int32_t* __restrict__ coords
     const float D = depth[pix];
     if (!(isfinite(D) && D > 0.0f)) continue;
     const float s = D - z;
-    if (!(fabsf(s) < trunc)) continue;
-    sd += s;
+    if (!(s >= -trunc)) continue;  // occluded: more than trunc behind the surface
+    sd += fminf(s, trunc);
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) acc[ch] += feat[pix * C + ch];
     ++cnt;

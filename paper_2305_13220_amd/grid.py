@@ -71,7 +71,7 @@ class Grid:
 
     @classmethod
     def from_depth(cls, cams: torch.Tensor, depth: torch.Tensor, voxel_size: float,
-                   origin=(0.0, 0.0, 0.0), dilate: int = 1, depth_max: float = float("inf"),
+                   origin=(0.0, 0.0, 0.0), dilate: int = 2, depth_max: float = float("inf"),
                    dense_map_max_cells: int = -1):
         """The grid of the blocks allocated for depth maps [F,H,W] seen by
         cams [F,16] (Sec. 3.4.1), built in one library call."""
@@ -391,7 +391,7 @@ def eikonal(grid: Grid, vox: torch.Tensor, points: torch.Tensor, weight: float =
 
 
 def alloc_blocks(cams: torch.Tensor, depth: torch.Tensor, voxel_size: float, origin=(0.0, 0.0, 0.0),
-                 dilate: int = 1, depth_max: float = float("inf")):
+                 dilate: int = 2, depth_max: float = float("inf")):
     """Block coordinates [n,3] int32 allocated for depth maps [F,H,W] seen by
     cams [F,16] (Sec. 3.4.1), in order of first occurrence."""
     want(cams, "cams", torch.float32, (None, 16))
@@ -417,7 +417,8 @@ def alloc_blocks(cams: torch.Tensor, depth: torch.Tensor, voxel_size: float, ori
 def fuse(grid: Grid, cams: torch.Tensor, depth: torch.Tensor, feat: torch.Tensor, trunc: float,
          n_sem: int = 0, vox=None, weight: bool = True):
     """Fused voxels [n,512,1+C] (and association counts [n,512]) of depth
-    [F,H,W] and features [F,H,W,C] seen by cams [F,16] (Sec. 3.4.2)."""
+    [F,H,W] and features [F,H,W,C] seen by cams [F,16] (Sec. 3.4.2).  The
+    supplement's defaults are dilate R = 2 at allocation and trunc = 8 h R."""
     want(cams, "cams", torch.float32, (None, 16), grid.device)
     F = cams.shape[0]
     want(depth, "depth", torch.float32, (F, None, None), grid.device)

@@ -57,13 +57,15 @@ def _check_fuse(g_vox, g_wt, o_vox, o_wt, trunc, what):
     assert err_f.max() <= 1e-5, f"{what}: feature error {err_f.max()}"
 
 
-@pytest.mark.parametrize("n_sem", [0, 16])
-def test_fuse_matches_oracle(n_sem):
+@pytest.mark.parametrize("n_sem,dilate,mu_blocks", [(0, 1, None), (16, 1, None), (16, 2, 2)])
+def test_fuse_matches_oracle(n_sem, dilate, mu_blocks):
+    """trunc 6 cm, or the supplement's mu = L R (L = 8 h) at R = 2."""
     sg = _sg()
     fr, depth = _frames(3, 160, 120, n_sem=n_sem)
-    blocks = oracle.alloc_blocks(fr["cams"], depth, fr["h"], fr["origin"], dilate=1, depth_max=20.0)
+    blocks = oracle.alloc_blocks(fr["cams"], depth, fr["h"], fr["origin"], dilate=dilate,
+                                 depth_max=20.0)
     g = sg.Grid(to_dev(blocks), float(fr["h"]), (0.0, 0.0, 0.0))
-    trunc = 0.06
+    trunc = 0.06 if mu_blocks is None else 8 * float(fr["h"]) * mu_blocks
     vox, wt = sg.fuse(g, to_dev(fr["cams"]), to_dev(depth), to_dev(fr["feat"]), trunc, n_sem=n_sem)
     o_vox, o_wt = oracle.fuse(blocks, fr["h"], fr["origin"], fr["cams"], depth, fr["feat"], trunc,
                               n_sem=n_sem)

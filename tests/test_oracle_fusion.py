@@ -6,10 +6,11 @@ permutation (exact in float32, and not symmetric, so using R for R^T fails):
 * a constant depth map lifts every pixel onto one plane, so the allocated
   blocks are a box of blocks (grown by the dilation radius), the first one
   the dilation of the first pixel's block;
-* fusing that depth map gives SDF = D - z (depth along the optical axis of
-  the voxel) wherever |D - z| < trunc, the constant colour, the normalised
-  semantic vector, and the truncation value with weight 0 elsewhere; two
-  frames average.
+* fusing that depth map gives SDF = min(D - z, trunc) (z the depth of the
+  voxel along the optical axis) wherever D - z >= -trunc (the truncation of
+  the supplement's Volumetric Fusion: clipped in front of the surface,
+  rejected behind it), the constant colour, the normalised semantic vector,
+  and the truncation value with weight 0 elsewhere; two frames average.
 """
 import numpy as np
 import pytest
@@ -105,12 +106,15 @@ def test_fuse_plane_closed_form(oracle_lib):
                               np.stack([cam, cam]), depth, feat, trunc, n_sem=2)
     X = _voxel_world(blocks)
     z = X[..., 0] - t[0]  # depth along the optical axis (+x)
-    a0 = np.abs(D0 - z) < trunc
-    a1 = np.abs(D1 - z) < trunc
+    mu = float(np.float32(trunc))
+    a0 = D0 - z >= -mu
+    a1 = D1 - z >= -mu
     n = a0.astype(int) + a1.astype(int)
     np.testing.assert_array_equal(wt, n)
     assert (n == 2).any() and (n == 1).any() and (n == 0).any()
-    sdf = np.where(n > 0, (a0 * (D0 - z) + a1 * (D1 - z)) / np.maximum(n, 1), np.float32(trunc))
+    assert (D0 - z > mu).any(), "no voxel far enough in front to be clipped"
+    s0, s1 = np.minimum(D0 - z, mu), np.minimum(D1 - z, mu)
+    sdf = np.where(n > 0, (a0 * s0 + a1 * s1) / np.maximum(n, 1), mu)
     np.testing.assert_allclose(vox[..., 0], sdf, rtol=0, atol=1e-12)
     rgb = (a0[..., None] * col[:3] + a1[..., None] * feat[1, 0, 0, :3]) / np.maximum(n, 1)[..., None]
     np.testing.assert_allclose(vox[..., 1:4], rgb, atol=1e-7)
