@@ -454,6 +454,21 @@ def crf_meanfield(pos, unary, w_p, iters):
     return Q
 
 
+def crf_meanfield_compat(pos, unary, compat, iters):
+    """Label marginals [N,L] after `iters` mean-field updates with the
+    label compatibility matrix compat [L,L] (Sec. 3.5.3)."""
+    lib = _load()
+    ps = _c(pos, np.float32)
+    N, d = ps.shape
+    u = _c(unary, np.float64).reshape(N, -1)
+    L = u.shape[1]
+    mu = _c(compat, np.float64).reshape(L, L)
+    Q = np.empty_like(u)
+    _check(lib.or_crf_meanfield_compat(_p(ps), _I64(N), _I32(d), _p(u), _I32(L), _p(mu),
+                                       _I32(iters), _p(Q)), "crf_meanfield_compat")
+    return Q
+
+
 def crf_label_loss(logits, Q, weight=1.0):
     """KL(softmax(logits) || Q) per node times weight, and its gradient with
     respect to the logits (Q fixed) (Sec. 3.5.3).  Returns (loss [N], g [N,L])."""

@@ -1317,6 +1317,56 @@ int or_crf_meanfield(const float* pos, int64_t N, int32_t d, const double* unary
 }
 
 /*
+ * Mean-field inference with a general label compatibility (Sec. 3.5.3: the
+ * pairwise potential is a compatibility mu(l, l') times the Gaussian
+ * kernel of the feature distance).  Q = softmax(-unary), then T times
+ *   Q_i(l) <- softmax_l( -unary_i(l) - sum_l' mu[l][l'] m_i(l') ),
+ *   m = lattice filter of Q (each point's own contribution included).
+ * compat [L,L] row-major: row l holds mu(l, .).  The Potts model is
+ * mu = w (1 - I).  unary, Q [N,L].
+ */
+int or_crf_meanfield_compat(const float* pos, int64_t N, int32_t d, const double* unary,
+                            int32_t L, const double* compat, int32_t T, double* Q) {
+  if (L < 1 || T < 0) return -1;
+  const size_t nl = (size_t)(N > 0 ? N : 1) * L;
+  double* m = (double*)malloc(nl * sizeof(double));
+  double* a = (double*)malloc((size_t)L * sizeof(double));
+  if (!m || !a) {
+    free(m);
+    free(a);
+    return -3;
+  }
+  for (int it = 0; it <= T; ++it) {
+    if (it > 0) {
+      int rc = or_lattice_filter(pos, N, d, Q, L, m, NULL);
+      if (rc) {
+        free(m);
+        free(a);
+        return rc;
+      }
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      double mx = -INFINITY, s = 0.0;
+      for (int l = 0; l < L; ++l) {
+        double e = -unary[i * L + l];
+        if (it > 0)
+          for (int k = 0; k < L; ++k) e -= compat[l * L + k] * m[i * L + k];
+        a[l] = e;
+        mx = fmax(mx, e);
+      }
+      for (int l = 0; l < L; ++l) {
+        a[l] = exp(a[l] - mx);
+        s += a[l];
+      }
+      for (int l = 0; l < L; ++l) Q[i * L + l] = a[l] / s;
+    }
+  }
+  free(m);
+  free(a);
+  return 0;
+}
+
+/*
  * Adjoint of the point query (Eq. 17-18) with respect to the voxels: for
  * upstream gradients g_f [m], g_grad [m,3], g_feat [m,C] (each nullable) of
  * a scalar loss, accumulates into grad_vox [n,512,1+C]

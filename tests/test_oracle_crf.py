@@ -12,6 +12,12 @@
 * Mean field: zero pairwise weight gives softmax(-unary); with a Potts
   weight, the update equals softmax(-unary + w F(Q)) computed here from the
   oracle's own filter (one step), and distributions stay normalised.
+* Mean field with a compatibility matrix mu: mu = 0 gives softmax(-unary);
+  the textbook Potts matrix w (1 - I) gives the Potts result above (the
+  per-point constant w sum_l F_l cancels in the softmax); an asymmetric mu
+  on one isolated point (its filter is a scalar multiple c of Q, c the
+  filter of ones) against the two-label closed form, which a transposed mu
+  fails.
 """
 import numpy as np
 import pytest
@@ -141,6 +147,31 @@ def test_meanfield_update(oracle_lib):
     np.testing.assert_allclose(Q1, sm(-U + 0.7 * F), rtol=1e-12)
     Q3 = oracle_lib.crf_meanfield(p, U, 0.7, 3)
     np.testing.assert_allclose(Q3.sum(1), 1.0, atol=1e-12)
+
+
+def test_meanfield_compatibility_matrix(oracle_lib):
+    rng = np.random.default_rng(4)
+    N, d, L = 150, 3, 5
+    p = rng.normal(scale=1.5, size=(N, d)).astype(np.float32)
+    U = rng.normal(size=(N, L))
+    sm = lambda a: np.exp(a - a.max(1, keepdims=True)) / np.exp(a - a.max(1, keepdims=True)).sum(1, keepdims=True)
+    np.testing.assert_allclose(oracle_lib.crf_meanfield_compat(p, U, np.zeros((L, L)), 2), sm(-U),
+                               rtol=1e-12)
+    w = 0.8
+    potts = w * (1.0 - np.eye(L))
+    for it in (1, 3):
+        np.testing.assert_allclose(oracle_lib.crf_meanfield_compat(p, U, potts, it),
+                                   oracle_lib.crf_meanfield(p, U, w, it), rtol=1e-10, atol=1e-13)
+    # one isolated point, two labels, mu(0, 1) = a the only non-zero entry
+    p1 = np.array([[0.3, -0.2, 0.1]], np.float32)
+    u1 = np.array([[0.2, 0.9]])
+    c = oracle_lib.lattice_filter(p1, np.ones((1, 1)))[0][0, 0]
+    a = 1.7
+    q = np.exp(-u1[0]) / np.exp(-u1[0]).sum()
+    want = np.exp([-u1[0, 0] - a * c * q[1], -u1[0, 1]])
+    want /= want.sum()
+    got = oracle_lib.crf_meanfield_compat(p1, u1, np.array([[0.0, a], [0.0, 0.0]]), 1)
+    np.testing.assert_allclose(got[0], want, rtol=1e-12)
 
 
 def test_label_loss_kl_and_gradient(oracle_lib):
