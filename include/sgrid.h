@@ -271,6 +271,13 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   Q = softmax(-unary) (a Potts compatibility of weight w_p; the message
  *   includes each point's own contribution).  d_unary [n, n_labels].
  *   Asynchronous; allocates nothing.
+ * sg_crf_meanfield_compat -- the same with a general label compatibility
+ *   (Sec. 3.5.3: the pairwise potential is a compatibility of the labels
+ *   times the Gaussian kernel): Q <- softmax(-unary - filter(Q) mu^T), that
+ *   is Q_i(l) <- softmax_l(-unary_i(l) - sum_k mu(l, k) filter(Q)_i(k)).
+ *   d_compat [n_labels, n_labels] device, row-major, row l = mu(l, .);
+ *   the Potts model of weight w is mu = w (1 - I), which gives the result
+ *   of sg_crf_meanfield with w_p = w.  Asynchronous; allocates nothing.
  * Filters and updates on one lattice share its value buffers: calls on the
  * same lattice must not overlap (issue them on one stream).
  * sg_lattice_destroy frees the lattice (waits for nothing: the caller makes
@@ -284,6 +291,8 @@ int sg_lattice_filter(const sg_lattice* lat, const float* d_val, int32_t n_value
                       sg_stream stream);
 int sg_crf_meanfield(const sg_lattice* lat, const float* d_unary, int32_t n_labels, float w_p,
                      int32_t iters, float* d_Q, sg_stream stream);
+int sg_crf_meanfield_compat(const sg_lattice* lat, const float* d_unary, int32_t n_labels,
+                            const float* d_compat, int32_t iters, float* d_Q, sg_stream stream);
 int sg_lattice_destroy(sg_lattice* lat);
 
 /*

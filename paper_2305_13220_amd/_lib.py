@@ -67,6 +67,7 @@ _SIGNATURES = {
     "sg_lattice_num_vertices": ([_vp, _vp], ctypes.c_int),
     "sg_lattice_filter": ([_vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "sg_crf_meanfield": ([_vp, _vp, _i32, ctypes.c_float, _i32, _vp, _vp], ctypes.c_int),
+    "sg_crf_meanfield_compat": ([_vp, _vp, _i32, _vp, _i32, _vp, _vp], ctypes.c_int),
     "sg_crf_label_loss": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_float, _vp, _vp, _i64, _vp],
                           ctypes.c_int),
     "sg_crf_property_loss": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_float, _vp, _vp, _i64, _vp],

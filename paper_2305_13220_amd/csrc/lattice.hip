@@ -262,6 +262,44 @@ __global__ void k_softmax(const float* __restrict__ unary, const float* __restri
     if (l < Lb) Q[i * Lb + l] = a[l] * inv;
 }
 
+// Mean-field update with a label compatibility matrix mu [Lb,Lb] (row l:
+// mu(l, .)): Q(l) = softmax_l(-unary(l) - sum_k mu(l,k) m(k)).  The matrix
+// indices are uniform across the wave, so mu is read through scalar loads;
+// the loops are unrolled to the label limit so that the message row stays in
+// registers.
+__global__ void k_softmax_compat(const float* __restrict__ unary, const float* __restrict__ m,
+                                 const float* __restrict__ mu, int64_t N, int Lb,
+                                 float* __restrict__ Q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float mm[kLatMaxV], a[kLatMaxV];
+#pragma unroll
+  for (int k = 0; k < kLatMaxV; ++k) mm[k] = k < Lb ? m[i * Lb + k] : 0.0f;
+  float mx = -INFINITY;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    float e = -INFINITY;
+    if (l < Lb) {
+      e = -unary[i * Lb + l];
+#pragma unroll
+      for (int k = 0; k < kLatMaxV; ++k)
+        if (k < Lb) e -= mu[l * Lb + k] * mm[k];
+    }
+    a[l] = e;
+    mx = fmaxf(mx, e);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    a[l] = l < Lb ? expf(a[l] - mx) : 0.0f;
+    s += a[l];
+  }
+  const float inv = 1.0f / s;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l)
+    if (l < Lb) Q[i * Lb + l] = a[l] * inv;
+}
+
 // Label loss of the CRF per node: x = softmax(logits), loss = weight *
 // KL(x || Q), gradient weight * x_k (a_k - KL) with a = log x - log Q
 // (Q a fixed target).  Row strides ld_s / ld_g (elements) let the logits
@@ -484,6 +522,25 @@ int sg_crf_meanfield(const sg_lattice* L, const float* d_unary, int32_t n_labels
   for (int it = 0; it < iters; ++it) {
     if ((rc = lat_filter(L, d_Q, n_labels, L->m, s))) return rc;
     k_softmax<<<grid_of(L->N, T), T, 0, s>>>(d_unary, L->m, w_p, L->N, n_labels, d_Q);
+  }
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+int sg_crf_meanfield_compat(const sg_lattice* L, const float* d_unary, int32_t n_labels,
+                            const float* d_compat, int32_t iters, float* d_Q, sg_stream stream) {
+  int rc = check_lat(L);
+  if (rc) return rc;
+  if (n_labels < 1 || n_labels > L->vmax)
+    return fail(SG_EINVAL, "n_labels must be in [1, max_values of the build]");
+  if (iters < 0) return fail(SG_EINVAL, "iters must be >= 0");
+  if (!d_unary || !d_Q || !d_compat) return fail(SG_EINVAL, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int T = 256;
+  k_softmax<<<grid_of(L->N, T), T, 0, s>>>(d_unary, nullptr, 0.0f, L->N, n_labels, d_Q);
+  for (int it = 0; it < iters; ++it) {
+    if ((rc = lat_filter(L, d_Q, n_labels, L->m, s))) return rc;
+    k_softmax_compat<<<grid_of(L->N, T), T, 0, s>>>(d_unary, L->m, d_compat, L->N, n_labels, d_Q);
   }
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;

@@ -523,12 +523,21 @@ class Lattice:
                                       stream_ptr(self.device)), "sg_lattice_filter")
         return out
 
-    def meanfield(self, unary: torch.Tensor, w_p: float, iters: int, out=None):
-        """Label marginals [n,L] after `iters` mean-field updates."""
+    def meanfield(self, unary: torch.Tensor, w_p: float, iters: int, out=None, compat=None):
+        """Label marginals [n,L] after `iters` mean-field updates: a Potts
+        compatibility of weight w_p, or, if compat [L,L] is given, the label
+        compatibility matrix compat (row l: mu(l, .); w_p is then unused)."""
         want(unary, "unary", torch.float32, (self.n, None), self.device)
+        L = unary.shape[1]
         if out is None:
             out = torch.empty_like(unary)
-        check(lib().sg_crf_meanfield(self._h, ptr(unary), unary.shape[1], ctypes.c_float(w_p),
+        if compat is not None:
+            want(compat, "compat", torch.float32, (L, L), self.device)
+            check(lib().sg_crf_meanfield_compat(self._h, ptr(unary), L, ptr(compat), iters,
+                                                ptr(out), stream_ptr(self.device)),
+                  "sg_crf_meanfield_compat")
+            return out
+        check(lib().sg_crf_meanfield(self._h, ptr(unary), L, ctypes.c_float(w_p),
                                      iters, ptr(out), stream_ptr(self.device)), "sg_crf_meanfield")
         return out
 

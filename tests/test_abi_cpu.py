@@ -89,6 +89,7 @@ def test_render_validation(L):
     assert L.sg_lattice_build(fake, 10, 3, 33, None, ctypes.byref(lat)) == -1
     assert L.sg_lattice_filter(None, fake, 1, fake, None) == -1
     assert L.sg_crf_meanfield(None, fake, 2, ctypes.c_float(1.0), 1, fake, None) == -1
+    assert L.sg_crf_meanfield_compat(None, fake, 2, fake, 1, fake, None) == -1
     assert L.sg_lattice_destroy(None) == 0
     assert L.sg_crf_label_loss(fake, 2, fake, 10, 4, ctypes.c_float(1.0), None, None, 4, None) == -1
     assert L.sg_crf_label_loss(fake, 4, fake, 10, 33, ctypes.c_float(1.0), None, None, 33, None) == -1

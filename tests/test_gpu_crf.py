@@ -75,6 +75,34 @@ def test_crf_meanfield_on_surface_samples():
     assert (q0.argmax(1) != want.argmax(1)).mean() > 0.01
 
 
+def test_crf_meanfield_compat_on_surface_samples():
+    """Mean field with a label compatibility matrix mu against the oracle.
+    The softmax arguments carry the message sum_k mu(l,k) F(k), so the bar
+    scales with the largest row sum of |mu|: 2e-6 of it, which is the 1e-5
+    bar of the Potts weight 5 above.  The textbook Potts matrix 5 (1 - I)
+    reproduces the oracle's Potts marginals, and an asymmetric matrix (a
+    label attracted to its own kind and pushed towards some others) its own."""
+    sg = _sg()
+    pos, unary = _surface_features()
+    L = unary.shape[1]
+    lat = sg.Lattice(to_dev(pos), max_values=16)
+    rng = np.random.default_rng(31)
+    potts = (5.0 * (1.0 - np.eye(L))).astype(np.float32)
+    asym = (-5.0 * np.eye(L) + 0.3 * rng.random((L, L))).astype(np.float32)
+    for mu, what in ((potts, "potts"), (asym, "asymmetric")):
+        tol = 2e-6 * np.abs(mu).sum(1).max()
+        for it in (1, 3):
+            Q = lat.meanfield(to_dev(unary), 0.0, it, compat=to_dev(mu)).cpu().numpy()
+            if what == "potts":
+                want = oracle.crf_meanfield(pos, unary, 5.0, it)
+            else:
+                want = oracle.crf_meanfield_compat(pos, unary, mu.astype(np.float64), it)
+            err = np.abs(Q - want).max()
+            assert err <= tol, f"{what}, iteration {it}: {err} > {tol}"
+    with pytest.raises(ValueError):
+        lat.meanfield(to_dev(unary), 0.0, 1, compat=to_dev(potts[:4, :4].copy()))
+
+
 def test_lattice_invalid_inputs():
     sg = _sg()
     pos = np.zeros((10, 3), np.float32)
