@@ -469,6 +469,36 @@ def crf_meanfield_compat(pos, unary, compat, iters):
     return Q
 
 
+def lattice_filter_adjoint(pos, values):
+    """Transpose of lattice_filter (the blur directions in reverse order)."""
+    lib = _load()
+    ps = _c(pos, np.float32)
+    N, d = ps.shape
+    v = _c(values, np.float64).reshape(N, -1)
+    out = np.empty_like(v)
+    _check(lib.or_lattice_filter_adjoint(_p(ps), _I64(N), _I32(d), _p(v), _I32(v.shape[1]),
+                                         _p(out)), "lattice_filter_adjoint")
+    return out
+
+
+def crf_meanfield_compat_backward(pos, unary, compat, iters, gQ):
+    """Gradients (g_unary [N,L], g_compat [L,L]) of a scalar with gradient
+    gQ [N,L] at the final marginals of crf_meanfield_compat."""
+    lib = _load()
+    ps = _c(pos, np.float32)
+    N, d = ps.shape
+    u = _c(unary, np.float64).reshape(N, -1)
+    L = u.shape[1]
+    mu = _c(compat, np.float64).reshape(L, L)
+    g = _c(gQ, np.float64).reshape(N, L)
+    gu = np.empty_like(u)
+    gm = np.empty((L, L), np.float64)
+    _check(lib.or_crf_meanfield_compat_backward(_p(ps), _I64(N), _I32(d), _p(u), _I32(L), _p(mu),
+                                                _I32(iters), _p(g), _p(gu), _p(gm)),
+           "crf_meanfield_compat_backward")
+    return gu, gm
+
+
 def crf_label_loss(logits, Q, weight=1.0):
     """KL(softmax(logits) || Q) per node times weight, and its gradient with
     respect to the logits (Q fixed) (Sec. 3.5.3).  Returns (loss [N], g [N,L])."""

@@ -1210,8 +1210,8 @@ static int64_t lat_find(lattice* L, const int32_t* k, int insert) {
  * filter response; n_vertices (nullable) the number of lattice points.
  * Returns -1 for bad sizes, -3 if out of memory.
  */
-int or_lattice_filter(const float* pos, int64_t N, int32_t d, const double* val, int32_t vd,
-                      double* out, int64_t* n_vertices) {
+static int lattice_filter_dirs(const float* pos, int64_t N, int32_t d, const double* val,
+                               int32_t vd, double* out, int64_t* n_vertices, int reverse) {
   if (d < 1 || d > LAT_MAX_D || vd < 1 || N < 0) return -1;
   lattice L;
   L.d = d;
@@ -1241,7 +1241,8 @@ int or_lattice_filter(const float* pos, int64_t N, int32_t d, const double* val,
     }
   }
   int32_t nk[LAT_MAX_D];
-  for (int j = 0; j <= d; ++j) { /* blur along direction j */
+  for (int jj = 0; jj <= d; ++jj) { /* blur along direction j */
+    const int j = reverse ? d - jj : jj;
     for (int64_t s = 0; s < L.cap; ++s) {
       if (!L.used[s]) continue;
       const int32_t* k = L.keys + s * d;
@@ -1268,6 +1269,23 @@ int or_lattice_filter(const float* pos, int64_t N, int32_t d, const double* val,
   if (n_vertices) *n_vertices = L.n;
   free(L.keys); free(L.used); free(L.val); free(tmp); free(vid); free(bw);
   return 0;
+}
+
+int or_lattice_filter(const float* pos, int64_t N, int32_t d, const double* val, int32_t vd,
+                      double* out, int64_t* n_vertices) {
+  return lattice_filter_dirs(pos, N, d, val, vd, out, n_vertices, 0);
+}
+
+/*
+ * Adjoint (transpose) of the lattice filter: the filter is slice . B_d ...
+ * B_0 . splat with slice the transpose of splat and every single-direction
+ * blur B_j symmetric (a neighbour pair exists from both ends), so its
+ * transpose is the same splat and slice around the blurs in the reverse
+ * direction order.
+ */
+int or_lattice_filter_adjoint(const float* pos, int64_t N, int32_t d, const double* val,
+                              int32_t vd, double* out) {
+  return lattice_filter_dirs(pos, N, d, val, vd, out, NULL, 1);
 }
 
 /* The simplex of each position (see lattice_simplex): keys [N][d+1][d],
@@ -1364,6 +1382,77 @@ int or_crf_meanfield_compat(const float* pos, int64_t N, int32_t d, const double
   free(m);
   free(a);
   return 0;
+}
+
+/*
+ * Gradient of or_crf_meanfield_compat: for upstream gQ = dE/dQ [N,L] of the
+ * final marginals of a scalar E, writes g_unary = dE/dunary [N,L] and
+ * g_compat = dE/dmu [L,L].  Reverse mode through the T updates, each
+ * Q = softmax(a), a = -unary - m mu^T, m = F(Q_prev):
+ *   ga = Q * (gQ - <Q, gQ>)          (softmax adjoint, per point)
+ *   g_unary -= ga;  g_compat(l,k) -= sum_i ga_i(l) m_i(k);
+ *   gm_i(k) = -sum_l ga_i(l) mu(l,k);  gQ_prev = F^T(gm),
+ * and finally g_unary -= ga of Q_0 = softmax(-unary).  The marginals of
+ * every update are recomputed and kept.
+ */
+int or_crf_meanfield_compat_backward(const float* pos, int64_t N, int32_t d, const double* unary,
+                                     int32_t L, const double* compat, int32_t T, const double* gQ,
+                                     double* g_unary, double* g_compat) {
+  if (L < 1 || T < 0 || N < 0) return -1;
+  const size_t nl = (size_t)(N > 0 ? N : 1) * L;
+  double* Qs = (double*)malloc(nl * (size_t)(T + 1) * sizeof(double));
+  double* m = (double*)malloc(nl * sizeof(double));
+  double* g = (double*)malloc(nl * sizeof(double));
+  double* gm = (double*)malloc(nl * sizeof(double));
+  double* ga = (double*)malloc((size_t)L * sizeof(double));
+  int rc = 0;
+  if (!Qs || !m || !g || !gm || !ga) {
+    rc = -3;
+    goto done;
+  }
+  for (int t = 0; t <= T; ++t) { /* forward, keeping every Q_t */
+    rc = or_crf_meanfield_compat(pos, N, d, unary, L, compat, t, Qs + (size_t)t * nl);
+    if (rc) goto done;
+  }
+  for (size_t e = 0; e < (size_t)N * L; ++e) {
+    g_unary[e] = 0.0;
+    g[e] = gQ[e];
+  }
+  for (int e = 0; e < L * L; ++e) g_compat[e] = 0.0;
+  for (int t = T; t >= 0; --t) {
+    const double* Q = Qs + (size_t)t * nl;
+    if (t > 0) {
+      rc = or_lattice_filter(pos, N, d, Qs + (size_t)(t - 1) * nl, L, m, NULL);
+      if (rc) goto done;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      double dot = 0.0;
+      for (int l = 0; l < L; ++l) dot += Q[i * L + l] * g[i * L + l];
+      for (int l = 0; l < L; ++l) {
+        ga[l] = Q[i * L + l] * (g[i * L + l] - dot);
+        g_unary[i * L + l] -= ga[l];
+      }
+      if (t == 0) continue;
+      for (int l = 0; l < L; ++l)
+        for (int k = 0; k < L; ++k) g_compat[l * L + k] -= ga[l] * m[i * L + k];
+      for (int k = 0; k < L; ++k) {
+        double acc = 0.0;
+        for (int l = 0; l < L; ++l) acc -= ga[l] * compat[l * L + k];
+        gm[i * L + k] = acc;
+      }
+    }
+    if (t > 0) {
+      rc = or_lattice_filter_adjoint(pos, N, d, gm, L, g);
+      if (rc) goto done;
+    }
+  }
+done:
+  free(Qs);
+  free(m);
+  free(g);
+  free(gm);
+  free(ga);
+  return rc;
 }
 
 /*

@@ -18,6 +18,10 @@
   on one isolated point (its filter is a scalar multiple c of Q, c the
   filter of ones) against the two-label closed form, which a transposed mu
   fails.
+* Filter adjoint: <F x, y> = <x, F^T y> for random x, y, d = 1, 3, 6.
+* Mean-field gradient (learning the compatibility matrix): the gradients
+  with respect to mu and to the unaries against central differences of
+  <gQ, Q_T> through the oracle's forward.
 """
 import numpy as np
 import pytest
@@ -172,6 +176,42 @@ def test_meanfield_compatibility_matrix(oracle_lib):
     want /= want.sum()
     got = oracle_lib.crf_meanfield_compat(p1, u1, np.array([[0.0, a], [0.0, 0.0]]), 1)
     np.testing.assert_allclose(got[0], want, rtol=1e-12)
+
+
+@pytest.mark.parametrize("d", [1, 3, 6])
+def test_filter_adjoint_identity(oracle_lib, d):
+    rng = np.random.default_rng(40 + d)
+    N, V = 300, 3
+    p = rng.normal(scale=1.2, size=(N, d)).astype(np.float32)
+    x = rng.normal(size=(N, V))
+    y = rng.normal(size=(N, V))
+    Fx, _ = oracle_lib.lattice_filter(p, x)
+    Fty = oracle_lib.lattice_filter_adjoint(p, y)
+    assert (Fx * y).sum() == pytest.approx((x * Fty).sum(), rel=1e-12)
+
+
+def test_meanfield_compat_gradient_central_differences(oracle_lib):
+    rng = np.random.default_rng(44)
+    N, d, L, T = 60, 2, 3, 2
+    p = rng.normal(scale=0.8, size=(N, d)).astype(np.float32)
+    U = rng.normal(size=(N, L))
+    mu = rng.normal(size=(L, L))
+    gQ = rng.normal(size=(N, L))
+    gu, gm = oracle_lib.crf_meanfield_compat_backward(p, U, mu, T, gQ)
+    E = lambda U_, mu_: (gQ * oracle_lib.crf_meanfield_compat(p, U_, mu_, T)).sum()
+    eps = 1e-6
+    for l, k in [(0, 0), (0, 2), (2, 1), (1, 0)]:
+        hi, lo = mu.copy(), mu.copy()
+        hi[l, k] += eps
+        lo[l, k] -= eps
+        fd = (E(U, hi) - E(U, lo)) / (2 * eps)
+        assert gm[l, k] == pytest.approx(fd, rel=1e-6, abs=1e-9), (l, k)
+    for i, l in [(0, 0), (7, 2), (31, 1), (59, 0)]:
+        hi, lo = U.copy(), U.copy()
+        hi[i, l] += eps
+        lo[i, l] -= eps
+        fd = (E(hi, mu) - E(lo, mu)) / (2 * eps)
+        assert gu[i, l] == pytest.approx(fd, rel=1e-6, abs=1e-9), (i, l)
 
 
 def test_label_loss_kl_and_gradient(oracle_lib):
