@@ -341,7 +341,9 @@ def fusion_bench(dev, n_frames=10, dilate=2, reps=5, n_sem=16):
 def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
     """Continuous-CRF message passing (Sec. 3.5.3) on 2^18 surface samples of
     the room: lattice build over 6-D features (xyz / 20 cm, rgb / 0.3), one
-    16-channel lattice filter, and 5 mean-field updates of 16 labels."""
+    16-channel lattice filter, 5 mean-field updates of 16 labels (Potts, and
+    a compatibility matrix), and the gradient of the latter with respect to
+    the unaries and the matrix."""
     import numpy as np
     import torch
     import paper_2305_13220_amd as sg
@@ -369,7 +371,7 @@ def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
         tb.append(time.perf_counter() - a)
     Q = lat.meanfield(unary, 5.0, 1)
     out = lat.filter(Q)
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
     for _ in range(reps):
         lat.filter(Q, out=out)
@@ -378,14 +380,35 @@ def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
         lat.meanfield(unary, 5.0, iters, out=Q)
     e[2].record()
     torch.cuda.synchronize()
+    # a compatibility matrix (Potts 5 (1 - I) plus seeded asymmetric terms):
+    # the forward, and the gradient with respect to the unaries and the matrix
+    mu = torch.from_numpy((5.0 * (1.0 - np.eye(n_sem)) + 0.3 * rng.random((n_sem, n_sem)))
+                          .astype(np.float32)).to(dev)
+    gQ = torch.from_numpy(rng.normal(size=(n, n_sem)).astype(np.float32)).to(dev)
+    lat.meanfield(unary, 0.0, iters, out=Q, compat=mu)
+    lat.meanfield_backward(unary, mu, iters, gQ)
+    torch.cuda.synchronize()
+    ec = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ec[0].record()
+    for _ in range(reps):
+        lat.meanfield(unary, 0.0, iters, out=Q, compat=mu)
+    ec[1].record()
+    for _ in range(reps):
+        lat.meanfield_backward(unary, mu, iters, gQ)
+    ec[2].record()
+    torch.cuda.synchronize()
     f_ms = e[0].elapsed_time(e[1]) / reps
     mf_ms = e[1].elapsed_time(e[2]) / reps
+    mfc_ms = ec[0].elapsed_time(ec[1]) / reps
+    mfb_ms = ec[1].elapsed_time(ec[2]) / reps  # includes the binding's workspace allocation
     res = {"workload": "room_surface_2^18_samples_d6_16labels", "points": n, "d": 6,
            "lattice_vertices": lat.n_vertices,
            "build_ms": round(float(np.median(tb)) * 1e3, 3), "filter_ms": round(f_ms, 4),
            "meanfield_ms": round(mf_ms, 4), "meanfield_iters": iters,
+           "meanfield_compat_ms": round(mfc_ms, 4),
+           "meanfield_compat_backward_ms": round(mfb_ms, 4),
            "points_per_s_per_update": n * iters / (mf_ms * 1e-3)}
-    del lat, pos, unary, Q, out
+    del lat, pos, unary, Q, out, mu, gQ
     torch.cuda.empty_cache()
     return res
 

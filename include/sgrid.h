@@ -278,6 +278,21 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   d_compat [n_labels, n_labels] device, row-major, row l = mu(l, .);
  *   the Potts model of weight w is mu = w (1 - I), which gives the result
  *   of sg_crf_meanfield with w_p = w.  Asynchronous; allocates nothing.
+ * sg_crf_meanfield_compat_backward -- gradients for learning the
+ *   compatibility (Sec. 3.5.3 calls it learnable): for d_gQ [n, n_labels],
+ *   the gradient of a scalar E at the marginals after `iters` updates of
+ *   sg_crf_meanfield_compat, writes d_g_unary [n, n_labels] = dE/dunary and
+ *   d_g_compat [n_labels, n_labels] = dE/dmu (both overwritten).  Reverse
+ *   mode through the updates, each Q = softmax(a), a = -unary - m mu^T,
+ *   m = filter(Q_prev): ga = Q (gQ - <Q, gQ>); g_unary -= ga;
+ *   g_mu(l, k) -= sum_i ga_i(l) m_i(k); gQ_prev = filter^T(-ga mu), the
+ *   transpose of the filter being the same filter with its blur directions
+ *   in reverse order.  Recomputes the forward and keeps every update's
+ *   marginals in d_ws (device, caller-owned, at least
+ *   sg_crf_meanfield_compat_backward_ws_bytes(n, n_labels, iters) bytes,
+ *   which returns 0 for invalid sizes).  g_mu sums per-workgroup partials
+ *   in a fixed order (deterministic); the filter's splat uses float
+ *   atomics.  Asynchronous; allocates nothing.
  * Filters and updates on one lattice share its value buffers: calls on the
  * same lattice must not overlap (issue them on one stream).
  * sg_lattice_destroy frees the lattice (waits for nothing: the caller makes
@@ -293,6 +308,12 @@ int sg_crf_meanfield(const sg_lattice* lat, const float* d_unary, int32_t n_labe
                      int32_t iters, float* d_Q, sg_stream stream);
 int sg_crf_meanfield_compat(const sg_lattice* lat, const float* d_unary, int32_t n_labels,
                             const float* d_compat, int32_t iters, float* d_Q, sg_stream stream);
+size_t sg_crf_meanfield_compat_backward_ws_bytes(int64_t n_points, int32_t n_labels,
+                                                int32_t iters);
+int sg_crf_meanfield_compat_backward(const sg_lattice* lat, const float* d_unary, int32_t n_labels,
+                                     const float* d_compat, int32_t iters, const float* d_gQ,
+                                     float* d_g_unary, float* d_g_compat, void* d_ws,
+                                     size_t ws_bytes, sg_stream stream);
 int sg_lattice_destroy(sg_lattice* lat);
 
 /*

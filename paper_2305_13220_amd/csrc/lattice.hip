@@ -300,6 +300,98 @@ __global__ void k_softmax_compat(const float* __restrict__ unary, const float* _
     if (l < Lb) Q[i * Lb + l] = a[l] * inv;
 }
 
+// Reverse step of the compatibility mean field, one lane per point, kMfT
+// points per workgroup.  With Q = softmax(a), a = -unary - m mu^T:
+//   ga = Q * (gQ - <Q, gQ>),  g_unary -= ga,
+//   gm(k) = -sum_l ga(l) mu(l,k)               (HAS_M),
+//   partial[block](l,k) = -sum_{points} ga(l) m(k)   (HAS_M),
+// the last an outer-product sum over the workgroup's points staged in LDS
+// (padded lanes contribute zeros), reduced later in a fixed order.
+constexpr int kMfT = 128;
+template <bool HAS_M>
+__global__ __launch_bounds__(kMfT) void k_mf_bwd(const float* __restrict__ Q,
+                                                 const float* __restrict__ gq,
+                                                 const float* __restrict__ m,
+                                                 const float* __restrict__ mu, int64_t N, int Lb,
+                                                 float* __restrict__ g_unary,
+                                                 float* __restrict__ gm,
+                                                 float* __restrict__ partial) {
+  __shared__ float s_ga[HAS_M ? kMfT * kLatMaxV : 1];
+  __shared__ float s_m[HAS_M ? kMfT * kLatMaxV : 1];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kMfT + tid;
+  const bool ok = i < N;
+  float q[kLatMaxV], ga[kLatMaxV];
+  float dot = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    const bool in = ok && l < Lb;
+    q[l] = in ? Q[i * Lb + l] : 0.0f;
+    ga[l] = in ? gq[i * Lb + l] : 0.0f;
+    dot += q[l] * ga[l];
+  }
+#pragma unroll
+  for (int l = 0; l < kLatMaxV; ++l) {
+    ga[l] = q[l] * (ga[l] - dot);
+    if (ok && l < Lb) g_unary[i * Lb + l] -= ga[l];
+  }
+  if constexpr (HAS_M) {
+#pragma unroll
+    for (int k = 0; k < kLatMaxV; ++k) {
+      if (k < Lb) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int l = 0; l < kLatMaxV; ++l)
+          if (l < Lb) acc -= ga[l] * mu[l * Lb + k];
+        if (ok) gm[i * Lb + k] = acc;
+        s_ga[tid * Lb + k] = ga[k];
+        s_m[tid * Lb + k] = ok ? m[i * Lb + k] : 0.0f;
+      }
+    }
+    __syncthreads();
+    const int LL = Lb * Lb;
+    for (int e = tid; e < LL; e += kMfT) {
+      const int l = e / Lb, k = e - l * Lb;
+      float acc = 0.0f;
+      for (int p = 0; p < kMfT; ++p) acc += s_ga[p * Lb + l] * s_m[p * Lb + k];
+      partial[(int64_t)blockIdx.x * LL + e] = -acc;
+    }
+  }
+}
+
+// g_compat[e] += sum over workgroups b (in order) of partial[b][e].
+__global__ void k_mf_reduce(const float* __restrict__ partial, int64_t nblk, int LL,
+                            float* __restrict__ g_compat) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= LL) return;
+  float acc = 0.0f;
+  for (int64_t b = 0; b < nblk; ++b) acc += partial[b * LL + e];
+  g_compat[e] += acc;
+}
+
+__global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+// Workspace of the mean-field backward: the marginals of every update,
+// the running gradient of the marginals and of the messages, and the
+// per-workgroup partial sums of the compatibility gradient.
+struct MfWs {
+  size_t qs, gq, gm, part, total;
+};
+static MfWs mf_ws(int64_t n, int Lb, int T) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t nl = (size_t)n * Lb * sizeof(float);
+  MfWs w;
+  w.qs = 0;
+  w.gq = al((size_t)(T + 1) * nl);
+  w.gm = w.gq + al(nl);
+  w.part = w.gm + al(nl);
+  w.total = w.part + al((size_t)((n + kMfT - 1) / kMfT) * Lb * Lb * sizeof(float));
+  return w;
+}
+
 // Label loss of the CRF per node: x = softmax(logits), loss = weight *
 // KL(x || Q), gradient weight * x_k (a_k - KL) with a = log x - log Q
 // (Q a fixed target).  Row strides ld_s / ld_g (elements) let the logits
@@ -391,7 +483,10 @@ static void free_lat(sg_lattice* L) {
   (void)hipFree(L->m);
   delete L;
 }
-static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_out, hipStream_t s) {
+// reverse: blur directions in the order d..0, which makes the filter its
+// own transpose (slice is the transpose of splat, each B_j is symmetric).
+static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_out, hipStream_t s,
+                      bool reverse = false) {
   const int T = 256;
   const int d = L->d;
   const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d};
@@ -401,7 +496,8 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
                                                               L->v0);
   float* a = L->v0;
   float* b = L->v1;
-  for (int j = 0; j <= d; ++j) {
+  for (int jj = 0; jj <= d; ++jj) {
+    const int j = reverse ? d - jj : jj;
     k_lat_blur<<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
     float* t = a;
     a = b;
@@ -542,6 +638,60 @@ int sg_crf_meanfield_compat(const sg_lattice* L, const float* d_unary, int32_t n
     if ((rc = lat_filter(L, d_Q, n_labels, L->m, s))) return rc;
     k_softmax_compat<<<grid_of(L->N, T), T, 0, s>>>(d_unary, L->m, d_compat, L->N, n_labels, d_Q);
   }
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+size_t sg_crf_meanfield_compat_backward_ws_bytes(int64_t n_points, int32_t n_labels,
+                                                int32_t iters) {
+  if (n_points < 1 || n_labels < 1 || n_labels > kLatMaxV || iters < 0) return 0;
+  return mf_ws(n_points, n_labels, iters).total;
+}
+
+int sg_crf_meanfield_compat_backward(const sg_lattice* L, const float* d_unary, int32_t n_labels,
+                                     const float* d_compat, int32_t iters, const float* d_gQ,
+                                     float* d_g_unary, float* d_g_compat, void* d_ws,
+                                     size_t ws_bytes, sg_stream stream) {
+  int rc = check_lat(L);
+  if (rc) return rc;
+  if (n_labels < 1 || n_labels > L->vmax)
+    return fail(SG_EINVAL, "n_labels must be in [1, max_values of the build]");
+  if (iters < 0) return fail(SG_EINVAL, "iters must be >= 0");
+  if (!d_unary || !d_compat || !d_gQ || !d_g_unary || !d_g_compat || !d_ws)
+    return fail(SG_EINVAL, "a required pointer is NULL");
+  const int64_t N = L->N;
+  const MfWs w = mf_ws(N, n_labels, iters);
+  if (ws_bytes < w.total) return fail(SG_EINVAL, "workspace smaller than the size query returns");
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)d_ws;
+  float* Qs = (float*)(base + w.qs);
+  float* gq = (float*)(base + w.gq);
+  float* gm = (float*)(base + w.gm);
+  float* part = (float*)(base + w.part);
+  const int64_t nl = N * n_labels;
+  const int T = 256;
+  // forward, keeping the marginals of every update
+  k_softmax<<<grid_of(N, T), T, 0, s>>>(d_unary, nullptr, 0.0f, N, n_labels, Qs);
+  for (int it = 1; it <= iters; ++it) {
+    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, L->m, s))) return rc;
+    k_softmax_compat<<<grid_of(N, T), T, 0, s>>>(d_unary, L->m, d_compat, N, n_labels,
+                                                 Qs + it * nl);
+  }
+  k_fill_zero<<<grid_of(nl, T), T, 0, s>>>(d_g_unary, nl);
+  const int LL = n_labels * n_labels;
+  k_fill_zero<<<grid_of(LL, T), T, 0, s>>>(d_g_compat, LL);
+  const int64_t nblk = (N + kMfT - 1) / kMfT;
+  const float* gin = d_gQ;
+  for (int it = iters; it >= 1; --it) {
+    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, L->m, s))) return rc;
+    k_mf_bwd<true><<<nblk, kMfT, 0, s>>>(Qs + it * nl, gin, L->m, d_compat, N, n_labels,
+                                         d_g_unary, gm, part);
+    k_mf_reduce<<<grid_of(LL, T), T, 0, s>>>(part, nblk, LL, d_g_compat);
+    if ((rc = lat_filter(L, gm, n_labels, gq, s, true))) return rc;
+    gin = gq;
+  }
+  k_mf_bwd<false><<<nblk, kMfT, 0, s>>>(Qs, gin, nullptr, d_compat, N, n_labels, d_g_unary,
+                                        nullptr, nullptr);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }

@@ -541,6 +541,26 @@ class Lattice:
                                      iters, ptr(out), stream_ptr(self.device)), "sg_crf_meanfield")
         return out
 
+    def meanfield_backward(self, unary: torch.Tensor, compat: torch.Tensor, iters: int,
+                           g_Q: torch.Tensor):
+        """Gradients (g_unary [n,L], g_compat [L,L]) of a scalar whose
+        gradient at meanfield(unary, compat=compat, iters)'s output is g_Q."""
+        want(unary, "unary", torch.float32, (self.n, None), self.device)
+        L = unary.shape[1]
+        want(compat, "compat", torch.float32, (L, L), self.device)
+        want(g_Q, "g_Q", torch.float32, (self.n, L), self.device)
+        nb = lib().sg_crf_meanfield_compat_backward_ws_bytes(self.n, L, iters)
+        if nb == 0:
+            raise ValueError("invalid sizes for the mean-field backward")
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        g_u = torch.empty_like(unary)
+        g_mu = torch.empty_like(compat)
+        check(lib().sg_crf_meanfield_compat_backward(self._h, ptr(unary), L, ptr(compat), iters,
+                                                     ptr(g_Q), ptr(g_u), ptr(g_mu), ptr(ws), nb,
+                                                     stream_ptr(self.device)),
+              "sg_crf_meanfield_compat_backward")
+        return g_u, g_mu
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
