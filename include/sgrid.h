@@ -288,7 +288,7 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   g_mu(l, k) -= sum_i ga_i(l) m_i(k); gQ_prev = filter^T(-ga mu), the
  *   transpose of the filter being the same filter with its blur directions
  *   in reverse order.  Recomputes the forward and keeps every update's
- *   marginals in d_ws (device, caller-owned, at least
+ *   marginals and messages in d_ws (device, caller-owned, at least
  *   sg_crf_meanfield_compat_backward_ws_bytes(n, n_labels, iters) bytes,
  *   which returns 0 for invalid sizes).  g_mu sums per-workgroup partials
  *   in a fixed order (deterministic); the filter's splat uses float

@@ -359,14 +359,25 @@ __global__ __launch_bounds__(kMfT) void k_mf_bwd(const float* __restrict__ Q,
   }
 }
 
-// g_compat[e] += sum over workgroups b (in order) of partial[b][e].
-__global__ void k_mf_reduce(const float* __restrict__ partial, int64_t nblk, int LL,
-                            float* __restrict__ g_compat) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= LL) return;
+// g_compat[e] += sum over workgroups b of partial[b][e]: one workgroup per
+// entry e, each lane summing a fixed stride of the partials, then a fixed
+// LDS tree, so the result does not depend on timing.
+constexpr int kMfRed = 256;
+__global__ __launch_bounds__(kMfRed) void k_mf_reduce(const float* __restrict__ partial,
+                                                      int64_t nblk, int LL,
+                                                      float* __restrict__ g_compat) {
+  __shared__ float red[kMfRed];
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x;
   float acc = 0.0f;
-  for (int64_t b = 0; b < nblk; ++b) acc += partial[b * LL + e];
-  g_compat[e] += acc;
+  for (int64_t b = tid; b < nblk; b += kMfRed) acc += partial[b * LL + e];
+  red[tid] = acc;
+  __syncthreads();
+  for (int w = kMfRed / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) g_compat[e] += red[0];
 }
 
 __global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
@@ -374,18 +385,19 @@ __global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0.0f;
 }
 
-// Workspace of the mean-field backward: the marginals of every update,
-// the running gradient of the marginals and of the messages, and the
-// per-workgroup partial sums of the compatibility gradient.
+// Workspace of the mean-field backward: the marginals and the messages of
+// every update, the running gradient of the marginals and of the messages,
+// and the per-workgroup partial sums of the compatibility gradient.
 struct MfWs {
-  size_t qs, gq, gm, part, total;
+  size_t qs, ms, gq, gm, part, total;
 };
 static MfWs mf_ws(int64_t n, int Lb, int T) {
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t nl = (size_t)n * Lb * sizeof(float);
   MfWs w;
   w.qs = 0;
-  w.gq = al((size_t)(T + 1) * nl);
+  w.ms = al((size_t)(T + 1) * nl);
+  w.gq = w.ms + al((size_t)T * nl);
   w.gm = w.gq + al(nl);
   w.part = w.gm + al(nl);
   w.total = w.part + al((size_t)((n + kMfT - 1) / kMfT) * Lb * Lb * sizeof(float));
@@ -665,17 +677,18 @@ int sg_crf_meanfield_compat_backward(const sg_lattice* L, const float* d_unary, 
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)d_ws;
   float* Qs = (float*)(base + w.qs);
+  float* ms = (float*)(base + w.ms);
   float* gq = (float*)(base + w.gq);
   float* gm = (float*)(base + w.gm);
   float* part = (float*)(base + w.part);
   const int64_t nl = N * n_labels;
   const int T = 256;
-  // forward, keeping the marginals of every update
+  // forward, keeping the marginals and the messages of every update
   k_softmax<<<grid_of(N, T), T, 0, s>>>(d_unary, nullptr, 0.0f, N, n_labels, Qs);
   for (int it = 1; it <= iters; ++it) {
-    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, L->m, s))) return rc;
-    k_softmax_compat<<<grid_of(N, T), T, 0, s>>>(d_unary, L->m, d_compat, N, n_labels,
-                                                 Qs + it * nl);
+    float* m = ms + (it - 1) * nl;
+    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, m, s))) return rc;
+    k_softmax_compat<<<grid_of(N, T), T, 0, s>>>(d_unary, m, d_compat, N, n_labels, Qs + it * nl);
   }
   k_fill_zero<<<grid_of(nl, T), T, 0, s>>>(d_g_unary, nl);
   const int LL = n_labels * n_labels;
@@ -683,10 +696,9 @@ int sg_crf_meanfield_compat_backward(const sg_lattice* L, const float* d_unary, 
   const int64_t nblk = (N + kMfT - 1) / kMfT;
   const float* gin = d_gQ;
   for (int it = iters; it >= 1; --it) {
-    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, L->m, s))) return rc;
-    k_mf_bwd<true><<<nblk, kMfT, 0, s>>>(Qs + it * nl, gin, L->m, d_compat, N, n_labels,
-                                         d_g_unary, gm, part);
-    k_mf_reduce<<<grid_of(LL, T), T, 0, s>>>(part, nblk, LL, d_g_compat);
+    k_mf_bwd<true><<<nblk, kMfT, 0, s>>>(Qs + it * nl, gin, ms + (it - 1) * nl, d_compat, N,
+                                         n_labels, d_g_unary, gm, part);
+    k_mf_reduce<<<LL, kMfRed, 0, s>>>(part, nblk, LL, d_g_compat);
     if ((rc = lat_filter(L, gm, n_labels, gq, s, true))) return rc;
     gin = gq;
   }

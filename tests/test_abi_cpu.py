@@ -95,9 +95,9 @@ def test_render_validation(L):
     assert L.sg_crf_meanfield_compat_backward_ws_bytes(0, 4, 1) == 0
     assert L.sg_crf_meanfield_compat_backward_ws_bytes(10, 33, 1) == 0
     assert L.sg_crf_meanfield_compat_backward_ws_bytes(10, 4, -1) == 0
-    # marginals of 3 updates (3 x 1600 B) + 2 gradient arrays of 1600 B, each region rounded up to
-    # 256 B, + one workgroup's 4x4 partial sums
-    assert L.sg_crf_meanfield_compat_backward_ws_bytes(100, 4, 2) == 4864 + 2 * 1792 + 256
+    # marginals of 3 updates (3 x 1600 B), messages of 2 (2 x 1600 B), 2 gradient arrays of
+    # 1600 B, each region rounded up to 256 B, + one workgroup's 4x4 partial sums
+    assert L.sg_crf_meanfield_compat_backward_ws_bytes(100, 4, 2) == 4864 + 3328 + 2 * 1792 + 256
     assert L.sg_lattice_destroy(None) == 0
     assert L.sg_crf_label_loss(fake, 2, fake, 10, 4, ctypes.c_float(1.0), None, None, 4, None) == -1
     assert L.sg_crf_label_loss(fake, 4, fake, 10, 33, ctypes.c_float(1.0), None, None, 33, None) == -1
