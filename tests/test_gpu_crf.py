@@ -127,6 +127,36 @@ def test_crf_meanfield_compat_backward_matches_oracle():
         assert e_u <= 1e-4, f"g_unary: {e_u}"
 
 
+@pytest.mark.parametrize("L,iters", [(16, 0), (1, 2), (5, 1)])
+def test_crf_meanfield_compat_edge_cases(L, iters):
+    """No update (the gradient of softmax(-unary) only, g_mu zero), a single
+    label (marginals 1, gradients zero) and a label count that is not a power
+    of two; 3,001 points (a ragged last workgroup)."""
+    sg = _sg()
+    rng = np.random.default_rng(50 + L)
+    n = 3001
+    pos = rng.normal(scale=1.5, size=(n, 3)).astype(np.float32)
+    unary = rng.normal(size=(n, L)).astype(np.float32)
+    mu = (-2.0 * np.eye(L) + 0.5 * rng.random((L, L))).astype(np.float32)
+    gQ = rng.normal(size=(n, L)).astype(np.float32)
+    lat = sg.Lattice(to_dev(pos), max_values=max(L, 1))
+    Q = lat.meanfield(to_dev(unary), 0.0, iters, compat=to_dev(mu)).cpu().numpy()
+    want_Q = oracle.crf_meanfield_compat(pos, unary, mu.astype(np.float64), iters)
+    assert np.abs(Q - want_Q).max() <= 2e-6 * max(1.0, np.abs(mu).sum(1).max())
+    g_u, g_mu = lat.meanfield_backward(to_dev(unary), to_dev(mu), iters, to_dev(gQ))
+    g_u, g_mu = g_u.cpu().numpy(), g_mu.cpu().numpy()
+    want_u, want_mu = oracle.crf_meanfield_compat_backward(pos, unary, mu.astype(np.float64),
+                                                            iters, gQ)
+    if L == 1:
+        assert not g_u.any() and not g_mu.any()
+        return
+    if iters == 0:
+        assert not g_mu.any()
+    else:
+        assert np.abs(g_mu - want_mu).max() <= 1e-3 * np.abs(want_mu).max()
+    assert np.abs(g_u - want_u).max() <= 1e-4 * np.abs(want_u).max()
+
+
 def test_lattice_invalid_inputs():
     sg = _sg()
     pos = np.zeros((10, 3), np.float32)
