@@ -290,7 +290,10 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   in reverse order.  Recomputes the forward and keeps every update's
  *   marginals and messages in d_ws (device, caller-owned, at least
  *   sg_crf_meanfield_compat_backward_ws_bytes(n, n_labels, iters) bytes,
- *   which returns 0 for invalid sizes).  g_mu sums per-workgroup partials
+ *   which returns 0 for invalid sizes).  d_g_unary, d_g_compat and d_ws
+ *   must not overlap d_gQ, d_unary or d_compat (the outputs are cleared
+ *   before the inputs are read; SG_EINVAL if d_g_unary or d_ws overlaps
+ *   d_gQ).  g_mu sums per-workgroup partials
  *   in a fixed order (deterministic); the filter's splat uses float
  *   atomics.  Asynchronous; allocates nothing.
  * Filters and updates on one lattice share its value buffers: calls on the

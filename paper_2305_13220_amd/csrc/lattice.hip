@@ -674,6 +674,15 @@ int sg_crf_meanfield_compat_backward(const sg_lattice* L, const float* d_unary, 
   const int64_t N = L->N;
   const MfWs w = mf_ws(N, n_labels, iters);
   if (ws_bytes < w.total) return fail(SG_EINVAL, "workspace smaller than the size query returns");
+  {
+    const size_t nlb = (size_t)N * n_labels * sizeof(float);
+    auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+      const char *pa = (const char*)a, *pb = (const char*)b;
+      return pa < pb + nb && pb < pa + na;
+    };
+    if (overlap(d_g_unary, nlb, d_gQ, nlb) || overlap(d_ws, w.total, d_gQ, nlb))
+      return fail(SG_EINVAL, "d_g_unary and d_ws must not overlap d_gQ");
+  }
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)d_ws;
   float* Qs = (float*)(base + w.qs);

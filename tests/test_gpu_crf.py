@@ -157,6 +157,27 @@ def test_crf_meanfield_compat_edge_cases(L, iters):
     assert np.abs(g_u - want_u).max() <= 1e-4 * np.abs(want_u).max()
 
 
+def test_crf_meanfield_compat_backward_rejects_overlap():
+    """The gradient of the unaries may not overwrite the upstream gradient it
+    still has to read: rejected on the host before any launch."""
+    sg = _sg()
+    from paper_2305_13220_amd import _lib
+    rng = np.random.default_rng(60)
+    n, L = 500, 4
+    lat = sg.Lattice(to_dev(rng.normal(size=(n, 3)).astype(np.float32)), max_values=L)
+    u = to_dev(rng.normal(size=(n, L)).astype(np.float32))
+    mu = to_dev(np.eye(L, dtype=np.float32))
+    gQ = to_dev(rng.normal(size=(n, L)).astype(np.float32))
+    nb = _lib.lib().sg_crf_meanfield_compat_backward_ws_bytes(n, L, 1)
+    ws = torch.empty(nb, dtype=torch.uint8, device=u.device)
+    g_mu = torch.empty((L, L), dtype=torch.float32, device=u.device)
+    rc = _lib.lib().sg_crf_meanfield_compat_backward(lat._h, _lib.ptr(u), L, _lib.ptr(mu), 1,
+                                                     _lib.ptr(gQ), _lib.ptr(gQ), _lib.ptr(g_mu),
+                                                     _lib.ptr(ws), nb, None)
+    assert rc == -1 and b"overlap" in _lib.lib().sg_last_error()
+    torch.cuda.synchronize()
+
+
 def test_lattice_invalid_inputs():
     sg = _sg()
     pos = np.zeros((10, 3), np.float32)
