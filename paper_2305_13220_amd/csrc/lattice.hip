@@ -154,15 +154,33 @@ __global__ void k_lat_simplex(const float* __restrict__ pos, int64_t N, LatView 
 }
 
 // List of the occupied slots (in no particular order) and their number.
-__global__ void k_lat_compact(const uint64_t* __restrict__ fp, int64_t cap,
-                              unsigned long long* __restrict__ n, int32_t* __restrict__ list) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One counter atomic per workgroup (the waves' counts are prefixed in LDS):
+// with one per wave the 4M-slot table of 2^18 points at d = 6 spent most of
+// the compaction serialised on the counter.
+constexpr int kLatCompactT = 1024;
+__global__ __launch_bounds__(kLatCompactT) void k_lat_compact(const uint64_t* __restrict__ fp,
+                                                              int64_t cap,
+                                                              unsigned long long* __restrict__ n,
+                                                              int32_t* __restrict__ list) {
+  __shared__ unsigned long long wbase[kLatCompactT / kWave];
+  __shared__ unsigned long long bbase;
+  const int64_t s = (int64_t)blockIdx.x * kLatCompactT + threadIdx.x;
+  const int w = threadIdx.x / kWave;
   const bool used = s < cap && fp[s] != kEmptyKey;
   const uint64_t b = __ballot(used);
-  unsigned long long base = 0;
-  if (lane_id() == 0 && b) base = atomicAdd(n, (unsigned long long)__popcll(b));
-  base = __shfl(base, 0);
-  if (used) list[base + rank_below(b)] = (int32_t)s;
+  if (lane_id() == 0) wbase[w] = (unsigned long long)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long acc = 0;
+    for (int k = 0; k < kLatCompactT / kWave; ++k) {
+      const unsigned long long c = wbase[k];
+      wbase[k] = acc;
+      acc += c;
+    }
+    bbase = acc ? atomicAdd(n, acc) : 0;
+  }
+  __syncthreads();
+  if (used) list[bbase + wbase[w] + rank_below(b)] = (int32_t)s;
 }
 
 // Zero the value rows of the occupied slots.
@@ -575,8 +593,8 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
   } else {
     k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 0, L->vid, L->bw, d_err);
     k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 1, L->vid, L->bw, d_err);
-    k_lat_compact<<<grid_of(L->cap, T), T, 0, s>>>(L->fp, L->cap, (unsigned long long*)d_n,
-                                                   L->list);
+    k_lat_compact<<<grid_of(L->cap, kLatCompactT), kLatCompactT, 0, s>>>(
+        L->fp, L->cap, (unsigned long long*)d_n, L->list);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&nv, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, s);
