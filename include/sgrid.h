@@ -293,9 +293,9 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   which returns 0 for invalid sizes).  d_g_unary, d_g_compat and d_ws
  *   must not overlap d_gQ, d_unary or d_compat (the outputs are cleared
  *   before the inputs are read; SG_EINVAL if d_g_unary or d_ws overlaps
- *   d_gQ).  g_mu sums per-workgroup partials
- *   in a fixed order (deterministic); the filter's splat uses float
- *   atomics.  Asynchronous; allocates nothing.
+ *   d_gQ).  g_mu sums per-workgroup partials in a fixed order; the
+ *   filter's splat uses float atomics, so the last bits may vary from call
+ *   to call.  Asynchronous; allocates nothing.
  * Filters and updates on one lattice share its value buffers: calls on the
  * same lattice must not overlap (issue them on one stream).
  * sg_lattice_destroy frees the lattice (waits for nothing: the caller makes
