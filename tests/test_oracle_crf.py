@@ -19,6 +19,14 @@
   filter of ones) against the two-label closed form, which a transposed mu
   fails.
 * Filter adjoint: <F x, y> = <x, F^T y> for random x, y, d = 1, 3, 6.
+* Width and isotropy of the Gaussian (Eq. 20's kernel with unit standard
+  deviation per scaled feature axis), d = 2, 3, 4, 6, derived from the
+  lattice's geometry and not from the lift's per-axis factors: on a dense
+  uniform point cloud the normalised moments F(s)/F(1) and F(s^2)/F(1) of
+  the coordinate s = u.x along the axes and random unit directions u give a
+  mean at the point and a variance of 1 in every direction; the response
+  to ones integrates to the density times the feature-space volume per
+  lattice vertex.
 * Mean-field gradient (learning the compatibility matrix): the gradients
   with respect to mu and to the unaries against central differences of
   <gQ, Q_T> through the oracle's forward.
@@ -281,3 +289,60 @@ def test_surface_points_on_a_plane_and_sphere(oracle_lib):
     hit, pts, _ = oracle_lib.surface_points(w["block_coords"], w["vox"], 3, w["h"], w["origin"], ray,
                                             w["params"])
     assert hit[0] and abs(np.linalg.norm(pts[0]) - 0.5) < 2e-3
+
+
+def _lattice_vertex_volume(d):
+    """Feature-space volume per vertex of the lattice, from its definition.
+
+    The lattice is {x in Z^(d+1): sum x = 0, all x_i congruent mod d+1}; it
+    has index (d+1)^(d-1) in A_d = {x in Z^(d+1): sum x = 0}, whose
+    covolume is sqrt(d+1).  Features enter the plane sum x = 0 through an
+    isometry times (d+1) sqrt(2/3), so a vertex owns
+    sqrt(d+1) (d+1)^(d-1) / ((d+1) sqrt(2/3))^d = (3/2)^(d/2) / sqrt(d+1)
+    of feature space."""
+    return np.sqrt(d + 1.0) * (d + 1.0) ** (d - 1) / ((d + 1.0) * np.sqrt(2.0 / 3.0)) ** d
+
+
+@pytest.mark.parametrize("d,N,A,margin", [(2, 50000, 8.0, 3.5), (3, 100000, 6.5, 3.5),
+                                          (4, 300000, 5.0, 3.0), (6, 400000, 4.0, 2.5)])
+def test_filter_is_an_isotropic_unit_gaussian(oracle_lib, d, N, A, margin):
+    """Width and isotropy of the filter's Gaussian (Eq. 20, Sec. 3.5.3).
+
+    Expected values, from the lattice alone: blurring with [1/4, 1/2, 1/4]
+    along the d+1 steps u_j = (1,...,1) - (d+1) e_j adds the covariance
+    (1/2) sum_j u_j u_j^T = ((d+1)^2 / 2) P (P the projector onto the
+    plane).  Splatting onto the barycentric vertices of a simplex, and
+    slicing from them, each add the vertex spread of the canonical simplex,
+    (1/(d+2)) sum_k c_k c_k^T with c_k its vertices about their centroid,
+    whose trace is (d+1)^2 d (d+2) / 12 and which averages over the
+    simplices (permutations of one another) to ((d+1)^2 / 12) P.  Together
+    (2/3)(d+1)^2 P: with features scaled by (d+1) sqrt(2/3) onto the plane
+    that is the identity, a unit Gaussian in feature units.  A wrong factor
+    on any axis makes the variance along that axis (or along random
+    directions) differ from 1; a wrong common scale moves every variance and
+    the mass.  The cloud is uniform, so the normalised moments at an interior
+    point are the kernel's own; the bar (2 %) covers the sampling noise and
+    the boundary and sparse-lattice effects (measured below 1 %)."""
+    rng = np.random.default_rng(60 + d)
+    p = rng.uniform(-A, A, size=(N, d)).astype(np.float32)
+    P = p.astype(np.float64)
+    dirs = [np.eye(d)[i] for i in range(d)]
+    for _ in range(2):
+        u = rng.normal(size=d)
+        dirs.append(u / np.linalg.norm(u))
+    vals = [np.ones(N)]
+    for u in dirs:
+        s = P @ u
+        vals += [s, s * s]
+    F, _ = oracle_lib.lattice_filter(p, np.stack(vals, 1))
+    inner = (np.abs(P) < A - margin).all(1)
+    assert inner.sum() > 1000
+    mass = F[inner, 0].mean() / (N / (2 * A) ** d * _lattice_vertex_volume(d))
+    assert abs(mass - 1.0) < 0.02, mass
+    for j, u in enumerate(dirs):
+        m1 = F[inner, 1 + 2 * j] / F[inner, 0]
+        m2 = F[inner, 2 + 2 * j] / F[inner, 0]
+        var = (m2 - m1 ** 2).mean()
+        bias = (m1 - P[inner] @ u).mean()
+        assert abs(var - 1.0) < 0.02, (j, var)
+        assert abs(bias) < 0.02, (j, bias)
