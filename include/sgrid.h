@@ -147,6 +147,11 @@ int sg_grid_copy_dense_map(const sg_grid* g, int32_t* d_out, sg_stream stream);
 /* Number of allocated (unique) blocks. */
 int sg_grid_num_blocks(const sg_grid* g, int64_t* n_blocks);
 
+/* Generation of the grid's index memory (host output): 0 when built, one
+ * more after every sg_grid_extend, which moves that memory.  A descriptor or
+ * captured launch made at an older generation refers to freed memory. */
+int sg_grid_generation(const sg_grid* g, uint64_t* generation);
+
 /* World geometry of the grid: voxel_size and origin[3] (host outputs). */
 int sg_grid_geometry(const sg_grid* g, float* voxel_size, float origin[3]);
 
@@ -353,7 +358,11 @@ int sg_crf_property_loss(const float* d_x, int64_t ld_x, const float* d_filtered
  * 3.4.1): the grid is rebuilt from its own block coordinates followed by
  * d_new_coords [n_new,3], so existing blocks keep their indices and new
  * ones get the next indices in order of first occurrence (the caller grows
- * its voxel arrays accordingly).  The handle stays valid.  Allocates device
+ * its voxel arrays accordingly).  The handle stays valid, but the grid's
+ * index memory moves: packed descriptors made from it before the call
+ * (sg_packed_grid_desc) and launches captured in a graph before it refer to
+ * freed memory and must not be used again (sg_packed_grid_check reports a
+ * stale descriptor; sg_grid_generation counts the moves).  Allocates device
  * memory and synchronises the stream; the caller makes sure no launched work
  * still uses the grid.  On error the grid is unchanged.
  */
@@ -574,6 +583,12 @@ typedef struct sg_packed_grid {
 
 int sg_packed_grid_desc(const sg_grid* g, const float* d_vox, int32_t C,
                         const sg_render_params* params, sg_packed_grid* out);
+
+/* SG_OK if desc (host copy) was made by sg_packed_grid_desc from grid g at
+ * its current generation; SG_ESTATE if it was made from another grid or
+ * before an sg_grid_extend of g moved the grid's memory (the descriptor then
+ * refers to freed memory); SG_EINVAL for a NULL pointer. */
+int sg_packed_grid_check(const sg_grid* g, const sg_packed_grid* desc);
 
 /*
  * One slot: pixels [pixel_begin, pixel_begin + count) (row-major linear

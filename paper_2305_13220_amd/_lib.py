@@ -45,6 +45,8 @@ _SIGNATURES = {
     "sg_grid_copy_dense_map": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_num_blocks": ([_vp, _vp], ctypes.c_int),
     "sg_grid_geometry": ([_vp, _vp, _vp], ctypes.c_int),
+    "sg_grid_generation": ([_vp, _vp], ctypes.c_int),
+    "sg_packed_grid_check": ([_vp, _vp], ctypes.c_int),
     "sg_grid_block_coords": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_neighbors": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_lookup": ([_vp, _vp, _i64, _vp, _vp], ctypes.c_int),

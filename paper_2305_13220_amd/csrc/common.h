@@ -223,6 +223,7 @@ struct sg_grid {
   float org[3];
   int32_t* d_map;          // dense block map over the bounding box, or nullptr
   int32_t mdim[3];
+  uint64_t generation;     // 0 when built, +1 per sg_grid_extend (its memory moves)
 };
 
 namespace sg {

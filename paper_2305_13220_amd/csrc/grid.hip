@@ -725,12 +725,15 @@ int sg_grid_extend(sg_grid* grid, const int32_t* d_new_coords, int64_t n_new, sg
   sg_grid* fresh = nullptr;
   const float org[3] = {grid->org[0], grid->org[1], grid->org[2]};
   if ((rc = sg_grid_build_ex(d_all, n, grid->h, org, stream, &fresh, nullptr, options))) return rc;
-  // the handle stays valid: its contents move to the new structure
+  // the handle stays valid: its contents move to the new structure, and the
+  // generation tells descriptors made before the move from current ones
   (void)hipFree(grid->d_slots);
   (void)hipFree(grid->d_nbr);
   (void)hipFree(grid->d_coords);
   if (grid->d_map) (void)hipFree(grid->d_map);
+  const uint64_t gen = grid->generation + 1;
   *grid = *fresh;
+  grid->generation = gen;
   fresh->magic = 0;
   delete fresh;
   return SG_OK;
@@ -778,6 +781,14 @@ int sg_grid_copy_dense_map(const sg_grid* g, int32_t* d_out, sg_stream stream) {
   SG_HIP_CHECK(hipMemcpyAsync(d_out, g->d_map,
                               sizeof(int32_t) * (size_t)g->mdim[0] * g->mdim[1] * g->mdim[2],
                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SG_OK;
+}
+
+int sg_grid_generation(const sg_grid* g, uint64_t* generation) {
+  int rc = check_grid(g);
+  if (rc) return rc;
+  if (!generation) return fail(SG_EINVAL, "generation is NULL");
+  *generation = g->generation;
   return SG_OK;
 }
 

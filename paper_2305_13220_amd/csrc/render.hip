@@ -719,6 +719,8 @@ struct PackedGrid {
   const float* vox;
   Params params;
   int32_t C;
+  const sg_grid* owner;  // host-side checks only (sg_packed_grid_check)
+  uint64_t generation;
 };
 static_assert(sizeof(PackedGrid) <= sizeof(sg_packed_grid), "descriptor does not fit");
 
@@ -742,6 +744,8 @@ struct PackedGridG {
   const SG_GLOBAL float* vox;
   Params params;
   int32_t C;
+  const void* owner;
+  uint64_t generation;
 };
 struct SlotG {
   int32_t grid, width;
@@ -1880,8 +1884,22 @@ int sg_packed_grid_desc(const sg_grid* grid, const float* d_vox, int32_t C,
   d.vox = d_vox;
   d.params = p;
   d.C = C;
+  d.owner = grid;
+  d.generation = grid->generation;
   memset(out, 0, sizeof(*out));
   memcpy(out->opaque, &d, sizeof(d));
+  return SG_OK;
+}
+
+int sg_packed_grid_check(const sg_grid* grid, const sg_packed_grid* desc) {
+  if (!desc) return fail(SG_EINVAL, "desc is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  PackedGrid d;
+  memcpy(&d, desc->opaque, sizeof(d));
+  if (d.owner != grid) return fail(SG_ESTATE, "descriptor was made from another grid");
+  if (d.generation != grid->generation)
+    return fail(SG_ESTATE, "descriptor predates an sg_grid_extend of its grid (stale memory)");
   return SG_OK;
 }
 

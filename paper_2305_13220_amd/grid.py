@@ -89,9 +89,30 @@ class Grid:
                   "sg_grid_from_depth")
         return cls(cams.device, voxel_size, origin, _handle=handle)
 
+    def pin(self):
+        """Register a user of the grid's index memory (a render server's
+        descriptors or captured launches): extend is refused until unpin."""
+        self._pins = getattr(self, "_pins", 0) + 1
+
+    def unpin(self):
+        self._pins = max(0, getattr(self, "_pins", 0) - 1)
+
+    @property
+    def generation(self):
+        """0 when built, one more per extend (which moves the grid's memory)."""
+        gen = ctypes.c_uint64()
+        check(lib().sg_grid_generation(self.handle, ctypes.byref(gen)), "sg_grid_generation")
+        return gen.value
+
     def extend(self, new_coords: torch.Tensor, dense_map_max_cells: int = -1):
         """Add blocks: existing blocks keep their indices, new ones follow in
-        order of first occurrence.  Returns the new number of blocks."""
+        order of first occurrence.  Returns the new number of blocks.  The
+        grid's memory moves, so this is refused while a server holds the grid
+        (descriptors and captured launches would point at freed memory)."""
+        if getattr(self, "_pins", 0) > 0:
+            raise SgridError("extend refused: the grid is pinned by a render server (its packed "
+                             "descriptors and captured launches would refer to freed memory); "
+                             "close the server first")
         want(new_coords, "new_coords", torch.int32, (None, 3), self.device)
         opts = _lib.BuildOptionsC(int(dense_map_max_cells))
         with torch.cuda.device(self.device):

@@ -162,6 +162,12 @@ class PackedServer:
                                         ctypes.byref(descs, PACKED_GRID_BYTES * i)),
                   "sg_packed_grid_desc")
         self.keep = grids  # grids and voxels must outlive the launches
+        # the grids' memory must not move while descriptors or captured
+        # launches refer to it: extend is refused until close()
+        for g, _, _ in grids:
+            g.pin()
+        self._closed = False
+        self._descs = descs
         self.grid_args = [(g, vox, RenderParams.of(prm).c()) for g, vox, prm in grids]
         self.n_grids = len(grids)
         self.q_cap = cap
@@ -181,6 +187,21 @@ class PackedServer:
         self.max_inflight = nt if max_inflight is None else max(1, int(max_inflight))
         self.next_b = 0
         self.keep_outputs = keep_outputs
+
+    def close(self):
+        """Release the grids (extend is allowed again) and the captured graphs."""
+        if not self._closed:
+            self.graphs.clear()
+            for g, _, _ in self.keep:
+                g.unpin()
+            self._closed = True
+
+    def check_grids(self):
+        """Raise if any resident grid's memory moved since the descriptors
+        were made (sg_packed_grid_check)."""
+        for i, (g, _, _) in enumerate(self.keep):
+            check(lib().sg_packed_grid_check(
+                g.handle, ctypes.byref(self._descs, PACKED_GRID_BYTES * i)), "sg_packed_grid_check")
 
     def _launch(self, b, gi, rays):
         if self.launch_mode == "per_grid":
@@ -243,6 +264,9 @@ class PackedServer:
 
     def run(self, requests, realtime=True):
         """Serve requests (sorted by arrival); fills req.done; returns the requests."""
+        if self._closed:
+            raise RuntimeError("server is closed")
+        self.check_grids()
         clock = _Clock()
         pending = list(requests)
         admitted = []  # requests with pixels left to schedule: [req, next_pixel]

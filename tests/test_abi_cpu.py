@@ -177,6 +177,38 @@ def test_aux_validation(L):
                              fake, fake, None, None) == -1
 
 
+def test_grid_generation_and_descriptor_check_validation(L):
+    gen = ctypes.c_uint64(7)
+    assert L.sg_grid_generation(None, ctypes.byref(gen)) == -1
+    assert gen.value == 7
+    desc = (ctypes.c_ubyte * 512)()
+    assert L.sg_packed_grid_check(None, desc) == -1
+    assert L.sg_packed_grid_check(None, None) == -1
+
+
+def test_extend_refused_while_a_server_holds_the_grid():
+    """A render server pins its grids: extend (which moves the grid's memory,
+    leaving descriptors and captured launches pointing at freed memory) is
+    refused before anything reaches the library, and allowed again after
+    the last unpin (it then fails here only on the CPU tensor)."""
+    import torch
+    import paper_2305_13220_amd as sg
+    g = sg.Grid.__new__(sg.Grid)
+    g._h = ctypes.c_void_p(0)
+    g.device = torch.device("cpu")
+    g.pin()
+    g.pin()
+    coords = torch.zeros((1, 3), dtype=torch.int32)
+    with pytest.raises(sg.SgridError, match="pinned"):
+        g.extend(coords)
+    g.unpin()
+    with pytest.raises(sg.SgridError, match="pinned"):
+        g.extend(coords)
+    g.unpin()
+    with pytest.raises(ValueError, match="GPU tensor"):
+        g.extend(coords)
+
+
 def test_binding_rejects_cpu_tensors():
     import torch
     import paper_2305_13220_amd as sg
