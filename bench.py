@@ -1,21 +1,25 @@
 """Benchmark: forward + backward rays/s of the sparse-dense SDF renderer.
 
-Workload (one GPU): the 6 x 6 x 3 m synthetic room at 2 cm voxels
-(11,542 allocated 8^3 blocks, SDF + RGB), batches of 65,536 random pixels
-from 30 seeded 640x480 poses, step 1 cm, t in [0, 12] m, beta = 2 cm, at
-most 128 samples per ray.  One step = camera rays for the batch, gradient
-zeroing, and the fused training kernel: block march, forward render
-(colour, depth, normal), squared-L2 losses against renders of the same room
-with a second texture, and the backward scatter into the voxels.  The same
-step built from separate calls (one march shared by forward and backward,
-loss gradient, backward) is timed too.  Inputs are resident on the GPU
-before timing starts.
+Headline workload (one GPU): differentiation at scale on the 6 x 6 x 3 m
+synthetic room at 2 cm voxels (11,542 allocated 8^3 blocks, SDF + RGB) with
+seeded noise on the voxels (0.5 voxel on SDF, 0.1 on RGB), batches of
+2^18 random pixels from 30 seeded 640x480 poses, step 1 cm, t in [0, 12] m,
+beta = 2 cm, at most 128 samples per ray, against renders of the clean grid.
+One step = camera rays for the batch, gradient zeroing, and the fused
+training kernel: block march, forward render (colour, depth, normal),
+squared-L2 losses (colour + 0.1 depth + 0.05 normal), and the backward
+scatter into the voxels.  Adam over every voxel parameter is timed on its
+own; the same step built from separate calls (one march shared by forward
+and backward, loss gradient, backward) is timed too.  Inputs are resident on
+the GPU before timing starts.  Extra objects repeat the step on the
+65,536-ray room batch (with the Eikonal term too) and on the 64x48 sphere.
 
-Prints one JSON line.  `roofline` is for the dominant kernel, timed with
-HIP events on its own stream over the timed steps; its algorithmic bytes
-come from exact per-ray footprint counts (samples, distinct voxels,
-distinct blocks).  `cpu_baseline` times the CPU oracle on a bounded
-sample of the same batch on the host.
+Prints one JSON line.  `roofline` is for the dominant kernel (the fused
+training kernel), timed with HIP events around each launch on the stream it
+runs on; its algorithmic bytes are the forward plus backward bytes from
+exact per-ray footprint counts (samples, distinct voxels, distinct blocks)
+of the timed batch.  `cpu_baseline` times the CPU oracle on bounded samples
+of the same workloads on the host, single-threaded and on all usable cores.
 
 `serving` measures render serving over three resident grids (the room at
 2 cm, the same room at 1 cm, a second room at 2 cm; C = 3): seeded Poisson
@@ -94,31 +98,125 @@ def measured_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, n_rays, min_seconds=10.0, max_passes=3):
-    """Oracle forward + loss gradient + backward on the first n_rays rays,
-    repeated (up to max_passes) until min_seconds of work have been timed.
+def _cpu_info():
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
-    The loss target is zero (the oracle takes no input from the GPU path;
-    the work done does not depend on the target values)."""
+
+def _oracle_fwd_bwd(w, vox64, rays, threads, C=3):
+    """Oracle forward, squared-L2 loss gradient and backward over `rays`, the
+    rays split into `threads` contiguous shards rendered by a thread pool
+    (ctypes releases the interpreter lock, so the shards run in parallel);
+    the loss gradient is taken over the whole batch and the per-shard voxel
+    gradients are summed.  The loss target is zero: the oracle takes no input
+    from the GPU path, and the work does not depend on the target values."""
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import oracle
-    rays = w["rays"][:n_rays]
-    target = {"feat": np.zeros((n_rays, 3)), "depth": np.zeros(n_rays), "normal": np.zeros((n_rays, 3))}
+    R = rays.shape[0]
+    cuts = np.linspace(0, R, threads + 1).astype(int)
+    shards = [(cuts[i], cuts[i + 1]) for i in range(threads) if cuts[i + 1] > cuts[i]]
+    args = (w["block_coords"], vox64, C, w["h"], w["origin"])
+    with ThreadPoolExecutor(len(shards)) as ex:
+        outs = list(ex.map(lambda ab: oracle.render_forward(*args, rays[ab[0]:ab[1]], w["params"]),
+                           shards))
+        feat = np.concatenate([o["feat"] for o in outs])
+        depth = np.concatenate([o["depth"] for o in outs])
+        normal = np.concatenate([o["normal"] for o in outs])
+        _, gc, gd, gn = oracle.l2_loss_grad(feat, np.zeros_like(feat), depth, np.zeros_like(depth),
+                                            normal, np.zeros_like(normal), 0.1, 0.05)
+        grads = list(ex.map(lambda ab: oracle.render_backward(
+            *args, rays[ab[0]:ab[1]], w["params"], gc[ab[0]:ab[1]], gd[ab[0]:ab[1]],
+            gn[ab[0]:ab[1]], None), shards))
+    total = grads[0]
+    for g in grads[1:]:
+        total += g
+    return total
+
+
+def _oracle_fwd(w, vox64, rays, threads, C):
+    """Oracle forward over `rays` in `threads` shards (thread pool)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import oracle
+    R = rays.shape[0]
+    cuts = np.linspace(0, R, threads + 1).astype(int)
+    shards = [(cuts[i], cuts[i + 1]) for i in range(threads) if cuts[i + 1] > cuts[i]]
+    with ThreadPoolExecutor(len(shards)) as ex:
+        list(ex.map(lambda ab: oracle.render_forward(w["block_coords"], vox64, C, w["h"],
+                                                     w["origin"], rays[ab[0]:ab[1]], w["params"]),
+                    shards))
+
+
+def _timed(fn, min_seconds, max_passes):
     done, dt = 0, 0.0
     while done < max_passes and (done == 0 or dt < min_seconds):
         t0 = time.perf_counter()
-        out = oracle.render_forward(w["block_coords"], w["vox"], 3, w["h"], w["origin"], rays,
-                                    w["params"])
-        L, gc, gd, gn = oracle.l2_loss_grad(out["feat"], target["feat"], out["depth"],
-                                            target["depth"], out["normal"], target["normal"], 0.1,
-                                            0.05)
-        oracle.render_backward(w["block_coords"], w["vox"], 3, w["h"], w["origin"], rays,
-                               w["params"], gc, gd, gn, None)
+        fn()
         dt += time.perf_counter() - t0
         done += 1
-    return {"value": done * n_rays / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} pass(es) over the first {n_rays} rays of the batch, forward + loss "
-                      f"gradient + backward, single thread ({dt:.1f} s)"}
+    return done, dt
+
+
+def cpu_baseline(w4, w2, w1, n_rays=65536, frames=True):
+    """The oracle on the host cores, one thread and all usable cores, on
+    bounded samples (rays/s of each leg):
+      * the differentiation-at-scale batch (noisy 2 cm room): forward + loss
+        gradient + backward on its first n_rays rays (the headline leg);
+      * the 65,536-ray 2 cm room batch, the same work;
+      * the 64x48 sphere frame, the same work, all 3,072 rays;
+      * frame 0 of the 1 cm semantic room (C = 19), forward only, all
+        1,254,528 rays with all cores, its first n_rays rays with one.
+    Each leg repeats until it has run for a few seconds (at most 3 passes)."""
+    import numpy as np
+    info = _cpu_info()
+    n_all = info["affinity"] or info["nproc"] or 1
+    legs = {}
+
+    def leg(name, w, rays, threads, fwd_only=False, C=3, min_s=3.0):
+        vox64 = np.ascontiguousarray(w["vox"], np.float64)
+        if fwd_only:
+            fn = lambda: _oracle_fwd(w, vox64, rays, threads, C)
+        else:
+            fn = lambda: _oracle_fwd_bwd(w, vox64, rays, threads, C)
+        done, dt = _timed(fn, min_s, 3)
+        r = {"threads": threads, "rays": int(rays.shape[0]), "passes": done,
+             "seconds": round(dt, 2), "rays_per_s": round(done * rays.shape[0] / dt, 1)}
+        legs.setdefault(name, []).append(r)
+        log(f"oracle {name} threads={threads}: {r['rays_per_s']:.0f} rays/s ({dt:.1f} s)")
+        return r
+
+    r4 = w4["rays"][:n_rays]
+    one = leg("noisy_room_2cm_fwd_bwd", w4, r4, 1, min_s=6.0)
+    full = leg("noisy_room_2cm_fwd_bwd", w4, r4, n_all, min_s=6.0)
+    r2 = w2["rays"][:n_rays]
+    leg("room_2cm_65536_fwd_bwd", w2, r2, 1)
+    leg("room_2cm_65536_fwd_bwd", w2, r2, n_all)
+    leg("sphere_64x48_fwd_bwd", w1, w1["rays"], 1, min_s=1.0)
+    leg("sphere_64x48_fwd_bwd", w1, w1["rays"], n_all, min_s=1.0)
+    if frames:
+        from synth import cameras, workloads
+        w3 = workloads.room_1cm_sem(n_cams=50)
+        r3 = cameras.pixel_rays(w3["cams"], cameras.frame_pixels(0, w3["W"], w3["H"]))
+        C3 = w3["vox"].shape[-1] - 1
+        leg("room_1cm_sem_frame0_fwd", w3, r3[:n_rays], 1, fwd_only=True, C=C3, min_s=1.0)
+        leg("room_1cm_sem_frame0_fwd", w3, r3, n_all, fwd_only=True, C=C3, min_s=1.0)
+    return {"value": full["rays_per_s"], "unit": "rays/s", "cores": n_all, "kind": "oracle",
+            "sample": f"forward + loss gradient + backward on the first {n_rays} rays of the "
+                      f"2^18-ray noisy-room batch, {n_all} threads over ray shards "
+                      f"({full['passes']} pass(es), {full['seconds']} s); single thread "
+                      f"{one['rays_per_s']} rays/s",
+            "value_1_thread": one["rays_per_s"], **info, "legs": legs}
 
 
 RESOLUTIONS = ((320, 240), (640, 480), (1296, 968), (1920, 1080))
@@ -413,64 +511,6 @@ def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
     return res
 
 
-def train_bench(dev, steps=20):
-    """Optimisation at scale: the 2 cm room with seeded noise on SDF and RGB,
-    batches of 2^18 rays against renders of the clean grid (photometric,
-    depth and normal L2), each step = rays + gradient zeroing + fused
-    forward/loss/backward + Adam over every voxel; Adam also timed alone."""
-    import numpy as np
-    import torch
-    import paper_2305_13220_amd as sg
-    from synth import workloads
-    w = workloads.room_2cm_noisy(n_rays=1 << 18)
-    grid = sg.Grid(torch.from_numpy(w["block_coords"]).to(dev), float(w["h"]),
-                   tuple(float(x) for x in w["origin"]))
-    vox = torch.from_numpy(w["vox"]).to(dev)
-    clean = torch.from_numpy(w["clean_vox"]).to(dev)
-    cams = torch.from_numpy(w["cams"]).to(dev)
-    pix = torch.from_numpy(w["pix"]).to(dev)
-    params = sg.RenderParams.of(w["params"])
-    R = pix.shape[0]
-    rays = sg.rays_pinhole(cams, pix)
-    target = {k: v.clone() for k, v in sg.render_forward(grid, clean, rays, params).items()}
-    grad = torch.zeros_like(vox)
-    m = torch.zeros_like(vox)
-    v = torch.zeros_like(vox)
-    C = vox.shape[-1] - 1
-    out = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
-           "normal": torch.empty((R, 3), device=dev), "wsum": torch.empty(R, device=dev),
-           "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
-
-    def step(t):
-        rr = sg.rays_pinhole(cams, pix)
-        grad.zero_()
-        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
-        sg.optim_step(0, vox, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, t)
-
-    for t in range(1, 4):
-        step(t)
-    torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    e[0].record()
-    for t in range(4, 4 + steps):
-        step(t)
-    e[1].record()
-    for t in range(steps):
-        sg.optim_step(0, vox, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, 100 + t)
-    e[2].record()
-    torch.cuda.synchronize()
-    ms = e[0].elapsed_time(e[1]) / steps
-    adam_ms = e[1].elapsed_time(e[2]) / steps
-    adam_bytes = 7 * vox.numel() * 4  # read p, g, m, v; write p, m, v
-    res = {"workload": "room_2cm_noisy_262144_adam", "rays_per_step": R, "ms_per_step": round(ms, 4),
-           "rays_per_s": R / (ms * 1e-3), "adam_ms": round(adam_ms, 4),
-           "adam_hbm_frac": round(adam_bytes / (adam_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-           "params": int(vox.numel())}
-    del grid, vox, clean, grad, m, v, out, target
-    torch.cuda.empty_cache()
-    return res
-
-
 def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
     """SDF and gradient at the k^3 lattice points of the grid's bounding box
     (the point-query timing of Sec. 4), one sg_query call per k.  Bytes per
@@ -525,19 +565,204 @@ def query_bench(grid, vox, block_coords, dev, ks=(16, 32, 64, 128, 256, 512)):
             "bytes_per_point": 32, "sizes": rows}
 
 
+def fused_bench(dev, w, target_vox, steps, warmup, lambda_d=0.1, lambda_n=0.05, adam=False,
+                separate=False, eikonal=False, cold=False):
+    """The training step on one batch: camera rays for the batch's (pose,
+    pixel) pairs, gradient zeroing, and the fused kernel (block march,
+    forward render, squared-L2 losses against the target renders, backward
+    scatter into the voxels).  The step is timed over `steps` steps after
+    `warmup`, with HIP events on the stream every kernel runs on (torch's
+    current stream), and the fused kernel on its own with events around
+    each launch.  Algorithmic bytes come from exact per-ray footprint counts
+    of the timed batch.  Optionally also: Adam over every voxel parameter
+    (timed alone), the same step from separate calls (march, forward, loss
+    gradient, backward), the step with the Eikonal term on the ray samples,
+    and the fused kernel with cold caches."""
+    import numpy as np
+    import torch
+    import paper_2305_13220_amd as sg
+    C = w["vox"].shape[-1] - 1
+    grid = sg.Grid(torch.from_numpy(w["block_coords"]).to(dev), float(w["h"]),
+                   tuple(float(x) for x in w["origin"]))
+    vox = torch.from_numpy(w["vox"]).to(dev)
+    tvox = torch.from_numpy(target_vox).to(dev)
+    cams = torch.from_numpy(w["cams"]).to(dev)
+    pix = torch.from_numpy(w["pix"]).to(dev)
+    params = sg.RenderParams.of(w["params"])
+    R = pix.shape[0]
+    rays = sg.rays_pinhole(cams, pix)
+    target = {k: v.clone() for k, v in sg.render_forward(grid, tvox, rays, params).items()}
+    del tvox
+    grad = torch.zeros_like(vox)
+    out = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
+           "normal": torch.empty((R, 3), device=dev), "wsum": torch.empty(R, device=dev),
+           "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
+    torch.cuda.synchronize()
+
+    def events(k):
+        return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+
+    fused_ev = []
+
+    def step_fused(timed, lam_e=0.0):
+        rr = sg.rays_pinhole(cams, pix)
+        grad.zero_()
+        e = events(2) if timed else None
+        if timed:
+            e[0].record()
+        sg.render_l2_step(grid, vox, rr, params, target, lambda_d, lambda_n, grad_vox=grad,
+                          out=out, lambda_e=lam_e)
+        if timed:
+            e[1].record()
+            fused_ev.append(e)
+
+    def run(step):
+        for _ in range(warmup):
+            step(False)
+        torch.cuda.synchronize()
+        start, end = events(2)
+        start.record()
+        for _ in range(steps):
+            step(True)
+        end.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / steps
+
+    ms = run(step_fused)
+    fused_each = np.array([a.elapsed_time(b) for a, b in fused_ev])
+    fused_ms = float(fused_each.mean())
+    counts, touched = sg.render_footprint(grid, rays, params, touched=True)
+    counts = counts.cpu().numpy()
+    fb, bb, fused_b = algorithmic_bytes(counts, C)
+    u_all = int(touched.sum().item())
+    k_all = int(touched.view(-1, 512).any(dim=1).sum().item())
+    comp_b = 2 * 4 * (1 + C) * u_all + 16 * k_all + R * (24 + 4 * (C + 5) + 4 * (C + 4))
+    del touched
+    S = int(counts[:, 0].astype(np.int64).sum())
+    fb_bb = fb + bb
+    res = {"rays_per_step": R, "ms_per_step": round(ms, 4), "rays_per_s": R / (ms * 1e-3),
+           "samples_per_s": S / (ms * 1e-3), "mean_samples_per_ray": S / R,
+           "mean_voxels_per_ray": float(counts[:, 1].astype(np.int64).sum()) / R,
+           "mean_blocks_per_ray": float(counts[:, 2].astype(np.int64).sum()) / R,
+           "fused_kernel_ms": round(fused_ms, 4),
+           "fused_kernel_ms_p50": round(float(np.median(fused_each)), 4),
+           "fused_kernel_ms_p90": round(float(np.percentile(fused_each, 90)), 4),
+           "bytes_fwd_plus_bwd": fb_bb, "bytes_fused": fused_b, "bytes_fwd": fb,
+           "bytes_compulsory": comp_b,
+           "hbm_frac_fwd_plus_bwd": round(fb_bb / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "hbm_frac_fused_bytes": round(fused_b / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "hbm_frac_compulsory": round(comp_b / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if eikonal:
+        res["ms_per_step_with_eikonal"] = round(run(lambda t: step_fused(t, 0.1)), 4)
+    if separate:
+        lists = torch.empty(sg.list_bytes(R, params), dtype=torch.uint8, device=dev)
+        gout = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
+                "normal": torch.empty((R, 3), device=dev)}
+        sep_ev = []
+
+        def step_separate(timed):
+            rr = sg.rays_pinhole(cams, pix)
+            e = events(5) if timed else None
+            if timed:
+                e[0].record()
+            sg.march(grid, rr, params, out=lists)
+            if timed:
+                e[1].record()
+            sg.render_forward(grid, vox, rr, params, out=out, lists=lists)
+            if timed:
+                e[2].record()
+            sg.l2_loss_grad(out, target, lambda_d, lambda_n, out=gout)
+            grad.zero_()
+            if timed:
+                e[3].record()
+            sg.render_backward(grid, vox, rr, params, gout["feat"], gout["depth"],
+                               gout["normal"], None, grad_vox=grad, lists=lists)
+            if timed:
+                e[4].record()
+                sep_ev.append(e)
+
+        ms_sep = run(step_separate)
+        fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sep_ev]))
+        bwd_ms = float(np.mean([e[3].elapsed_time(e[4]) for e in sep_ev]))
+        res["separate_calls"] = {
+            "ms_per_step": round(ms_sep, 4), "rays_per_s": R / (ms_sep * 1e-3),
+            "march_ms": round(float(np.mean([e[0].elapsed_time(e[1]) for e in sep_ev])), 4),
+            "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
+            "forward_hbm_frac": round(fb / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "backward_hbm_frac": round(bb / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del lists, gout
+    if cold:
+        # cold caches: 1 GiB written between steps evicts L2 and the Infinity Cache
+        flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        ev = []
+        for _ in range(10):
+            rr = sg.rays_pinhole(cams, pix)
+            grad.zero_()
+            flush.fill_(1.0)
+            e = events(2)
+            e[0].record()
+            sg.render_l2_step(grid, vox, rr, params, target, lambda_d, lambda_n, grad_vox=grad,
+                              out=out)
+            e[1].record()
+            ev.append(e)
+        torch.cuda.synchronize()
+        res["fused_kernel_ms_cold"] = round(float(np.median([a.elapsed_time(b) for a, b in ev])), 4)
+        del flush
+    if adam:
+        m = torch.zeros_like(vox)
+        v = torch.zeros_like(vox)
+        for t in range(1, 4):
+            sg.optim_step(0, vox, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, t)
+        torch.cuda.synchronize()
+        e = events(2)
+        e[0].record()
+        for t in range(steps):
+            sg.optim_step(0, vox, grad, m, v, 1e-3, 0.9, 0.999, 1e-8, 4 + t)
+        e[1].record()
+        torch.cuda.synchronize()
+        adam_ms = e[0].elapsed_time(e[1]) / steps
+        res["adam_ms"] = round(adam_ms, 4)
+        res["adam_hbm_frac"] = round(7 * vox.numel() * 4 / (adam_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        res["ms_per_step_with_adam"] = round(ms + adam_ms, 4)
+        res["params"] = int(vox.numel())
+        del m, v
+    res["_grid"] = (grid, vox)
+    del grad, out, target
+    return res
+
+
+def copy_ceiling(dev):
+    """Empirical HBM ceiling: device copy of 1 GiB (reads 1 GiB, writes 1 GiB)."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    for _ in range(5):
+        dst.copy_(src)
+    e[1].record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * (1 << 30) / (e[0].elapsed_time(e[1]) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rays", type=int, default=65536)
+    ap.add_argument("--rays", type=int, default=1 << 18,
+                    help="rays per step of the headline (noisy-room) workload")
     ap.add_argument("--cpu-rays", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-query", action="store_true", help="skip the k^3 point-query timing")
     ap.add_argument("--no-crf", action="store_true", help="skip the CRF message-passing timing")
-    ap.add_argument("--no-train", action="store_true",
-                    help="skip the 2^18-ray noisy-room training timing")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 65,536-ray room and the sphere training steps")
     ap.add_argument("--no-fusion", action="store_true",
                     help="skip the allocation + fusion timing")
     ap.add_argument("--no-frames", action="store_true",
@@ -555,188 +780,82 @@ def main():
               "voxel gradients). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import paper_2305_13220_amd as sg
     from synth import workloads
 
     dev = torch.device("cuda:0")
-    t_setup = time.perf_counter()
-    w = workloads.room_2cm(n_rays=args.rays)
-    tgt_scene = workloads.room_2cm_target()
-    C = 3
-    grid = sg.Grid(torch.from_numpy(w["block_coords"]).to(dev), float(w["h"]),
-                   tuple(float(x) for x in w["origin"]))
-    vox = torch.from_numpy(w["vox"]).to(dev)
-    tvox = torch.from_numpy(tgt_scene["vox"]).to(dev)
-    cams = torch.from_numpy(w["cams"]).to(dev)
-    pix = torch.from_numpy(w["pix"]).to(dev)
-    params = sg.RenderParams.of(w["params"])
-    R = args.rays
-    rays = sg.rays_pinhole(cams, pix)
-    target = sg.render_forward(grid, tvox, rays, params)
-    target = {k: v.clone() for k, v in target.items()}
-    grad = torch.zeros_like(vox)
-    out = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
-           "normal": torch.empty((R, 3), device=dev), "wsum": torch.empty(R, device=dev),
-           "nsamples": torch.empty(R, dtype=torch.int32, device=dev)}
-    gout = {"feat": torch.empty((R, C), device=dev), "depth": torch.empty(R, device=dev),
-            "normal": torch.empty((R, 3), device=dev)}
     if args.calib_mib > 0:
         a = torch.ones(args.calib_mib << 18, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.neg(a, out=b)
+        torch.cuda.synchronize()
         del a, b
-    torch.cuda.synchronize()
-    log(f"setup {time.perf_counter() - t_setup:.1f}s: {grid.n_blocks} blocks, {R} rays")
-
-    def events(k):
-        return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
-
-    fused_ev, sep_ev = [], []
-    lists = torch.empty(sg.list_bytes(R, params), dtype=torch.uint8, device=dev)
-
-    def step_fused(timed):
-        """camera rays -> zero gradients -> fused march + forward + L2 loss + backward"""
-        rr = sg.rays_pinhole(cams, pix)
-        grad.zero_()
-        e = events(2) if timed else None
-        if timed:
-            e[0].record()
-        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
-        if timed:
-            e[1].record()
-            fused_ev.append(e)
-
-    def step_separate(timed):
-        """camera rays -> march -> forward -> loss gradient -> zero gradients -> backward
-        (the backward reuses the forward's sample lists, as the autograd path does)"""
-        rr = sg.rays_pinhole(cams, pix)
-        e = events(5) if timed else None
-        if timed:
-            e[0].record()
-        sg.march(grid, rr, params, out=lists)
-        if timed:
-            e[1].record()
-        sg.render_forward(grid, vox, rr, params, out=out, lists=lists)
-        if timed:
-            e[2].record()
-        sg.l2_loss_grad(out, target, 0.1, 0.05, out=gout)
-        grad.zero_()
-        if timed:
-            e[3].record()
-        sg.render_backward(grid, vox, rr, params, gout["feat"], gout["depth"], gout["normal"],
-                           None, grad_vox=grad, lists=lists)
-        if timed:
-            e[4].record()
-            sep_ev.append(e)
-
-    def run(step):
-        for _ in range(args.warmup):
-            step(False)
-        torch.cuda.synchronize()
-        start, end = events(2)
-        start.record()
-        for _ in range(args.steps):
-            step(True)
-        end.record()
-        torch.cuda.synchronize()
-        return start.elapsed_time(end) / args.steps
-
-    ms = run(step_fused)
-    ms_sep = run(step_separate)
-
-    def step_eikonal(timed):
-        """the fused step with the Eikonal term on the ray samples (weight 0.1)"""
-        rr = sg.rays_pinhole(cams, pix)
-        grad.zero_()
-        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out,
-                          lambda_e=0.1)
-
-    ms_eik = run(step_eikonal)
-    fused_each = np.array([e[0].elapsed_time(e[1]) for e in fused_ev])
-    fused_ms = float(fused_each.mean())
-    fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in sep_ev]))
-    bwd_ms = float(np.mean([e[3].elapsed_time(e[4]) for e in sep_ev]))
-
-    # cold caches: 1 GiB written between steps evicts L2 and the Infinity Cache
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    cold = []
-    for _ in range(max(5, min(args.steps, 20))):
-        rr = sg.rays_pinhole(cams, pix)
-        grad.zero_()
-        flush.fill_(1.0)
-        e = events(2)
-        e[0].record()
-        sg.render_l2_step(grid, vox, rr, params, target, 0.1, 0.05, grad_vox=grad, out=out)
-        e[1].record()
-        cold.append(e)
-    torch.cuda.synchronize()
-    cold_ms = float(np.median([e[0].elapsed_time(e[1]) for e in cold]))
-    # empirical HBM ceiling: device copy of 1 GiB (reads 1 GiB, writes 1 GiB)
-    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-    flush.copy_(src)
-    e = events(2)
-    e[0].record()
-    for _ in range(5):
-        flush.copy_(src)
-    e[1].record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * (1 << 30) / (e[0].elapsed_time(e[1]) * 1e-3) / 1e9
-    del flush, src
-
-    counts, touched = sg.render_footprint(grid, rays, params, touched=True)
-    counts = counts.cpu().numpy()
-    fb, bb, fused_b = algorithmic_bytes(counts, C)
-    # compulsory traffic of the whole batch: every touched voxel read and its
-    # gradient written once, every block entry once, the per-ray inputs/outputs
-    u_all = int(touched.sum().item())
-    k_all = int(touched.view(-1, 512).any(dim=1).sum().item())
-    comp_b = 2 * 4 * (1 + C) * u_all + 16 * k_all + R * (24 + 4 * (C + 5) + 4 * (C + 4))
-    S = int(counts[:, 0].sum())
+    t_setup = time.perf_counter()
+    w4 = workloads.room_2cm_noisy(n_rays=args.rays)
+    log(f"setup {time.perf_counter() - t_setup:.1f}s: {w4['block_coords'].shape[0]} blocks, "
+        f"{args.rays} rays")
+    head = fused_bench(dev, w4, w4["clean_vox"], args.steps, args.warmup, adam=True,
+                       separate=True, cold=True)
+    grid4, vox4 = head.pop("_grid")
+    log(f"headline: {head['ms_per_step']:.4f} ms/step, fused kernel {head['fused_kernel_ms']:.4f} "
+        f"ms, frac {head['hbm_frac_fwd_plus_bwd']}")
     kname = "k_render_bwd<3, true, false>"
-    achieved = fused_b / (fused_ms * 1e-3) / 1e9
+    fused_ms = head["fused_kernel_ms"]
+    achieved = head["bytes_fwd_plus_bwd"] / (fused_ms * 1e-3) / 1e9
+    copy_gbs = copy_ceiling(dev)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kname, "room_2cm_65536"), "kernel": kname,
-            "algorithmic_bytes_per_launch": fused_b, "launch_ms": round(fused_ms, 4),
-            "launch_ms_p50": round(float(np.median(fused_each)), 4),
-            "launch_ms_p90": round(float(np.percentile(fused_each, 90)), 4),
-            "launch_ms_cold": round(cold_ms, 4),
-            "compulsory_bytes_per_launch": comp_b,
-            "compulsory_frac": round(comp_b / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kname, "noisy_room_2cm_262144"), "kernel": kname,
+            "bytes_per_launch": head["bytes_fwd_plus_bwd"],
+            "bytes_definition": "sum over rays of B_f + B_b (forward and backward algorithmic "
+                                "bytes from exact per-ray footprint counts)",
+            "launch_ms": fused_ms, "launch_ms_p50": head["fused_kernel_ms_p50"],
+            "launch_ms_p90": head["fused_kernel_ms_p90"],
+            "launch_ms_cold": head.get("fused_kernel_ms_cold"),
+            "frac_fused_bytes": head["hbm_frac_fused_bytes"],
+            "fused_bytes_per_launch": head["bytes_fused"],
+            "compulsory_bytes_per_launch": head["bytes_compulsory"],
+            "compulsory_frac": head["hbm_frac_compulsory"],
             "copy_ceiling_GBps": round(copy_gbs, 1)}
+    R = head["rays_per_step"]
     res = {
-        "metric": METRIC, "value": R / (ms * 1e-3), "unit": "rays/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "room_2cm_65536", "scene": "6x6x3 m room, 20 primitives, h=2 cm",
-                   "blocks": grid.n_blocks, "rays_per_step": R, "step_m": 0.01, "t_far_m": 12.0,
-                   "beta_m": 0.02, "max_samples": 128, "C": C, "loss": "L2 colour + 0.1 depth "
-                   "+ 0.05 normal"},
-        "samples_per_s": S / (ms * 1e-3),
-        "mean_samples_per_ray": S / R,
-        "fused_kernel_ms": round(fused_ms, 4),
-        "ms_per_step_with_eikonal": round(ms_eik, 4),
+        "metric": METRIC, "value": head["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"noisy_room_2cm_{R}", "scene": "6x6x3 m room, 20 primitives, "
+                   "h=2 cm, SDF noise 0.5 voxel, RGB noise 0.1; target = clean renders",
+                   "blocks": grid4.n_blocks, "rays_per_step": R, "step_m": 0.01, "t_far_m": 12.0,
+                   "beta_m": 0.02, "max_samples": 128, "C": 3,
+                   "loss": "L2 colour + 0.1 depth + 0.05 normal",
+                   "step": "camera rays + gradient zeroing + fused march/forward/loss/backward "
+                           "(Adam timed separately)"},
+        "samples_per_s": head["samples_per_s"],
         "roofline": roof,
-        "separate_calls": {"ms_per_step": round(ms_sep, 4), "rays_per_s": R / (ms_sep * 1e-3),
-                           "forward_ms": round(fwd_ms, 4), "backward_ms": round(bwd_ms, 4),
-                           "forward_hbm_frac": round(fb / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "backward_hbm_frac": round(bb / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "march_ms": round(float(np.mean([e[0].elapsed_time(e[1])
-                                                            for e in sep_ev])), 4),
-                           "traffic_forward": measured_traffic("k_render_fwd<3, true>",
-                                                               "room_2cm_65536"),
-                           "traffic_backward": measured_traffic("k_render_bwd<3, false, true>",
-                                                                "room_2cm_65536")},
+        "headline": head,
     }
+    if not args.no_query:
+        res["query"] = query_bench(grid4, vox4, w4["block_coords"], dev)
+    del grid4, vox4
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        w2 = workloads.room_2cm(n_rays=65536)
+        c2 = fused_bench(dev, w2, workloads.room_2cm_target()["vox"], args.steps, args.warmup,
+                         eikonal=True, separate=True)
+        c2.pop("_grid")
+        c2["workload"] = "room_2cm_65536"
+        res["room_2cm_65536"] = c2
+        w1 = workloads.sphere_tiny()
+        c1 = fused_bench(dev, w1, w1["target_vox"], args.steps, args.warmup, lambda_d=0.0,
+                         lambda_n=0.0)
+        c1.pop("_grid")
+        c1["workload"] = "sphere_64x48"
+        c1["loss"] = "L2 colour only"
+        res["sphere_64x48"] = c1
+        torch.cuda.empty_cache()
     if not args.no_frames:
         res["frames"] = frames_bench(dev)
-    if not args.no_train:
-        res["training"] = train_bench(dev)
-    if not args.no_query:
-        res["query"] = query_bench(grid, vox, w["block_coords"], dev)
     if not args.no_fusion:
         res["fusion"] = fusion_bench(dev)
     if not args.no_crf:
@@ -746,7 +865,10 @@ def main():
     if not args.no_cpu:
         import oracle
         oracle.build(force=False)
-        res["cpu_baseline"] = cpu_baseline(w, min(args.cpu_rays, R))
+        oracle._load()
+        res["cpu_baseline"] = cpu_baseline(w4, workloads.room_2cm(n_rays=65536),
+                                           workloads.sphere_tiny(), min(args.cpu_rays, R),
+                                           frames=not args.no_frames)
     print(json.dumps(res), flush=True)
 
 

@@ -125,6 +125,20 @@ typedef struct sg_build_options {
   int64_t dense_map_max_cells;
 } sg_build_options;
 
+/*
+ * Dense-map plan of a grid (a host computation, for memory planning): for a
+ * block bounding box [bmin, bmax] (inclusive, each coordinate in
+ * [-2^20, 2^20)) holding n_blocks allocated blocks, the dims[3] and cell
+ * count (*cells, int32 entries) of the dense block map that sg_grid_build_ex
+ * with these options would build, or all zeros if it would build none (more
+ * cells than the limit, or n_blocks >= 2^23).  The cell count of a box that
+ * spans the whole coordinate range, 2^63, is decided without overflow.
+ * SG_ERANGE for a box outside the range, SG_EINVAL for bmin > bmax,
+ * n_blocks < 0 or a NULL pointer.
+ */
+int sg_grid_dense_map_plan(const int32_t bmin[3], const int32_t bmax[3], int64_t n_blocks,
+                           const sg_build_options* options, int32_t dims[3], int64_t* cells);
+
 /* sg_grid_build with options (NULL = defaults); otherwise identical. */
 int sg_grid_build_ex(const int32_t* d_block_coords, int64_t n, float voxel_size,
                      const float origin[3], sg_stream stream, sg_grid** out,
@@ -261,9 +275,16 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   vertices and barycentric weights; float32 without fused multiply-add,
  *   so the vertices are the same integers for any evaluation of the same
  *   steps) and the hash of all vertices.  max_values (1..32) bounds the
- *   value channels of later filters.  Allocates device memory and
- *   synchronises the stream.  SG_ERANGE if two lattice keys share a 64-bit
- *   fingerprint (checked, never silently merged).
+ *   value channels of later filters.  Allocates device memory (the
+ *   sg_lattice_bytes(n_points, d, max_values) bytes) and synchronises the
+ *   stream.  SG_ERANGE if two lattice keys share a 64-bit fingerprint
+ *   (checked, never silently merged).
+ * sg_lattice_bytes -- device bytes a build of these sizes allocates (a host
+ *   computation, for memory planning): a hash table of the smallest power
+ *   of two >= 2 n (d+1) slots (8-byte fingerprint, d int32 key, two
+ *   max_values-float value rows, an int32 slot-list entry each) plus n (d+1)
+ *   vertex ids and weights and n max_values slice outputs; 0 for invalid
+ *   sizes (the limits of sg_lattice_build).
  * sg_lattice_filter -- d_out [n, n_values] = slice(blur(splat(d_val))):
  *   values splatted onto the simplex vertices with the barycentric weights,
  *   blurred with [1/4, 1/2, 1/4] along each of the d+1 lattice directions
@@ -309,6 +330,7 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
 typedef struct sg_lattice sg_lattice;
 int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
                      sg_stream stream, sg_lattice** out);
+size_t sg_lattice_bytes(int64_t n_points, int32_t d, int32_t max_values);
 int sg_lattice_num_vertices(const sg_lattice* lat, int64_t* n_vertices);
 int sg_lattice_filter(const sg_lattice* lat, const float* d_val, int32_t n_values, float* d_out,
                       sg_stream stream);

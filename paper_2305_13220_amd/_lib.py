@@ -46,6 +46,8 @@ _SIGNATURES = {
     "sg_grid_num_blocks": ([_vp, _vp], ctypes.c_int),
     "sg_grid_geometry": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_generation": ([_vp, _vp], ctypes.c_int),
+    "sg_grid_dense_map_plan": ([_vp, _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "sg_lattice_bytes": ([_i64, _i32, _i32], ctypes.c_size_t),
     "sg_packed_grid_check": ([_vp, _vp], ctypes.c_int),
     "sg_grid_block_coords": ([_vp, _vp, _vp], ctypes.c_int),
     "sg_grid_neighbors": ([_vp, _vp, _vp], ctypes.c_int),

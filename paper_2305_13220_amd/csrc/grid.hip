@@ -546,6 +546,30 @@ int sg_grid_build(const int32_t* d_block_coords, int64_t n, float voxel_size,
                           nullptr);
 }
 
+// Dense block map of a bounding box [bmin, bmax] (block coordinates, each in
+// [-2^20, 2^20)) for n_blocks allocated blocks: dims and cell count when the
+// box has at most `limit` cells and n_blocks < 2^23 (the map packs a block
+// index into 23 bits), else dims = 0 and cells = 0.  The box may span up to
+// 2^21 blocks per axis, whose product (2^63) overflows int64: the decision
+// is taken in floating point before the (then small) integer count is
+// formed.  Returns false for an invalid box.
+static bool map_plan(const int32_t bmin[3], const int32_t bmax[3], int64_t n_blocks, int64_t limit,
+                     int32_t dims[3], int64_t& cells) {
+  dims[0] = dims[1] = dims[2] = 0;
+  cells = 0;
+  double cells_d = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    if (bmin[a] > bmax[a] || bmin[a] < -kCoordLimit || bmax[a] >= kCoordLimit) return false;
+    cells_d *= (double)bmax[a] - (double)bmin[a] + 1.0;
+  }
+  if (n_blocks < 0) return false;
+  if (limit < 0) limit = SG_DEFAULT_DENSE_MAP_CELLS;
+  if (!(cells_d <= (double)limit) || n_blocks >= (int64_t(1) << 23)) return true;
+  for (int a = 0; a < 3; ++a) dims[a] = bmax[a] - bmin[a] + 1;
+  cells = (int64_t)dims[0] * dims[1] * dims[2];
+  return true;
+}
+
 int sg_grid_build_ex(const int32_t* d_block_coords, int64_t n, float voxel_size,
                      const float origin[3], sg_stream stream, sg_grid** out,
                      int32_t* d_index_of_input, const sg_build_options* options) {
@@ -639,13 +663,8 @@ int sg_grid_build_ex(const int32_t* d_block_coords, int64_t n, float voxel_size,
   }
   g->d_map = nullptr;
   g->mdim[0] = g->mdim[1] = g->mdim[2] = 0;
-  // The box may span up to 2^21 blocks per axis: decide in floating point
-  // before forming the (then small) integer cell count.
-  double cells_d = 1.0;
-  for (int a = 0; a < 3; ++a) cells_d *= (double)g->bmax[a] - (double)g->bmin[a] + 1.0;
-  if (cells_d <= (double)map_limit && nu < (int64_t(1) << 23)) {
-    const int64_t cells = (int64_t)cells_d;
-    for (int a = 0; a < 3; ++a) g->mdim[a] = g->bmax[a] - g->bmin[a] + 1;
+  int64_t cells = 0;
+  if (map_plan(g->bmin, g->bmax, nu, map_limit, g->mdim, cells) && cells > 0) {
     SG_ALLOC(keep, g->d_map, sizeof(int32_t) * cells);
     k_map_fill<<<grid1d(cells, T), T, 0, s>>>(g->d_map, cells);
     k_map_blocks<<<grid1d(nu, T), T, 0, s>>>(g->d_coords, g->d_nbr, nu, g->bmin[0], g->bmin[1],
@@ -781,6 +800,25 @@ int sg_grid_copy_dense_map(const sg_grid* g, int32_t* d_out, sg_stream stream) {
   SG_HIP_CHECK(hipMemcpyAsync(d_out, g->d_map,
                               sizeof(int32_t) * (size_t)g->mdim[0] * g->mdim[1] * g->mdim[2],
                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SG_OK;
+}
+
+int sg_grid_dense_map_plan(const int32_t bmin[3], const int32_t bmax[3], int64_t n_blocks,
+                           const sg_build_options* options, int32_t dims[3], int64_t* cells) {
+  if (!bmin || !bmax || !dims || !cells) return fail(SG_EINVAL, "a required pointer is NULL");
+  int64_t c = 0;
+  int32_t d[3];
+  const int64_t limit = options ? options->dense_map_max_cells : -1;
+  if (!map_plan(bmin, bmax, n_blocks, limit, d, c)) {
+    dims[0] = dims[1] = dims[2] = 0;
+    *cells = 0;
+    for (int a = 0; a < 3; ++a)
+      if (bmin[a] < -kCoordLimit || bmax[a] >= kCoordLimit)
+        return fail(SG_ERANGE, "box outside [-2^20, 2^20)");
+    return fail(SG_EINVAL, "bmin must not exceed bmax and n_blocks must be >= 0");
+  }
+  for (int a = 0; a < 3; ++a) dims[a] = d[a];
+  *cells = c;
   return SG_OK;
 }
 

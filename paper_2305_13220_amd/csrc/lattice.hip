@@ -537,11 +537,44 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }
+// Table capacity (a power of two, at least twice the n (d+1) vertex keys)
+// and the byte sizes of the build's eight device arrays: fingerprints,
+// keys, per-point vertex ids and weights, two value buffers, the slice
+// output, the occupied-slot list.  The caller has checked
+// n (d+1) < 2^30, so every size fits 64 bits.
+static int64_t lat_sizes(int64_t n_points, int d, int max_values, size_t sz[8]) {
+  int64_t cap = 1;
+  while (cap < 2 * n_points * (d + 1)) cap <<= 1;
+  sz[0] = sizeof(uint64_t) * cap;
+  sz[1] = sizeof(int32_t) * cap * d;
+  sz[2] = sizeof(int32_t) * n_points * (d + 1);
+  sz[3] = sizeof(float) * n_points * (d + 1);
+  sz[4] = sizeof(float) * cap * max_values;
+  sz[5] = sizeof(float) * cap * max_values;
+  sz[6] = sizeof(float) * n_points * max_values;
+  sz[7] = sizeof(int32_t) * cap;
+  return cap;
+}
+
+static bool lat_args_ok(int64_t n_points, int32_t d, int32_t max_values) {
+  return d >= 1 && d <= kLatMaxD && max_values >= 1 && max_values <= kLatMaxV && n_points >= 1 &&
+         n_points <= (int64_t)INT_MAX && n_points * (d + 1) <= (int64_t)INT_MAX / 2;
+}
+
 }  // namespace sg
 
 using namespace sg;
 
 extern "C" {
+
+size_t sg_lattice_bytes(int64_t n_points, int32_t d, int32_t max_values) {
+  if (!lat_args_ok(n_points, d, max_values)) return 0;
+  size_t sz[8];
+  lat_sizes(n_points, d, max_values, sz);
+  size_t total = 0;
+  for (int k = 0; k < 8; ++k) total += sz[k];
+  return total;
+}
 
 int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
                      sg_stream stream, sg_lattice** out) {
@@ -549,7 +582,7 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
   *out = nullptr;
   if (d < 1 || d > kLatMaxD) return fail(SG_EINVAL, "d must be in [1, 16]");
   if (max_values < 1 || max_values > kLatMaxV) return fail(SG_EINVAL, "max_values must be in [1, 32]");
-  if (n_points < 1 || n_points * (d + 1) > (int64_t)INT_MAX / 2)
+  if (!lat_args_ok(n_points, d, max_values))
     return fail(SG_EINVAL, "n_points must be >= 1 and n_points * (d+1) < 2^30");
   if (!d_pos) return fail(SG_EINVAL, "d_pos is NULL");
   hipStream_t s = (hipStream_t)stream;
@@ -558,12 +591,8 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
   L->d = d;
   L->vmax = max_values;
   L->N = n_points;
-  L->cap = 1;
-  while (L->cap < 2 * n_points * (d + 1)) L->cap <<= 1;
-  const size_t sz[8] = {sizeof(uint64_t) * L->cap, sizeof(int32_t) * L->cap * d,
-                        sizeof(int32_t) * n_points * (d + 1), sizeof(float) * n_points * (d + 1),
-                        sizeof(float) * L->cap * max_values, sizeof(float) * L->cap * max_values,
-                        sizeof(float) * n_points * max_values, sizeof(int32_t) * L->cap};
+  size_t sz[8];
+  L->cap = lat_sizes(n_points, d, max_values, sz);
   void** ptrs[8] = {(void**)&L->fp, (void**)&L->keys, (void**)&L->vid, (void**)&L->bw,
                     (void**)&L->v0, (void**)&L->v1, (void**)&L->m, (void**)&L->list};
   for (int k = 0; k < 8; ++k)

@@ -177,6 +177,72 @@ def test_aux_validation(L):
                              fake, fake, None, None) == -1
 
 
+def _plan(L, bmin, bmax, n_blocks, max_cells=None):
+    from paper_2305_13220_amd._lib import BuildOptionsC
+    lo = (ctypes.c_int32 * 3)(*bmin)
+    hi = (ctypes.c_int32 * 3)(*bmax)
+    dims = (ctypes.c_int32 * 3)(7, 7, 7)
+    cells = ctypes.c_int64(-1)
+    opts = None if max_cells is None else ctypes.byref(BuildOptionsC(max_cells))
+    rc = L.sg_grid_dense_map_plan(lo, hi, n_blocks, opts, dims, ctypes.byref(cells))
+    return rc, tuple(dims), cells.value
+
+
+def test_dense_map_plan(L):
+    """The dense map's size decision on the host, including the box that
+    spans the whole coordinate range, (2^21)^3 = 2^63 cells, whose int64
+    product once wrapped negative and passed the size check."""
+    lim = 1 << 20
+    assert _plan(L, (-lim,) * 3, (lim - 1,) * 3, 2) == (0, (0, 0, 0), 0)
+    assert _plan(L, (-lim, 0, 0), (lim - 1, 0, 0), 2) == (0, (1 << 21, 1, 1), 1 << 21)
+    assert _plan(L, (-lim, -lim, 0), (lim - 1, lim - 1, 0), 2) == (0, (0, 0, 0), 0)
+    assert _plan(L, (0, 0, 0), (511, 511, 511), 100) == (0, (512, 512, 512), 1 << 27)
+    assert _plan(L, (0, 0, 0), (1023, 1023, 255), 100) == (0, (1024, 1024, 256), 1 << 28)
+    assert _plan(L, (0, 0, 0), (1023, 1023, 256), 100) == (0, (0, 0, 0), 0)
+    assert _plan(L, (-3, 5, -7), (10, 5, 2), 40) == (0, (14, 1, 10), 140)
+    # block indices must fit the map's 23 bits
+    assert _plan(L, (0, 0, 0), (9, 9, 9), (1 << 23) - 1)[2] == 1000
+    assert _plan(L, (0, 0, 0), (9, 9, 9), 1 << 23)[2] == 0
+    # options: 0 disables the map, a limit below the count disables it, < 0 is the default
+    assert _plan(L, (0, 0, 0), (9, 9, 9), 5, max_cells=0)[2] == 0
+    assert _plan(L, (0, 0, 0), (9, 9, 9), 5, max_cells=999)[2] == 0
+    assert _plan(L, (0, 0, 0), (9, 9, 9), 5, max_cells=1000)[2] == 1000
+    assert _plan(L, (0, 0, 0), (9, 9, 9), 5, max_cells=-1)[2] == 1000
+    assert _plan(L, (0, 0, 0), (lim, 0, 0), 5)[0] == -2
+    assert _plan(L, (-lim - 1, 0, 0), (0, 0, 0), 5)[0] == -2
+    assert _plan(L, (3, 0, 0), (2, 0, 0), 5)[0] == -1
+    assert _plan(L, (0, 0, 0), (2, 0, 0), -1)[0] == -1
+
+
+def test_lattice_and_workspace_sizes(L):
+    """Host-side byte counts of the lattice build and the mean-field
+    gradient's workspace, and their limits."""
+    def lat(n, d, v):
+        cap = 1
+        while cap < 2 * n * (d + 1):
+            cap <<= 1
+        return cap * (8 + 4 * d + 8 * v + 4) + n * (d + 1) * 8 + n * v * 4
+    for n, d, v in ((1, 1, 1), (1000, 6, 16), (262144, 6, 16), (5, 16, 32)):
+        assert L.sg_lattice_bytes(n, d, v) == lat(n, d, v)
+    assert L.sg_lattice_bytes(0, 6, 16) == 0
+    assert L.sg_lattice_bytes(10, 0, 16) == 0
+    assert L.sg_lattice_bytes(10, 17, 16) == 0
+    assert L.sg_lattice_bytes(10, 6, 33) == 0
+    assert L.sg_lattice_bytes((1 << 30) // 7 + 1, 6, 1) == 0  # n (d+1) beyond 2^30
+    assert L.sg_lattice_bytes((1 << 30) // 7 - 1, 6, 1) > 0
+
+    def ws(n, lb, t):
+        al = lambda b: (b + 255) // 256 * 256
+        nl = n * lb * 4
+        return (al((t + 1) * nl) + al(t * nl) + al(nl) + al(nl)
+                + al((n + 127) // 128 * lb * lb * 4))
+    assert L.sg_crf_meanfield_compat_backward_ws_bytes(262144, 16, 5) == ws(262144, 16, 5)
+    assert L.sg_crf_meanfield_compat_backward_ws_bytes(1, 1, 0) == ws(1, 1, 0)
+    assert L.sg_crf_meanfield_compat_backward_ws_bytes(0, 16, 5) == 0
+    assert L.sg_crf_meanfield_compat_backward_ws_bytes(10, 33, 5) == 0
+    assert L.sg_crf_meanfield_compat_backward_ws_bytes(10, 16, -1) == 0
+
+
 def test_grid_generation_and_descriptor_check_validation(L):
     gen = ctypes.c_uint64(7)
     assert L.sg_grid_generation(None, ctypes.byref(gen)) == -1
