@@ -344,6 +344,31 @@ int sg_crf_meanfield_compat_backward(const sg_lattice* lat, const float* d_unary
                                      const float* d_compat, int32_t iters, const float* d_gQ,
                                      float* d_g_unary, float* d_g_compat, void* d_ws,
                                      size_t ws_bytes, sg_stream stream);
+/*
+ * sg_crf_meanfield_compat_backward_noalloc -- for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid hipMalloc): the same gradients as
+ * sg_crf_meanfield_compat_backward (same arguments, same kernels, same
+ * results up to the order of the splat's float atomics) with the workspace
+ * taken from a fixed array inside the library instead of d_ws.  The array
+ * holds sg_crf_meanfield_compat_backward_noalloc_max_bytes() bytes (64 MiB)
+ * on each device the library runs on, allocated when the library is loaded
+ * onto the device and kept until the process ends; SG_EINVAL if
+ * sg_crf_meanfield_compat_backward_ws_bytes(n, n_labels, iters) exceeds it
+ * (for example n * n_labels * (2 iters + 3) > 16 M floats) or the current
+ * device is not the lattice's.  Calls on one device share that array and
+ * its contents persist between calls (every part is written before it is
+ * read, so nothing needs clearing): calls that overlap on one device (other
+ * streams, other threads) race and give wrong results; issue them in
+ * order.  Calls no hipMalloc, hipFree or allocating library routine; the
+ * first call on a device looks up the array's device address once.
+ * Asynchronous; d_g_unary must not overlap d_gQ (SG_EINVAL).
+ */
+size_t sg_crf_meanfield_compat_backward_noalloc_max_bytes(void);
+int sg_crf_meanfield_compat_backward_noalloc(const sg_lattice* lat, const float* d_unary,
+                                             int32_t n_labels, const float* d_compat,
+                                             int32_t iters, const float* d_gQ, float* d_g_unary,
+                                             float* d_g_compat, sg_stream stream);
 int sg_lattice_destroy(sg_lattice* lat);
 
 /*

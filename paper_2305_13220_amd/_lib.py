@@ -75,6 +75,9 @@ _SIGNATURES = {
     "sg_crf_meanfield_compat_backward_ws_bytes": ([_i64, _i32, _i32], ctypes.c_size_t),
     "sg_crf_meanfield_compat_backward": ([_vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp,
                                           ctypes.c_size_t, _vp], ctypes.c_int),
+    "sg_crf_meanfield_compat_backward_noalloc_max_bytes": ([], ctypes.c_size_t),
+    "sg_crf_meanfield_compat_backward_noalloc": ([_vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp],
+                                                 ctypes.c_int),
     "sg_crf_label_loss": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_float, _vp, _vp, _i64, _vp],
                           ctypes.c_int),
     "sg_crf_property_loss": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_float, _vp, _vp, _i64, _vp],

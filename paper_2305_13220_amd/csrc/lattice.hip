@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -483,6 +484,7 @@ static unsigned grid_of(int64_t n, int t) { return (unsigned)((n + t - 1) / t); 
 
 struct sg_lattice {
   uint32_t magic;
+  int device;  // the device current at build, which holds the arrays below
   int d, vmax;
   int64_t N, cap, n_vertices;
   uint64_t* fp;
@@ -561,6 +563,95 @@ static bool lat_args_ok(int64_t n_points, int32_t d, int32_t max_values) {
          n_points <= (int64_t)INT_MAX && n_points * (d + 1) <= (int64_t)INT_MAX / 2;
 }
 
+
+// The mean-field backward's checks shared by its two entry points (the
+// caller-workspace one and the allocation-free one).
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+static int mf_backward_check(const sg_lattice* L, const float* d_unary, int32_t n_labels,
+                             const float* d_compat, int32_t iters, const float* d_gQ,
+                             const float* d_g_unary, const float* d_g_compat) {
+  int rc = check_lat(L);
+  if (rc) return rc;
+  if (n_labels < 1 || n_labels > L->vmax)
+    return fail(SG_EINVAL, "n_labels must be in [1, max_values of the build]");
+  if (iters < 0) return fail(SG_EINVAL, "iters must be >= 0");
+  if (!d_unary || !d_compat || !d_gQ || !d_g_unary || !d_g_compat)
+    return fail(SG_EINVAL, "a required pointer is NULL");
+  const size_t nlb = (size_t)L->N * n_labels * sizeof(float);
+  if (ranges_overlap(d_g_unary, nlb, d_gQ, nlb))
+    return fail(SG_EINVAL, "d_g_unary must not overlap d_gQ");
+  return SG_OK;
+}
+
+// Reverse mode through `iters` compatibility mean-field updates with the
+// workspace at `base` (layout of mf_ws; every part is written before it is
+// read, so nothing in it needs to start at zero).
+static int mf_backward_run(const sg_lattice* L, const float* d_unary, int32_t n_labels,
+                           const float* d_compat, int32_t iters, const float* d_gQ,
+                           float* d_g_unary, float* d_g_compat, char* base, hipStream_t s) {
+  const int64_t N = L->N;
+  const MfWs w = mf_ws(N, n_labels, iters);
+  float* Qs = (float*)(base + w.qs);
+  float* ms = (float*)(base + w.ms);
+  float* gq = (float*)(base + w.gq);
+  float* gm = (float*)(base + w.gm);
+  float* part = (float*)(base + w.part);
+  const int64_t nl = N * n_labels;
+  const int T = 256;
+  int rc = SG_OK;
+  // forward, keeping the marginals and the messages of every update
+  k_softmax<<<grid_of(N, T), T, 0, s>>>(d_unary, nullptr, 0.0f, N, n_labels, Qs);
+  for (int it = 1; it <= iters; ++it) {
+    float* m = ms + (it - 1) * nl;
+    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, m, s))) return rc;
+    k_softmax_compat<<<grid_of(N, T), T, 0, s>>>(d_unary, m, d_compat, N, n_labels, Qs + it * nl);
+  }
+  k_fill_zero<<<grid_of(nl, T), T, 0, s>>>(d_g_unary, nl);
+  const int LL = n_labels * n_labels;
+  k_fill_zero<<<grid_of(LL, T), T, 0, s>>>(d_g_compat, LL);
+  const int64_t nblk = (N + kMfT - 1) / kMfT;
+  const float* gin = d_gQ;
+  for (int it = iters; it >= 1; --it) {
+    k_mf_bwd<true><<<nblk, kMfT, 0, s>>>(Qs + it * nl, gin, ms + (it - 1) * nl, d_compat, N,
+                                         n_labels, d_g_unary, gm, part);
+    k_mf_reduce<<<LL, kMfRed, 0, s>>>(part, nblk, LL, d_g_compat);
+    if ((rc = lat_filter(L, gm, n_labels, gq, s, true))) return rc;
+    gin = gq;
+  }
+  k_mf_bwd<false><<<nblk, kMfT, 0, s>>>(Qs, gin, nullptr, d_compat, N, n_labels, d_g_unary,
+                                        nullptr, nullptr);
+  SG_HIP_CHECK(hipGetLastError());
+  return SG_OK;
+}
+
+// Fixed workspace of the allocation-free mean-field backward: one array in
+// each device's copy of the code object, held until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: kernels
+// and copies take the address hipGetSymbolAddress returns for the current
+// device, looked up once per device and kept in mf_scratch_ptr.
+constexpr size_t kMfScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kMfScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex mf_scratch_mu;
+static char* mf_scratch_ptr[kMaxDevices];
+
+static int mf_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SG_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(mf_scratch_mu);
+  if (!mf_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SG_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    mf_scratch_ptr[dev] = (char*)p;
+  }
+  *out = mf_scratch_ptr[dev];
+  return SG_OK;
+}
 }  // namespace sg
 
 using namespace sg;
@@ -586,8 +677,11 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
     return fail(SG_EINVAL, "n_points must be >= 1 and n_points * (d+1) < 2^30");
   if (!d_pos) return fail(SG_EINVAL, "d_pos is NULL");
   hipStream_t s = (hipStream_t)stream;
+  int dev = -1;
+  SG_HIP_CHECK(hipGetDevice(&dev));
   sg_lattice* L = new sg_lattice();
   memset(L, 0, sizeof(*L));
+  L->device = dev;
   L->d = d;
   L->vmax = max_values;
   L->N = n_points;
@@ -711,57 +805,40 @@ int sg_crf_meanfield_compat_backward(const sg_lattice* L, const float* d_unary, 
                                      const float* d_compat, int32_t iters, const float* d_gQ,
                                      float* d_g_unary, float* d_g_compat, void* d_ws,
                                      size_t ws_bytes, sg_stream stream) {
-  int rc = check_lat(L);
+  int rc = mf_backward_check(L, d_unary, n_labels, d_compat, iters, d_gQ, d_g_unary, d_g_compat);
   if (rc) return rc;
-  if (n_labels < 1 || n_labels > L->vmax)
-    return fail(SG_EINVAL, "n_labels must be in [1, max_values of the build]");
-  if (iters < 0) return fail(SG_EINVAL, "iters must be >= 0");
-  if (!d_unary || !d_compat || !d_gQ || !d_g_unary || !d_g_compat || !d_ws)
-    return fail(SG_EINVAL, "a required pointer is NULL");
-  const int64_t N = L->N;
-  const MfWs w = mf_ws(N, n_labels, iters);
+  if (!d_ws) return fail(SG_EINVAL, "a required pointer is NULL");
+  const MfWs w = mf_ws(L->N, n_labels, iters);
   if (ws_bytes < w.total) return fail(SG_EINVAL, "workspace smaller than the size query returns");
-  {
-    const size_t nlb = (size_t)N * n_labels * sizeof(float);
-    auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
-      const char *pa = (const char*)a, *pb = (const char*)b;
-      return pa < pb + nb && pb < pa + na;
-    };
-    if (overlap(d_g_unary, nlb, d_gQ, nlb) || overlap(d_ws, w.total, d_gQ, nlb))
-      return fail(SG_EINVAL, "d_g_unary and d_ws must not overlap d_gQ");
-  }
-  hipStream_t s = (hipStream_t)stream;
-  char* base = (char*)d_ws;
-  float* Qs = (float*)(base + w.qs);
-  float* ms = (float*)(base + w.ms);
-  float* gq = (float*)(base + w.gq);
-  float* gm = (float*)(base + w.gm);
-  float* part = (float*)(base + w.part);
-  const int64_t nl = N * n_labels;
-  const int T = 256;
-  // forward, keeping the marginals and the messages of every update
-  k_softmax<<<grid_of(N, T), T, 0, s>>>(d_unary, nullptr, 0.0f, N, n_labels, Qs);
-  for (int it = 1; it <= iters; ++it) {
-    float* m = ms + (it - 1) * nl;
-    if ((rc = lat_filter(L, Qs + (it - 1) * nl, n_labels, m, s))) return rc;
-    k_softmax_compat<<<grid_of(N, T), T, 0, s>>>(d_unary, m, d_compat, N, n_labels, Qs + it * nl);
-  }
-  k_fill_zero<<<grid_of(nl, T), T, 0, s>>>(d_g_unary, nl);
-  const int LL = n_labels * n_labels;
-  k_fill_zero<<<grid_of(LL, T), T, 0, s>>>(d_g_compat, LL);
-  const int64_t nblk = (N + kMfT - 1) / kMfT;
-  const float* gin = d_gQ;
-  for (int it = iters; it >= 1; --it) {
-    k_mf_bwd<true><<<nblk, kMfT, 0, s>>>(Qs + it * nl, gin, ms + (it - 1) * nl, d_compat, N,
-                                         n_labels, d_g_unary, gm, part);
-    k_mf_reduce<<<LL, kMfRed, 0, s>>>(part, nblk, LL, d_g_compat);
-    if ((rc = lat_filter(L, gm, n_labels, gq, s, true))) return rc;
-    gin = gq;
-  }
-  k_mf_bwd<false><<<nblk, kMfT, 0, s>>>(Qs, gin, nullptr, d_compat, N, n_labels, d_g_unary,
-                                        nullptr, nullptr);
-  SG_HIP_CHECK(hipGetLastError());
-  return SG_OK;
+  if (ranges_overlap(d_ws, w.total, d_gQ, (size_t)L->N * n_labels * sizeof(float)))
+    return fail(SG_EINVAL, "d_g_unary and d_ws must not overlap d_gQ");
+  return mf_backward_run(L, d_unary, n_labels, d_compat, iters, d_gQ, d_g_unary, d_g_compat,
+                         (char*)d_ws, (hipStream_t)stream);
+}
+
+size_t sg_crf_meanfield_compat_backward_noalloc_max_bytes(void) { return kMfScratchBytes; }
+
+int sg_crf_meanfield_compat_backward_noalloc(const sg_lattice* L, const float* d_unary,
+                                             int32_t n_labels, const float* d_compat,
+                                             int32_t iters, const float* d_gQ, float* d_g_unary,
+                                             float* d_g_compat, sg_stream stream) {
+  int rc = mf_backward_check(L, d_unary, n_labels, d_compat, iters, d_gQ, d_g_unary, d_g_compat);
+  if (rc) return rc;
+  const MfWs w = mf_ws(L->N, n_labels, iters);
+  if (w.total > kMfScratchBytes)
+    return fail(SG_EINVAL, "n_points * n_labels * (2 iters + 3) floats plus the partial sums "
+                           "exceed the library's fixed scratch of " +
+                               std::to_string(kMfScratchBytes) + " bytes (" +
+                               std::to_string(w.total) + " needed); use "
+                               "sg_crf_meanfield_compat_backward with a caller workspace");
+  int dev = -1;
+  SG_HIP_CHECK(hipGetDevice(&dev));
+  if (dev != L->device)
+    return fail(SG_EINVAL, "the lattice's device must be the current device");
+  char* base = nullptr;
+  if ((rc = mf_scratch(dev, &base))) return rc;
+  return mf_backward_run(L, d_unary, n_labels, d_compat, iters, d_gQ, d_g_unary, d_g_compat,
+                         base, (hipStream_t)stream);
 }
 
 int sg_crf_label_loss(const float* d_logits, int64_t ld_logits, const float* d_Q, int64_t n,
