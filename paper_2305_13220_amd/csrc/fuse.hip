@@ -142,28 +142,48 @@ __global__ __launch_bounds__(512) void k_denoise(GridView g, const int32_t* __re
   for (int ch = 0; ch < V; ++ch) o[ch] = acc[ch] * inv;
 }
 
-// The same blur through an LDS tile (radius <= kTileR): the block and its
-// halo, (8 + 2 radius)^3 voxels, four channels at a time, loaded once with
-// consecutive lanes on consecutive voxels, together with an allocated flag;
-// each lane then sums its neighbourhood from LDS.  The weights are taken
-// from a small LDS table.  Results equal k_denoise's up to summation order.
+// The same blur, separably, through an LDS tile (radius <= kTileR).  The
+// Gaussian weight of an offset is the product of three 1-D weights, and the
+// two sums of the renormalised blur, of m theta and of the allocation mask
+// m, are both convolutions with it: each is taken as three 1-D passes.  The
+// tile holds the block and its halo, side^3 voxels (side = 8 + 2 radius),
+// four channels at a time (one 16-byte load per voxel when 1 + C is a
+// multiple of four, with consecutive lanes on consecutive voxels); the x
+// pass reduces it to an (8, side, side) slab, the y pass to (8, 8, side)
+// (written over the tile), the z pass to the block's 512 voxels, one per
+// lane.  The mask is filtered the same way once, before the channels.
+// `vec`: both arrays are 16-byte aligned, so a voxel's channels c0..c0+3 are
+// one 16-byte access when 1 + C is a multiple of four.
+// Results equal k_denoise's up to rounding order.
 constexpr int kTileR = 2;
-constexpr int kTileSide = 8 + 2 * kTileR;
-constexpr int kTileMax = kTileSide * kTileSide * kTileSide;
+
+__host__ __device__ constexpr int denoise_side(int radius) { return 8 + 2 * radius; }
+
+// LDS bytes of the separable kernel: the tile (side^3) and the slab of the
+// x pass (8 side^2), float4 each.
+static size_t denoise_lds_bytes(int radius) {
+  const size_t side = (size_t)denoise_side(radius);
+  return (side * side * side + 8 * side * side) * sizeof(float4);
+}
 
 template <int C>
-__global__ __launch_bounds__(512) void k_denoise_tile(GridView g, const int32_t* __restrict__ coords,
-                                                      const float* __restrict__ vox, int32_t radius,
-                                                      float inv_2s2, float* __restrict__ out) {
+__global__ __launch_bounds__(512) void k_denoise_sep(GridView g, const int32_t* __restrict__ coords,
+                                                     const float* __restrict__ vox, int32_t radius,
+                                                     float inv_2s2, float* __restrict__ out,
+                                                     bool vec) {
   constexpr int V = 1 + C;
+  extern __shared__ float4 lds4[];
   __shared__ int32_t nb[27];
-  __shared__ float4 tile[kTileMax];
-  __shared__ float present[kTileMax];
-  __shared__ float wtab[(2 * kTileR + 1) * (2 * kTileR + 1) * (2 * kTileR + 1)];
+  __shared__ float w1[2 * kTileR + 1];
   const int64_t b = blockIdx.x;
   const int t = threadIdx.x;
+  const int side = denoise_side(radius), kw = 2 * radius + 1;
+  const int n_tile = side * side * side, n_x = 8 * side * side, n_y = 64 * side;
+  float4* A = lds4;           // tile, then the y pass
+  float4* B = lds4 + n_tile;  // x pass
+  float* Am = reinterpret_cast<float*>(A);
+  float* Bm = reinterpret_cast<float*>(B);
   const int32_t bc[3] = {coords[3 * b], coords[3 * b + 1], coords[3 * b + 2]};
-  const int side = 8 + 2 * radius, n_tile = side * side * side, kw = 2 * radius + 1;
   if (t < 27) {
     const int32_t x = bc[0] + t % 3 - 1, y = bc[1] + (t / 3) % 3 - 1, z = bc[2] + t / 9 - 1;
     int32_t idx = -1, nm = 0, dist = 0;
@@ -172,52 +192,104 @@ __global__ __launch_bounds__(512) void k_denoise_tile(GridView g, const int32_t*
       block_state(g, x, y, z, idx, nm, dist);
     nb[t] = idx;
   }
-  if (t < kw * kw * kw) {
-    const int dx = t % kw - radius, dy = (t / kw) % kw - radius, dz = t / (kw * kw) - radius;
-    wtab[t] = expf(-(float)(dx * dx + dy * dy + dz * dz) * inv_2s2);
+  if (t < kw) {
+    const int d = t - radius;
+    w1[t] = expf(-(float)(d * d) * inv_2s2);
   }
   __syncthreads();
-  const int l[3] = {t & 7, (t >> 3) & 7, t >> 6};
+  // Block index of tile voxel e ((x, y, z), x fastest, at offset -radius) and
+  // the element offset of that voxel, or -1 where its block is absent.
+  auto tile_voxel = [&](int e) -> int64_t {
+    const int x = e % side - radius, y = (e / side) % side - radius, z = e / (side * side) - radius;
+    const int32_t n = nb[((x >> 3) + 1) + 3 * ((y >> 3) + 1) + 9 * ((z >> 3) + 1)];
+    return n < 0 ? -1 : (int64_t)n * SG_BLOCK_VOXELS + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
+  };
+  const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+  // The mask: tile, x, y and z passes; wsum > 0 (the voxel itself is allocated).
+  for (int e = t; e < n_tile; e += 512) Am[e] = tile_voxel(e) >= 0 ? 1.0f : 0.0f;
+  __syncthreads();
+  for (int e = t; e < n_x; e += 512) {
+    const int xo = e & 7, yz = e >> 3;
+    float a = 0.0f;
+    for (int i = 0; i < kw; ++i) a += w1[i] * Am[xo + i + side * yz];
+    Bm[e] = a;
+  }
+  __syncthreads();
+  for (int e = t; e < n_y; e += 512) {
+    const int xo = e & 7, yo = (e >> 3) & 7, z = e >> 6;
+    float a = 0.0f;
+    for (int i = 0; i < kw; ++i) a += w1[i] * Bm[xo + 8 * ((yo + i) + side * z)];
+    Am[e] = a;
+  }
+  __syncthreads();
+  float wsum = 0.0f;
+  for (int i = 0; i < kw; ++i) wsum += w1[i] * Am[lx + 8 * (ly + 8 * (lz + i))];
+  const float inv = 1.0f / wsum;
   float* o = out + (b * SG_BLOCK_VOXELS + t) * V;
   for (int c0 = 0; c0 < V; c0 += 4) {
+    __syncthreads();  // the previous passes' reads of A are done
     for (int e = t; e < n_tile; e += 512) {
-      // tile voxel e = (x, y, z), x fastest, at voxel offset -radius
-      const int x = e % side - radius, y = (e / side) % side - radius, z = e / (side * side) - radius;
-      const int ox = (x >> 3) + 1, oy = (y >> 3) + 1, oz = (z >> 3) + 1;
-      const int32_t n = nb[ox + 3 * oy + 9 * oz];
+      const int64_t off = tile_voxel(e);
       float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (n >= 0) {
-        const float* th = vox + ((int64_t)n * SG_BLOCK_VOXELS + (x & 7) + 8 * (y & 7) + 64 * (z & 7)) * V;
-        v.x = th[c0];
-        if (c0 + 1 < V) v.y = th[c0 + 1];
-        if (c0 + 2 < V) v.z = th[c0 + 2];
-        if (c0 + 3 < V) v.w = th[c0 + 3];
+      if (off >= 0) {
+        const float* th = vox + off * V + c0;
+        if (V % 4 == 0 && vec) {
+          v = *reinterpret_cast<const float4*>(th);
+        } else {
+          v.x = th[0];
+          if (c0 + 1 < V) v.y = th[1];
+          if (c0 + 2 < V) v.z = th[2];
+          if (c0 + 3 < V) v.w = th[3];
+        }
       }
-      tile[e] = v;
-      present[e] = n >= 0 ? 1.0f : 0.0f;
+      A[e] = v;
     }
     __syncthreads();
-    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float wsum = 0.0f;
-    int wi = 0;
-    for (int dz = 0; dz < kw; ++dz)
-      for (int dy = 0; dy < kw; ++dy)
-        for (int dx = 0; dx < kw; ++dx, ++wi) {
-          const int e = (l[0] + dx) + side * ((l[1] + dy) + side * (l[2] + dz));
-          const float w = wtab[wi] * present[e];
-          const float4 v = tile[e];
-          acc.x += w * v.x;
-          acc.y += w * v.y;
-          acc.z += w * v.z;
-          acc.w += w * v.w;
-          wsum += w;
-        }
-    const float inv = 1.0f / wsum;  // > 0: the voxel itself is allocated
-    o[c0] = acc.x * inv;
-    if (c0 + 1 < V) o[c0 + 1] = acc.y * inv;
-    if (c0 + 2 < V) o[c0 + 2] = acc.z * inv;
-    if (c0 + 3 < V) o[c0 + 3] = acc.w * inv;
-    __syncthreads();  // the tile is reloaded for the next channels
+    for (int e = t; e < n_x; e += 512) {
+      const int xo = e & 7, yz = e >> 3;
+      float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int i = 0; i < kw; ++i) {
+        const float w = w1[i];
+        const float4 v = A[xo + i + side * yz];
+        a.x += w * v.x;
+        a.y += w * v.y;
+        a.z += w * v.z;
+        a.w += w * v.w;
+      }
+      B[e] = a;
+    }
+    __syncthreads();
+    for (int e = t; e < n_y; e += 512) {
+      const int xo = e & 7, yo = (e >> 3) & 7, z = e >> 6;
+      float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int i = 0; i < kw; ++i) {
+        const float w = w1[i];
+        const float4 v = B[xo + 8 * ((yo + i) + side * z)];
+        a.x += w * v.x;
+        a.y += w * v.y;
+        a.z += w * v.z;
+        a.w += w * v.w;
+      }
+      A[e] = a;
+    }
+    __syncthreads();
+    float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int i = 0; i < kw; ++i) {
+      const float w = w1[i];
+      const float4 v = A[lx + 8 * (ly + 8 * (lz + i))];
+      a.x += w * v.x;
+      a.y += w * v.y;
+      a.z += w * v.z;
+      a.w += w * v.w;
+    }
+    if (V % 4 == 0 && vec) {
+      *reinterpret_cast<float4*>(o + c0) = make_float4(a.x * inv, a.y * inv, a.z * inv, a.w * inv);
+    } else {
+      o[c0] = a.x * inv;
+      if (c0 + 1 < V) o[c0 + 1] = a.y * inv;
+      if (c0 + 2 < V) o[c0 + 2] = a.z * inv;
+      if (c0 + 3 < V) o[c0 + 3] = a.w * inv;
+    }
   }
 }
 
@@ -287,13 +359,16 @@ int sg_denoise(const sg_grid* grid, const float* d_vox, int32_t C, int32_t radiu
   if (grid->n_blocks > INT_MAX) return fail(SG_EINVAL, "too many blocks for one launch");
   const GridView g = view_of(grid);
   const float inv_2s2 = (float)(1.0 / (2.0 * (double)sigma * (double)sigma));
+  const bool vec = reinterpret_cast<uintptr_t>(d_vox) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(d_out) % 16 == 0;
   hipStream_t s = (hipStream_t)stream;
   switch (C) {
 #define SG_DENOISE_CASE(CC)                                                                 \
   case CC:                                                                                  \
     if (radius <= kTileR)                                                                   \
-      hipLaunchKernelGGL(k_denoise_tile<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, \
-                         g, grid->d_coords, d_vox, radius, inv_2s2, d_out);                 \
+      hipLaunchKernelGGL(k_denoise_sep<CC>, dim3((unsigned)grid->n_blocks), dim3(512),      \
+                         denoise_lds_bytes(radius), s, g, grid->d_coords, d_vox, radius,    \
+                         inv_2s2, d_out, vec);                                              \
     else                                                                                    \
       hipLaunchKernelGGL(k_denoise<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, g,  \
                          grid->d_coords, d_vox, radius, inv_2s2, d_out);                    \

@@ -994,16 +994,25 @@ __global__ __launch_bounds__(256) void k_query_backward(GridView g, const float*
 // (likewise for y and z).  Where |g| = 0 the direction is undefined and
 // nothing is scattered.  V = 1 + C floats per voxel; only the SDF channel is
 // read and written.
+// The scatter runs with lanes laid out (point, x corner): lanes 2j and
+// 2j + 1 add the two x-neighbouring corners of one row of cell j of a half
+// wave, so one atomic instruction covers the same row of 32 cells, which
+// along a lattice or a batch of nearby points mostly share 64-byte pieces
+// (float atomics on device memory are performed past the L2, one request
+// per piece an instruction touches).
 __global__ __launch_bounds__(256) void k_eikonal(GridView g, const float* __restrict__ vox,
                                                  int32_t V, const float* __restrict__ pts,
                                                  int64_t m, float weight,
                                                  float* __restrict__ loss_out,
                                                  float* __restrict__ grad_vox) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
   Cell cell;
   float l = 0.0f;
-  if (point_cell(g, pts + 3 * q, cell)) {
+  float d[8];
+  bool scatter = false;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) d[a] = 0.0f;
+  if (q < m && point_cell(g, pts + 3 * q, cell)) {
     const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
                 wz[2] = {1.0f - cell.u[2], cell.u[2]};
     float sdf[8];
@@ -1024,11 +1033,9 @@ __global__ __launch_bounds__(256) void k_eikonal(GridView g, const float* __rest
     const float n = sqrtf(gx * gx + gy * gy + gz * gz);
     l = weight * (n - 1.0f) * (n - 1.0f);
     if (grad_vox && n > 0.0f) {
+      scatter = true;
       const float coef = weight * 2.0f * (n - 1.0f) / n * g.inv_h;
       const float ax = coef * gx, ay = coef * gy, az = coef * gz;
-      float d[8];
-#pragma unroll
-      for (int a = 0; a < 8; ++a) d[a] = 0.0f;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int lo = e & 1, hi = e >> 1;
@@ -1041,11 +1048,25 @@ __global__ __launch_bounds__(256) void k_eikonal(GridView g, const float* __rest
         d[c0z | 4] += ez;
         d[c0z] -= ez;
       }
-#pragma unroll
-      for (int a = 0; a < 8; ++a) unsafeAtomicAdd(grad_vox + (int64_t)cell.off[a] * V, d[a]);
     }
   }
-  if (loss_out) loss_out[q] = l;
+  if (q < m && loss_out) loss_out[q] = l;
+  if (!grad_vox) return;  // uniform over the launch
+  int32_t off[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) off[a] = scatter ? cell.off[a] : -1;
+  const int lane = lane_id(), ax = lane & 1;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int src = half * (kWave / 2) + (lane >> 1);
+#pragma unroll
+    for (int row = 0; row < 4; ++row) {
+      const float v0 = shfl(d[2 * row], src), v1 = shfl(d[2 * row + 1], src);
+      const int o0 = shfl(off[2 * row], src), o1 = shfl(off[2 * row + 1], src);
+      const int o = ax ? o1 : o0;
+      if (o >= 0) unsafeAtomicAdd(grad_vox + (int64_t)o * V, ax ? v1 : v0);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1056,36 +1077,54 @@ struct SampleState {
 
 // Scatter of the adjoint into grad_vox.  Float atomics on device memory are
 // performed past the L2 (each XCD has its own L2), one request per 64-byte
-// piece of memory that an instruction touches, so the number of distinct
-// pieces per instruction is what costs.
+// piece of memory that an instruction touches, so the corner terms of a
+// chunk of samples are first summed per voxel and each voxel then gets one
+// atomic add per channel, with lanes laid out (voxel, channel).
 //
-// Per-wave LDS staging of one chunk's scatter.  During staging and merging
-// the arrays are column-major (entry [j][lane]: 64 lanes write 64
-// consecutive words); the merged sums are then compacted, row-major by head
-// rank, into the same memory for the scatter.
-struct BwdScratch {
-  float val[16 * kWave];   // SDF-gradient term of corners 0..7, then w * r_a
-  int32_t off[8 * kWave];  // element offsets of the 8 corners
-  int32_t key[kWave];      // cell id (offset of corner 0), unique negative if unused
-  float gC[32];            // upstream feature gradient of the ray
+// Per voxel, without atomics in LDS: the samples of a chunk form a monotone
+// path of cells (each coordinate of the base voxel is monotone along the
+// ray), so the cells holding a voxel as a corner are consecutive lanes.  The
+// first of them owns the voxel (it is not a corner of the previous lane's
+// cell); the owners' (lane, corner) pairs are listed with a prefix sum, and
+// each listed voxel is summed by one lane walking forward from its owner
+// while the voxel stays a corner of the lane's cell.
+struct Scat {
+  float val[16 * kWave];    // [a][lane]: SDF term of corner a, then w r_a at [8 + a][lane]
+  int32_t off[8 * kWave];   // [a][lane]: element offset of corner a
+  int4 base[kWave];         // base voxel of the lane's cell; w = 1 if the lane holds a sample
+  uint16_t pair[8 * kWave]; // owned (lane, corner) pairs, lane * 8 + a
+  int32_t e_off[kWave];     // emission staging: element offset and the two sums of 64 voxels
+  float e_vs[kWave];
+  float e_vw[kWave];
+  float gC[32];             // upstream feature gradient of the ray
 };
+
+// Bits a = ax + 2 ay + 4 az of the corners of a cell with base b that are
+// also corners of the cell with base b - d: per axis, d = 0 shares both
+// corners, d = 1 the lower, d = -1 the upper, anything else none.
+__device__ __forceinline__ int shared_corners(int dx, int dy, int dz) {
+  auto axis = [](int d, int lo, int hi) {
+    return (d == 0 ? (lo | hi) : 0) | (d == 1 ? lo : 0) | (d == -1 ? hi : 0);
+  };
+  return axis(dx, 0x55, 0xAA) & axis(dy, 0x33, 0xCC) & axis(dz, 0x0F, 0xF0);
+}
 
 // Adjoint scatter of one chunk.  Lane holds a sample (act) with its cell,
 // weight w, dL/df and gA = dL/d(grad f) of the sample (w g_N from the normal
 // output, plus the Eikonal term where it is on); the per-corner terms
 //   dL/dtheta_d[a] += r_a dL/df + (dr_a/du . gA) / h      (Eq. 17-18)
 //   dL/dtheta_c[a] += w r_a g_C
-// are staged in LDS, runs of lanes in one cell are merged (positions are
-// monotone per axis, so a cell's samples are adjacent in either lane
-// order), and the sums are added to grad_vox with lanes laid out as (cell,
-// corner, channel) so that each atomic instruction covers few lines.
+// are summed per voxel and added to grad_vox.  The samples may be in ray
+// order or in reverse order along the lanes.
 template <int C>
-__device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Cell& cell, float w,
+__device__ __forceinline__ void scatter_chunk(Scat* sc, bool act, const Cell& cell, float w,
                                               float df, const float gA[3], float inv_h,
                                               const March& m, float* __restrict__ grad_vox) {
   constexpr int V = 1 + C;
   const int lane = lane_id();
-  int key = -1 - lane;
+  int bi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) bi[a] = (int32_t)floorf(lattice_x(m.ov[a], m.dv[a], cell.t));
   if (act) {
     const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
                 wz[2] = {1.0f - cell.u[2], cell.u[2]};
@@ -1094,125 +1133,63 @@ __device__ __forceinline__ void scatter_chunk(BwdScratch* sc, bool act, const Ce
     for (int a = 0; a < 8; ++a) {
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       const float ra = wx[ax] * wy[ay] * wz[az];
-      const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gx +
-                       (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gy +
-                       (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gz;
-      sc->val[a * kWave + lane] = ra * df + gn;
+      sc->val[a * kWave + lane] = ra * df + (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gx +
+                                  (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gy +
+                                  (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gz;
       sc->val[(8 + a) * kWave + lane] = w * ra;
       sc->off[a * kWave + lane] = cell.off[a];
     }
-    key = cell.off[0];
   }
-  sc->key[lane] = key;
-  const int kp = shfl(key, lane > 0 ? lane - 1 : 0);
-  const bool head = act && (lane == 0 || kp != key);
-  const uint64_t hm = __ballot(head);
-  const int H = (int)__popcll(hm);
+  sc->base[lane] = make_int4(bi[0], bi[1], bi[2], act ? 1 : 0);
   wave_sync();
-  // merge each run into its first lane
-  float mv[16];
-  int32_t mo[8];
-  if (head) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) mv[j] = sc->val[j * kWave + lane];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) mo[a] = sc->off[a * kWave + lane];
-    for (int l2 = lane + 1; l2 < kWave && sc->key[l2] == key; ++l2) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) mv[j] += sc->val[j * kWave + l2];
+  // owned corners: not corners of the previous lane's cell
+  int owned = 0;
+  if (act) {
+    owned = 0xFF;
+    if (lane > 0) {
+      const int4 bp = sc->base[lane - 1];
+      if (bp.w) owned &= ~shared_corners(bi[0] - bp.x, bi[1] - bp.y, bi[2] - bp.z);
     }
   }
-  // Base voxel of each cell, relative to the first cell of the chunk and
-  // packed 10 bits per axis (-1: too far to pack; such a cell shares no
-  // corner in the merge below, which is always correct).
-  int packed = -1;
-  {
-    int32_t i[3];
+  const int cnt = __popc(owned);
+  const int incl = (int)wave_inclusive_sum((float)cnt);  // exact: at most 512
+  const int n_own = __builtin_amdgcn_readlane(incl, kWave - 1);
+  int at = incl - cnt;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) i[a] = (int32_t)floorf(lattice_x(m.ov[a], m.dv[a], cell.t));
-    const int first = hm ? __builtin_ctzll(hm) : 0;
-    bool fits = head;
-    int32_t d[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      d[a] = i[a] - __builtin_amdgcn_readlane(i[a], first);
-      fits = fits && d[a] > -511 && d[a] < 511;
-    }
-    if (fits) packed = ((d[0] + 512) << 20) | ((d[1] + 512) << 10) | (d[2] + 512);
+  for (int a = 0; a < 8; ++a) {
+    if ((owned >> a) & 1) sc->pair[at++] = (uint16_t)(lane * 8 + a);
   }
   wave_sync();
-  // compact: row-major by head rank (all staged reads are done)
-  if (head) {
-    const int rk = rank_below(hm);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) sc->val[rk * 16 + j] = mv[j];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) sc->off[rk * 8 + a] = mo[a];
-    sc->key[rk] = packed;
-  }
-  wave_sync();
-  // Consecutive cells along a ray share corners.  The cells holding one
-  // voxel are consecutive (each coordinate of the base voxel is monotone
-  // along the ray), at most four.  The first of them takes the sums of the
-  // others (at most three cells on), the others drop that corner, so each
-  // voxel gets one atomic add per chunk.
-  if (lane < H) {
-    float tv[16];
-    bool own[8];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) tv[j] = sc->val[lane * 16 + j];
-    const int pc = sc->key[lane];
-    const int pp = lane > 0 ? sc->key[lane - 1] : -1;
-    int pn[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pn[k] = lane + 1 + k < H ? sc->key[lane + 1 + k] : -1;
-    const int cx = pc >> 20, cy = (pc >> 10) & 1023, cz = pc & 1023;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int vx = cx + (a & 1), vy = cy + ((a >> 1) & 1), vz = cz + (a >> 2);
-      // corner index of voxel v in the cell packed as q, or -1
-      auto corner_in = [&](int q) {
-        if (pc < 0 || q < 0) return -1;
-        const int dx = vx - (q >> 20), dy = vy - ((q >> 10) & 1023), dz = vz - (q & 1023);
-        return ((unsigned)dx | (unsigned)dy | (unsigned)dz) <= 1u ? dx + 2 * dy + 4 * dz : -1;
-      };
-      own[a] = corner_in(pp) < 0;
-      if (own[a]) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int b = corner_in(pn[k]);
-          if (b < 0) break;
-          tv[a] += sc->val[(lane + 1 + k) * 16 + b];
-          tv[8 + a] += sc->val[(lane + 1 + k) * 16 + 8 + b];
-        }
+  for (int e0 = 0; e0 < n_own; e0 += kWave) {
+    const int e = e0 + lane;
+    if (e < n_own) {
+      const int pr = sc->pair[e];
+      const int j = pr >> 3, a = pr & 7;
+      const int4 bj = sc->base[j];
+      const int cx = bj.x + (a & 1), cy = bj.y + ((a >> 1) & 1), cz = bj.z + (a >> 2);
+      float vs = 0.0f, vw = 0.0f;
+      for (int k = j; k < kWave; ++k) {
+        const int4 bk = sc->base[k];
+        const unsigned dx = (unsigned)(cx - bk.x), dy = (unsigned)(cy - bk.y),
+                       dz = (unsigned)(cz - bk.z);
+        if (!bk.w || (dx | dy | dz) > 1u) break;
+        const int ak = (int)(dx + 2 * dy + 4 * dz);
+        vs += sc->val[ak * kWave + k];
+        vw += sc->val[(8 + ak) * kWave + k];
       }
+      sc->e_off[lane] = sc->off[a * kWave + j];
+      sc->e_vs[lane] = vs;
+      sc->e_vw[lane] = vw;
     }
     wave_sync();
-#pragma unroll
-    for (int j = 0; j < 16; ++j) sc->val[lane * 16 + j] = tv[j];
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-      if (!own[a]) sc->off[lane * 8 + a] = -1;
-  } else {
+    const int n_e = min(kWave, n_own - e0);
+    for (int f = lane; f < n_e * V; f += kWave) {
+      const int i = f / V, ch = f - i * V;
+      const float v = ch == 0 ? sc->e_vs[i] : sc->e_vw[i] * sc->gC[ch > 0 ? ch - 1 : 0];
+      unsafeAtomicAdd(grad_vox + (int64_t)sc->e_off[i] * V + ch, v);
+    }
     wave_sync();
   }
-  wave_sync();
-  // Lanes laid out (row, cell, x corner, channel): an instruction covers the
-  // same row of corners (fixed y and z offsets) of consecutive cells, which
-  // along a ray mostly fall in the same or neighbouring 64-byte pieces.
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    for (int idx = lane; idx < H * 2 * V; idx += kWave) {
-      const int hh = idx / (2 * V), e = idx - hh * (2 * V);
-      const int ax = e / V, ch = e - ax * V;
-      const int a = ax + 2 * t;
-      const float v = sc->val[hh * 16 + (ch == 0 ? a : 8 + a)];
-      const float mult = ch == 0 ? 1.0f : sc->gC[ch > 0 ? ch - 1 : 0];
-      const int32_t o = sc->off[hh * 8 + a];
-      if (o >= 0) unsafeAtomicAdd(grad_vox + (int64_t)o * V + ch, v * mult);
-    }
-  }
-  wave_sync();  // the staging arrays are rewritten by the next chunk
 }
 
 // Sum over lanes m > l of v_m (lane order), without cancellation: the wave
@@ -1275,7 +1252,7 @@ __device__ __forceinline__ void load_ray_inputs(int64_t r, const float* __restri
 // Stage the ray's upstream feature gradient in LDS for the scatter
 // (selects: a dynamic index into a register array would go to scratch).
 template <int C>
-__device__ __forceinline__ void stage_gC(const Upstream<C>& up, BwdScratch* sc) {
+__device__ __forceinline__ void stage_gC(const Upstream<C>& up, Scat* sc) {
   const int lane = lane_id();
   float mine = 0.0f;
 #pragma unroll
@@ -1290,7 +1267,7 @@ __device__ __forceinline__ void write_outputs_and_l2_grad(
     int64_t r, int64_t R, int n, float accC[C > 0 ? C : 1], float accD, float accN[3], float accW,
     float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
     float* __restrict__ wsum, int32_t* __restrict__ nsamples, const L2Ref& ref,
-    const Upstream<C>& refv, Upstream<C>& up, BwdScratch* sc, float eik) {
+    const Upstream<C>& refv, Upstream<C>& up, Scat* sc, float eik) {
   const int lane = lane_id();
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
@@ -1351,8 +1328,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   int2* const q = lds_q + (int64_t)w * p.max_samples;
   SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples);
   SampleState* st = st_base + (int64_t)w * p.max_samples;
-  BwdScratch* sc_base = reinterpret_cast<BwdScratch*>(st_base + (int64_t)wpb * p.max_samples);
-  BwdScratch* sc = sc_base + w;
+  Scat* sc_base = reinterpret_cast<Scat*>(st_base + (int64_t)wpb * p.max_samples);
+  Scat* sc = sc_base + w;
   // Fused multi-chunk rays: t, grad f and features of every sample, kept
   // from pass 1 for pass 2 (structure of arrays [4 + C][max_samples]) when
   // the launch has the room; otherwise pass 2 interpolates again.
@@ -1804,7 +1781,7 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   bool list;
   if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
   const Launch l =
-      plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch));
+      plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(Scat));
   const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f, nullptr};
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, true>), dim3(l.blocks),
@@ -1846,12 +1823,12 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   bool list;
   if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
   // Per-wave LDS: sample queue, per-sample state, scatter staging, and (when
-  // a wave's LDS then stays within 16 KiB, so that a CU's LDS still holds the
-  // waves its registers allow) the values pass 2 reuses.
+  // the 12 waves a CU's registers allow, three per SIMD, still fit its
+  // 160 KiB of LDS with them) the values pass 2 reuses.
   const size_t base =
-      (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(BwdScratch);
+      (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(Scat);
   const size_t vbytes = sizeof(float) * (size_t)(4 + C) * p.max_samples;
-  const bool keep_v = (base + vbytes) * 4 <= 64 * 1024;
+  const bool keep_v = (base + vbytes) * 12 <= 160 * 1024;
   const Launch l = plan(n_rays, base + (keep_v ? vbytes : 0));
   const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, lambda_e,
                      d_loss_ray};
