@@ -147,42 +147,72 @@ __global__ __launch_bounds__(512) void k_denoise(GridView g, const int32_t* __re
 // two sums of the renormalised blur, of m theta and of the allocation mask
 // m, are both convolutions with it: each is taken as three 1-D passes.  The
 // tile holds the block and its halo, side^3 voxels (side = 8 + 2 radius),
-// four channels at a time (one 16-byte load per voxel when 1 + C is a
-// multiple of four, with consecutive lanes on consecutive voxels); the x
-// pass reduces it to an (8, side, side) slab, the y pass to (8, 8, side)
-// (written over the tile), the z pass to the block's 512 voxels, one per
-// lane.  The mask is filtered the same way once, before the channels.
-// `vec`: both arrays are 16-byte aligned, so a voxel's channels c0..c0+3 are
-// one 16-byte access when 1 + C is a multiple of four.
-// Results equal k_denoise's up to rounding order.
+// G channels at a time (all of a voxel's channels when they fit, so that a
+// voxel's contiguous record is read once, with consecutive lanes on
+// consecutive floats); each pass runs in place, one lane per line of the
+// tile and channel: along x over side^2 lines, along y over 8 side (the x
+// range left by the first pass), and along z over the block's 8 x 8 columns,
+// which write the output.  The mask goes through the same passes once, and
+// each voxel's weight sum is kept for the renormalisation.  Results equal
+// k_denoise's up to rounding order.
 constexpr int kTileR = 2;
 
 __host__ __device__ constexpr int denoise_side(int radius) { return 8 + 2 * radius; }
 
-// LDS bytes of the separable kernel: the tile (side^3) and the slab of the
-// x pass (8 side^2), float4 each.
-static size_t denoise_lds_bytes(int radius) {
-  const size_t side = (size_t)denoise_side(radius);
-  return (side * side * side + 8 * side * side) * sizeof(float4);
+// Channels per tile pass: as many as fit a 79 KiB LDS budget (two
+// 1024-lane workgroups per CU, so that one loads while the other filters),
+// balanced over the passes, and a multiple of four when the voxel record is
+// (16-byte loads).
+constexpr int kDenoiseT = 1024;
+__host__ __device__ constexpr int denoise_group(int V, int radius) {
+  const int n3 = denoise_side(radius) * denoise_side(radius) * denoise_side(radius);
+  const int gmax = (73 * 1024) / (4 * n3);
+  const int g4 = (V % 4 == 0 && gmax >= 4) ? gmax / 4 * 4 : gmax;
+  const int passes = (V + g4 - 1) / g4;
+  const int gb = (V + passes - 1) / passes;
+  return (V % 4 == 0 && gmax >= 4) ? (gb + 3) / 4 * 4 : gb;
 }
 
-template <int C>
-__global__ __launch_bounds__(512) void k_denoise_sep(GridView g, const int32_t* __restrict__ coords,
-                                                     const float* __restrict__ vox, int32_t radius,
-                                                     float inv_2s2, float* __restrict__ out,
-                                                     bool vec) {
+template <int C, int R>
+static size_t denoise_lds_bytes() {
+  constexpr int side = denoise_side(R), n3 = side * side * side;
+  return sizeof(float) * ((size_t)n3 * denoise_group(1 + C, R) + n3 + SG_BLOCK_VOXELS);
+}
+
+// One 1-D pass of width 2R + 1 in place over a line of side values at
+// stride st: out[o] = sum_i w[i] in[o + i], o < 8.
+template <int R>
+__device__ __forceinline__ void denoise_line(float* p, int st, const float* w) {
+  constexpr int side = denoise_side(R);
+  float v[side];
+#pragma unroll
+  for (int x = 0; x < side; ++x) v[x] = p[x * st];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) a += w[i] * v[o + i];
+    p[o * st] = a;
+  }
+}
+
+template <int C, int R>
+__global__ __launch_bounds__(kDenoiseT) void k_denoise_sep(GridView g,
+                                                           const int32_t* __restrict__ coords,
+                                                           const float* __restrict__ vox,
+                                                           float inv_2s2, float* __restrict__ out,
+                                                           bool vec) {
   constexpr int V = 1 + C;
-  extern __shared__ float4 lds4[];
+  constexpr int side = denoise_side(R), n2 = side * side, n3 = n2 * side;
+  constexpr int G = denoise_group(V, R);
+  extern __shared__ float lds[];
+  float* tile = lds;               // [n3][G]: voxel (x, y, z) at x + side (y + side z)
+  float* mk = lds + n3 * G;        // [n3] the mask, then its passes
+  float* inv = mk + n3;            // [512] 1 / weight sum of each voxel of the block
   __shared__ int32_t nb[27];
-  __shared__ float w1[2 * kTileR + 1];
+  __shared__ float w1[2 * R + 1];
   const int64_t b = blockIdx.x;
   const int t = threadIdx.x;
-  const int side = denoise_side(radius), kw = 2 * radius + 1;
-  const int n_tile = side * side * side, n_x = 8 * side * side, n_y = 64 * side;
-  float4* A = lds4;           // tile, then the y pass
-  float4* B = lds4 + n_tile;  // x pass
-  float* Am = reinterpret_cast<float*>(A);
-  float* Bm = reinterpret_cast<float*>(B);
   const int32_t bc[3] = {coords[3 * b], coords[3 * b + 1], coords[3 * b + 2]};
   if (t < 27) {
     const int32_t x = bc[0] + t % 3 - 1, y = bc[1] + (t / 3) % 3 - 1, z = bc[2] + t / 9 - 1;
@@ -192,103 +222,75 @@ __global__ __launch_bounds__(512) void k_denoise_sep(GridView g, const int32_t* 
       block_state(g, x, y, z, idx, nm, dist);
     nb[t] = idx;
   }
-  if (t < kw) {
-    const int d = t - radius;
+  if (t <= 2 * R) {
+    const int d = t - R;
     w1[t] = expf(-(float)(d * d) * inv_2s2);
   }
   __syncthreads();
-  // Block index of tile voxel e ((x, y, z), x fastest, at offset -radius) and
-  // the element offset of that voxel, or -1 where its block is absent.
+  // element offset of tile voxel e (at voxel offset -R), or -1 where its block is absent
   auto tile_voxel = [&](int e) -> int64_t {
-    const int x = e % side - radius, y = (e / side) % side - radius, z = e / (side * side) - radius;
+    const int x = e % side - R, y = (e / side) % side - R, z = e / n2 - R;
     const int32_t n = nb[((x >> 3) + 1) + 3 * ((y >> 3) + 1) + 9 * ((z >> 3) + 1)];
     return n < 0 ? -1 : (int64_t)n * SG_BLOCK_VOXELS + (x & 7) + 8 * (y & 7) + 64 * (z & 7);
   };
-  const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-  // The mask: tile, x, y and z passes; wsum > 0 (the voxel itself is allocated).
-  for (int e = t; e < n_tile; e += 512) Am[e] = tile_voxel(e) >= 0 ? 1.0f : 0.0f;
+  for (int e = t; e < n3; e += kDenoiseT) mk[e] = tile_voxel(e) >= 0 ? 1.0f : 0.0f;
   __syncthreads();
-  for (int e = t; e < n_x; e += 512) {
-    const int xo = e & 7, yz = e >> 3;
+  for (int l = t; l < n2; l += kDenoiseT) denoise_line<R>(mk + l * side, 1, w1);
+  __syncthreads();
+  for (int l = t; l < 8 * side; l += kDenoiseT) denoise_line<R>(mk + (l & 7) + n2 * (l >> 3), side, w1);
+  __syncthreads();
+  if (t < SG_BLOCK_VOXELS) {
+    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
     float a = 0.0f;
-    for (int i = 0; i < kw; ++i) a += w1[i] * Am[xo + i + side * yz];
-    Bm[e] = a;
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) a += w1[i] * mk[lx + side * (ly + side * (lz + i))];
+    inv[t] = 1.0f / a;  // > 0: the voxel itself is allocated
   }
-  __syncthreads();
-  for (int e = t; e < n_y; e += 512) {
-    const int xo = e & 7, yo = (e >> 3) & 7, z = e >> 6;
-    float a = 0.0f;
-    for (int i = 0; i < kw; ++i) a += w1[i] * Bm[xo + 8 * ((yo + i) + side * z)];
-    Am[e] = a;
-  }
-  __syncthreads();
-  float wsum = 0.0f;
-  for (int i = 0; i < kw; ++i) wsum += w1[i] * Am[lx + 8 * (ly + 8 * (lz + i))];
-  const float inv = 1.0f / wsum;
-  float* o = out + (b * SG_BLOCK_VOXELS + t) * V;
-  for (int c0 = 0; c0 < V; c0 += 4) {
-    __syncthreads();  // the previous passes' reads of A are done
-    for (int e = t; e < n_tile; e += 512) {
-      const int64_t off = tile_voxel(e);
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (off >= 0) {
-        const float* th = vox + off * V + c0;
-        if (V % 4 == 0 && vec) {
-          v = *reinterpret_cast<const float4*>(th);
-        } else {
-          v.x = th[0];
-          if (c0 + 1 < V) v.y = th[1];
-          if (c0 + 2 < V) v.z = th[2];
-          if (c0 + 3 < V) v.w = th[3];
-        }
+  for (int c0 = 0; c0 < V; c0 += G) {
+    const int gc = min(G, V - c0);
+    __syncthreads();  // the previous group's reads of the tile are done
+    if (V % 4 == 0 && G % 4 == 0 && vec) {
+      // 16-byte pieces of the voxel records (c0 and gc are multiples of 4)
+      const int gq = gc / 4;
+      for (int f = t; f < n3 * gq; f += kDenoiseT) {
+        const int e = f / gq, q = f - e * gq;
+        const int64_t off = tile_voxel(e);
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (off >= 0) v = *reinterpret_cast<const float4*>(vox + off * V + c0 + 4 * q);
+        *reinterpret_cast<float4*>(tile + e * G + 4 * q) = v;
       }
-      A[e] = v;
-    }
-    __syncthreads();
-    for (int e = t; e < n_x; e += 512) {
-      const int xo = e & 7, yz = e >> 3;
-      float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      for (int i = 0; i < kw; ++i) {
-        const float w = w1[i];
-        const float4 v = A[xo + i + side * yz];
-        a.x += w * v.x;
-        a.y += w * v.y;
-        a.z += w * v.z;
-        a.w += w * v.w;
-      }
-      B[e] = a;
-    }
-    __syncthreads();
-    for (int e = t; e < n_y; e += 512) {
-      const int xo = e & 7, yo = (e >> 3) & 7, z = e >> 6;
-      float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      for (int i = 0; i < kw; ++i) {
-        const float w = w1[i];
-        const float4 v = B[xo + 8 * ((yo + i) + side * z)];
-        a.x += w * v.x;
-        a.y += w * v.y;
-        a.z += w * v.z;
-        a.w += w * v.w;
-      }
-      A[e] = a;
-    }
-    __syncthreads();
-    float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int i = 0; i < kw; ++i) {
-      const float w = w1[i];
-      const float4 v = A[lx + 8 * (ly + 8 * (lz + i))];
-      a.x += w * v.x;
-      a.y += w * v.y;
-      a.z += w * v.z;
-      a.w += w * v.w;
-    }
-    if (V % 4 == 0 && vec) {
-      *reinterpret_cast<float4*>(o + c0) = make_float4(a.x * inv, a.y * inv, a.z * inv, a.w * inv);
     } else {
-      o[c0] = a.x * inv;
-      if (c0 + 1 < V) o[c0 + 1] = a.y * inv;
-      if (c0 + 2 < V) o[c0 + 2] = a.z * inv;
-      if (c0 + 3 < V) o[c0 + 3] = a.w * inv;
+      for (int f = t; f < n3 * gc; f += kDenoiseT) {
+        const int e = f / gc, j = f - e * gc;
+        const int64_t off = tile_voxel(e);
+        tile[e * G + j] = off >= 0 ? vox[off * V + c0 + j] : 0.0f;
+      }
+    }
+    __syncthreads();
+    for (int f = t; f < n2 * gc; f += kDenoiseT) {
+      const int l = f / gc, j = f - l * gc;
+      denoise_line<R>(tile + l * side * G + j, G, w1);
+    }
+    __syncthreads();
+    for (int f = t; f < 8 * side * gc; f += kDenoiseT) {
+      const int l = f / gc, j = f - l * gc;
+      denoise_line<R>(tile + ((l & 7) + n2 * (l >> 3)) * G + j, side * G, w1);
+    }
+    __syncthreads();
+    for (int f = t; f < 64 * gc; f += kDenoiseT) {
+      const int l = f / gc, j = f - l * gc;
+      const int lx = l & 7, ly = l >> 3;
+      float v[side];
+#pragma unroll
+      for (int z = 0; z < side; ++z) v[z] = tile[(lx + side * (ly + side * z)) * G + j];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        float a = 0.0f;
+#pragma unroll
+        for (int i = 0; i <= 2 * R; ++i) a += w1[i] * v[o + i];
+        const int vi = lx + 8 * ly + 64 * o;
+        out[(b * SG_BLOCK_VOXELS + vi) * V + c0 + j] = a * inv[vi];
+      }
     }
   }
 }
@@ -359,16 +361,26 @@ int sg_denoise(const sg_grid* grid, const float* d_vox, int32_t C, int32_t radiu
   if (grid->n_blocks > INT_MAX) return fail(SG_EINVAL, "too many blocks for one launch");
   const GridView g = view_of(grid);
   const float inv_2s2 = (float)(1.0 / (2.0 * (double)sigma * (double)sigma));
-  const bool vec = reinterpret_cast<uintptr_t>(d_vox) % 16 == 0 &&
-                   reinterpret_cast<uintptr_t>(d_out) % 16 == 0;
+  const bool vec = reinterpret_cast<uintptr_t>(d_vox) % 16 == 0;
+  int dev = 0, lds_max = 0;
+  SG_HIP_CHECK(hipGetDevice(&dev));
+  SG_HIP_CHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   hipStream_t s = (hipStream_t)stream;
   switch (C) {
 #define SG_DENOISE_CASE(CC)                                                                 \
   case CC:                                                                                  \
-    if (radius <= kTileR)                                                                   \
-      hipLaunchKernelGGL(k_denoise_sep<CC>, dim3((unsigned)grid->n_blocks), dim3(512),      \
-                         denoise_lds_bytes(radius), s, g, grid->d_coords, d_vox, radius,    \
-                         inv_2s2, d_out, vec);                                              \
+    if (radius == 0)                                                                        \
+      hipLaunchKernelGGL((k_denoise_sep<CC, 0>), dim3((unsigned)grid->n_blocks), dim3(kDenoiseT), \
+                         (denoise_lds_bytes<CC, 0>()), s, g, grid->d_coords, d_vox, inv_2s2,  \
+                         d_out, vec);                                                       \
+    else if (radius == 1 && (denoise_lds_bytes<CC, 1>()) <= (size_t)lds_max)         \
+      hipLaunchKernelGGL((k_denoise_sep<CC, 1>), dim3((unsigned)grid->n_blocks), dim3(kDenoiseT), \
+                         (denoise_lds_bytes<CC, 1>()), s, g, grid->d_coords, d_vox, inv_2s2,  \
+                         d_out, vec);                                                       \
+    else if (radius == 2 && (denoise_lds_bytes<CC, 2>()) <= (size_t)lds_max)         \
+      hipLaunchKernelGGL((k_denoise_sep<CC, 2>), dim3((unsigned)grid->n_blocks), dim3(kDenoiseT), \
+                         (denoise_lds_bytes<CC, 2>()), s, g, grid->d_coords, d_vox, inv_2s2,  \
+                         d_out, vec);                                                       \
     else                                                                                    \
       hipLaunchKernelGGL(k_denoise<CC>, dim3((unsigned)grid->n_blocks), dim3(512), 0, s, g,  \
                          grid->d_coords, d_vox, radius, inv_2s2, d_out);                    \

@@ -111,7 +111,7 @@ def test_fuse_invalid_arguments():
     assert empty.shape == (0, 3)
 
 
-@pytest.mark.parametrize("radius,sigma,C", [(1, 1.0, 3), (2, 0.8, 0), (1, 1.5, 19)])
+@pytest.mark.parametrize("radius,sigma,C", [(1, 1.0, 3), (2, 0.8, 0), (1, 1.5, 19), (2, 1.0, 19), (1, 1.0, 32), (0, 1.0, 19)])
 def test_denoise_matches_oracle(radius, sigma, C):
     """Gaussian de-noising (Sec. 3.4.3) within 1e-5 of sum w|theta| / sum w."""
     sg = _sg()
