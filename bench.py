@@ -436,77 +436,181 @@ def fusion_bench(dev, n_frames=10, dilate=2, reps=5, n_sem=16):
     return res
 
 
-def crf_bench(dev, n=1 << 18, n_sem=16, iters=5, reps=5):
-    """Continuous-CRF message passing (Sec. 3.5.3) on 2^18 surface samples of
-    the room: lattice build over 6-D features (xyz / 20 cm, rgb / 0.3), one
-    16-channel lattice filter, 5 mean-field updates of 16 labels (Potts, and
-    a compatibility matrix), and the gradient of the latter with respect to
-    the unaries and the matrix."""
+# Widths of the CRF's Gaussian kernels (features are divided by them): the
+# supplement fixes sigma_color = 0.1 and sigma_sdf = 1.0 (taken here for the
+# SDF-gradient, that is normal, features); the position and label-logit
+# widths are readings (5 cm, 2.5 voxels of the 2 cm grid; 1.0).
+CRF_SIGMA = {"pos": 0.05, "color": 0.1, "normal": 1.0, "label": 1.0}
+# Loss weights of the supplement's hyper-parameters.
+CRF_LAMBDA = {"color": 1e-3, "label": 0.1, "normal": 1.0}
+
+
+def crf_bench(dev, n_rays=1 << 18, n_sem=16, iters=5, reps=5, w_potts=1.0):
+    """The continuous CRF of Sec. 3.5.3 on the 2 cm room with 16 semantic
+    logits per voxel (C = 19), as one training chain:
+
+      nodes      zero crossings of the SDF along 2^18 rays from the room's 30
+                 seeded poses (sg_surface_points), the rays that hit;
+      features   sg_query at the nodes: position, RGB, grad f (the normal),
+                 16 label logits;
+      label      lattice over (position, RGB, normal) (d = 9), mean field of
+                 5 updates from the logits (unary -logits, Potts
+                 compatibility), KL label loss, lambda_label = 0.1;
+      colour     lattice over (position, normal, logits) (d = 22), RGB
+                 filtered and normalised, property loss, lambda_color = 1e-3;
+      normal     lattice over (position, RGB, logits) (d = 22), the normal
+                 filtered and normalised, property loss, lambda_normal = 1;
+      adjoint    the three losses' gradients (logits, RGB, grad f) into the
+                 voxels through sg_query_backward.
+
+    Feature scaling and concatenation are torch glue; every step of the
+    method is a library call.  The chain is timed on the host around
+    synchronisations (the lattice builds synchronise); the filters, mean
+    fields and the mean-field gradient (workspace allocated beforehand) are
+    also timed with events."""
     import numpy as np
     import torch
     import paper_2305_13220_amd as sg
-    from synth import cameras, workloads
+    from synth import workloads
     t0 = time.perf_counter()
-    fr = workloads.room_depth_frames(n_frames=10, W=640, H=480, n_sem=n_sem)
-    pix = np.concatenate([cameras.frame_pixels(i, 640, 480) for i in range(10)])
-    d = fr["depth"].reshape(-1)
-    rng = np.random.default_rng(0)
-    idx = rng.choice(np.flatnonzero(np.isfinite(d)), n, replace=False)
-    rays = cameras.pixel_rays(fr["cams"], pix[idx]).astype(np.float64)
-    Rz = fr["cams"][pix[idx, 0], 4:].astype(np.float64).reshape(-1, 3, 4)[:, :, 2]
-    t = d[idx] / np.einsum("ij,ij->i", rays[:, 3:], Rz)
-    xyz = rays[:, :3] + t[:, None] * rays[:, 3:]
-    feat = fr["feat"].reshape(-1, 3 + n_sem)[idx]
-    pos = torch.from_numpy(np.concatenate([xyz / 0.2, feat[:, :3] / 0.3], 1).astype(np.float32)).to(dev)
-    unary = torch.from_numpy((-np.log(feat[:, 3:] * 0.7 + 0.3 / n_sem)).astype(np.float32)).to(dev)
-    log(f"crf setup {time.perf_counter() - t0:.1f}s")
-    sg.Lattice(pos, max_values=n_sem)
+    base = workloads.room_2cm(n_rays=n_rays)
+    sem = workloads._room(0, 0.02, n_sem)
+    C = 3 + n_sem
+    grid = sg.Grid(torch.from_numpy(sem["block_coords"]).to(dev), float(sem["h"]),
+                   tuple(float(x) for x in sem["origin"]))
+    vox = torch.from_numpy(sem["vox"]).to(dev)
+    rays = sg.rays_pinhole(torch.from_numpy(base["cams"]).to(dev),
+                           torch.from_numpy(base["pix"]).to(dev))
+    params = base["params"]
+    log(f"crf setup {time.perf_counter() - t0:.1f}s: {grid.n_blocks} blocks, C={C}")
+    sp, sc, sn, sl = (CRF_SIGMA[k] for k in ("pos", "color", "normal", "label"))
+    mu = (w_potts * (1.0 - torch.eye(n_sem, device=dev))).contiguous()
+
+    def chain(stats=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        pts, hit = sg.surface_points(grid, vox, rays, params)
+        idx = torch.nonzero(hit, as_tuple=False).squeeze(1)
+        nodes = pts.index_select(0, idx).contiguous()
+        q = sg.query(grid, vox, nodes)
+        rgb, logit, nrm = q["feat"][:, :3], q["feat"][:, 3:], q["grad"]
+        f_lab = torch.cat([nodes / sp, rgb / sc, nrm / sn], 1).contiguous()
+        f_col = torch.cat([nodes / sp, nrm / sn, logit / sl], 1).contiguous()
+        f_nrm = torch.cat([nodes / sp, rgb / sc, logit / sl], 1).contiguous()
+        ones = torch.ones((nodes.shape[0], 1), device=dev)
+        lat_l = sg.Lattice(f_lab, max_values=n_sem)
+        lat_c = sg.Lattice(f_col, max_values=4)
+        lat_n = sg.Lattice(f_nrm, max_values=4)
+        g_feat = torch.zeros_like(q["feat"])
+        ev[0].record()
+        Q = lat_l.meanfield((-logit).contiguous(), 0.0, iters, compat=mu)
+        l_lab, _ = sg.crf_label_loss(q["feat"], Q, col0=3, weight=CRF_LAMBDA["label"], g_feat=g_feat)
+        fc = lat_c.filter(torch.cat([rgb, ones], 1).contiguous())
+        l_col, _ = sg.crf_property_loss(q["feat"], fc, col0=0, weight=CRF_LAMBDA["color"],
+                                        g_feat=g_feat)
+        fn = lat_n.filter(torch.cat([nrm, ones], 1).contiguous())
+        l_nrm, g_nrm = sg.crf_property_loss(nrm.contiguous(), fn, col0=0,
+                                            weight=CRF_LAMBDA["normal"])
+        grad = sg.query_backward(grid, vox.shape, nodes, g_grad=g_nrm, g_feat=g_feat)
+        ev[1].record()
+        if stats is not None:
+            torch.cuda.synchronize()
+            stats.update(nodes=int(nodes.shape[0]), vertices={"label_d9": lat_l.n_vertices,
+                                                               "color_d22": lat_c.n_vertices,
+                                                               "normal_d22": lat_n.n_vertices},
+                         loss={"label": float(l_lab.sum()), "color": float(l_col.sum()),
+                               "normal": float(l_nrm.sum())},
+                         after_builds_ms=ev[0].elapsed_time(ev[1]),
+                         lat=(lat_l, lat_c, lat_n), Q=Q, logit=logit.contiguous(), rgb=rgb, nrm=nrm,
+                         f_lab=f_lab, f_col=f_col, f_nrm=f_nrm)
+        return grad
+
+    chain()
     torch.cuda.synchronize()
-    tb = []
+    tc = []
     for _ in range(reps):
         a = time.perf_counter()
-        lat = sg.Lattice(pos, max_values=n_sem)
-        tb.append(time.perf_counter() - a)
-    Q = lat.meanfield(unary, 5.0, 1)
-    out = lat.filter(Q)
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    e[0].record()
+        chain()
+        torch.cuda.synchronize()
+        tc.append(time.perf_counter() - a)
+    st = {}
+    chain(st)
+    lat_l, lat_c, lat_n = st.pop("lat")
+    Q, logit = st.pop("Q"), st.pop("logit")
+    n = st["nodes"]
+    ones = torch.ones((n, 1), device=dev)
+    v4 = torch.cat([st.pop("rgb"), ones], 1).contiguous()
+    st.pop("nrm")
+    # kernels on their own, with events
+    ws = torch.empty(sg._lib.lib().sg_crf_meanfield_compat_backward_ws_bytes(n, n_sem, iters),
+                     dtype=torch.uint8, device=dev)
+    gQ = torch.from_numpy(np.random.default_rng(0).normal(size=(n, n_sem)).astype(np.float32)).to(dev)
+    g_u = torch.empty((n, n_sem), device=dev)
+    g_mu = torch.empty((n_sem, n_sem), device=dev)
+    out16 = torch.empty((n, n_sem), device=dev)
+    out4 = torch.empty((n, 4), device=dev)
+    unary = (-logit).contiguous()
+    L = sg._lib.lib()
+
+    def mf_bwd():
+        sg._lib.check(L.sg_crf_meanfield_compat_backward(
+            lat_l._h, sg._lib.ptr(unary), n_sem, sg._lib.ptr(mu), iters, sg._lib.ptr(gQ),
+            sg._lib.ptr(g_u), sg._lib.ptr(g_mu), sg._lib.ptr(ws), ws.numel(),
+            sg._lib.stream_ptr(dev)), "sg_crf_meanfield_compat_backward")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        for _ in range(reps):
+            fn()
+        e[1].record()
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / reps
+
+    f16_ms = timed(lambda: lat_l.filter(Q, out=out16))
+    f4_ms = timed(lambda: lat_c.filter(v4, out=out4))
+    mf_ms = timed(lambda: lat_l.meanfield(unary, 0.0, iters, out=out16, compat=mu))
+    mfb_ms = timed(mf_bwd)
+    f_lab, f_col = st.pop("f_lab"), st.pop("f_col")
+    st.pop("f_nrm")
+    tb9, tb22 = [], []
     for _ in range(reps):
-        lat.filter(Q, out=out)
-    e[1].record()
-    for _ in range(reps):
-        lat.meanfield(unary, 5.0, iters, out=Q)
-    e[2].record()
-    torch.cuda.synchronize()
-    # a compatibility matrix (Potts 5 (1 - I) plus seeded asymmetric terms):
-    # the forward, and the gradient with respect to the unaries and the matrix
-    mu = torch.from_numpy((5.0 * (1.0 - np.eye(n_sem)) + 0.3 * rng.random((n_sem, n_sem)))
-                          .astype(np.float32)).to(dev)
-    gQ = torch.from_numpy(rng.normal(size=(n, n_sem)).astype(np.float32)).to(dev)
-    lat.meanfield(unary, 0.0, iters, out=Q, compat=mu)
-    lat.meanfield_backward(unary, mu, iters, gQ)
-    torch.cuda.synchronize()
-    ec = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ec[0].record()
-    for _ in range(reps):
-        lat.meanfield(unary, 0.0, iters, out=Q, compat=mu)
-    ec[1].record()
-    for _ in range(reps):
-        lat.meanfield_backward(unary, mu, iters, gQ)
-    ec[2].record()
-    torch.cuda.synchronize()
-    f_ms = e[0].elapsed_time(e[1]) / reps
-    mf_ms = e[1].elapsed_time(e[2]) / reps
-    mfc_ms = ec[0].elapsed_time(ec[1]) / reps
-    mfb_ms = ec[1].elapsed_time(ec[2]) / reps  # includes the binding's workspace allocation
-    res = {"workload": "room_surface_2^18_samples_d6_16labels", "points": n, "d": 6,
-           "lattice_vertices": lat.n_vertices,
-           "build_ms": round(float(np.median(tb)) * 1e3, 3), "filter_ms": round(f_ms, 4),
-           "meanfield_ms": round(mf_ms, 4), "meanfield_iters": iters,
-           "meanfield_compat_ms": round(mfc_ms, 4),
-           "meanfield_compat_backward_ms": round(mfb_ms, 4),
-           "points_per_s_per_update": n * iters / (mf_ms * 1e-3)}
-    del lat, pos, unary, Q, out, mu, gQ
+        a = time.perf_counter()
+        sg.Lattice(f_lab, max_values=n_sem)
+        tb9.append(time.perf_counter() - a)
+        a = time.perf_counter()
+        sg.Lattice(f_col, max_values=4)
+        tb22.append(time.perf_counter() - a)
+
+    def filt_bytes(lat, d, vd):
+        # splat: (vid, weight) per point-vertex pair, the point's values,
+        # one value row update per pair; blur: per vertex and direction the
+        # two neighbours' fingerprints and keys and three value rows read,
+        # one written; slice: the pairs again, the values out
+        nv = lat.n_vertices
+        pairs = n * (d + 1)
+        return (pairs * (8 + 4 * vd) + 4 * n * vd + (d + 1) * nv * (2 * (8 + 4 * d) + 16 * vd)
+                + pairs * (8 + 4 * vd) + 4 * n * vd)
+
+    b16 = filt_bytes(lat_l, 9, n_sem)
+    b4 = filt_bytes(lat_c, 22, 4)
+    res = {"workload": "room_2cm_sem_surface_nodes_2^18_rays", "C": C, "rays": n_rays,
+           "sigma": CRF_SIGMA, "lambda": CRF_LAMBDA, "potts_weight": w_potts,
+           "chain_ms_p50": round(float(np.median(tc)) * 1e3, 3),
+           "chain_after_lattice_builds_ms": round(st.pop("after_builds_ms"), 4),
+           "build_d9_ms": round(float(np.median(tb9)) * 1e3, 3),
+           "build_d22_ms": round(float(np.median(tb22)) * 1e3, 3),
+           "filter_d9_16ch_ms": round(f16_ms, 4), "filter_d22_4ch_ms": round(f4_ms, 4),
+           "meanfield_d9_ms": round(mf_ms, 4), "meanfield_iters": iters,
+           "meanfield_backward_d9_ms": round(mfb_ms, 4),
+           "filter_d9_16ch_hbm_frac": round(b16 / (f16_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "filter_d22_4ch_hbm_frac": round(b4 / (f4_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "filter_bytes_definition": "splat (vid, weight, values, row update per point-vertex "
+                                      "pair), blur (two neighbour lookups and three value rows "
+                                      "per vertex and direction, one row written), slice",
+           **st}
+    del lat_l, lat_c, lat_n, ws, gQ, Q, grid, vox, rays, f_lab, f_col
     torch.cuda.empty_cache()
     return res
 

@@ -270,7 +270,7 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  * collision-free hash of lattice points.
  *
  * sg_lattice_build -- the lattice of n_points feature positions d_pos
- *   float [n,d], 1 <= d <= 16, already divided by the per-feature standard
+ *   float [n,d], 1 <= d <= 24, already divided by the per-feature standard
  *   deviations (finite, |p| < 2^20): each position's enclosing simplex (d+1
  *   vertices and barycentric weights; float32 without fused multiply-add,
  *   so the vertices are the same integers for any evaluation of the same

@@ -1097,7 +1097,7 @@ int or_denoise(const int32_t* block_coords, int64_t n_blocks, const double* vox,
 /* Permutohedral-lattice Gaussian filtering and a mean-field step of the     */
 /* continuous CRF (Sec. 3.5.3).                                              */
 
-#define LAT_MAX_D 16
+#define LAT_MAX_D 24
 
 /* Enclosing simplex of a d-dimensional (already scaled) feature position in
  * the permutohedral lattice A*_d: the position is lifted onto the plane

@@ -15,7 +15,7 @@
 
 namespace sg {
 
-constexpr int kLatMaxD = 16;
+constexpr int kLatMaxD = 24;
 constexpr int kLatMaxV = 32;
 
 // Enclosing simplex of one scaled position (float32, no fused multiply-add,
@@ -210,6 +210,8 @@ __global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __rest
 
 // Blur along direction j: new = v/2 + (v(n-) + v(n+))/4, n+- = key +-
 // ((1,...,1) - (d+1) e_j) (first d coordinates); absent neighbours add 0.
+// MAXD >= d bounds the key loops (8, 16 or 24, the smallest that holds d).
+template <int MAXD>
 __global__ void k_lat_blur(LatView L, const int32_t* __restrict__ list, int64_t nv, int j,
                            const float* __restrict__ src, int vd, float* __restrict__ dst) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -220,17 +222,17 @@ __global__ void k_lat_blur(LatView L, const int32_t* __restrict__ list, int64_t 
   float acc[kLatMaxV];
 #pragma unroll
   for (int c = 0; c < kLatMaxV; ++c) acc[c] = c < vd ? 0.5f * src[s * vd + c] : 0.0f;
-  int32_t nk[kLatMaxD];
+  int32_t nk[MAXD];
 #pragma unroll
   for (int sgn = -1; sgn <= 1; sgn += 2) {
 #pragma unroll
-    for (int c = 0; c < kLatMaxD; ++c)
+    for (int c = 0; c < MAXD; ++c)
       nk[c] = c < d ? L.keys[s * d + c] + sgn * (c == j ? -d : 1) : 0;
     const int64_t t = lat_slot(L, nk, false);
     if (t < 0) continue;
     bool same = true;
 #pragma unroll
-    for (int c = 0; c < kLatMaxD; ++c) same = same && (c >= d || L.keys[t * d + c] == nk[c]);
+    for (int c = 0; c < MAXD; ++c) same = same && (c >= d || L.keys[t * d + c] == nk[c]);
     if (!same) continue;  // a fingerprint alias of an absent key: no neighbour
 #pragma unroll
     for (int c = 0; c < kLatMaxV; ++c)
@@ -530,7 +532,12 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   float* b = L->v1;
   for (int jj = 0; jj <= d; ++jj) {
     const int j = reverse ? d - jj : jj;
-    k_lat_blur<<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
+    if (d <= 8)
+      k_lat_blur<8><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
+    else if (d <= 16)
+      k_lat_blur<16><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
+    else
+      k_lat_blur<kLatMaxD><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
     float* t = a;
     a = b;
     b = t;
@@ -671,7 +678,7 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
                      sg_stream stream, sg_lattice** out) {
   if (!out) return fail(SG_EINVAL, "out is NULL");
   *out = nullptr;
-  if (d < 1 || d > kLatMaxD) return fail(SG_EINVAL, "d must be in [1, 16]");
+  if (d < 1 || d > kLatMaxD) return fail(SG_EINVAL, "d must be in [1, 24]");
   if (max_values < 1 || max_values > kLatMaxV) return fail(SG_EINVAL, "max_values must be in [1, 32]");
   if (!lat_args_ok(n_points, d, max_values))
     return fail(SG_EINVAL, "n_points must be >= 1 and n_points * (d+1) < 2^30");

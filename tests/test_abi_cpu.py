@@ -85,7 +85,7 @@ def test_render_validation(L):
                      None) == -1
     assert L.sg_denoise(None, fake, 3, 1, ctypes.c_float(1.0), fake, None) == -1
     lat = ctypes.c_void_p()
-    assert L.sg_lattice_build(fake, 10, 17, 4, None, ctypes.byref(lat)) == -1 and not lat.value
+    assert L.sg_lattice_build(fake, 10, 25, 4, None, ctypes.byref(lat)) == -1 and not lat.value
     assert L.sg_lattice_build(fake, 10, 3, 33, None, ctypes.byref(lat)) == -1
     assert L.sg_lattice_filter(None, fake, 1, fake, None) == -1
     assert L.sg_crf_meanfield(None, fake, 2, ctypes.c_float(1.0), 1, fake, None) == -1
@@ -226,7 +226,8 @@ def test_lattice_and_workspace_sizes(L):
         assert L.sg_lattice_bytes(n, d, v) == lat(n, d, v)
     assert L.sg_lattice_bytes(0, 6, 16) == 0
     assert L.sg_lattice_bytes(10, 0, 16) == 0
-    assert L.sg_lattice_bytes(10, 17, 16) == 0
+    assert L.sg_lattice_bytes(10, 25, 16) == 0
+    assert L.sg_lattice_bytes(10, 24, 16) > 0
     assert L.sg_lattice_bytes(10, 6, 33) == 0
     assert L.sg_lattice_bytes((1 << 30) // 7 + 1, 6, 1) == 0  # n (d+1) beyond 2^30
     assert L.sg_lattice_bytes((1 << 30) // 7 - 1, 6, 1) > 0

@@ -44,7 +44,7 @@ def _surface_features(n_sem=16, n=20000, seed=0):
     return pos, unary
 
 
-@pytest.mark.parametrize("d", [1, 3, 6])
+@pytest.mark.parametrize("d", [1, 3, 6, 9, 17, 22])
 def test_lattice_filter_matches_oracle(d):
     sg = _sg()
     rng = np.random.default_rng(d)
@@ -185,7 +185,7 @@ def test_lattice_invalid_inputs():
     with pytest.raises(sg.SgridError, match="finite"):
         sg.Lattice(to_dev(pos))
     with pytest.raises(sg.SgridError):
-        sg.Lattice(to_dev(np.zeros((10, 17), np.float32)))
+        sg.Lattice(to_dev(np.zeros((10, 25), np.float32)))
     lat = sg.Lattice(to_dev(np.zeros((10, 3), np.float32)), max_values=2)
     with pytest.raises(sg.SgridError):
         lat.filter(to_dev(np.zeros((10, 3), np.float32)))

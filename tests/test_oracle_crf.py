@@ -49,7 +49,7 @@ def _lift(p):
     return el
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 22])
 def test_simplex_reproduces_the_lifted_position(oracle_lib, d):
     rng = np.random.default_rng(d)
     p = rng.normal(scale=3.0, size=(500, d)).astype(np.float32)
@@ -62,6 +62,15 @@ def test_simplex_reproduces_the_lifted_position(oracle_lib, d):
     np.testing.assert_allclose(w.sum(-1), 1.0, atol=1e-9)
     rec = (w[..., None] * full).sum(1)
     np.testing.assert_allclose(rec, _lift(p.astype(np.float64)), atol=2e-5 * (1 + np.abs(p).max()))
+    # Independently of the lift's per-axis factors: the lift is (d+1) sqrt(2/3)
+    # times an isometry onto the plane sum x = 0, so the reconstructed points
+    # keep every inner product up to that factor (a wrong factor on any axis
+    # i breaks it for the points' i-th components).
+    P = p.astype(np.float64)
+    np.testing.assert_allclose(rec.sum(-1), 0.0, atol=1e-4 * (1 + np.abs(rec).max()))
+    gram = rec @ rec.T
+    want = (2.0 / 3.0) * (d + 1) ** 2 * (P @ P.T)
+    assert np.abs(gram - want).max() <= 1e-5 * np.abs(want).max() * (d + 1), d
     # the d+1 vertices are distinct and pairwise adjacent (differ by a 0/1 pattern times d+1 shift)
     for i in range(0, 500, 50):
         assert len({tuple(v) for v in keys[i]}) == d + 1
