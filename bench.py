@@ -585,12 +585,12 @@ def crf_bench(dev, n_rays=1 << 18, n_sem=16, iters=5, reps=5, w_potts=1.0):
 
     def filt_bytes(lat, d, vd):
         # splat: (vid, weight) per point-vertex pair, the point's values,
-        # one value row update per pair; blur: per vertex and direction the
-        # two neighbours' fingerprints and keys and three value rows read,
-        # one written; slice: the pairs again, the values out
+        # one value row update per pair; blur: per vertex and direction its
+        # list entry and two neighbour slots, three value rows read, one
+        # written; slice: the pairs again, the values out
         nv = lat.n_vertices
         pairs = n * (d + 1)
-        return (pairs * (8 + 4 * vd) + 4 * n * vd + (d + 1) * nv * (2 * (8 + 4 * d) + 16 * vd)
+        return (pairs * (8 + 4 * vd) + 4 * n * vd + (d + 1) * nv * (12 + 16 * vd)
                 + pairs * (8 + 4 * vd) + 4 * n * vd)
 
     b16 = filt_bytes(lat_l, 9, n_sem)
@@ -607,8 +607,8 @@ def crf_bench(dev, n_rays=1 << 18, n_sem=16, iters=5, reps=5, w_potts=1.0):
            "filter_d9_16ch_hbm_frac": round(b16 / (f16_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "filter_d22_4ch_hbm_frac": round(b4 / (f4_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "filter_bytes_definition": "splat (vid, weight, values, row update per point-vertex "
-                                      "pair), blur (two neighbour lookups and three value rows "
-                                      "per vertex and direction, one row written), slice",
+                                      "pair), blur (list entry, two neighbour slots, three value "
+                                      "rows read and one written per vertex and direction), slice",
            **st}
     del lat_l, lat_c, lat_n, ws, gQ, Q, grid, vox, rays, f_lab, f_col
     torch.cuda.empty_cache()

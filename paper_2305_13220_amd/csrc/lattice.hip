@@ -208,39 +208,51 @@ __global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __rest
   unsafeAtomicAdd(lv + (int64_t)vid[pr] * vd + c, bw[pr] * val[i * vd + c]);
 }
 
-// Blur along direction j: new = v/2 + (v(n-) + v(n+))/4, n+- = key +-
-// ((1,...,1) - (d+1) e_j) (first d coordinates); absent neighbours add 0.
-// MAXD >= d bounds the key loops (8, 16 or 24, the smallest that holds d).
+// Blur neighbours of every occupied vertex, found once at build: for list
+// entry k and direction j, the slots of key -+ ((1,...,1) - (d+1) e_j) (first
+// d coordinates), -1 where absent; filters then blur through this table.
 template <int MAXD>
-__global__ void k_lat_blur(LatView L, const int32_t* __restrict__ list, int64_t nv, int j,
-                           const float* __restrict__ src, int vd, float* __restrict__ dst) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nv) return;
-  const int64_t s = list[k];
+__global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int64_t nv,
+                                int32_t* __restrict__ nbr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int d = L.d;
-  // fixed-size loops with guards keep the arrays in registers
-  float acc[kLatMaxV];
-#pragma unroll
-  for (int c = 0; c < kLatMaxV; ++c) acc[c] = c < vd ? 0.5f * src[s * vd + c] : 0.0f;
+  if (t >= nv * (d + 1)) return;
+  const int j = (int)(t / nv);
+  const int64_t k = t - (int64_t)j * nv;
+  const int64_t s = list[k];
   int32_t nk[MAXD];
 #pragma unroll
-  for (int sgn = -1; sgn <= 1; sgn += 2) {
+  for (int h = 0; h < 2; ++h) {
+    const int sgn = h == 0 ? -1 : 1;
 #pragma unroll
     for (int c = 0; c < MAXD; ++c)
       nk[c] = c < d ? L.keys[s * d + c] + sgn * (c == j ? -d : 1) : 0;
-    const int64_t t = lat_slot(L, nk, false);
-    if (t < 0) continue;
-    bool same = true;
+    int64_t n = lat_slot(L, nk, false);
+    if (n >= 0) {
+      bool same = true;
 #pragma unroll
-    for (int c = 0; c < MAXD; ++c) same = same && (c >= d || L.keys[t * d + c] == nk[c]);
-    if (!same) continue;  // a fingerprint alias of an absent key: no neighbour
-#pragma unroll
-    for (int c = 0; c < kLatMaxV; ++c)
-      if (c < vd) acc[c] += 0.25f * src[t * vd + c];
+      for (int c = 0; c < MAXD; ++c) same = same && (c >= d || L.keys[n * d + c] == nk[c]);
+      if (!same) n = -1;  // a fingerprint alias of an absent key: no neighbour
+    }
+    nbr[2 * t + h] = (int32_t)n;
   }
-#pragma unroll
-  for (int c = 0; c < kLatMaxV; ++c)
-    if (c < vd) dst[s * vd + c] = acc[c];
+}
+
+// Blur along direction j through the neighbour table, lanes laid out
+// (vertex, channel): new = v/2 + (v(n-) + v(n+))/4.
+__global__ void k_lat_blur_tab(const int32_t* __restrict__ list, const int32_t* __restrict__ nbr,
+                               int64_t nv, const float* __restrict__ src, int vd,
+                               float* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nv * vd) return;
+  const int64_t k = t / vd;
+  const int c = (int)(t - k * vd);
+  const int64_t s = list[k];
+  const int32_t a = nbr[2 * k], b = nbr[2 * k + 1];
+  float v = 0.5f * src[s * vd + c];
+  if (a >= 0) v += 0.25f * src[(int64_t)a * vd + c];
+  if (b >= 0) v += 0.25f * src[(int64_t)b * vd + c];
+  dst[s * vd + c] = v;
 }
 
 // Lanes laid out (point, channel): consecutive lanes read one vertex row.
@@ -497,6 +509,7 @@ struct sg_lattice {
   float* v0;
   float* v1;
   float* m;  // [N, vmax] message buffer of the mean-field update
+  int32_t* nbr;  // [d+1][n_vertices][2] blur neighbours' slots (-1: absent)
 };
 
 namespace sg {
@@ -515,6 +528,7 @@ static void free_lat(sg_lattice* L) {
   (void)hipFree(L->v0);
   (void)hipFree(L->v1);
   (void)hipFree(L->m);
+  (void)hipFree(L->nbr);
   delete L;
 }
 // reverse: blur directions in the order d..0, which makes the filter its
@@ -532,12 +546,8 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   float* b = L->v1;
   for (int jj = 0; jj <= d; ++jj) {
     const int j = reverse ? d - jj : jj;
-    if (d <= 8)
-      k_lat_blur<8><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
-    else if (d <= 16)
-      k_lat_blur<16><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
-    else
-      k_lat_blur<kLatMaxD><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, j, a, vd, b);
+    k_lat_blur_tab<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, L->nbr + (int64_t)j * nv * 2, nv, a,
+                                                      vd, b);
     float* t = a;
     a = b;
     b = t;
@@ -671,7 +681,8 @@ size_t sg_lattice_bytes(int64_t n_points, int32_t d, int32_t max_values) {
   lat_sizes(n_points, d, max_values, sz);
   size_t total = 0;
   for (int k = 0; k < 8; ++k) total += sz[k];
-  return total;
+  // blur neighbour table: 2 (d+1) slots per vertex, at most n (d+1) vertices
+  return total + sizeof(int32_t) * 2 * (size_t)(d + 1) * (size_t)n_points * (size_t)(d + 1);
 }
 
 int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t max_values,
@@ -740,6 +751,29 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
     return rc;
   }
   L->n_vertices = nv;
+  {
+    const size_t nb_bytes = sizeof(int32_t) * 2 * (size_t)(d + 1) * (size_t)(nv > 0 ? nv : 1);
+    if (hipMalloc((void**)&L->nbr, nb_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      free_lat(L);
+      return fail(SG_ENOMEM, "device allocation for the lattice failed");
+    }
+    if (nv > 0) {
+      const int64_t n_t = nv * (d + 1);
+      if (d <= 8)
+        k_lat_neighbors<8><<<grid_of(n_t, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+      else if (d <= 16)
+        k_lat_neighbors<16><<<grid_of(n_t, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+      else
+        k_lat_neighbors<kLatMaxD><<<grid_of(n_t, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        free_lat(L);
+        return hip_fail(e, "lattice neighbours");
+      }
+    }
+  }
   L->magic = kLatMagic;
   *out = L;
   return SG_OK;
