@@ -150,13 +150,16 @@ __device__ __forceinline__ bool in_block_cube(const March& m, const Params& p, i
   return true;
 }
 
-// Lattice point k lies in the empty block c whose Chebyshev ball of radius
-// D-1 holds no allocated block.  Returns the last lattice index j >= k that
-// still lies in that ball.  Each coordinate of the float32 position is
-// monotone in k, so the lattice points in the ball form one run: if k and j
-// both lie in it, every point between them does too and can be skipped.
-// The exit estimate only seeds the search; membership is decided exactly.
-__device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, const int32_t c[3],
+// Lattice point kk lies in the empty block c whose Chebyshev ball of radius
+// D-1 holds no allocated block.  Returns (in every lane) a lattice index
+// j >= kk such that every point of [kk, j] lies in that ball.  Each
+// coordinate of the float32 position is monotone in k, so the lattice points
+// in the ball form one run: if kk and j both lie in it, every point between
+// them does too and can be skipped.  The ray's exit from the ball's box gives
+// an estimate of the run's end; the 64 lanes test the 64 points at and below
+// one past it at once, so membership is decided exactly and the estimate only
+// places the window.  Called by all lanes with uniform arguments.
+__device__ int32_t empty_run_end(const March& m, const Params& p, int32_t kk, const int32_t c[3],
                                  int32_t D, int32_t k_hi) {
   float t_exit = 3.0e38f;
 #pragma unroll
@@ -166,28 +169,36 @@ __device__ int32_t empty_run_end(const March& m, const Params& p, int32_t k, con
     if (d > 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] + D) - o) * inv);
     else if (d < 0.0f) t_exit = fminf(t_exit, (8.0f * (float)(c[a] - D + 1) - o) * inv);
   }
-  const float est = floorf((t_exit - p.t_near) * p.inv_step);
-  // NaN (0 * inf from the reciprocal of a tiny d) falls back to k: the
-  // result is always in [k, k_hi], so the march advances.
-  int32_t hi = !(est > (float)k) ? k : (est >= (float)k_hi ? k_hi : (int32_t)est);
-  if (in_block_cube(m, p, hi, c, D - 1)) return hi;
-  int32_t lo = k;  // invariant: lo inside, hi outside
-  while (hi - lo > 1) {
-    const int32_t mid = lo + (hi - lo) / 2;
-    if (in_block_cube(m, p, mid, c, D - 1)) lo = mid;
-    else hi = mid;
-  }
-  return lo;
+  const float top_f = floorf((t_exit - p.t_near) * p.inv_step) + 1.0f;
+  // NaN (0 * inf from the reciprocal of a tiny d) falls back to kk: the
+  // window top is always in [kk, k_hi].
+  const int32_t top =
+      !(top_f > (float)kk) ? kk : (top_f >= (float)k_hi ? k_hi : (int32_t)top_f);
+  const int32_t j = top - lane_id();
+  const bool in = j <= kk || in_block_cube(m, p, j, c, D - 1);
+  // the inside points of the window are its lanes from the first set one on
+  const uint64_t bal = __ballot(in);
+  return bal ? top - (int32_t)__builtin_ctzll(bal) : kk;
 }
 
-// March: kept samples of the ray, in lattice order, into q[0..n) (n <= M).
-// When the last of the 64 tested points lies in an empty block with empty
-// surroundings (dense map), the run of lattice points inside that empty
-// region is skipped.
+// The next first lattice point of a march after the 64 points from k0: past
+// the empty run when the last of them lies in an empty block at distance >= 2
+// from every allocated block.
+__device__ __forceinline__ int32_t march_next(const March& m, const Params& p, int32_t k0,
+                                              int32_t idx, int32_t dist, const int32_t b[3]) {
+  const int32_t D = __builtin_amdgcn_readlane(idx < 0 ? dist : 0, kWave - 1);
+  if (D < 2) return k0 + kWave;
+  const int32_t c[3] = {__builtin_amdgcn_readlane(b[0], kWave - 1),
+                        __builtin_amdgcn_readlane(b[1], kWave - 1),
+                        __builtin_amdgcn_readlane(b[2], kWave - 1)};
+  return empty_run_end(m, p, k0 + kWave - 1, c, D, m.k_hi) + 1;
+}
+
 // One lattice point against the dense block map, without branches: every
 // lane loads a map entry (index clamped into the map), and out-of-range
-// points read as empty with distance 1.
-__device__ __forceinline__ void map_point(const GridView& g, const March& m, const Params& p,
+// points read as empty with distance 1.  Returns whether the point is in
+// range with a representable position (then b is its block).
+__device__ __forceinline__ bool map_point(const GridView& g, const March& m, const Params& p,
                                           int32_t k, bool in_range, bool& valid, int32_t& idx,
                                           int32_t& dist, int32_t b[3]) {
   const float t = lattice_t(p, k);
@@ -212,25 +223,67 @@ __device__ __forceinline__ void map_point(const GridView& g, const March& m, con
   dist = e >= 0 ? 0 : -e;
   const int need = need_mask(i[0] & 7, i[1] & 7, i[2] & 7);
   valid = e >= 0 && ((e & 255) & need) == need;
+  return ok;
 }
 
+// Lattice points per segment of the coarse pass of the dense-map march.
+constexpr int kSeg = 8;
+
+// March: kept samples of the ray, in lattice order, into q[0..n) (n <= M).
+//
+// Dense map: two passes per 8 * 64 lattice points.  The coarse pass gives
+// each lane a segment of 8 consecutive points and proves it empty when its
+// first point lies in an empty block at Chebyshev distance D >= 1 from every
+// allocated block and its last point lies in the ball of radius D-1 around
+// that block: each coordinate of the float32 position is monotone in k, so
+// every point between lies in the ball too, in blocks that hold no voxel.
+// The fine pass then tests the points of the other segments one per lane,
+// eight segments per batch, in lattice order.
+//
+// Hash lookups (no map): 64 points per batch; when the last of them lies in
+// an empty block with empty surroundings, the run of points inside that
+// empty region is skipped.
 __device__ int march_collect(const GridView& g, const March& m, const Params& p, int2* q) {
   const int lane = lane_id();
   int n = 0;
   int32_t k0 = m.k_lo;
   if (g.map) {
+    constexpr int32_t kSpan = kSeg * kWave;
+    const int seg = lane >> 3, sub = lane & (kSeg - 1);
     while (k0 <= m.k_hi && n < p.max_samples) {
-      const int32_t k = k0 + lane;
-      bool valid;
-      int32_t idx, dist, b[3];
-      map_point(g, m, p, k, k <= m.k_hi, valid, idx, dist, b);
-      const uint64_t bal = __ballot(valid);
-      const int r = rank_below(bal);
-      if (valid && n + r < p.max_samples) q[n + r] = make_int2(k, idx);
-      n = min(p.max_samples, n + (int)__popcll(bal));
-      int32_t next = k0 + kWave;
-      if (lane == kWave - 1 && idx < 0 && dist >= 2) next = empty_run_end(m, p, k, b, dist, m.k_hi) + 1;
-      k0 = __builtin_amdgcn_readlane(next, kWave - 1);
+      bool need;
+      {
+        const bool in = lane <= (m.k_hi - k0) / kSeg;  // first point <= k_hi, no overflow
+        const int32_t ks = in ? k0 + kSeg * lane : k0;
+        bool valid;
+        int32_t idx, dist, b[3];
+        const bool ok = map_point(g, m, p, ks, in, valid, idx, dist, b);
+        const int32_t ke = in ? min(m.k_hi - ks, kSeg - 1) + ks : ks;
+        need = in && !(ok && idx < 0 && in_block_cube(m, p, ke, b, dist - 1));
+      }
+      uint64_t mask = __ballot(need);
+      while (mask && n < p.max_samples) {
+        // this lane's segment: the seg-th set bit of the mask
+        const int cnt = (int)__popcll(mask);
+        int32_t pos = 0;
+#pragma unroll
+        for (int i = 0; i < kWave / kSeg; ++i) {
+          const int32_t pi = mask ? (int32_t)__builtin_ctzll(mask) : 0;
+          pos = seg == i ? pi : pos;
+          mask &= mask - 1;
+        }
+        const int32_t k = k0 + kSeg * pos + sub;
+        const bool in = seg < cnt && kSeg * pos + sub <= m.k_hi - k0;
+        bool valid;
+        int32_t idx, dist, b[3];
+        map_point(g, m, p, k, in, valid, idx, dist, b);
+        const uint64_t bal = __ballot(valid);
+        const int r = rank_below(bal);
+        if (valid && n + r < p.max_samples) q[n + r] = make_int2(k, idx);
+        n = min(p.max_samples, n + (int)__popcll(bal));
+      }
+      if (m.k_hi - k0 < kSpan) break;
+      k0 += kSpan;
     }
     wave_sync();
     return n;
@@ -269,9 +322,7 @@ __device__ int march_collect(const GridView& g, const March& m, const Params& p,
     const int r = rank_below(bal);
     if (valid && n + r < p.max_samples) q[n + r] = make_int2(k, idx);
     n = min(p.max_samples, n + (int)__popcll(bal));
-    int32_t next = k0 + kWave;
-    if (lane == kWave - 1 && idx < 0 && dist >= 2) next = empty_run_end(m, p, k, b, dist, m.k_hi) + 1;
-    k0 = __builtin_amdgcn_readlane(next, kWave - 1);
+    k0 = march_next(m, p, k0, idx, dist, b);
   }
   wave_sync();
   return n;
