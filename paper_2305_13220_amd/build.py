@@ -30,6 +30,10 @@ FLAGS = [
     # packed-FP32 instructions stay off: some of their forms have given silently
     # wrong results on gfx950, so scalar FP32 code is kept unpacked
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused within a statement only: the rounding of a
+    # value follows from its source expression, so kernels that compute the
+    # same quantity (the fused step and the separate forward) agree bit for bit
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",

@@ -445,6 +445,13 @@ __device__ __forceinline__ float density(float f, const Params& p, float& e) {
   return psi * p.inv_beta;
 }
 
+// Weight w = T (1 - exp(-sigma delta)) of a sample (Eq. 12-13), rounded once
+// and accumulated with explicit fused multiply-adds: every kernel that forms
+// a ray's outputs gets the same bits, whatever else the compiler fuses.
+__device__ __forceinline__ float sample_weight(float T, float sd) {
+  return __fmul_rn(T, -expm1f(-sd));
+}
+
 // Rays of one wave: r, r + stride, ...; the next ray is loaded (scalar
 // loads: the index is wave-uniform) while the current one is processed.
 struct RayStream {
@@ -624,15 +631,13 @@ __device__ __forceinline__ void shade_ray(const GridView& g, const float* __rest
     const float incl = wave_inclusive_sum(sd);
     const float excl = wave_shift_up(incl);
     if (act) {
-      const float T = expf(-(tau + excl));
-      const float alpha = -expm1f(-sd);
-      const float wt = T * alpha;
+      const float wt = sample_weight(expf(-(tau + excl)), sd);
 #pragma unroll
-      for (int ch = 0; ch < C; ++ch) accC[ch] += wt * col[ch];
-      accD += wt * cell.t;
-      accN[0] += wt * grad[0];
-      accN[1] += wt * grad[1];
-      accN[2] += wt * grad[2];
+      for (int ch = 0; ch < C; ++ch) accC[ch] = fmaf(wt, col[ch], accC[ch]);
+      accD = fmaf(wt, cell.t, accD);
+      accN[0] = fmaf(wt, grad[0], accN[0]);
+      accN[1] = fmaf(wt, grad[1], accN[1]);
+      accN[2] = fmaf(wt, grad[2], accN[2]);
       accW += wt;
     }
     tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
@@ -1139,16 +1144,34 @@ struct SampleState {
 // cell); the owners' (lane, corner) pairs are listed with a prefix sum, and
 // each listed voxel is summed by one lane walking forward from its owner
 // while the voxel stays a corner of the lane's cell.
-struct Scat {
+//
+// Per-wave LDS: 8 KiB, with the ray's upstream feature gradient added in
+// LDS only when C > 4 (up to four channels it is selected from registers).
+struct ScatCore {
   float val[16 * kWave];    // [a][lane]: SDF term of corner a, then w r_a at [8 + a][lane]
   int32_t off[8 * kWave];   // [a][lane]: element offset of corner a
   int4 base[kWave];         // base voxel of the lane's cell; w = 1 if the lane holds a sample
   uint16_t pair[8 * kWave]; // owned (lane, corner) pairs, lane * 8 + a
-  int32_t e_off[kWave];     // emission staging: element offset and the two sums of 64 voxels
-  float e_vs[kWave];
-  float e_vw[kWave];
-  float gC[32];             // upstream feature gradient of the ray
 };
+template <int C, bool IN_LDS = (C > 4)>
+struct Scat : ScatCore {
+  float gC[C];
+};
+template <int C>
+struct Scat<C, false> : ScatCore {};
+
+// The feature gradient factor of channel ch (1..C) of a voxel's emission.
+template <int C>
+__device__ __forceinline__ float emit_gC(const Scat<C>* sc, const float gC[C > 0 ? C : 1], int ch) {
+  if constexpr (C > 4) {
+    return sc->gC[ch > 0 ? ch - 1 : 0];
+  } else {
+    float v = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) v = ch == c + 1 ? gC[c] : v;
+    return v;
+  }
+}
 
 // Bits a = ax + 2 ay + 4 az of the corners of a cell with base b that are
 // also corners of the cell with base b - d: per axis, d = 0 shares both
@@ -1168,8 +1191,9 @@ __device__ __forceinline__ int shared_corners(int dx, int dy, int dz) {
 // are summed per voxel and added to grad_vox.  The samples may be in ray
 // order or in reverse order along the lanes.
 template <int C>
-__device__ __forceinline__ void scatter_chunk(Scat* sc, bool act, const Cell& cell, float w,
-                                              float df, const float gA[3], float inv_h,
+__device__ __forceinline__ void scatter_chunk(Scat<C>* sc, bool act, const Cell& cell, float w,
+                                              float df, const float gA[3],
+                                              const float gC[C > 0 ? C : 1], float inv_h,
                                               const March& m, float* __restrict__ grad_vox) {
   constexpr int V = 1 + C;
   const int lane = lane_id();
@@ -1213,6 +1237,8 @@ __device__ __forceinline__ void scatter_chunk(Scat* sc, bool act, const Cell& ce
   wave_sync();
   for (int e0 = 0; e0 < n_own; e0 += kWave) {
     const int e = e0 + lane;
+    int32_t e_off = 0;
+    float e_vs = 0.0f, e_vw = 0.0f;
     if (e < n_own) {
       const int pr = sc->pair[e];
       const int j = pr >> 3, a = pr & 7;
@@ -1228,19 +1254,23 @@ __device__ __forceinline__ void scatter_chunk(Scat* sc, bool act, const Cell& ce
         vs += sc->val[ak * kWave + k];
         vw += sc->val[(8 + ak) * kWave + k];
       }
-      sc->e_off[lane] = sc->off[a * kWave + j];
-      sc->e_vs[lane] = vs;
-      sc->e_vw[lane] = vw;
+      e_off = sc->off[a * kWave + j];
+      e_vs = vs;
+      e_vw = vw;
     }
-    wave_sync();
+    // emission: lanes laid out (voxel, channel), each voxel's sums read from
+    // the lane that walked it (every lane active for the shuffles)
     const int n_e = min(kWave, n_own - e0);
-    for (int f = lane; f < n_e * V; f += kWave) {
-      const int i = f / V, ch = f - i * V;
-      const float v = ch == 0 ? sc->e_vs[i] : sc->e_vw[i] * sc->gC[ch > 0 ? ch - 1 : 0];
-      unsafeAtomicAdd(grad_vox + (int64_t)sc->e_off[i] * V + ch, v);
+    for (int f0 = 0; f0 < n_e * V; f0 += kWave) {
+      const int f = f0 + lane;
+      const int i = min(f / V, kWave - 1), ch = f - (f / V) * V;
+      const int32_t o = shfl(e_off, i);
+      const float vs = shfl(e_vs, i), vw = shfl(e_vw, i);
+      if (f < n_e * V)
+        unsafeAtomicAdd(grad_vox + (int64_t)o * V + ch, ch == 0 ? vs : vw * emit_gC<C>(sc, gC, ch));
     }
-    wave_sync();
   }
+  wave_sync();
 }
 
 // Sum over lanes m > l of v_m (lane order), without cancellation: the wave
@@ -1303,12 +1333,14 @@ __device__ __forceinline__ void load_ray_inputs(int64_t r, const float* __restri
 // Stage the ray's upstream feature gradient in LDS for the scatter
 // (selects: a dynamic index into a register array would go to scratch).
 template <int C>
-__device__ __forceinline__ void stage_gC(const Upstream<C>& up, Scat* sc) {
-  const int lane = lane_id();
-  float mine = 0.0f;
+__device__ __forceinline__ void stage_gC(const Upstream<C>& up, Scat<C>* sc) {
+  if constexpr (C > 4) {
+    const int lane = lane_id();
+    float mine = 0.0f;
 #pragma unroll
-  for (int ch = 0; ch < C; ++ch) mine = lane == ch ? up.gC[ch] : mine;
-  if (lane < C) sc->gC[lane] = mine;
+    for (int ch = 0; ch < C; ++ch) mine = lane == ch ? up.gC[ch] : mine;
+    if (lane < C) sc->gC[lane] = mine;
+  }
 }
 
 // Forward outputs of a ray are reduced over the wave and written by lane 0;
@@ -1318,7 +1350,7 @@ __device__ __forceinline__ void write_outputs_and_l2_grad(
     int64_t r, int64_t R, int n, float accC[C > 0 ? C : 1], float accD, float accN[3], float accW,
     float* __restrict__ feat_out, float* __restrict__ depth, float* __restrict__ normal,
     float* __restrict__ wsum, int32_t* __restrict__ nsamples, const L2Ref& ref,
-    const Upstream<C>& refv, Upstream<C>& up, Scat* sc, float eik) {
+    const Upstream<C>& refv, Upstream<C>& up, Scat<C>* sc, float eik) {
   const int lane = lane_id();
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) accC[ch] = wave_sum(accC[ch]);
@@ -1376,16 +1408,22 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   extern __shared__ int2 lds_q[];
   const int wpb = blockDim.x / kWave, lane = lane_id();
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  int2* const q = lds_q + (int64_t)w * p.max_samples;
-  SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * p.max_samples);
-  SampleState* st = st_base + (int64_t)w * p.max_samples;
-  Scat* sc_base = reinterpret_cast<Scat*>(st_base + (int64_t)wpb * p.max_samples);
-  Scat* sc = sc_base + w;
+  const int M = p.max_samples;
+  // Per-sample state of multi-chunk rays: the last chunk's (the first one
+  // pass 2 takes) in the scatter staging, which is free until that chunk's
+  // scatter; the others (at most the whole chunks below max_samples - 1) in
+  // their own entries.
+  const int M_st = (M - 1) / kWave * kWave;
+  int2* const q = lds_q + (int64_t)w * M;
+  SampleState* st_base = reinterpret_cast<SampleState*>(lds_q + (int64_t)wpb * M);
+  SampleState* st = st_base + (int64_t)w * M_st;
+  Scat<C>* sc_base = reinterpret_cast<Scat<C>*>(st_base + (int64_t)wpb * M_st);
+  Scat<C>* sc = sc_base + w;
+  SampleState* st_last = reinterpret_cast<SampleState*>(sc->val);
   // Fused multi-chunk rays: t, grad f and features of every sample, kept
   // from pass 1 for pass 2 (structure of arrays [4 + C][max_samples]) when
   // the launch has the room; otherwise pass 2 interpolates again.
-  float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (4 + C) * p.max_samples;
-  const int M = p.max_samples;
+  float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (4 + C) * M;
   BatchRays rs((int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   ListPrefetch pf;
   if (LIST) pf.load(lq, lc, M, rs.r, R);
@@ -1418,20 +1456,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       const float excl = wave_shift_up(incl);
       float wt = 0.0f, tn = 0.0f;
       if (act) {
-        wt = expf(-excl) * -expm1f(-sd);
+        wt = sample_weight(expf(-excl), sd);
         tn = expf(-incl);
       }
       float ce = 0.0f;  // Eikonal adjoint factor of this sample
       if constexpr (FUSED) {
         float accC[C > 0 ? C : 1], accN[3], eik = 0.0f;
+        // the forward's first-chunk accumulation, fma onto zero
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) accC[ch] = wt * col[ch];
-        accN[0] = wt * grad[0];
-        accN[1] = wt * grad[1];
-        accN[2] = wt * grad[2];
+        for (int ch = 0; ch < C; ++ch) accC[ch] = fmaf(wt, col[ch], 0.0f);
+        accN[0] = fmaf(wt, grad[0], 0.0f);
+        accN[1] = fmaf(wt, grad[1], 0.0f);
+        accN[2] = fmaf(wt, grad[2], 0.0f);
         if (ref.lambda_e != 0.0f && act) ce = eikonal_sample(grad, ref.lambda_e * (1.0f / (float)R), eik);
-        write_outputs_and_l2_grad<C>(r, R, n, accC, wt * cell.t, accN, wt, feat_out, depth, normal,
-                                     wsum, nsamples, ref, pre, up, sc, eik);
+        write_outputs_and_l2_grad<C>(r, R, n, accC, fmaf(wt, cell.t, 0.0f), accN, wt, feat_out,
+                                     depth, normal, wsum, nsamples, ref, pre, up, sc, eik);
         if (n == 0) continue;
       }
       float s = up.gD * cell.t + up.gW + up.gN[0] * grad[0] + up.gN[1] * grad[1] +
@@ -1447,7 +1486,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       }
       const float gA[3] = {wt * up.gN[0] + ce * grad[0], wt * up.gN[1] + ce * grad[1],
                            wt * up.gN[2] + ce * grad[2]};
-      scatter_chunk<C>(sc, act, cell, wt, df, gA, g.inv_h, m, grad_vox);
+      scatter_chunk<C>(sc, act, cell, wt, df, gA, up.gC, g.inv_h, m, grad_vox);
       continue;
     }
     // Several chunks.  Pass 1: recompute the forward quantities of every
@@ -1456,6 +1495,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
 #pragma unroll
     for (int ch = 0; ch < C; ++ch) accC[ch] = 0.0f;
     float tau = 0.0f, eik = 0.0f;
+    const int last = (n - 1) / kWave * kWave;  // first chunk of pass 2
     for (int c0 = 0; c0 < n; c0 += kWave) {
       const int j = c0 + lane;
       const bool act = j < n;
@@ -1472,7 +1512,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       const float excl = wave_shift_up(incl);
       if (act) {
         SampleState s;
-        s.w = expf(-(tau + excl)) * -expm1f(-sd);
+        s.w = sample_weight(expf(-(tau + excl)), sd);
         s.tn = expf(-(tau + incl));
         s.f = f;
         if constexpr (FUSED) {
@@ -1485,11 +1525,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(
             for (int ch = 0; ch < C; ++ch) vst[(4 + ch) * M + j] = col[ch];
           }
 #pragma unroll
-          for (int ch = 0; ch < C; ++ch) accC[ch] += s.w * col[ch];
-          accD += s.w * cell.t;
-          accN[0] += s.w * grad[0];
-          accN[1] += s.w * grad[1];
-          accN[2] += s.w * grad[2];
+          for (int ch = 0; ch < C; ++ch) accC[ch] = fmaf(s.w, col[ch], accC[ch]);
+          accD = fmaf(s.w, cell.t, accD);
+          accN[0] = fmaf(s.w, grad[0], accN[0]);
+          accN[1] = fmaf(s.w, grad[1], accN[1]);
+          accN[2] = fmaf(s.w, grad[2], accN[2]);
           accW += s.w;
           if (ref.lambda_e != 0.0f) eikonal_sample(grad, 0.0f, eik);
           s.s = 0.0f;  // formed in pass 2, once the outputs are known
@@ -1500,7 +1540,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(
           for (int ch = 0; ch < C; ++ch) dw += up.gC[ch] * col[ch];
           s.s = dw;
         }
-        st[j] = s;
+        if (j >= last) st_last[j - last] = s;
+        else st[j] = s;
       }
       tau += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), kWave - 1));
     }
@@ -1512,7 +1553,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(
     // holds sample c0 + 63 - l), so sum_{j>k} w_j s_j is an exclusive prefix
     // sum over lanes.
     float carry = 0.0f;
-    const int last = (n - 1) / kWave * kWave;
     for (int c0 = last; c0 >= 0; c0 -= kWave) {
       const int j = c0 + (kWave - 1 - lane);
       const bool act = j < n;
@@ -1521,7 +1561,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
       cell.t = 0.0f;
       float gA[3] = {0.0f, 0.0f, 0.0f};
       if (act) {
-        s = st[j];
+        s = j >= last ? st_last[j - last] : st[j];
         locate(g, m, p, q[j], cell);
 #pragma unroll
         for (int a = 0; a < 3; ++a) gA[a] = s.w * up.gN[a];
@@ -1559,7 +1599,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         const float e = 0.5f * expf(-fabsf(s.f) * p.inv_beta);
         df = dsig * (-e * p.inv_beta * p.inv_beta);
       }
-      scatter_chunk<C>(sc, act, cell, s.w, df, gA, g.inv_h, m, grad_vox);
+      scatter_chunk<C>(sc, act, cell, s.w, df, gA, up.gC, g.inv_h, m, grad_vox);
       carry += total;
     }
   }
@@ -1717,6 +1757,15 @@ static Launch plan(int64_t R, size_t lds_per_wave, int wpb = 1, int rays_per_wav
     default: break;                                   \
   }
 
+// LDS of one wave of k_render_bwd (without the pass-2 values): sample
+// queue, per-sample state of all but the last chunk, scatter staging.
+static size_t bwd_lds_per_wave(int C, int32_t M) {
+  size_t scat = sizeof(ScatCore);
+  SG_DISPATCH_C(C, scat = sizeof(Scat<CC>));
+  return sizeof(int2) * (size_t)M + sizeof(SampleState) * (size_t)((M - 1) / kWave * kWave) +
+         scat;
+}
+
 // Workspace of the sample lists: [R][max_samples] int2, then [R] int32.
 static bool list_bytes(int64_t R, int32_t M, size_t& bytes) {
   const double b = (double)R * (double)M * 8.0 + (double)R * 4.0;
@@ -1831,8 +1880,7 @@ int sg_render_backward(const sg_grid* grid, const float* d_vox, int32_t C, const
   SampleList L;
   bool list;
   if ((rc = list_view(d_lists, lists_bytes, n_rays, p, L, list))) return rc;
-  const Launch l =
-      plan(n_rays, (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(Scat));
+  const Launch l = plan(n_rays, bwd_lds_per_wave(C, p.max_samples));
   const L2Ref none = {nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f, nullptr};
   if (list) {
     SG_DISPATCH_C(C, hipLaunchKernelGGL((k_render_bwd<CC, false, true>), dim3(l.blocks),
@@ -1876,8 +1924,7 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   // Per-wave LDS: sample queue, per-sample state, scatter staging, and (when
   // the 12 waves a CU's registers allow, three per SIMD, still fit its
   // 160 KiB of LDS with them) the values pass 2 reuses.
-  const size_t base =
-      (sizeof(int2) + sizeof(SampleState)) * p.max_samples + sizeof(Scat);
+  const size_t base = bwd_lds_per_wave(C, p.max_samples);
   const size_t vbytes = sizeof(float) * (size_t)(4 + C) * p.max_samples;
   const bool keep_v = (base + vbytes) * 12 <= 160 * 1024;
   const Launch l = plan(n_rays, base + (keep_v ? vbytes : 0));

@@ -102,6 +102,20 @@ def test_dense_map_and_hash_paths_agree(room, room_hash_only):
     assert torch.equal(ca, cb)
 
 
+@pytest.mark.parametrize("max_samples", [1, 9, 65, 1024])
+def test_dense_map_and_hash_paths_agree_at_caps(room, room_hash_only, max_samples):
+    """The two-pass map march stops at the same sample as the hash march when
+    the cap falls inside a batch of segments."""
+    w, g, vox, rays = room
+    _, gh, _, _ = room_hash_only
+    prm = dict(w["params"], max_samples=max_samples)
+    sub = rays[:16384]
+    a = _sg().render_forward(g, vox, sub, prm)
+    b = _sg().render_forward(gh, vox, sub, prm)
+    for k in a:
+        assert torch.equal(a[k], b[k]), (k, max_samples)
+
+
 def test_forward_hash_path_matches_oracle(room_hash_only):
     w, g, vox, _ = room_hash_only
     sub = w["rays"][:8192]
@@ -215,7 +229,7 @@ def test_backward_room_full_batch(room):
     _check_backward(w, g, vox, w["rays"], 3, seed=3, what="room backward full batch")
 
 
-@pytest.mark.parametrize("max_samples", [1, 65, 1024])
+@pytest.mark.parametrize("max_samples", [1, 65, 100, 129, 1024])
 def test_backward_sample_caps(sphere, max_samples):
     w, g, vox, _ = sphere
     w2 = dict(w, params=dict(w["params"], max_samples=max_samples))
@@ -367,10 +381,13 @@ def test_fused_l2_step_sphere(sphere):
     _fused_check(w, g, vox, w["rays"], seed=11, what="fused sphere")
 
 
-def test_fused_l2_step_multichunk(sphere):
-    """max_samples 1024: rays with more than 64 samples take the chunked path."""
+@pytest.mark.parametrize("max_samples", [100, 1024])
+def test_fused_l2_step_multichunk(sphere, max_samples):
+    """Rays with more than 64 samples take the chunked path (a cap of 100
+    leaves a ragged last chunk)."""
     w, g, vox, _ = sphere
-    _fused_check(w, g, vox, w["rays"][::3], seed=12, what="fused sphere 1024", max_samples=1024)
+    _fused_check(w, g, vox, w["rays"][::3], seed=12, what=f"fused sphere {max_samples}",
+                 max_samples=max_samples)
 
 
 def test_fused_l2_step_room_full_batch(room):
@@ -419,7 +436,7 @@ def test_march_kernel_and_inkernel_march_agree(room):
     torch.testing.assert_close(fa, fb, rtol=1e-5, atol=1e-6 * fb.abs().max().item())
 
 
-@pytest.mark.parametrize("max_samples", [1, 65, 1024])
+@pytest.mark.parametrize("max_samples", [1, 65, 100, 129, 1024])
 def test_inkernel_march_sample_caps(sphere, max_samples):
     """The in-kernel march path (no workspace) against the oracle."""
     w, g, vox, rays = sphere
