@@ -1420,10 +1420,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(
   Scat<C>* sc_base = reinterpret_cast<Scat<C>*>(st_base + (int64_t)wpb * M_st);
   Scat<C>* sc = sc_base + w;
   SampleState* st_last = reinterpret_cast<SampleState*>(sc->val);
-  // Fused multi-chunk rays: t, grad f and features of every sample, kept
-  // from pass 1 for pass 2 (structure of arrays [4 + C][max_samples]) when
-  // the launch has the room; otherwise pass 2 interpolates again.
-  float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (4 + C) * M;
+  // Fused multi-chunk rays: grad f and features of every sample, kept from
+  // pass 1 for pass 2 (structure of arrays [3 + C][max_samples]; t follows
+  // from the lattice index again) when the launch has the room; otherwise
+  // pass 2 interpolates again.
+  float* vst = reinterpret_cast<float*>(sc_base + wpb) + (int64_t)w * (3 + C) * M;
   BatchRays rs((int64_t)blockIdx.x * wpb + w, (int64_t)gridDim.x * wpb, R);
   ListPrefetch pf;
   if (LIST) pf.load(lq, lc, M, rs.r, R);
@@ -1517,12 +1518,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         s.f = f;
         if constexpr (FUSED) {
           if (keep_v) {
-            vst[j] = cell.t;
-            vst[M + j] = grad[0];
-            vst[2 * M + j] = grad[1];
-            vst[3 * M + j] = grad[2];
+            vst[j] = grad[0];
+            vst[M + j] = grad[1];
+            vst[2 * M + j] = grad[2];
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) vst[(4 + ch) * M + j] = col[ch];
+            for (int ch = 0; ch < C; ++ch) vst[(3 + ch) * M + j] = col[ch];
           }
 #pragma unroll
           for (int ch = 0; ch < C; ++ch) accC[ch] = fmaf(s.w, col[ch], accC[ch]);
@@ -1568,11 +1568,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(
         if constexpr (FUSED) {
           float f, grad[3], col[C > 0 ? C : 1];
           if (keep_v) {
-            grad[0] = vst[M + j];
-            grad[1] = vst[2 * M + j];
-            grad[2] = vst[3 * M + j];
+            grad[0] = vst[j];
+            grad[1] = vst[M + j];
+            grad[2] = vst[2 * M + j];
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) col[ch] = vst[(4 + ch) * M + j];
+            for (int ch = 0; ch < C; ++ch) col[ch] = vst[(3 + ch) * M + j];
           } else {
             interpolate<C>(vox, cell, g.inv_h, f, grad, col);
           }
@@ -1925,7 +1925,7 @@ int sg_render_l2_step(const sg_grid* grid, const float* d_vox, int32_t C, const 
   // the 12 waves a CU's registers allow, three per SIMD, still fit its
   // 160 KiB of LDS with them) the values pass 2 reuses.
   const size_t base = bwd_lds_per_wave(C, p.max_samples);
-  const size_t vbytes = sizeof(float) * (size_t)(4 + C) * p.max_samples;
+  const size_t vbytes = sizeof(float) * (size_t)(3 + C) * p.max_samples;
   const bool keep_v = (base + vbytes) * 12 <= 160 * 1024;
   const Launch l = plan(n_rays, base + (keep_v ? vbytes : 0));
   const L2Ref ref = {d_ref_feat, d_ref_depth, d_ref_normal, lambda_d, lambda_n, lambda_e,
