@@ -662,18 +662,6 @@ __device__ __forceinline__ void shade_ray(const GridView& g, const float* __rest
   wave_sync();  // q is reused by the next ray of this wave
 }
 
-template <int C>
-__device__ __forceinline__ void render_ray(const GridView& g, const float* __restrict__ vox,
-                                           const Params& p, const float ray[6], int2* q, int64_t o,
-                                           float* __restrict__ feat_out, float* __restrict__ depth,
-                                           float* __restrict__ normal, float* __restrict__ wsum,
-                                           int32_t* __restrict__ nsamples) {
-  March m;
-  int n = 0;
-  if (march_setup(g, ray, p, m)) n = march_collect(g, m, p, q);
-  shade_ray<C>(g, vox, p, m, n, q, o, feat_out, depth, normal, wsum, nsamples);
-}
-
 template <int C, bool LIST>
 __global__ __launch_bounds__(256) void k_render_fwd(GridView g, const float* __restrict__ vox,
                                                     const float* __restrict__ rays, int64_t R,
@@ -838,6 +826,11 @@ __device__ __forceinline__ GridView view_of(const GridViewG& x) {
   return v;
 }
 
+// Each wave sets up a batch of its rays lane-parallel (slot lookup, the
+// slot's grid, pinhole ray and march clip for ray i in lane i, with that
+// grid's box read per lane); the rays are then marched and shaded one by
+// one with their grid's view in scalar registers, exactly as k_render_fwd
+// does, so every pixel gets the same bits as alone.
 template <int C>
 __global__ __launch_bounds__(256) void k_render_packed(const sg_packed_grid* __restrict__ grids,
                                                        int32_t n_grids,
@@ -850,30 +843,63 @@ __global__ __launch_bounds__(256) void k_render_packed(const sg_packed_grid* __r
   int2* q = lds_q + (int64_t)w * q_cap;
   const int32_t ns = min(*d_n_slots, max_slots);
   if (ns <= 0) return;
-  const int64_t total = slots[ns - 1].ray_base + slots[ns - 1].count;
   const SlotG* sl = reinterpret_cast<const SlotG*>(slots);
-  for (int64_t r = (int64_t)blockIdx.x * wpb + w; r < total; r += (int64_t)gridDim.x * wpb) {
-    int32_t lo = 0, hi = ns - 1;  // last slot with ray_base <= r
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (sl[mid].ray_base <= r) lo = mid;
-      else hi = mid - 1;
+  const int64_t total = sl[ns - 1].ray_base + sl[ns - 1].count;
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  const int lane = lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * wpb + w; base < total; base += (int64_t)kWave * stride) {
+    const int64_t rl = base + (int64_t)lane * stride;
+    int32_t lo = 0, gi = 0;
+    int64_t pix = 0;
+    March ml;
+    bool ok = false, use = false;
+    if (rl < total) {
+      int32_t hi = ns - 1;  // last slot with ray_base <= r
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (sl[mid].ray_base <= rl) lo = mid;
+        else hi = mid - 1;
+      }
+      const SlotG& S = sl[lo];
+      gi = S.grid;
+      // slots whose ranges leave a gap: rays in the gap belong to no slot
+      if (gi >= 0 && gi < n_grids && S.width > 0 && rl - S.ray_base < S.count) {
+        // descriptors are sg_packed_grid-sized (512 B) records, not PackedGrid-sized
+        const PackedGridG& G = *reinterpret_cast<const PackedGridG*>(grids + gi);
+        if (G.C == C && G.params.max_samples <= q_cap) {
+          use = true;
+          pix = S.pixel_begin + (rl - S.ray_base);
+          // a frame has fewer than 2^31 pixels: 32-bit division
+          const uint32_t pu = (uint32_t)pix, wu = (uint32_t)S.width;
+          const uint32_t row = pu / wu;
+          float ray[6];
+          pinhole_ray(S.cam, (int32_t)(pu - row * wu), (int32_t)row, ray);
+          ok = march_setup(view_of(G.view), ray, G.params, ml);
+        }
+      }
     }
-    const SlotG& S = sl[lo];
-    const int32_t gi = S.grid;
-    // slots whose ranges leave a gap: rays in the gap belong to no slot
-    if (gi < 0 || gi >= n_grids || S.width <= 0 || r - S.ray_base >= S.count) continue;
-    // descriptors are sg_packed_grid-sized (512 B) records, not PackedGrid-sized
-    const PackedGridG& G = *reinterpret_cast<const PackedGridG*>(grids + gi);
-    if (G.C != C || G.params.max_samples > q_cap) continue;
-    const int64_t pix = S.pixel_begin + (r - S.ray_base);
-    // a frame has fewer than 2^31 pixels: 32-bit division
-    const uint32_t pu = (uint32_t)pix, wu = (uint32_t)S.width;
-    const uint32_t row = pu / wu;
-    float ray[6];
-    pinhole_ray(S.cam, (int32_t)(pu - row * wu), (int32_t)row, ray);
-    render_ray<C>(view_of(G.view), (const float*)G.vox, G.params, ray, q, pix, (float*)S.feat,
-                  (float*)S.depth, (float*)S.normal, (float*)S.wsum, (int32_t*)S.nsamples);
+    const uint64_t use_m = __ballot(use), ok_m = __ballot(ok);
+    const int nb = (int)min((int64_t)kWave, (total - base + stride - 1) / stride);
+    for (int i = 0; i < nb; ++i) {
+      if (!((use_m >> i) & 1)) continue;
+      const SlotG& S = sl[__builtin_amdgcn_readlane(lo, i)];
+      const PackedGridG& G =
+          *reinterpret_cast<const PackedGridG*>(grids + __builtin_amdgcn_readlane(gi, i));
+      const int64_t pi = ((int64_t)__builtin_amdgcn_readlane((int32_t)(pix >> 32), i) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int32_t)pix, i);
+      March m;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        m.ov[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ml.ov[a]), i));
+        m.dv[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ml.dv[a]), i));
+      }
+      m.k_lo = __builtin_amdgcn_readlane(ml.k_lo, i);
+      m.k_hi = __builtin_amdgcn_readlane(ml.k_hi, i);
+      const GridView g = view_of(G.view);
+      const int n = ((ok_m >> i) & 1) ? march_collect(g, m, G.params, q) : 0;
+      shade_ray<C>(g, (const float*)G.vox, G.params, m, n, q, pi, (float*)S.feat, (float*)S.depth,
+                   (float*)S.normal, (float*)S.wsum, (int32_t*)S.nsamples);
+    }
   }
 }
 
