@@ -65,6 +65,7 @@ class Request:
     height: int
     arrival: float         # seconds, relative to the start of the run
     out: dict = field(default=None, repr=False)
+    out_ptrs: tuple = field(default=None, repr=False)  # device addresses of the outputs
     done: float = None     # completion time, seconds relative to the start of the run
 
     @property
@@ -76,11 +77,16 @@ class Request:
 
 
 def alloc_outputs(n, C, device):
-    return {"feat": torch.empty((n, C), dtype=torch.float32, device=device),
-            "depth": torch.empty(n, dtype=torch.float32, device=device),
-            "normal": torch.empty((n, 3), dtype=torch.float32, device=device),
-            "wsum": torch.empty(n, dtype=torch.float32, device=device),
-            "nsamples": torch.empty(n, dtype=torch.int32, device=device)}
+    """The five per-pixel outputs of a request as views of one allocation."""
+    buf = torch.empty(n * (C + 6), dtype=torch.float32, device=device)
+    o = {}
+    at = 0
+    for k, w in (("feat", C), ("depth", 1), ("normal", 3), ("wsum", 1), ("nsamples", 1)):
+        v = buf[at:at + n * w]
+        o[k] = v.view(n, w) if k in ("feat", "normal") else v
+        at += n * w
+    o["nsamples"] = o["nsamples"].view(torch.int32)
+    return o
 
 
 class _Clock:
@@ -175,18 +181,37 @@ class PackedServer:
         n = self.max_slots
         self.n_tables = max(2, int(n_tables))
         nt = self.n_tables
-        self.h_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8).pin_memory()
-                        for _ in range(nt)]
-        self.h_count = [torch.zeros(1, dtype=torch.int32).pin_memory() for _ in range(nt)]
-        self.d_slots = [torch.zeros(n * SLOT_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
-                        for _ in range(nt)]
-        self.d_count = [torch.zeros(1, dtype=torch.int32, device=self.dev) for _ in range(nt)]
+        # one table = [slot count (int32), padding to 256 B | slots]: filled in
+        # place in pinned memory and sent with one copy
+        hdr = self._hdr = 256
+        size = hdr + n * SLOT_DTYPE.itemsize
+        self.h_tab = [torch.zeros(size, dtype=torch.uint8).pin_memory() for _ in range(nt)]
+        self._h_count = [t.numpy()[:4].view(np.int32) for t in self.h_tab]
+        self._h_slots = [t.numpy()[hdr:].view(SLOT_DTYPE) for t in self.h_tab]
+        self.d_tab = [torch.zeros(size, dtype=torch.uint8, device=self.dev) for _ in range(nt)]
+        self.d_count = [ctypes.c_void_p(t.data_ptr()) for t in self.d_tab]
+        self.d_slots = [ctypes.c_void_p(t.data_ptr() + hdr) for t in self.d_tab]
         self.graphs = {}  # (table, grid or -1, rays) -> captured graph
         self.use_graph = use_graph
         self.busy = [None] * nt  # end event of the tick that last used each table
         self.max_inflight = nt if max_inflight is None else max(1, int(max_inflight))
         self.next_b = 0
         self.keep_outputs = keep_outputs
+        if use_graph:
+            # capture every (table, grid, launch size) now, on empty tables,
+            # so that no capture lands inside a run
+            for b in range(nt):
+                for gi in (range(self.n_grids) if self.launch_mode == "per_grid" else (0,)):
+                    for rays in self._launch_sizes():
+                        self._render(b, gi, rays)
+            torch.cuda.synchronize()
+
+    def _launch_sizes(self):
+        rays, out = 1 << 16, []
+        while rays < self.tick_rays:
+            out.append(rays)
+            rays <<= 1
+        return out + [self.tick_rays]
 
     def close(self):
         """Release the grids (extend is allowed again) and the captured graphs."""
@@ -207,12 +232,12 @@ class PackedServer:
         if self.launch_mode == "per_grid":
             g, vox, pc = self.grid_args[gi]
             check(lib().sg_render_forward_slots(g.handle, ptr(vox), self.C, ctypes.byref(pc),
-                                                ptr(self.d_slots[b]), ptr(self.d_count[b]),
+                                                self.d_slots[b], self.d_count[b],
                                                 self.max_slots, rays, stream_ptr(self.dev)),
                   "sg_render_forward_slots")
             return
-        check(lib().sg_render_forward_packed(ptr(self.d_grids), self.n_grids, ptr(self.d_slots[b]),
-                                             ptr(self.d_count[b]), self.max_slots, self.C,
+        check(lib().sg_render_forward_packed(ptr(self.d_grids), self.n_grids, self.d_slots[b],
+                                             self.d_count[b], self.max_slots, self.C,
                                              self.q_cap, rays, stream_ptr(self.dev)),
               "sg_render_forward_packed")
 
@@ -242,21 +267,19 @@ class PackedServer:
         self.next_b = (b + 1) % self.n_tables
         if self.busy[b] is not None:
             self.busy[b].synchronize()  # the table is free once its tick has finished
-        slots = np.zeros(len(work), dtype=SLOT_DTYPE)
+        slots = self._h_slots[b]
         base = 0
         for i, (req, p0, cnt) in enumerate(work):
-            o = req.out
-            slots[i] = (req.grid, req.width, p0, cnt, base, req.cam, o["feat"].data_ptr(),
-                        o["depth"].data_ptr(), o["normal"].data_ptr(), o["wsum"].data_ptr(),
-                        o["nsamples"].data_ptr())
+            slots[i] = (req.grid, req.width, p0, cnt, base, req.cam) + req.out_ptrs
             base += cnt
-        raw = slots.view(np.uint8)
-        self.h_slots[b][: raw.size].copy_(torch.from_numpy(raw))
-        self.h_count[b][0] = len(work)
-        self.d_slots[b][: raw.size].copy_(self.h_slots[b][: raw.size], non_blocking=True)
-        self.d_count[b].copy_(self.h_count[b], non_blocking=True)
-        total = sum(c for _, _, c in work)
-        self._render(b, work[0][0].grid, self.small_tick if total <= self.small_tick else self.tick_rays)
+        self._h_count[b][0] = len(work)
+        nbytes = self._hdr + len(work) * SLOT_DTYPE.itemsize
+        self.d_tab[b][:nbytes].copy_(self.h_tab[b][:nbytes], non_blocking=True)
+        total = base
+        # launch grid: the smallest of the launch sizes that holds the tick, so
+        # a tick of one small request does not launch a full tick's waves
+        rays = next(r for r in self._launch_sizes() if r >= total or r == self.tick_rays)
+        self._render(b, work[0][0].grid, rays)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         self.busy[b] = ev
@@ -300,7 +323,7 @@ class PackedServer:
             inflight = keep
             if not admitted or len(inflight) >= self.max_inflight:
                 if inflight:
-                    time.sleep(0.0002 if not admitted else 0.00005)
+                    time.sleep(0.00002)
                 elif i < len(pending):
                     wait = pending[i].arrival - clock.now()
                     if wait > 0:
@@ -323,6 +346,10 @@ class PackedServer:
                 cnt = min(budget, req.pixels - nxt)
                 if req.out is None:
                     req.out = alloc_outputs(req.pixels, self.C, self.dev)
+                    o = req.out
+                    req.out_ptrs = (o["feat"].data_ptr(), o["depth"].data_ptr(),
+                                    o["normal"].data_ptr(), o["wsum"].data_ptr(),
+                                    o["nsamples"].data_ptr())
                 work.append((req, nxt, cnt))
                 budget -= cnt
                 if nxt + cnt == req.pixels:
