@@ -1174,7 +1174,7 @@ struct SampleState {
 // Per-wave LDS: 8 KiB, with the ray's upstream feature gradient added in
 // LDS only when C > 4 (up to four channels it is selected from registers).
 struct ScatCore {
-  float val[16 * kWave];    // [a][lane]: SDF term of corner a, then w r_a at [8 + a][lane]
+  float2 val[8 * kWave];    // [a][lane]: (SDF term, w r_a) of corner a
   int32_t off[8 * kWave];   // [a][lane]: element offset of corner a
   int4 base[kWave];         // base voxel of the lane's cell; w = 1 if the lane holds a sample
   uint16_t pair[8 * kWave]; // owned (lane, corner) pairs, lane * 8 + a
@@ -1234,10 +1234,10 @@ __device__ __forceinline__ void scatter_chunk(Scat<C>* sc, bool act, const Cell&
     for (int a = 0; a < 8; ++a) {
       const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
       const float ra = wx[ax] * wy[ay] * wz[az];
-      sc->val[a * kWave + lane] = ra * df + (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gx +
-                                  (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gy +
-                                  (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gz;
-      sc->val[(8 + a) * kWave + lane] = w * ra;
+      const float vs = ra * df + (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gx +
+                       (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gy +
+                       (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gz;
+      sc->val[a * kWave + lane] = make_float2(vs, w * ra);
       sc->off[a * kWave + lane] = cell.off[a];
     }
   }
@@ -1277,8 +1277,9 @@ __device__ __forceinline__ void scatter_chunk(Scat<C>* sc, bool act, const Cell&
                        dz = (unsigned)(cz - bk.z);
         if (!bk.w || (dx | dy | dz) > 1u) break;
         const int ak = (int)(dx + 2 * dy + 4 * dz);
-        vs += sc->val[ak * kWave + k];
-        vw += sc->val[(8 + ak) * kWave + k];
+        const float2 v = sc->val[ak * kWave + k];
+        vs += v.x;
+        vw += v.y;
       }
       e_off = sc->off[a * kWave + j];
       e_vs = vs;
