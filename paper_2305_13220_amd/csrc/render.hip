@@ -352,14 +352,23 @@ __device__ __forceinline__ void cell_at(const GridView& g, const float x[3], int
   const int64_t bi = min(max((int64_t)block, (int64_t)0), g.n_blocks - 1);
   const int4* row = reinterpret_cast<const int4*>(g.nbr + 8 * bi);
   const int4 n0 = row[0], n1 = row[1];
-  const int32_t nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+  int32_t nb[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
   const int lx = i[0] & 7, ly = i[1] & 7, lz = i[2] & 7;
+  // Corner a lies in neighbour block a & o, o = the axes along which the
+  // cell crosses its block's upper face (local coordinate 7): one select
+  // stage per axis, in place, instead of an 8-way choice per corner.
+  const bool ox = lx == 7, oy = ly == 7, oz = lz == 7;
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int cx = lx + (a & 1), cy = ly + ((a >> 1) & 1), cz = lz + ((a >> 2) & 1);
-    const int s = (cx >> 3) | ((cy >> 3) << 1) | ((cz >> 3) << 2);
-    c.off[a] = max(nb[s], 0) * SG_BLOCK_VOXELS + (cx & 7) + 8 * (cy & 7) + 64 * (cz & 7);
-  }
+  for (int a = 1; a < 8; a += 2) nb[a] = ox ? nb[a] : nb[a - 1];
+#pragma unroll
+  for (int a = 2; a < 8; a += (a & 1) ? 3 : 1) nb[a] = oy ? nb[a] : nb[a - 2];
+#pragma unroll
+  for (int a = 4; a < 8; ++a) nb[a] = oz ? nb[a] : nb[a - 4];
+  const int px[2] = {lx, (lx + 1) & 7}, py[2] = {8 * ly, 8 * ((ly + 1) & 7)},
+            pz[2] = {64 * lz, 64 * ((lz + 1) & 7)};
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    c.off[a] = max(nb[a], 0) * SG_BLOCK_VOXELS + px[a & 1] + py[(a >> 1) & 1] + pz[a >> 2];
 }
 
 __device__ __forceinline__ void locate(const GridView& g, const March& m, const Params& p, int2 e,
@@ -412,15 +421,28 @@ __device__ __forceinline__ void interpolate(const float* __restrict__ vox, const
   f = 0.0f;
 #pragma unroll
   for (int ch = 0; ch < C; ++ch) feat[ch] = 0.0f;
+  // Records of up to four floats: the eight loads are written before any
+  // use, so that they are in flight together (the compiler otherwise may
+  // wait on each before the next where registers are tight); longer records
+  // are consumed corner by corner.
+  constexpr int kAhead = 1 + C <= 4 ? 8 : 1;
+  float th[kAhead][1 + C];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    float th[1 + C];
-    load_voxel<C>(vox, c.off[a], th);
-    const float r = wx[a & 1] * wy[(a >> 1) & 1] * wz[(a >> 2) & 1];
-    sdf[a] = th[0];
-    f += r * th[0];
+    if (kAhead == 8) {
+      if (a == 0) {
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch) feat[ch] += r * th[1 + ch];
+        for (int b = 0; b < 8; ++b) load_voxel<C>(vox, c.off[b], th[b % kAhead]);
+      }
+    } else {
+      load_voxel<C>(vox, c.off[a], th[0]);
+    }
+    const float* t = th[a % kAhead];
+    const float r = wx[a & 1] * wy[(a >> 1) & 1] * wz[(a >> 2) & 1];
+    sdf[a] = t[0];
+    f += r * t[0];
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch) feat[ch] += r * t[1 + ch];
   }
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
 #pragma unroll
