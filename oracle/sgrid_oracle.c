@@ -324,8 +324,13 @@ static void corner_weights(const float uf[3], double r[8], double dr[8][3]) {
  * the same polynomial; grouping the two ends of each edge first makes a
  * direction in which the SDF is constant give exactly zero.
  */
-static void interpolate(const sample* s, const double* vox, int C, double h,
-                        double* f, double grad[3], double* feat) {
+/*
+ * gmag (nullable): per axis, sum over the cell's edges along it of
+ * |dr| (|theta_1| + |theta_0|) / h, the size of every term of the gradient
+ * before the edge differences cancel: the scale of its float32 rounding.
+ */
+static void interpolate_mag(const sample* s, const double* vox, int C, double h,
+                            double* f, double grad[3], double* feat, double gmag[3]) {
   double r[8], dr[8][3], th0[8];
   corner_weights(s->u, r, dr);
   *f = 0.0;
@@ -339,10 +344,20 @@ static void interpolate(const sample* s, const double* vox, int C, double h,
   for (int ax = 0; ax < 3; ++ax) {
     const int bit = 1 << ax;
     double g = 0.0;
+    double gm = 0.0;
     for (int a = 0; a < 8; ++a)
-      if (!(a & bit)) g += dr[a | bit][ax] * (th0[a | bit] - th0[a]); /* dr of the x=1 end: +w w */
+      if (!(a & bit)) {
+        g += dr[a | bit][ax] * (th0[a | bit] - th0[a]); /* dr of the x=1 end: +w w */
+        gm += fabs(dr[a | bit][ax]) * (fabs(th0[a | bit]) + fabs(th0[a]));
+      }
     grad[ax] = g / h;
+    if (gmag) gmag[ax] = gm / h;
   }
+}
+
+static void interpolate(const sample* s, const double* vox, int C, double h,
+                        double* f, double grad[3], double* feat) {
+  interpolate_mag(s, vox, C, h, f, grad, feat, NULL);
 }
 
 /* Laplace-CDF density sigma(f) = (1/beta) Psi_beta(-f) and d sigma / d f. */
@@ -497,7 +512,9 @@ int or_eikonal_rays(const int32_t* block_coords, int64_t n_blocks, const double*
 /*
  * For every ray: feat_out [R,C], depth [R], normal [R,3], wsum [R],
  * nsamples [R]; plus the magnitudes sum_k |w_k v_k| of every output element
- * (mag_* arrays, same shapes, nullable) used to scale tolerances.
+ * (mag_* arrays, same shapes, nullable) used to scale tolerances; for the
+ * normal, v_k is the sum of the absolute terms of the edge-grouped gradient
+ * (before its edge differences cancel), so the scale bounds its rounding.
  */
 int or_render_forward(const int32_t* block_coords, int64_t n_blocks, const double* vox,
                       int32_t C, float h, const float org[3], const float* rays, int64_t R,
@@ -526,8 +543,8 @@ int or_render_forward(const int32_t* block_coords, int64_t n_blocks, const doubl
     for (int ch = 0; ch < C; ++ch) accC[ch] = magC[ch] = 0.0;
     double tau = 0.0; /* sum_{j<k} sigma_j delta_j */
     for (int q = 0; q < n; ++q) {
-      double f, grad[3];
-      interpolate(&smp[q], vox, C, (double)h, &f, grad, c);
+      double f, grad[3], gm[3];
+      interpolate_mag(&smp[q], vox, C, (double)h, &f, grad, c, gm);
       double sigma = density(f, (double)beta, NULL);
       double T = exp(-tau);
       double alpha = -expm1(-sigma * (double)step); /* 1 - exp(-sigma delta) */
@@ -540,7 +557,7 @@ int or_render_forward(const int32_t* block_coords, int64_t n_blocks, const doubl
       magD += fabs(w * (double)smp[q].t);
       for (int a = 0; a < 3; ++a) {
         accN[a] += w * grad[a];
-        magN[a] += fabs(w * grad[a]);
+        magN[a] += fabs(w) * gm[a]; /* >= |w grad|: the terms before cancellation */
       }
       accW += w;
       tau += sigma * (double)step;

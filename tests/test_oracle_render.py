@@ -11,7 +11,10 @@ Each check compares the oracle with something other than its own formula:
     continuum offset, normal = -d;
   * compositing two halves of a ray with (T1 T2, A1 + T1 A2) gives the whole;
   * empty and non-finite rays give exact zeros;
-  * the adjoint equals float64 central differences of the forward.
+  * the adjoint equals float64 central differences of the forward;
+  * the normal's tolerance scale is the size of the gradient's terms before
+    its edge differences cancel (a cell whose edge differences cancel exactly:
+    normal 0, scale w * 4 in closed form).
 """
 import numpy as np
 import pytest
@@ -235,3 +238,40 @@ def test_backward_matches_central_differences(oracle_lib):
         vm[b, v, ch] -= eps
         fd = (_loss(oracle_lib, w, vp, rays, prm, g) - _loss(oracle_lib, w, vm, rays, prm, g)) / (2 * eps)
         assert abs(fd - grad[b, v, ch]) <= 1e-6 * mag[b, v, ch] + 1e-9, (b, v, ch, fd, grad[b, v, ch])
+
+
+def test_normal_scale_counts_terms_before_cancellation(oracle_lib):
+    """One sample at the centre of a cell face (u = (1/2, 1/2, 0)) in a single
+    block, h = 1: the cell's SDF corners are 1, 3 (x edge +2) and 3, 1 (x edge
+    -2) on the z = 0 face and 2 on the z = 1 face, so every gradient component
+    cancels to 0 while each sums four terms of size 1/2 (|theta_1| + |theta_0|)
+    (or 1/4 of it along z): the tolerance scale of the normal is w (4, 4, 4)."""
+    C = 1
+    blocks = np.zeros((1, 3), np.int32)
+    vox = np.full((1, 512, 1 + C), 2.0)
+    vox[..., 1] = 0.5
+
+    def at(x, y, z):
+        return x + 8 * y + 64 * z
+
+    vox[0, at(3, 2, 0), 0] = 1.0
+    vox[0, at(4, 2, 0), 0] = 3.0
+    vox[0, at(3, 3, 0), 0] = 3.0
+    vox[0, at(4, 3, 0), 0] = 1.0
+    ray = np.array([[3.5, 2.5, -5.0, 0.0, 0.0, 1.0]], np.float32)
+    prm = _params(0.5, 0.0, 20.0, 1.0, 1)
+    out = oracle_lib.render_forward(blocks, vox, C, np.float32(1.0), np.zeros(3, np.float32), ray,
+                                    prm, with_mag=True)
+    assert out["nsamples"][0] == 1
+    f = 0.25 * (1.0 + 3.0 + 3.0 + 1.0)
+    sigma = 0.5 * np.exp(-f)  # beta = 1, f >= 0
+    w = -np.expm1(-sigma * 0.5)
+    assert out["wsum"][0] == pytest.approx(w, rel=1e-12)
+    np.testing.assert_allclose(out["normal"][0], 0.0, atol=1e-15)
+    np.testing.assert_allclose(out["mag_normal"][0], 4.0 * w, rtol=1e-12)
+    # never below the magnitude after cancellation, on an ordinary scene
+    P = _plane_setup(cos_theta=0.7)
+    prm = _params(float(H) / 2, P["t_hit"] - 0.6, P["t_hit"] + 0.8, P["beta"], 128)
+    o = oracle_lib.render_forward(P["blocks"], P["vox"], 1, H, np.zeros(3, np.float32),
+                                  P["ray"][None], prm, with_mag=True)
+    assert np.all(o["mag_normal"] >= np.abs(o["normal"]) * (1 - 1e-12))
