@@ -1792,6 +1792,9 @@ static Launch plan(int64_t R, size_t lds_per_wave, int wpb = 1, int rays_per_wav
   return l;
 }
 
+// Rays per wave of the packed serving launches.
+constexpr int kPackedRays = 16;
+
 #define SG_DISPATCH_C(C, ...)                         \
   switch (C) {                                        \
     case 0: { constexpr int CC = 0; __VA_ARGS__; } break;   \
@@ -2037,7 +2040,10 @@ int sg_render_forward_packed(const sg_packed_grid* d_grids, int32_t n_grids,
   if (max_samples_cap < 1 || max_samples_cap > SG_MAX_SAMPLES_LIMIT)
     return fail(SG_EINVAL, "max_samples_cap must be in [1, 1024]");
   if (launch_rays < 1) return fail(SG_EINVAL, "launch_rays must be >= 1");
-  const Launch l = plan(launch_rays, sizeof(int2) * max_samples_cap, 4, 4);
+  // 16 rays per wave: a batch's set-up (slot search, slot, descriptor: several
+  // dependent memory round trips) is shared by more rays than the plain
+  // forward's (one ray load) needs to be
+  const Launch l = plan(launch_rays, sizeof(int2) * max_samples_cap, 4, kPackedRays);
   hipStream_t s = (hipStream_t)stream;
   if (reinterpret_cast<uintptr_t>(d_grids) % alignof(PackedGrid) != 0)
     return fail(SG_EINVAL, "d_grids must be 8-byte aligned");
@@ -2061,7 +2067,7 @@ int sg_render_forward_slots(const sg_grid* grid, const float* d_vox, int32_t C,
   if (max_slots < 1) return fail(SG_EINVAL, "max_slots must be >= 1");
   if (launch_rays < 1) return fail(SG_EINVAL, "launch_rays must be >= 1");
   const GridView g = view_of(grid);
-  const Launch l = plan(launch_rays, sizeof(int2) * p.max_samples, 4, 4);
+  const Launch l = plan(launch_rays, sizeof(int2) * p.max_samples, 4, kPackedRays);
   SG_DISPATCH_C(C, hipLaunchKernelGGL(k_render_slots<CC>, dim3(l.blocks), dim3(l.threads), l.lds,
                                       (hipStream_t)stream, g, d_vox, p, d_slots, d_n_slots,
                                       max_slots));
