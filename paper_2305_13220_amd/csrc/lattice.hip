@@ -86,12 +86,37 @@ __device__ inline int32_t vertex_coord(const Simplex& s, int d, int r, int i) {
   return s.rank[i] <= d - r ? s.rem0[i] + r : s.rem0[i] + r - (d + 1);
 }
 
-// 64-bit fingerprint of a key (never the empty marker).
-__device__ inline uint64_t key_fp(const int32_t* k, int d) {
-  uint64_t h = 0x9e3779b97f4a7c15ull;
-  for (int i = 0; i < d; ++i) h = mix64(h ^ ((uint64_t)(uint32_t)k[i] + 0x632be59bd9b4e019ull * (i + 1)));
+// 64-bit fingerprint of a key (never the empty marker): a mixed linear form
+// sum_i k_i P_i (mod 2^64) with fixed pseudo-random odd multipliers P_i.  The
+// form is additive, so the neighbours of a vertex along the lattice
+// directions (key + the same offset vector, up to sign) are fingerprinted
+// from the vertex's form with one multiply-add each.  Two keys share a
+// fingerprint only if their forms collide; the build checks every vertex
+// against its full key, and every neighbour found is checked too.
+__host__ __device__ constexpr uint64_t lat_coef_of(int i) {
+  uint64_t z = 0x632be59bd9b4e019ull * (uint64_t)(i + 1) + 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return (z ^ (z >> 31)) | 1ull;
+}
+#define SG_LC(i) lat_coef_of(i)
+__constant__ uint64_t kLatCoef[kLatMaxD] = {
+    SG_LC(0),  SG_LC(1),  SG_LC(2),  SG_LC(3),  SG_LC(4),  SG_LC(5),  SG_LC(6),  SG_LC(7),
+    SG_LC(8),  SG_LC(9),  SG_LC(10), SG_LC(11), SG_LC(12), SG_LC(13), SG_LC(14), SG_LC(15),
+    SG_LC(16), SG_LC(17), SG_LC(18), SG_LC(19), SG_LC(20), SG_LC(21), SG_LC(22), SG_LC(23)};
+#undef SG_LC
+static_assert(kLatMaxD == 24, "one multiplier per key coordinate");
+
+__device__ inline uint64_t key_lin(const int32_t* k, int d) {
+  uint64_t h = 0;
+  for (int i = 0; i < d; ++i) h += (uint64_t)(int64_t)k[i] * kLatCoef[i];
+  return h;
+}
+__device__ inline uint64_t lin_fp(uint64_t lin) {
+  const uint64_t h = mix64(lin ^ 0x9e3779b97f4a7c15ull);
   return h == kEmptyKey ? h - 1 : h;
 }
+__device__ inline uint64_t key_fp(const int32_t* k, int d) { return lin_fp(key_lin(k, d)); }
 
 struct LatView {
   uint64_t* fp;    // [cap] fingerprints (kEmptyKey: free)
@@ -100,9 +125,10 @@ struct LatView {
   int d;
 };
 
-// Slot of a key: insert (the CAS winner writes the full key) or find.
-__device__ inline int64_t lat_slot(const LatView& L, const int32_t* k, bool insert) {
-  const uint64_t f = key_fp(k, L.d);
+// Slot of a key of fingerprint f: insert (the CAS winner writes the full
+// key) or find.
+__device__ inline int64_t lat_slot_fp(const LatView& L, const int32_t* k, uint64_t f,
+                                      bool insert) {
   uint64_t s = mix64(f) & L.mask;
   for (;;) {
     const uint64_t cur = insert ? (uint64_t)atomicCAS((unsigned long long*)&L.fp[s],
@@ -117,6 +143,10 @@ __device__ inline int64_t lat_slot(const LatView& L, const int32_t* k, bool inse
     if (cur == f) return (int64_t)s;
     s = (s + 1) & L.mask;
   }
+}
+
+__device__ inline int64_t lat_slot(const LatView& L, const int32_t* k, bool insert) {
+  return lat_slot_fp(L, k, key_fp(k, L.d), insert);
 }
 
 // Per point: simplex, insertion of its d+1 vertices (mode 0), or the check
@@ -214,27 +244,39 @@ __global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __rest
 template <int MAXD>
 __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int64_t nv,
                                 int32_t* __restrict__ nbr) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one lane per vertex, every direction: the key is read once, and each
+  // neighbour's fingerprint is the vertex's linear form plus or minus the
+  // direction's offset form
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int d = L.d;
-  if (t >= nv * (d + 1)) return;
-  const int j = (int)(t / nv);
-  const int64_t k = t - (int64_t)j * nv;
+  if (k >= nv) return;
   const int64_t s = list[k];
-  int32_t nk[MAXD];
+  int32_t key[MAXD];
+  uint64_t lin = 0, sum = 0;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int sgn = h == 0 ? -1 : 1;
-#pragma unroll
-    for (int c = 0; c < MAXD; ++c)
-      nk[c] = c < d ? L.keys[s * d + c] + sgn * (c == j ? -d : 1) : 0;
-    int64_t n = lat_slot(L, nk, false);
-    if (n >= 0) {
-      bool same = true;
-#pragma unroll
-      for (int c = 0; c < MAXD; ++c) same = same && (c >= d || L.keys[n * d + c] == nk[c]);
-      if (!same) n = -1;  // a fingerprint alias of an absent key: no neighbour
+  for (int c = 0; c < MAXD; ++c) {
+    key[c] = c < d ? L.keys[s * d + c] : 0;
+    if (c < d) {
+      lin += (uint64_t)(int64_t)key[c] * kLatCoef[c];
+      sum += kLatCoef[c];
     }
-    nbr[2 * t + h] = (int32_t)n;
+  }
+  for (int j = 0; j <= d; ++j) {
+    // offset of direction j: +1 on every coordinate, -d on coordinate j
+    const uint64_t off = sum - (j < d ? (uint64_t)(d + 1) * kLatCoef[j] : 0ull);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int sgn = h == 0 ? -1 : 1;
+      int64_t n = lat_slot_fp(L, nullptr, lin_fp(h == 0 ? lin - off : lin + off), false);
+      if (n >= 0) {
+        bool same = true;
+#pragma unroll
+        for (int c = 0; c < MAXD; ++c)
+          same = same && (c >= d || L.keys[n * d + c] == key[c] + sgn * (c == j ? -d : 1));
+        if (!same) n = -1;  // a fingerprint alias of an absent key: no neighbour
+      }
+      nbr[2 * ((int64_t)j * nv + k) + h] = (int32_t)n;
+    }
   }
 }
 
@@ -759,13 +801,12 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
       return fail(SG_ENOMEM, "device allocation for the lattice failed");
     }
     if (nv > 0) {
-      const int64_t n_t = nv * (d + 1);
       if (d <= 8)
-        k_lat_neighbors<8><<<grid_of(n_t, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+        k_lat_neighbors<8><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, L->nbr);
       else if (d <= 16)
-        k_lat_neighbors<16><<<grid_of(n_t, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+        k_lat_neighbors<16><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, L->nbr);
       else
-        k_lat_neighbors<kLatMaxD><<<grid_of(n_t, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+        k_lat_neighbors<kLatMaxD><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, L->nbr);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) {
