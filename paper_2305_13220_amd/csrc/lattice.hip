@@ -24,39 +24,58 @@ constexpr int kLatMaxV = 32;
 // rounded to the nearest remainder-0 lattice point through the ranks of the
 // residuals, and the barycentric weights follow from the sorted residuals.
 // Vertex r has coordinates rem0[i] + r (rank[i] <= d - r) or
-// rem0[i] + r - (d+1) otherwise; only the first d are stored.
+// rem0[i] + r - (d+1) otherwise; only the first d are stored.  MAXD bounds d
+// at compile time: every loop runs to it with a guard, so the arrays stay in
+// registers (a loop to the run-time d puts them in scratch memory).
+template <int MAXD>
 struct Simplex {
-  int32_t rem0[kLatMaxD + 1], rank[kLatMaxD + 1];
-  float w[kLatMaxD + 2];
+  int32_t rem0[MAXD + 1], rank[MAXD + 1];
+  float w[MAXD + 2];
 };
 
-__device__ inline void lattice_simplex(const float* __restrict__ pos, int d, Simplex& s) {
+template <int MAXD>
+__device__ inline void lattice_simplex(const float* __restrict__ pos, int d, Simplex<MAXD>& s) {
 #pragma clang fp contract(off)
-  float el[kLatMaxD + 1];
+  float el[MAXD + 1];
   float sm = 0.0f;
-  for (int i = d; i >= 1; --i) {
-    const float scale = (float)(d + 1) * sqrtf(2.0f / 3.0f) / sqrtf((float)(i * (i + 1)));
-    const float cf = pos[i - 1] * scale;
-    el[i] = sm - (float)i * cf;
-    sm += cf;
+#pragma unroll
+  for (int i = MAXD; i >= 1; --i) {
+    if (i <= d) {
+      const float scale = (float)(d + 1) * sqrtf(2.0f / 3.0f) / sqrtf((float)(i * (i + 1)));
+      const float cf = pos[i - 1] * scale;
+      el[i] = sm - (float)i * cf;
+      sm += cf;
+    } else {
+      el[i] = 0.0f;
+    }
   }
   el[0] = sm;
   int sum = 0;
   const float inv = 1.0f / (float)(d + 1);
-  for (int i = 0; i <= d; ++i) {
-    const float v = el[i] * inv;
-    const float up = ceilf(v) * (float)(d + 1), dn = floorf(v) * (float)(d + 1);
-    s.rem0[i] = (int32_t)((up - el[i] < el[i] - dn) ? up : dn);
-    sum += s.rem0[i] / (d + 1);
+#pragma unroll
+  for (int i = 0; i <= MAXD; ++i) {
+    s.rem0[i] = 0;
     s.rank[i] = 0;
-  }
-  for (int i = 0; i < d; ++i)
-    for (int j = i + 1; j <= d; ++j) {
-      const float di = el[i] - (float)s.rem0[i], dj = el[j] - (float)s.rem0[j];
-      if (di < dj) ++s.rank[i];
-      else ++s.rank[j];
+    if (i <= d) {
+      const float v = el[i] * inv;
+      const float up = ceilf(v) * (float)(d + 1), dn = floorf(v) * (float)(d + 1);
+      s.rem0[i] = (int32_t)((up - el[i] < el[i] - dn) ? up : dn);
+      sum += s.rem0[i] / (d + 1);
     }
-  for (int i = 0; i <= d; ++i) {
+  }
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i)
+#pragma unroll
+    for (int j = i + 1; j <= MAXD; ++j) {
+      if (j <= d) {
+        const float di = el[i] - (float)s.rem0[i], dj = el[j] - (float)s.rem0[j];
+        if (di < dj) ++s.rank[i];
+        else ++s.rank[j];
+      }
+    }
+#pragma unroll
+  for (int i = 0; i <= MAXD; ++i) {
+    if (i > d) continue;
     if (sum > 0) {
       if (s.rank[i] >= d + 1 - sum) {
         s.rank[i] -= d + 1 - sum;
@@ -73,16 +92,30 @@ __device__ inline void lattice_simplex(const float* __restrict__ pos, int d, Sim
       }
     }
   }
-  for (int i = 0; i <= d + 1; ++i) s.w[i] = 0.0f;
-  for (int i = 0; i <= d; ++i) {
-    const float t = (el[i] - (float)s.rem0[i]) * inv;
-    s.w[d - s.rank[i]] += t;
-    s.w[d + 1 - s.rank[i]] -= t;
+  // w[d - rank_i] += t_i and w[d + 1 - rank_i] -= t_i, i in order: slot by
+  // slot, the same updates in the same order, picked by compares rather than
+  // an index into a register array
+  float t[MAXD + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXD; ++i) t[i] = i <= d ? (el[i] - (float)s.rem0[i]) * inv : 0.0f;
+  float wd1 = 0.0f;  // w[d + 1]
+#pragma unroll
+  for (int q = 0; q <= MAXD + 1; ++q) {
+    float wq = 0.0f;
+#pragma unroll
+    for (int i = 0; i <= MAXD; ++i) {
+      if (i > d) continue;
+      if (s.rank[i] == d - q) wq += t[i];
+      if (s.rank[i] == d + 1 - q) wq -= t[i];
+    }
+    s.w[q] = wq;
+    if (q == d + 1) wd1 = wq;
   }
-  s.w[0] += 1.0f + s.w[d + 1];
+  s.w[0] += 1.0f + wd1;
 }
 
-__device__ inline int32_t vertex_coord(const Simplex& s, int d, int r, int i) {
+template <int MAXD>
+__device__ inline int32_t vertex_coord(const Simplex<MAXD>& s, int d, int r, int i) {
   return s.rank[i] <= d - r ? s.rem0[i] + r : s.rem0[i] + r - (d + 1);
 }
 
@@ -107,16 +140,22 @@ __constant__ uint64_t kLatCoef[kLatMaxD] = {
 #undef SG_LC
 static_assert(kLatMaxD == 24, "one multiplier per key coordinate");
 
+// (MAXD bounds d at compile time, so a key held in registers is indexed by
+// constants: a loop to the run-time d would put it in scratch memory.)
+template <int MAXD>
 __device__ inline uint64_t key_lin(const int32_t* k, int d) {
   uint64_t h = 0;
-  for (int i = 0; i < d; ++i) h += (uint64_t)(int64_t)k[i] * kLatCoef[i];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i)
+    if (i < d) h += (uint64_t)(int64_t)k[i] * kLatCoef[i];
   return h;
 }
 __device__ inline uint64_t lin_fp(uint64_t lin) {
   const uint64_t h = mix64(lin ^ 0x9e3779b97f4a7c15ull);
   return h == kEmptyKey ? h - 1 : h;
 }
-__device__ inline uint64_t key_fp(const int32_t* k, int d) { return lin_fp(key_lin(k, d)); }
+template <int MAXD>
+__device__ inline uint64_t key_fp(const int32_t* k, int d) { return lin_fp(key_lin<MAXD>(k, d)); }
 
 struct LatView {
   uint64_t* fp;    // [cap] fingerprints (kEmptyKey: free)
@@ -127,6 +166,7 @@ struct LatView {
 
 // Slot of a key of fingerprint f: insert (the CAS winner writes the full
 // key) or find.
+template <int MAXD>
 __device__ inline int64_t lat_slot_fp(const LatView& L, const int32_t* k, uint64_t f,
                                       bool insert) {
   uint64_t s = mix64(f) & L.mask;
@@ -137,7 +177,9 @@ __device__ inline int64_t lat_slot_fp(const LatView& L, const int32_t* k, uint64
                                 : L.fp[s];
     if (cur == kEmptyKey) {
       if (!insert) return -1;
-      for (int i = 0; i < L.d; ++i) L.keys[s * L.d + i] = k[i];
+#pragma unroll
+      for (int i = 0; i < MAXD; ++i)
+        if (i < L.d) L.keys[s * L.d + i] = k[i];
       return (int64_t)s;
     }
     if (cur == f) return (int64_t)s;
@@ -145,14 +187,16 @@ __device__ inline int64_t lat_slot_fp(const LatView& L, const int32_t* k, uint64
   }
 }
 
+template <int MAXD>
 __device__ inline int64_t lat_slot(const LatView& L, const int32_t* k, bool insert) {
-  return lat_slot_fp(L, k, key_fp(k, L.d), insert);
+  return lat_slot_fp<MAXD>(L, k, key_fp<MAXD>(k, L.d), insert);
 }
 
 // Per point: simplex, insertion of its d+1 vertices (mode 0), or the check
 // that every vertex's slot holds its full key (mode 1: a fingerprint
 // collision raises the error flag).
-__global__ void k_lat_simplex(const float* __restrict__ pos, int64_t N, LatView L, int mode,
+template <int MAXD>
+__global__ __launch_bounds__(256) void k_lat_simplex(const float* __restrict__ pos, int64_t N, LatView L, int mode,
                               int32_t* __restrict__ vid, float* __restrict__ bw,
                               int* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,19 +210,23 @@ __global__ void k_lat_simplex(const float* __restrict__ pos, int64_t N, LatView 
       atomicOr(err, 2);
       return;
     }
-  Simplex s;
-  lattice_simplex(pos + i * d, d, s);
-  int32_t k[kLatMaxD];
-  for (int r = 0; r <= d; ++r) {
-    for (int c = 0; c < d; ++c) k[c] = vertex_coord(s, d, r, c);
+  Simplex<MAXD> s;
+  lattice_simplex<MAXD>(pos + i * d, d, s);
+  int32_t k[MAXD];
+#pragma unroll
+  for (int r = 0; r <= MAXD; ++r) {
+    if (r > d) continue;
+#pragma unroll
+    for (int c = 0; c < MAXD; ++c) k[c] = c < d ? vertex_coord(s, d, r, c) : 0;
     if (mode == 0) {
-      const int64_t slot = lat_slot(L, k, true);
+      const int64_t slot = lat_slot<MAXD>(L, k, true);
       vid[i * (d + 1) + r] = (int32_t)slot;
       bw[i * (d + 1) + r] = s.w[r];
     } else {
       const int64_t slot = vid[i * (d + 1) + r];
       bool same = true;
-      for (int c = 0; c < d; ++c) same = same && L.keys[slot * d + c] == k[c];
+#pragma unroll
+      for (int c = 0; c < MAXD; ++c) same = same && (c >= d || L.keys[slot * d + c] == k[c]);
       if (!same) atomicOr(err, 1);
     }
   }
@@ -267,7 +315,7 @@ __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int sgn = h == 0 ? -1 : 1;
-      int64_t n = lat_slot_fp(L, nullptr, lin_fp(h == 0 ? lin - off : lin + off), false);
+      int64_t n = lat_slot_fp<MAXD>(L, nullptr, lin_fp(h == 0 ? lin - off : lin + off), false);
       if (n >= 0) {
         bool same = true;
 #pragma unroll
@@ -774,8 +822,14 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
       hipMemsetAsync(d_n, 0, sizeof(int64_t), s) != hipSuccess) {
     rc = fail(SG_EHIP, "hipMemsetAsync failed");
   } else {
-    k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 0, L->vid, L->bw, d_err);
-    k_lat_simplex<<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, 1, L->vid, L->bw, d_err);
+    for (int mode = 0; mode < 2; ++mode) {
+      if (d <= 8)
+        k_lat_simplex<8><<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, mode, L->vid, L->bw, d_err);
+      else if (d <= 16)
+        k_lat_simplex<16><<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, mode, L->vid, L->bw, d_err);
+      else
+        k_lat_simplex<kLatMaxD><<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, mode, L->vid, L->bw, d_err);
+    }
     k_lat_compact<<<grid_of(L->cap, kLatCompactT), kLatCompactT, 0, s>>>(
         L->fp, L->cap, (unsigned long long*)d_n, L->list);
     hipError_t e = hipGetLastError();
