@@ -211,7 +211,13 @@ __global__ __launch_bounds__(kDenoiseT) void k_denoise_sep(GridView g,
   float* inv = mk + n3;            // [512] 1 / weight sum of each voxel of the block
   __shared__ int32_t nb[27];
   __shared__ float w1[2 * R + 1];
-  const int64_t b = blockIdx.x;
+  // Workgroups are dealt to the 8 XCDs round-robin and each XCD has its own
+  // L2: XCD x takes the x-th eighth of the blocks, in their index order
+  // (allocation order, which follows the frames and so keeps neighbours
+  // close), so the halo a block reads was mostly just read by its neighbours
+  // on the same L2.  Every block costs the same, so the eighths balance.
+  const int64_t nb_all = gridDim.x, xcd = blockIdx.x % 8, per = nb_all / 8, rem = nb_all % 8;
+  const int64_t b = xcd * per + (xcd < rem ? xcd : rem) + blockIdx.x / 8;
   const int t = threadIdx.x;
   const int32_t bc[3] = {coords[3 * b], coords[3 * b + 1], coords[3 * b + 2]};
   if (t < 27) {
