@@ -173,10 +173,29 @@ __host__ __device__ constexpr int denoise_group(int V, int radius) {
   return (V % 4 == 0 && gmax >= 4) ? (gb + 3) / 4 * 4 : gb;
 }
 
+// Channels a voxel record keeps in LDS until its last group is filtered:
+// with several groups, the outputs of all but the last are held back and
+// every record is written once, whole, after the last group (written group
+// by group, the partly written lines of a block's output left the L2 between
+// the groups and went to memory twice).  Only where it stays within the
+// 80 KiB of two workgroups per CU; otherwise each group writes directly.
+__host__ __device__ constexpr int denoise_held(int V, int radius) {
+  const int G = denoise_group(V, radius), n3 = denoise_side(radius) * denoise_side(radius) *
+                                                denoise_side(radius);
+  const int ng = (V + G - 1) / G, last = V - (ng - 1) * G;
+  const int held = ng > 1 ? V - last : 0;
+  const int bytes = 4 * (n3 * G + n3 + SG_BLOCK_VOXELS + SG_BLOCK_VOXELS * held);
+  return held > 0 && bytes <= 80 * 1024 && SG_BLOCK_VOXELS * V <= n3 * G &&
+                 64 * last <= 1024
+             ? held
+             : 0;
+}
+
 template <int C, int R>
 static size_t denoise_lds_bytes() {
   constexpr int side = denoise_side(R), n3 = side * side * side;
-  return sizeof(float) * ((size_t)n3 * denoise_group(1 + C, R) + n3 + SG_BLOCK_VOXELS);
+  return sizeof(float) * ((size_t)n3 * denoise_group(1 + C, R) + n3 + SG_BLOCK_VOXELS +
+                          (size_t)SG_BLOCK_VOXELS * denoise_held(1 + C, R));
 }
 
 // One 1-D pass of width 2R + 1 in place over a line of side values at
@@ -205,10 +224,13 @@ __global__ __launch_bounds__(kDenoiseT) void k_denoise_sep(GridView g,
   constexpr int V = 1 + C;
   constexpr int side = denoise_side(R), n2 = side * side, n3 = n2 * side;
   constexpr int G = denoise_group(V, R);
-  extern __shared__ float lds[];
+  extern __shared__ float4 lds_q4[];  // 16-byte aligned: the tile takes 16-byte accesses
+  float* lds = reinterpret_cast<float*>(lds_q4);
   float* tile = lds;               // [n3][G]: voxel (x, y, z) at x + side (y + side z)
   float* mk = lds + n3 * G;        // [n3] the mask, then its passes
   float* inv = mk + n3;            // [512] 1 / weight sum of each voxel of the block
+  constexpr int HELD = denoise_held(V, R);
+  float* held = inv + SG_BLOCK_VOXELS;  // [512][HELD] outputs of the earlier groups
   __shared__ int32_t nb[27];
   __shared__ float w1[2 * R + 1];
   // Workgroups are dealt to the 8 XCDs round-robin and each XCD has its own
@@ -283,6 +305,41 @@ __global__ __launch_bounds__(kDenoiseT) void k_denoise_sep(GridView g,
       denoise_line<R>(tile + ((l & 7) + n2 * (l >> 3)) * G + j, side * G, w1);
     }
     __syncthreads();
+    if (HELD > 0 && c0 + gc == V) {
+      // last group: each lane's column (at most one per lane) into registers,
+      // then the whole records assembled over the tile and stored once
+      const bool has = t < 64 * gc;
+      const int l = has ? t / gc : 0, j = has ? t - (t / gc) * gc : 0;
+      const int lx = l & 7, ly = l >> 3;
+      float v[side];
+#pragma unroll
+      for (int z = 0; z < side; ++z) v[z] = has ? tile[(lx + side * (ly + side * z)) * G + j] : 0.0f;
+      __syncthreads();  // every column read: the tile becomes the records
+      float* rec = tile;  // [512][V]
+      if (has) {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+          float a = 0.0f;
+#pragma unroll
+          for (int i = 0; i <= 2 * R; ++i) a += w1[i] * v[o + i];
+          const int vi = lx + 8 * ly + 64 * o;
+          rec[vi * V + c0 + j] = a * inv[vi];
+        }
+      }
+      for (int f = t; f < SG_BLOCK_VOXELS * HELD; f += kDenoiseT) {
+        const int vi = f / HELD;
+        rec[vi * V + (f - vi * HELD)] = held[f];
+      }
+      __syncthreads();
+      float* ob = out + b * SG_BLOCK_VOXELS * V;
+      if ((reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+        for (int f = t; f < SG_BLOCK_VOXELS * V / 4; f += kDenoiseT)
+          reinterpret_cast<float4*>(ob)[f] = reinterpret_cast<const float4*>(rec)[f];
+      } else {
+        for (int f = t; f < SG_BLOCK_VOXELS * V; f += kDenoiseT) ob[f] = rec[f];
+      }
+      continue;
+    }
     for (int f = t; f < 64 * gc; f += kDenoiseT) {
       const int l = f / gc, j = f - l * gc;
       const int lx = l & 7, ly = l >> 3;
@@ -295,7 +352,10 @@ __global__ __launch_bounds__(kDenoiseT) void k_denoise_sep(GridView g,
 #pragma unroll
         for (int i = 0; i <= 2 * R; ++i) a += w1[i] * v[o + i];
         const int vi = lx + 8 * ly + 64 * o;
-        out[(b * SG_BLOCK_VOXELS + vi) * V + c0 + j] = a * inv[vi];
+        if (HELD > 0)
+          held[vi * HELD + c0 + j] = a * inv[vi];
+        else
+          out[(b * SG_BLOCK_VOXELS + vi) * V + c0 + j] = a * inv[vi];
       }
     }
   }
