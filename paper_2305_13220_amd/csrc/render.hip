@@ -1055,6 +1055,12 @@ __global__ __launch_bounds__(256) void k_query(GridView g, const float* __restri
 // gradients of f, grad f and the features at each valid point, corner a
 // receives r_a g_f + (dr_a/du . g_grad) / h in the SDF channel and
 // r_a g_feat[c] in feature channel c (float atomics).
+// The atomics run with lanes laid out (point, channel) over the wave's 64
+// points, corner by corner: consecutive lanes add consecutive channels of
+// one voxel's record, so an instruction covers about three records of
+// 4(1 + C) bytes instead of 64 scattered ones (float atomics on device
+// memory are performed past the L2, one request per 64-byte piece an
+// instruction touches).
 template <int C>
 __global__ __launch_bounds__(256) void k_query_backward(GridView g, const float* __restrict__ pts,
                                                         int64_t m, const float* __restrict__ g_f,
@@ -1063,29 +1069,54 @@ __global__ __launch_bounds__(256) void k_query_backward(GridView g, const float*
                                                         float* __restrict__ grad_vox) {
   constexpr int V = 1 + C;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
+  const int lane = lane_id();
   Cell cell;
-  if (!point_cell(g, pts + 3 * q, cell)) return;
-  const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
-              wz[2] = {1.0f - cell.u[2], cell.u[2]};
-  const float gf = g_f ? g_f[q] : 0.0f;
-  float gg[3] = {0.0f, 0.0f, 0.0f};
-  if (g_grad) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) gg[a] = g_grad[3 * q + a] * g.inv_h;
-  }
+  const bool valid = q < m && point_cell(g, pts + 3 * q, cell);
+  const uint64_t vmask = __ballot(valid);
+  if (vmask == 0) return;  // wave-uniform
+  float ra[8], v0[8];
+  int32_t off[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-    const float ra = wx[ax] * wy[ay] * wz[az];
-    const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gg[0] +
-                     (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gg[1] +
-                     (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gg[2];
-    float* dst = grad_vox + (int64_t)cell.off[a] * V;
-    if (g_f || g_grad) unsafeAtomicAdd(dst, ra * gf + gn);
-    if (g_feat) {
+    ra[a] = 0.0f;
+    v0[a] = 0.0f;
+    off[a] = 0;
+  }
+  if (valid) {
+    const float wx[2] = {1.0f - cell.u[0], cell.u[0]}, wy[2] = {1.0f - cell.u[1], cell.u[1]},
+                wz[2] = {1.0f - cell.u[2], cell.u[2]};
+    const float gf = g_f ? g_f[q] : 0.0f;
+    float gg[3] = {0.0f, 0.0f, 0.0f};
+    if (g_grad) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) unsafeAtomicAdd(dst + 1 + c, ra * g_feat[(int64_t)C * q + c]);
+      for (int a = 0; a < 3; ++a) gg[a] = g_grad[3 * q + a] * g.inv_h;
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      ra[a] = wx[ax] * wy[ay] * wz[az];
+      const float gn = (ax ? 1.0f : -1.0f) * wy[ay] * wz[az] * gg[0] +
+                       (ay ? 1.0f : -1.0f) * wx[ax] * wz[az] * gg[1] +
+                       (az ? 1.0f : -1.0f) * wx[ax] * wy[ay] * gg[2];
+      v0[a] = ra[a] * gf + gn;
+      off[a] = cell.off[a];
+    }
+  }
+  const int64_t q0 = q - lane;  // the wave's first point
+  const bool sdf_side = g_f || g_grad;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    for (int f0 = 0; f0 < kWave * V; f0 += kWave) {
+      const int f = f0 + lane, i = f / V, ch = f - i * V;  // i < kWave
+      const int32_t o = shfl(off[a], i);
+      const float r = shfl(ra[a], i), s0 = shfl(v0[a], i);
+      if ((vmask >> i) & 1) {
+        if (ch == 0) {
+          if (sdf_side) unsafeAtomicAdd(grad_vox + (int64_t)o * V, s0);
+        } else if (g_feat) {
+          unsafeAtomicAdd(grad_vox + (int64_t)o * V + ch, r * g_feat[(int64_t)C * (q0 + i) + ch - 1]);
+        }
+      }
     }
   }
 }
