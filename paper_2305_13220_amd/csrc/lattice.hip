@@ -159,10 +159,29 @@ __device__ inline uint64_t key_fp(const int32_t* k, int d) { return lin_fp(key_l
 
 struct LatView {
   uint64_t* fp;    // [cap] fingerprints (kEmptyKey: free)
-  int32_t* keys;   // [cap][d]
+  int32_t* keys;   // [cap][ks]: the d coordinates, then zeros to ks
   uint64_t mask;   // cap - 1
   int d;
+  int ks;          // row stride: d rounded up to a multiple of 4 (16-byte rows)
 };
+
+__host__ __device__ constexpr int lat_key_stride(int d) { return (d + 3) / 4 * 4; }
+
+// A key row read with 16-byte loads (MAXD is a multiple of 4 and at least
+// ks); k[c] = 0 for c >= d.
+template <int MAXD>
+__device__ inline void load_key(const LatView& L, int64_t s, int32_t k[MAXD]) {
+  static_assert(MAXD % 4 == 0, "whole 16-byte pieces");
+  const int4* row = reinterpret_cast<const int4*>(L.keys + s * L.ks);
+#pragma unroll
+  for (int q = 0; q < MAXD / 4; ++q) {
+    const int4 v = 4 * q < L.d ? row[q] : make_int4(0, 0, 0, 0);
+    k[4 * q] = v.x;
+    k[4 * q + 1] = v.y;
+    k[4 * q + 2] = v.z;
+    k[4 * q + 3] = v.w;
+  }
+}
 
 // Slot of a key of fingerprint f: insert (the CAS winner writes the full
 // key) or find.
@@ -177,9 +196,11 @@ __device__ inline int64_t lat_slot_fp(const LatView& L, const int32_t* k, uint64
                                 : L.fp[s];
     if (cur == kEmptyKey) {
       if (!insert) return -1;
+      // k[c] = 0 for c >= d, so the row's padding is written as zeros
+      int4* row = reinterpret_cast<int4*>(L.keys + s * L.ks);
 #pragma unroll
-      for (int i = 0; i < MAXD; ++i)
-        if (i < L.d) L.keys[s * L.d + i] = k[i];
+      for (int q = 0; q < MAXD / 4; ++q)
+        if (4 * q < L.d) row[q] = make_int4(k[4 * q], k[4 * q + 1], k[4 * q + 2], k[4 * q + 3]);
       return (int64_t)s;
     }
     if (cur == f) return (int64_t)s;
@@ -224,9 +245,11 @@ __global__ __launch_bounds__(256) void k_lat_simplex(const float* __restrict__ p
       bw[i * (d + 1) + r] = s.w[r];
     } else {
       const int64_t slot = vid[i * (d + 1) + r];
+      int32_t held[MAXD];
+      load_key<MAXD>(L, slot, held);
       bool same = true;
 #pragma unroll
-      for (int c = 0; c < MAXD; ++c) same = same && (c >= d || L.keys[slot * d + c] == k[c]);
+      for (int c = 0; c < MAXD; ++c) same = same && (c >= d || held[c] == k[c]);
       if (!same) atomicOr(err, 1);
     }
   }
@@ -300,10 +323,10 @@ __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int
   if (k >= nv) return;
   const int64_t s = list[k];
   int32_t key[MAXD];
+  load_key<MAXD>(L, s, key);
   uint64_t lin = 0, sum = 0;
 #pragma unroll
   for (int c = 0; c < MAXD; ++c) {
-    key[c] = c < d ? L.keys[s * d + c] : 0;
     if (c < d) {
       lin += (uint64_t)(int64_t)key[c] * kLatCoef[c];
       sum += kLatCoef[c];
@@ -317,10 +340,12 @@ __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int
       const int sgn = h == 0 ? -1 : 1;
       int64_t n = lat_slot_fp<MAXD>(L, nullptr, lin_fp(h == 0 ? lin - off : lin + off), false);
       if (n >= 0) {
+        int32_t cand[MAXD];
+        load_key<MAXD>(L, n, cand);
         bool same = true;
 #pragma unroll
         for (int c = 0; c < MAXD; ++c)
-          same = same && (c >= d || L.keys[n * d + c] == key[c] + sgn * (c == j ? -d : 1));
+          same = same && (c >= d || cand[c] == key[c] + sgn * (c == j ? -d : 1));
         if (!same) n = -1;  // a fingerprint alias of an absent key: no neighbour
       }
       nbr[2 * ((int64_t)j * nv + k) + h] = (int32_t)n;
@@ -627,7 +652,7 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
                       bool reverse = false) {
   const int T = 256;
   const int d = L->d;
-  const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d};
+  const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d, lat_key_stride(d)};
   const int64_t nv = L->n_vertices;
   k_lat_zero<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, nv, vd, L->v0);
   k_lat_splat<<<grid_of(L->N * (d + 1) * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, d_val, vd,
@@ -655,7 +680,7 @@ static int64_t lat_sizes(int64_t n_points, int d, int max_values, size_t sz[8]) 
   int64_t cap = 1;
   while (cap < 2 * n_points * (d + 1)) cap <<= 1;
   sz[0] = sizeof(uint64_t) * cap;
-  sz[1] = sizeof(int32_t) * cap * d;
+  sz[1] = sizeof(int32_t) * cap * lat_key_stride(d);
   sz[2] = sizeof(int32_t) * n_points * (d + 1);
   sz[3] = sizeof(float) * n_points * (d + 1);
   sz[4] = sizeof(float) * cap * max_values;
@@ -813,7 +838,7 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
     return fail(SG_ENOMEM, "device allocation for the lattice failed");
   }
   const int T = 256;
-  const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d};
+  const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d, lat_key_stride(d)};
   int rc = SG_OK;
   int err = 0;
   int64_t nv = 0;

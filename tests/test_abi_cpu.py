@@ -221,7 +221,8 @@ def test_lattice_and_workspace_sizes(L):
         cap = 1
         while cap < 2 * n * (d + 1):
             cap <<= 1
-        return (cap * (8 + 4 * d + 8 * v + 4) + n * (d + 1) * 8 + n * v * 4
+        ks = (d + 3) // 4 * 4  # key rows padded to 16 bytes
+        return (cap * (8 + 4 * ks + 8 * v + 4) + n * (d + 1) * 8 + n * v * 4
                 + 4 * 2 * (d + 1) * n * (d + 1))
     for n, d, v in ((1, 1, 1), (1000, 6, 16), (262144, 6, 16), (5, 16, 32)):
         assert L.sg_lattice_bytes(n, d, v) == lat(n, d, v)
