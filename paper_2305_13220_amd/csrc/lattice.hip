@@ -370,6 +370,33 @@ __global__ void k_lat_blur_tab(const int32_t* __restrict__ list, const int32_t* 
   dst[s * vd + c] = v;
 }
 
+// The same with lanes laid out (vertex, four channels) where a row is a
+// whole number of 16-byte pieces (vd a multiple of 4): a quarter of the
+// memory instructions for the same per-channel arithmetic.
+__global__ void k_lat_blur_tab4(const int32_t* __restrict__ list, const int32_t* __restrict__ nbr,
+                                int64_t nv, const float* __restrict__ src, int vd,
+                                float* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int vq = vd / 4;
+  if (t >= nv * vq) return;
+  const int64_t k = t / vq;
+  const int c = (int)(t - k * vq);
+  const int64_t s = list[k];
+  const int2 ab = reinterpret_cast<const int2*>(nbr)[k];
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  const float4 o = s4[s * vq + c];
+  const float4 na = ab.x >= 0 ? s4[(int64_t)ab.x * vq + c] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float4 nb = ab.y >= 0 ? s4[(int64_t)ab.y * vq + c] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float v[4] = {0.5f * o.x, 0.5f * o.y, 0.5f * o.z, 0.5f * o.w};
+  const float va[4] = {na.x, na.y, na.z, na.w}, vb[4] = {nb.x, nb.y, nb.z, nb.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (ab.x >= 0) v[e] += 0.25f * va[e];
+    if (ab.y >= 0) v[e] += 0.25f * vb[e];
+  }
+  reinterpret_cast<float4*>(dst)[s * vq + c] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // Lanes laid out (point, channel): consecutive lanes read one vertex row.
 __global__ void k_lat_slice(const int32_t* __restrict__ vid, const float* __restrict__ bw,
                             int64_t N, int d, const float* __restrict__ lv, int vd,
@@ -661,8 +688,12 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   float* b = L->v1;
   for (int jj = 0; jj <= d; ++jj) {
     const int j = reverse ? d - jj : jj;
-    k_lat_blur_tab<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, L->nbr + (int64_t)j * nv * 2, nv, a,
-                                                      vd, b);
+    if (vd % 4 == 0)
+      k_lat_blur_tab4<<<grid_of(nv * (vd / 4), T), T, 0, s>>>(L->list, L->nbr + (int64_t)j * nv * 2,
+                                                               nv, a, vd, b);
+    else
+      k_lat_blur_tab<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, L->nbr + (int64_t)j * nv * 2, nv,
+                                                        a, vd, b);
     float* t = a;
     a = b;
     b = t;
