@@ -285,6 +285,17 @@ __global__ __launch_bounds__(kLatCompactT) void k_lat_compact(const uint64_t* __
   if (used) list[bbase + wbase[w] + rank_below(b)] = (int32_t)s;
 }
 
+// Zero the value rows of the occupied slots (lanes (vertex, four channels)
+// with 16-byte stores where a row is a whole number of them).
+__global__ void k_lat_zero4(const int32_t* __restrict__ list, int64_t nv, int vd,
+                            float* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int vq = vd / 4;
+  if (t >= nv * vq) return;
+  const int64_t k = t / vq;
+  reinterpret_cast<float4*>(v)[(int64_t)list[k] * vq + (t - k * vq)] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 // Zero the value rows of the occupied slots.
 __global__ void k_lat_zero(const int32_t* __restrict__ list, int64_t nv, int vd,
                            float* __restrict__ v) {
@@ -411,6 +422,31 @@ __global__ void k_lat_slice(const int32_t* __restrict__ vid, const float* __rest
     acc += bw[pr] * lv[(int64_t)vid[pr] * vd + c];
   }
   out[t] = acc;
+}
+
+// The same with lanes laid out (point, four channels) where a row is a
+// whole number of 16-byte pieces; each channel sums the vertices in the
+// same order.
+__global__ void k_lat_slice4(const int32_t* __restrict__ vid, const float* __restrict__ bw,
+                             int64_t N, int d, const float* __restrict__ lv, int vd,
+                             float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int vq = vd / 4;
+  if (t >= N * vq) return;
+  const int64_t i = t / vq;
+  const int c = (int)(t - i * vq);
+  const float4* l4 = reinterpret_cast<const float4*>(lv);
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int r = 0; r <= d; ++r) {
+    const int64_t pr = i * (d + 1) + r;
+    const float w = bw[pr];
+    const float4 x = l4[(int64_t)vid[pr] * vq + c];
+    acc[0] += w * x.x;
+    acc[1] += w * x.y;
+    acc[2] += w * x.z;
+    acc[3] += w * x.w;
+  }
+  reinterpret_cast<float4*>(out)[t] = make_float4(acc[0], acc[1], acc[2], acc[3]);
 }
 
 // Q = softmax(-unary + w_p * m) per point (m may be null: w_p ignored).
@@ -681,7 +717,10 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   const int d = L->d;
   const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d, lat_key_stride(d)};
   const int64_t nv = L->n_vertices;
-  k_lat_zero<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, nv, vd, L->v0);
+  if (vd % 4 == 0)
+    k_lat_zero4<<<grid_of(nv * (vd / 4), T), T, 0, s>>>(L->list, nv, vd, L->v0);
+  else
+    k_lat_zero<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, nv, vd, L->v0);
   k_lat_splat<<<grid_of(L->N * (d + 1) * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, d_val, vd,
                                                               L->v0);
   float* a = L->v0;
@@ -698,7 +737,10 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
     a = b;
     b = t;
   }
-  k_lat_slice<<<grid_of(L->N * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, a, vd, d_out);
+  if (vd % 4 == 0 && reinterpret_cast<uintptr_t>(d_out) % 16 == 0)
+    k_lat_slice4<<<grid_of(L->N * (vd / 4), T), T, 0, s>>>(L->vid, L->bw, L->N, d, a, vd, d_out);
+  else
+    k_lat_slice<<<grid_of(L->N * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, a, vd, d_out);
   SG_HIP_CHECK(hipGetLastError());
   return SG_OK;
 }
