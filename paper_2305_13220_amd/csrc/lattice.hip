@@ -285,24 +285,30 @@ __global__ __launch_bounds__(kLatCompactT) void k_lat_compact(const uint64_t* __
   if (used) list[bbase + wbase[w] + rank_below(b)] = (int32_t)s;
 }
 
-// Zero the value rows of the occupied slots (lanes (vertex, four channels)
-// with 16-byte stores where a row is a whole number of them).
-__global__ void k_lat_zero4(const int32_t* __restrict__ list, int64_t nv, int vd,
-                            float* __restrict__ v) {
+// Zero the value rows of the nv vertices (contiguous: rows are indexed by
+// vertex number), 16-byte stores where the count allows.
+__global__ void k_lat_zero(int64_t n, float* __restrict__ v) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int vq = vd / 4;
-  if (t >= nv * vq) return;
-  const int64_t k = t / vq;
-  reinterpret_cast<float4*>(v)[(int64_t)list[k] * vq + (t - k * vq)] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (t < n) v[t] = 0.0f;
+}
+__global__ void k_lat_zero4(int64_t n4, float4* __restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n4) v[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Zero the value rows of the occupied slots.
-__global__ void k_lat_zero(const int32_t* __restrict__ list, int64_t nv, int vd,
-                           float* __restrict__ v) {
+// Vertex numbers: vertex k of the occupied-slot list is number k; num is a
+// slot-indexed scratch array.  The per-point vertex ids and the blur
+// neighbours are then held as numbers, so the value rows are compact
+// (rows 0..nv-1) rather than spread over the table's slots.
+__global__ void k_lat_number(const int32_t* __restrict__ list, int64_t nv,
+                             int32_t* __restrict__ num) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nv) num[list[k]] = (int32_t)k;
+}
+__global__ void k_lat_renumber(int32_t* __restrict__ vid, int64_t n,
+                               const int32_t* __restrict__ num) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nv * vd) return;
-  const int64_t k = t / vd;
-  v[(int64_t)list[k] * vd + (t - k * vd)] = 0.0f;
+  if (t < n) vid[t] = num[vid[t]];
 }
 
 // Lanes laid out (point-vertex pair, channel): the channels of one vertex
@@ -321,11 +327,12 @@ __global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __rest
 }
 
 // Blur neighbours of every occupied vertex, found once at build: for list
-// entry k and direction j, the slots of key -+ ((1,...,1) - (d+1) e_j) (first
-// d coordinates), -1 where absent; filters then blur through this table.
+// entry k and direction j, the vertex numbers of key -+ ((1,...,1) - (d+1) e_j)
+// (first d coordinates), -1 where absent; filters then blur through this
+// table.
 template <int MAXD>
 __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int64_t nv,
-                                int32_t* __restrict__ nbr) {
+                                const int32_t* __restrict__ num, int32_t* __restrict__ nbr) {
   // one lane per vertex, every direction: the key is read once, and each
   // neighbour's fingerprint is the vertex's linear form plus or minus the
   // direction's offset form
@@ -359,43 +366,39 @@ __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int
           same = same && (c >= d || cand[c] == key[c] + sgn * (c == j ? -d : 1));
         if (!same) n = -1;  // a fingerprint alias of an absent key: no neighbour
       }
-      nbr[2 * ((int64_t)j * nv + k) + h] = (int32_t)n;
+      nbr[2 * ((int64_t)j * nv + k) + h] = n >= 0 ? num[n] : -1;
     }
   }
 }
 
 // Blur along direction j through the neighbour table, lanes laid out
 // (vertex, channel): new = v/2 + (v(n-) + v(n+))/4.
-__global__ void k_lat_blur_tab(const int32_t* __restrict__ list, const int32_t* __restrict__ nbr,
-                               int64_t nv, const float* __restrict__ src, int vd,
-                               float* __restrict__ dst) {
+__global__ void k_lat_blur_tab(const int32_t* __restrict__ nbr, int64_t nv,
+                               const float* __restrict__ src, int vd, float* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nv * vd) return;
   const int64_t k = t / vd;
   const int c = (int)(t - k * vd);
-  const int64_t s = list[k];
   const int32_t a = nbr[2 * k], b = nbr[2 * k + 1];
-  float v = 0.5f * src[s * vd + c];
+  float v = 0.5f * src[t];
   if (a >= 0) v += 0.25f * src[(int64_t)a * vd + c];
   if (b >= 0) v += 0.25f * src[(int64_t)b * vd + c];
-  dst[s * vd + c] = v;
+  dst[t] = v;
 }
 
 // The same with lanes laid out (vertex, four channels) where a row is a
 // whole number of 16-byte pieces (vd a multiple of 4): a quarter of the
 // memory instructions for the same per-channel arithmetic.
-__global__ void k_lat_blur_tab4(const int32_t* __restrict__ list, const int32_t* __restrict__ nbr,
-                                int64_t nv, const float* __restrict__ src, int vd,
-                                float* __restrict__ dst) {
+__global__ void k_lat_blur_tab4(const int32_t* __restrict__ nbr, int64_t nv,
+                                const float* __restrict__ src, int vd, float* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int vq = vd / 4;
   if (t >= nv * vq) return;
   const int64_t k = t / vq;
   const int c = (int)(t - k * vq);
-  const int64_t s = list[k];
   const int2 ab = reinterpret_cast<const int2*>(nbr)[k];
   const float4* s4 = reinterpret_cast<const float4*>(src);
-  const float4 o = s4[s * vq + c];
+  const float4 o = s4[t];
   const float4 na = ab.x >= 0 ? s4[(int64_t)ab.x * vq + c] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   const float4 nb = ab.y >= 0 ? s4[(int64_t)ab.y * vq + c] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   float v[4] = {0.5f * o.x, 0.5f * o.y, 0.5f * o.z, 0.5f * o.w};
@@ -405,7 +408,7 @@ __global__ void k_lat_blur_tab4(const int32_t* __restrict__ list, const int32_t*
     if (ab.x >= 0) v[e] += 0.25f * va[e];
     if (ab.y >= 0) v[e] += 0.25f * vb[e];
   }
-  reinterpret_cast<float4*>(dst)[s * vq + c] = make_float4(v[0], v[1], v[2], v[3]);
+  reinterpret_cast<float4*>(dst)[t] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
 // Lanes laid out (point, channel): consecutive lanes read one vertex row.
@@ -681,13 +684,13 @@ struct sg_lattice {
   int64_t N, cap, n_vertices;
   uint64_t* fp;
   int32_t* keys;
-  int32_t* list;  // [cap] occupied slots, n_vertices of them
-  int32_t* vid;
+  int32_t* list;  // [cap] occupied slots, n_vertices of them (vertex k at list[k])
+  int32_t* vid;   // [N][d+1] vertex numbers of each point's simplex
   float* bw;
-  float* v0;
+  float* v0;  // [n_vertices, vd] value rows by vertex number (allocated for cap rows)
   float* v1;
   float* m;  // [N, vmax] message buffer of the mean-field update
-  int32_t* nbr;  // [d+1][n_vertices][2] blur neighbours' slots (-1: absent)
+  int32_t* nbr;  // [d+1][n_vertices][2] blur neighbours' vertex numbers (-1: absent)
 };
 
 namespace sg {
@@ -717,10 +720,10 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   const int d = L->d;
   const LatView V = {L->fp, L->keys, (uint64_t)L->cap - 1, d, lat_key_stride(d)};
   const int64_t nv = L->n_vertices;
-  if (vd % 4 == 0)
-    k_lat_zero4<<<grid_of(nv * (vd / 4), T), T, 0, s>>>(L->list, nv, vd, L->v0);
+  if ((nv * vd) % 4 == 0)
+    k_lat_zero4<<<grid_of(nv * vd / 4, T), T, 0, s>>>(nv * vd / 4, reinterpret_cast<float4*>(L->v0));
   else
-    k_lat_zero<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, nv, vd, L->v0);
+    k_lat_zero<<<grid_of(nv * vd, T), T, 0, s>>>(nv * vd, L->v0);
   k_lat_splat<<<grid_of(L->N * (d + 1) * vd, T), T, 0, s>>>(L->vid, L->bw, L->N, d, d_val, vd,
                                                               L->v0);
   float* a = L->v0;
@@ -728,11 +731,10 @@ static int lat_filter(const sg_lattice* L, const float* d_val, int vd, float* d_
   for (int jj = 0; jj <= d; ++jj) {
     const int j = reverse ? d - jj : jj;
     if (vd % 4 == 0)
-      k_lat_blur_tab4<<<grid_of(nv * (vd / 4), T), T, 0, s>>>(L->list, L->nbr + (int64_t)j * nv * 2,
-                                                               nv, a, vd, b);
+      k_lat_blur_tab4<<<grid_of(nv * (vd / 4), T), T, 0, s>>>(L->nbr + (int64_t)j * nv * 2, nv, a,
+                                                               vd, b);
     else
-      k_lat_blur_tab<<<grid_of(nv * vd, T), T, 0, s>>>(L->list, L->nbr + (int64_t)j * nv * 2, nv,
-                                                        a, vd, b);
+      k_lat_blur_tab<<<grid_of(nv * vd, T), T, 0, s>>>(L->nbr + (int64_t)j * nv * 2, nv, a, vd, b);
     float* t = a;
     a = b;
     b = t;
@@ -953,12 +955,18 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
       return fail(SG_ENOMEM, "device allocation for the lattice failed");
     }
     if (nv > 0) {
+      // slot -> vertex number in the second value buffer (cap >= nv int32 of
+      // room; filters overwrite it later), then the point-vertex ids and the
+      // neighbour table as numbers
+      int32_t* num = reinterpret_cast<int32_t*>(L->v1);
+      k_lat_number<<<grid_of(nv, T), T, 0, s>>>(L->list, nv, num);
+      k_lat_renumber<<<grid_of(L->N * (d + 1), T), T, 0, s>>>(L->vid, L->N * (d + 1), num);
       if (d <= 8)
-        k_lat_neighbors<8><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+        k_lat_neighbors<8><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, num, L->nbr);
       else if (d <= 16)
-        k_lat_neighbors<16><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+        k_lat_neighbors<16><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, num, L->nbr);
       else
-        k_lat_neighbors<kLatMaxD><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, L->nbr);
+        k_lat_neighbors<kLatMaxD><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, num, L->nbr);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) {
