@@ -350,23 +350,25 @@ __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int
       sum += kLatCoef[c];
     }
   }
+  // The relation is symmetric: when B is A's neighbour on the plus side
+  // of direction j, A is B's on the minus side.  So each vertex probes the
+  // plus side only and writes both entries (the table starts at -1; each
+  // entry has one writer, the vertex one step below along j).
   for (int j = 0; j <= d; ++j) {
     // offset of direction j: +1 on every coordinate, -d on coordinate j
     const uint64_t off = sum - (j < d ? (uint64_t)(d + 1) * kLatCoef[j] : 0ull);
+    const int64_t n = lat_slot_fp<MAXD>(L, nullptr, lin_fp(lin + off), false);
+    if (n >= 0) {
+      int32_t cand[MAXD];
+      load_key<MAXD>(L, n, cand);
+      bool same = true;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int sgn = h == 0 ? -1 : 1;
-      int64_t n = lat_slot_fp<MAXD>(L, nullptr, lin_fp(h == 0 ? lin - off : lin + off), false);
-      if (n >= 0) {
-        int32_t cand[MAXD];
-        load_key<MAXD>(L, n, cand);
-        bool same = true;
-#pragma unroll
-        for (int c = 0; c < MAXD; ++c)
-          same = same && (c >= d || cand[c] == key[c] + sgn * (c == j ? -d : 1));
-        if (!same) n = -1;  // a fingerprint alias of an absent key: no neighbour
+      for (int c = 0; c < MAXD; ++c) same = same && (c >= d || cand[c] == key[c] + (c == j ? -d : 1));
+      if (same) {  // otherwise a fingerprint alias of an absent key: no neighbour
+        const int32_t b = num[n];
+        nbr[2 * ((int64_t)j * nv + k) + 1] = b;
+        nbr[2 * ((int64_t)j * nv + b)] = (int32_t)k;
       }
-      nbr[2 * ((int64_t)j * nv + k) + h] = n >= 0 ? num[n] : -1;
     }
   }
 }
@@ -960,6 +962,11 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
       // neighbour table as numbers
       int32_t* num = reinterpret_cast<int32_t*>(L->v1);
       k_lat_number<<<grid_of(nv, T), T, 0, s>>>(L->list, nv, num);
+      if (hipMemsetAsync(L->nbr, 0xff, nb_bytes, s) != hipSuccess) {  // every entry -1
+        (void)hipGetLastError();
+        free_lat(L);
+        return fail(SG_EHIP, "hipMemsetAsync failed");
+      }
       k_lat_renumber<<<grid_of(L->N * (d + 1), T), T, 0, s>>>(L->vid, L->N * (d + 1), num);
       if (d <= 8)
         k_lat_neighbors<8><<<grid_of(nv, T), T, 0, s>>>(V, L->list, nv, num, L->nbr);
