@@ -333,8 +333,8 @@ __global__ void k_lat_splat(const int32_t* __restrict__ vid, const float* __rest
 template <int MAXD>
 __global__ void k_lat_neighbors(LatView L, const int32_t* __restrict__ list, int64_t nv,
                                 const int32_t* __restrict__ num, int32_t* __restrict__ nbr) {
-  // one lane per vertex, every direction: the key is read once, and each
-  // neighbour's fingerprint is the vertex's linear form plus or minus the
+  // one lane per vertex, every direction: the key is read once, and the
+  // plus-side neighbour's fingerprint is the vertex's linear form plus the
   // direction's offset form
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int d = L.d;
