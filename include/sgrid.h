@@ -281,12 +281,13 @@ int sg_denoise(const sg_grid* g, const float* d_vox, int32_t C, int32_t radius, 
  *   (checked, never silently merged).
  * sg_lattice_bytes -- device bytes a build of these sizes allocates at most
  *   (a host computation, for memory planning): a hash table of the smallest
- *   power of two >= 2 n (d+1) slots (8-byte fingerprint, d int32 key, two
- *   max_values-float value rows, an int32 slot-list entry each) plus n (d+1)
- *   vertex ids and weights, n max_values slice outputs, and the blur
- *   neighbour table (the two neighbours' slots of each vertex along each of
- *   the d+1 directions, 2 (d+1) int32 per vertex, sized for the at most
- *   n (d+1) vertices); 0 for invalid sizes (the limits of sg_lattice_build).
+ *   power of two >= 2 n (d+1) slots (8-byte fingerprint, an int32 key of d
+ *   coordinates padded to a multiple of 4, two max_values-float value rows,
+ *   an int32 slot-list entry each) plus n (d+1) vertex ids and weights,
+ *   n max_values slice outputs, and the blur neighbour table (the two
+ *   neighbours of each vertex along each of the d+1 directions, 2 (d+1)
+ *   int32 per vertex, sized for the at most n (d+1) vertices); 0 for invalid
+ *   sizes (the limits of sg_lattice_build).
  * sg_lattice_filter -- d_out [n, n_values] = slice(blur(splat(d_val))):
  *   values splatted onto the simplex vertices with the barycentric weights,
  *   blurred with [1/4, 1/2, 1/4] along each of the d+1 lattice directions
