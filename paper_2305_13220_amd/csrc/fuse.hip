@@ -152,7 +152,9 @@ __global__ __launch_bounds__(512) void k_denoise(GridView g, const int32_t* __re
 // consecutive floats); each pass runs in place, one lane per line of the
 // tile and channel: along x over side^2 lines, along y over 8 side (the x
 // range left by the first pass), and along z over the block's 8 x 8 columns,
-// which write the output.  The mask goes through the same passes once, and
+// which write the output (or, with several channel groups where LDS allows,
+// hold it until whole records are written after the last group, as
+// denoise_held below describes).  The mask goes through the same passes once, and
 // each voxel's weight sum is kept for the renormalisation.  Results equal
 // k_denoise's up to rounding order.
 constexpr int kTileR = 2;
