@@ -256,33 +256,49 @@ __global__ __launch_bounds__(256) void k_lat_simplex(const float* __restrict__ p
 }
 
 // List of the occupied slots (in no particular order) and their number.
-// One counter atomic per workgroup (the waves' counts are prefixed in LDS):
-// with one per wave the 4M-slot table of 2^18 points at d = 6 spent most of
-// the compaction serialised on the counter.
-constexpr int kLatCompactT = 1024;
+// Each 1024-lane workgroup takes kLatCompactPer slots per lane (lane l's
+// i-th is slot base + l + 1024 i, so every pass is coalesced), counts them
+// per wave and pass into LDS, and takes its range of the list with one
+// counter atomic: the atomics on the one counter are serialised, so with
+// one per 1024 slots the 16M-slot table of a d = 22 build spent most of the
+// compaction on them.
+constexpr int kLatCompactT = 1024, kLatCompactPer = 16;
 __global__ __launch_bounds__(kLatCompactT) void k_lat_compact(const uint64_t* __restrict__ fp,
                                                               int64_t cap,
                                                               unsigned long long* __restrict__ n,
                                                               int32_t* __restrict__ list) {
-  __shared__ unsigned long long wbase[kLatCompactT / kWave];
+  constexpr int NW = kLatCompactT / kWave;
+  __shared__ unsigned long long off[kLatCompactPer][NW];
   __shared__ unsigned long long bbase;
-  const int64_t s = (int64_t)blockIdx.x * kLatCompactT + threadIdx.x;
   const int w = threadIdx.x / kWave;
-  const bool used = s < cap && fp[s] != kEmptyKey;
-  const uint64_t b = __ballot(used);
-  if (lane_id() == 0) wbase[w] = (unsigned long long)__popcll(b);
+  const int64_t base = (int64_t)blockIdx.x * kLatCompactT * kLatCompactPer + threadIdx.x;
+  uint32_t used = 0;
+#pragma unroll
+  for (int i = 0; i < kLatCompactPer; ++i) {
+    const int64_t s = base + (int64_t)i * kLatCompactT;
+    const bool u = s < cap && fp[s] != kEmptyKey;
+    used |= (uint32_t)u << i;
+    const uint64_t b = __ballot(u);
+    if (lane_id() == 0) off[i][w] = (unsigned long long)__popcll(b);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long acc = 0;
-    for (int k = 0; k < kLatCompactT / kWave; ++k) {
-      const unsigned long long c = wbase[k];
-      wbase[k] = acc;
-      acc += c;
-    }
+    for (int i = 0; i < kLatCompactPer; ++i)
+      for (int k = 0; k < NW; ++k) {
+        const unsigned long long c = off[i][k];
+        off[i][k] = acc;
+        acc += c;
+      }
     bbase = acc ? atomicAdd(n, acc) : 0;
   }
   __syncthreads();
-  if (used) list[bbase + wbase[w] + rank_below(b)] = (int32_t)s;
+#pragma unroll
+  for (int i = 0; i < kLatCompactPer; ++i) {
+    const bool u = (used >> i) & 1u;
+    const uint64_t b = __ballot(u);
+    if (u) list[bbase + off[i][w] + rank_below(b)] = (int32_t)(base + (int64_t)i * kLatCompactT);
+  }
 }
 
 // Zero the value rows of the nv vertices (contiguous: rows are indexed by
@@ -932,7 +948,7 @@ int sg_lattice_build(const float* d_pos, int64_t n_points, int32_t d, int32_t ma
       else
         k_lat_simplex<kLatMaxD><<<grid_of(n_points, T), T, 0, s>>>(d_pos, n_points, V, mode, L->vid, L->bw, d_err);
     }
-    k_lat_compact<<<grid_of(L->cap, kLatCompactT), kLatCompactT, 0, s>>>(
+    k_lat_compact<<<grid_of(L->cap, kLatCompactT * kLatCompactPer), kLatCompactT, 0, s>>>(
         L->fp, L->cap, (unsigned long long*)d_n, L->list);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s);
