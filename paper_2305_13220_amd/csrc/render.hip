@@ -1060,7 +1060,8 @@ __global__ __launch_bounds__(256) void k_query(GridView g, const float* __restri
 // one voxel's record, so an instruction covers about three records of
 // 4(1 + C) bytes instead of 64 scattered ones (float atomics on device
 // memory are performed past the L2, one request per 64-byte piece an
-// instruction touches).
+// instruction touches).  Without feature gradients only the SDF channel is
+// emitted, one lane per point.
 template <int C>
 __global__ __launch_bounds__(256) void k_query_backward(GridView g, const float* __restrict__ pts,
                                                         int64_t m, const float* __restrict__ g_f,
@@ -1104,10 +1105,11 @@ __global__ __launch_bounds__(256) void k_query_backward(GridView g, const float*
   }
   const int64_t q0 = q - lane;  // the wave's first point
   const bool sdf_side = g_f || g_grad;
+  const int VE = g_feat ? V : 1;  // channels emitted per voxel (uniform)
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    for (int f0 = 0; f0 < kWave * V; f0 += kWave) {
-      const int f = f0 + lane, i = f / V, ch = f - i * V;  // i < kWave
+    for (int f0 = 0; f0 < kWave * VE; f0 += kWave) {
+      const int f = f0 + lane, i = f / VE, ch = f - i * VE;  // i < kWave
       const int32_t o = shfl(off[a], i);
       const float r = shfl(ra[a], i), s0 = shfl(v0[a], i);
       if ((vmask >> i) & 1) {
